@@ -362,3 +362,36 @@ def turbulence(n=768, seed=4, kmax=8, mach=0.3, gamma=5.0 / 3.0,
         U[:, z0:z1] = sl.astype(dtype)
     return Problem(U=U, dx=(1.0 / n,) * 3, gamma=gamma, name="turbulence",
                    meta={"seed": seed, "mach": mach})
+
+
+def batch_pool(specs, ng=4, dtype=np.float64, align=64, gamma=5.0 / 3.0):
+    """Pack the interior states of `specs` into one flat pool: patch p holds 5
+    planes of (n+2ng)^3 elements (x fastest) starting at a multiple of
+    `align` elements; ghost layers hold the periodic wrap of the interior.
+    Returns (pool, patches) with patches[p] = (offset_elems, nx, ny, nz, ng,
+    dx, dy, dz)."""
+    offsets = []
+    off = 0
+    for s in specs:
+        m = s.n + 2 * ng
+        offsets.append(off)
+        off += 5 * m ** 3
+        off = (off + align - 1) // align * align
+    pool = np.zeros(off, dtype=dtype)
+    patches = []
+    for s, o in zip(specs, offsets):
+        m = s.n + 2 * ng
+        U = kh_patch(s, gamma)
+        if ng:
+            U = np.pad(U, ((0, 0), (ng, ng), (ng, ng), (ng, ng)), mode="wrap")
+        pool[o:o + 5 * m ** 3] = U.astype(dtype).ravel()
+        d = 1.0 / s.n
+        patches.append((o, s.n, s.n, s.n, ng, d, d, d))
+    return pool, patches
+
+
+def patch_view(pool, patch):
+    """(5, n+2ng, n+2ng, n+2ng) view of one patch of a pool."""
+    o, nx, ny, nz, ng = patch[:5]
+    return pool[o:o + 5 * (nx + 2 * ng) * (ny + 2 * ng) * (nz + 2 * ng)].reshape(
+        5, nz + 2 * ng, ny + 2 * ng, nx + 2 * ng)

@@ -1,0 +1,235 @@
+/*
+ * hydro.h -- C ABI of libhydro: the finite-volume compressible-Euler zone
+ * update on one AMD Instinct MI355X (gfx950).
+ *
+ * Zingale, Calder, Malone & Timmes (arXiv:1510.05061) model an exploding
+ * star as a fluid on a decomposed grid, with nearest-neighbour and global
+ * communication every timestep (introduction; section "Capabilities
+ * needed"), and argue for suites of independent runs (section "Increasing
+ * computing power"; capacity computing under "Capabilities needed").  The
+ * paper gives no numerical method.  This library implements the standard
+ * one for that setting:
+ *   - ideal-gas Euler equations, U = (rho, mx, my, mz, E),
+ *     p = (gamma-1)(E - |m|^2/(2 rho));
+ *   - primitive piecewise-linear reconstruction with the MC limiter
+ *     (van Leer 1977) and the MUSCL-Hancock predictor (Toro 2009 sec. 14.4);
+ *   - HLLC fluxes with Davis wave speeds (Toro, Spruce & Speares 1994;
+ *     Toro 2009 sec. 10.4);
+ *   - conservative, dimensionally split sweeps: x,y,z on even steps and
+ *     z,y,x on odd steps (Strang 1968); a sweep along an axis with one cell
+ *     is skipped;
+ *   - a constant gravity source (predictor half kick, time-centred momentum
+ *     source, energy source from the face mass fluxes);
+ *   - dt = cfl / max over cells and active axes of (|v_d| + c) / dx_d, a
+ *     global max reduction kept in FP64 on the device.
+ *
+ * Data layout (caller-owned device memory, never allocated or freed here):
+ *   state = 5 planes (rho, mx, my, mz, E); each plane holds
+ *   (nz+2ng)(ny+2ng)(nx+2ng) elements, x fastest, then y, then z; plane v
+ *   starts at element v * plane_elems.  Elements are float (HYDRO_FP32) or
+ *   double (HYDRO_FP64).  Interior cell (i,j,k) sits at stored index
+ *   (i+ng, j+ng, k+ng).  Stored ghost layers (ng > 0) are never read or
+ *   written: boundary conditions are applied on the fly.  The state pointer
+ *   must be 16-byte aligned; 256-byte alignment is recommended.
+ *
+ * Precision: HYDRO_FP32 keeps the state and the per-zone arithmetic in FP32
+ * while dt, t, the CFL maximum and the conserved totals are FP64.
+ * HYDRO_FP64 runs everything in FP64.
+ *
+ * Streams and synchronisation: every call enqueues on the stream given at
+ * init (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream) and
+ * returns without waiting, except the calls marked "Synchronous", which
+ * wait for that stream.  A context is not thread-safe; separate contexts on
+ * separate streams may run concurrently if their buffers do not overlap.
+ *
+ * Errors: every function returns a hydro_status; no C++ exception crosses
+ * this interface.  hydro_last_error() describes the last failure of the
+ * calling thread.
+ */
+#ifndef HYDRO_H
+#define HYDRO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HYDRO_ABI_VERSION 1
+
+typedef enum hydro_status {
+  HYDRO_OK = 0,
+  HYDRO_EINVAL = 1,   /* bad descriptor, argument, pointer or workspace size */
+  HYDRO_EDEVICE = 2,  /* a HIP runtime call failed */
+  HYDRO_ENUMERIC = 3, /* sticky device flag: rho <= 0, p <= 0 or a non-finite
+                         value after an update, or a zero/non-finite signal
+                         speed */
+  HYDRO_ESTATE = 4    /* call out of order (e.g. a batch call on a grid ctx) */
+} hydro_status;
+
+typedef enum hydro_bc {
+  HYDRO_BC_PERIODIC = 0, /* wrap; must be set on both sides of an axis */
+  HYDRO_BC_OUTFLOW = 1,  /* zero gradient: ghosts copy the edge cell */
+  HYDRO_BC_REFLECT = 2   /* mirror: ghost -k copies cell k-1 with the normal
+                            momentum negated; gravity is mirrored too */
+} hydro_bc;
+
+typedef enum hydro_precision { HYDRO_FP32 = 0, HYDRO_FP64 = 1 } hydro_precision;
+
+/* hydro_desc.flags */
+#define HYDRO_FLAG_NO_GRAPH 0x1u /* launch kernels one by one, no hipGraph */
+#define HYDRO_FLAG_NO_TUNE 0x2u  /* skip the autotuner and its cache; use the
+                                    built-in default configuration */
+
+/* dt argument of hydro_step / hydro_batch_step: use the CFL dt held on the
+ * device (no host synchronisation). */
+#define HYDRO_DT_CFL 0.0
+
+typedef struct hydro_desc {
+  int32_t nx, ny, nz;  /* interior cells per axis (>= 1; an axis with more
+                          than one cell needs at least 2) */
+  int32_t ng;          /* stored ghost layers per side (>= 0) */
+  double dx, dy, dz;   /* cell widths (> 0) */
+  double gamma;        /* ratio of specific heats (> 1) */
+  double cfl;          /* Courant number in (0, 1] */
+  double grav[3];      /* constant gravitational acceleration */
+  int32_t bc[6];       /* hydro_bc for x-lo, x-hi, y-lo, y-hi, z-lo, z-hi */
+  int32_t precision;   /* hydro_precision */
+  uint32_t flags;      /* HYDRO_FLAG_* */
+} hydro_desc;
+
+/* One patch of a batch.  The patch's 5 planes start at element
+ * offset_elems of the pool, each plane (nz+2ng)(ny+2ng)(nx+2ng) elements,
+ * x fastest.  offset_elems must keep the patch 16-byte aligned. */
+typedef struct hydro_patch {
+  int64_t offset_elems;
+  int32_t nx, ny, nz, ng;
+  double dx, dy, dz;
+} hydro_patch;
+
+typedef struct hydro_ctx hydro_ctx;
+
+/* ABI version of the loaded library (HYDRO_ABI_VERSION). */
+int hydro_abi_version(void);
+
+/* Human-readable name of a status code (static storage). */
+const char* hydro_strerror(int status);
+
+/* Description of the last failure on the calling thread (static storage,
+ * valid until the next call on that thread). */
+const char* hydro_last_error(void);
+
+/* Bytes of device workspace hydro_init needs for this descriptor.  The
+ * workspace holds the device scalars (dt, t, CFL maximum, error flag, work
+ * tickets) and reduction partials. */
+int hydro_workspace_bytes(const hydro_desc* d, size_t* bytes);
+
+/* Bind a context to caller-owned device buffers.  `state` is the grid
+ * (layout above) of `state_bytes` bytes (at least 5 planes), `workspace` at
+ * least hydro_workspace_bytes bytes (16-byte aligned), `stream` a
+ * hipStream_t (NULL: the null stream).  Validates the
+ * descriptor, picks the kernel configuration (autotuner cache, or a timing
+ * search with dt = 0, which leaves the state bit for bit), captures the
+ * even- and odd-step graphs, sets t = 0 and step = 0.  Synchronous.
+ * On success *out owns only host objects and hipGraphExecs; free it with
+ * hydro_destroy.  Errors: HYDRO_EINVAL, HYDRO_EDEVICE. */
+int hydro_init(const hydro_desc* d, void* state, size_t state_bytes, void* workspace,
+               size_t ws_bytes, void* stream, hydro_ctx** out);
+
+/* Compute dt = cfl / max signal speed from the current state (capped so
+ * that t does not pass t_end when a final time is set), store it on the
+ * device for the next HYDRO_DT_CFL step and return it in *dt.  Synchronous.
+ * Returns HYDRO_ENUMERIC (and *dt = 0) when the sticky error flag is set or
+ * the state holds rho <= 0, p <= 0 or a non-finite value. */
+int hydro_cfl_dt(hydro_ctx* c, double* dt);
+
+/* Enqueue one full split step of the grid.  dt > 0 uses exactly that dt;
+ * dt == HYDRO_DT_CFL uses the CFL dt on the device (computed from the
+ * current state before the first such step, then by the last sweep of each
+ * step).  Advances t by dt and the step counter by one; the counter's parity
+ * sets the sweep order.  Asynchronous.  Errors: HYDRO_EINVAL (dt < 0 or not
+ * finite), HYDRO_EDEVICE, HYDRO_ESTATE (batch context). */
+int hydro_step(hydro_ctx* c, double dt);
+
+/* Enqueue a single directional sweep along `axis` (0 = x, 1 = y, 2 = z)
+ * with the given dt > 0 (or HYDRO_DT_CFL), without touching t or the step
+ * counter.  fold_cfl != 0 also folds the CFL maximum of the updated cells
+ * (as the last sweep of a step does).  For tests and per-kernel timing.
+ * Asynchronous. */
+int hydro_sweep(hydro_ctx* c, int axis, double dt, int fold_cfl);
+
+/* Bytes of device workspace hydro_batch_init needs. */
+int hydro_batch_workspace_bytes(const hydro_patch* p, int32_t n, const hydro_desc* common,
+                                size_t* bytes);
+
+/* Bind a context to a batch of n independent patches stored in the
+ * caller-owned `pool` of `pool_bytes` bytes (offsets in p[]; every patch
+ * must lie inside the pool and patches must not overlap).  `common` gives gamma, cfl, grav,
+ * bc, precision and flags (its nx..dz are ignored).  The patch table and
+ * the per-axis work lists (largest patches first) are written into the
+ * workspace.  Synchronous.  Errors: HYDRO_EINVAL, HYDRO_EDEVICE. */
+int hydro_batch_init(const hydro_patch* p, int32_t n, const hydro_desc* common, void* pool,
+                     size_t pool_bytes, void* workspace, size_t ws_bytes, void* stream,
+                     hydro_ctx** out);
+
+/* Enqueue one split step of every patch of the batch: one persistent
+ * launch per sweep direction over the whole work list, with one global dt
+ * (the minimum over patches: an AMR level without subcycling).  dt as in
+ * hydro_step.  Asynchronous. */
+int hydro_batch_step(hydro_ctx* c, double dt);
+
+/* FP64 totals of the current state: sum over cells of (rho, mx, my, mz, E,
+ * E + rho*phi) times the cell volume, phi = -(g . x) at cell centres with
+ * the origin at the low corner of the grid (of each patch).  Fixed
+ * summation order: bitwise reproducible for a given shape.  Synchronous. */
+int hydro_totals(hydro_ctx* c, double out[6]);
+
+/* Simulated time and step counter (Synchronous).  hydro_set_time restores a
+ * checkpoint: the counter's parity selects the next sweep order, and the
+ * device dt is recomputed before the next HYDRO_DT_CFL step. */
+int hydro_get_time(hydro_ctx* c, double* t, int64_t* step);
+int hydro_set_time(hydro_ctx* c, double t, int64_t step);
+
+/* Final time: HYDRO_DT_CFL steps are shortened so that t lands on t_end,
+ * and become empty afterwards.  t_end <= 0 removes the cap. */
+int hydro_set_t_end(hydro_ctx* c, double t_end);
+
+/* Declare that the caller changed the state behind the library's back (the
+ * device dt is then recomputed before the next HYDRO_DT_CFL step). */
+int hydro_state_changed(hydro_ctx* c);
+
+/* Sticky device error flag, read synchronously: HYDRO_OK or HYDRO_ENUMERIC.
+ * hydro_clear_error resets it. */
+int hydro_get_error(hydro_ctx* c);
+int hydro_clear_error(hydro_ctx* c);
+
+/* Kernel configuration as text, "x:v=4,b=256;y:q=64,s=4;z:q=64,s=4"
+ * (hydro_get_config writes at most len bytes including the NUL).
+ * hydro_set_config replaces it (validated; graphs are re-captured). */
+int hydro_get_config(hydro_ctx* c, char* buf, size_t len);
+int hydro_set_config(hydro_ctx* c, const char* cfg);
+
+/* Mean device time in milliseconds of each sweep kernel (x, y, z) over
+ * `reps` launches, measured with hipEvents on the context's stream with
+ * dt = 0 (the state is unchanged bit for bit).  An inactive axis reports 0.
+ * Synchronous. */
+int hydro_time_sweeps(hydro_ctx* c, int reps, double ms[3]);
+
+/* One full split step like hydro_step / hydro_batch_step, launched kernel
+ * by kernel with a hipEvent pair around each sweep on the context's stream;
+ * ms[0..2] receive the device time of the x, y and z sweep kernels (0 for
+ * an inactive axis) and ms[3] their sum.  For measurement; it waits after
+ * each sweep, so the step as a whole runs slower than hydro_step.
+ * Synchronous. */
+int hydro_profile_step(hydro_ctx* c, double dt, double ms[4]);
+
+/* Release the host objects of a context (device buffers stay with the
+ * caller).  Waits for the context's stream. */
+int hydro_destroy(hydro_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYDRO_H */

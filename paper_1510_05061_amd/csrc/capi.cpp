@@ -1,0 +1,1134 @@
+// capi.cpp -- C ABI and host runtime of libhydro (see include/hydro.h).
+//
+// The runtime validates descriptors, lays out the caller's workspace,
+// chooses a kernel configuration per sweep axis (built-in default, forced
+// text, cached autotune result, or a timing search), builds the batched
+// work lists, captures the even/odd step graphs and enqueues steps on the
+// caller's stream.  It never allocates device memory.
+#include <hip/hip_runtime.h>
+#include <sys/stat.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/hydro.h"
+#include "layout.hpp"
+
+namespace hydro {
+// kernels.hip
+struct LaunchSweep {
+  void* pool;
+  const PatchDev* patches;
+  PatchDev single;
+  const WorkItem* items;
+  int32_t nitems;
+  int32_t nblocks;
+  int32_t axis;
+  int32_t bc_lo, bc_hi;
+  int32_t do_cfl;
+  double grav;
+  double gamma;
+  DevScalars* scal;
+  SweepCfg cfg;
+  int32_t persistent;
+  int32_t fp64;
+};
+struct LaunchReduce {
+  const void* pool;
+  const PatchDev* patches;
+  PatchDev single;
+  int32_t npatch;
+  int32_t chunks;
+  double gamma;
+  double grav[3];
+  DevScalars* scal;
+  double* partials;
+  int32_t fp64;
+};
+hipError_t launch_sweep(const LaunchSweep& L, hipStream_t st);
+hipError_t launch_cfl(const LaunchReduce& L, hipStream_t st);
+hipError_t launch_totals(const LaunchReduce& L, hipStream_t st);
+hipError_t launch_finish_step(DevScalars* s, hipStream_t st);
+hipError_t launch_finish_cfl(DevScalars* s, hipStream_t st);
+hipError_t launch_init_scalars(DevScalars* s, double cfl, double t, double t_end,
+                               hipStream_t st);
+hipError_t launch_set_dt(DevScalars* s, double dt, hipStream_t st);
+hipError_t launch_set_time(DevScalars* s, double t, double t_end, hipStream_t st);
+hipError_t launch_clear_error(DevScalars* s, hipStream_t st);
+hipError_t launch_timing_begin(DevScalars* s, hipStream_t st);
+hipError_t launch_timing_end(DevScalars* s, hipStream_t st);
+hipError_t launch_reset_tickets(DevScalars* s, hipStream_t st);
+int64_t x_tiles(const PatchDev& P, const SweepCfg& c);
+int64_t col_tiles(const PatchDev& P, int axis, const SweepCfg& c);
+size_t x_lds_bytes(const SweepCfg& c, int fp64);
+}  // namespace hydro
+
+using namespace hydro;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(HYDRO_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kScalarBytes = 256;
+constexpr int kReduceBlock = 256;
+constexpr int kMaxChunks = 1024;
+constexpr int kBatchChunks = 4;
+constexpr int kMaxBlock = 512;  // launch bound of the sweep kernels
+static_assert(sizeof(DevScalars) <= kScalarBytes, "scalar block");
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int chunks_for(int64_t cells) {
+  int64_t c = (cells + int64_t(kReduceBlock) * 8 - 1) / (int64_t(kReduceBlock) * 8);
+  return int(std::max<int64_t>(1, std::min<int64_t>(kMaxChunks, c)));
+}
+
+// ------------------------------------------------------------------------
+// descriptor checks
+// ------------------------------------------------------------------------
+
+int check_common(const hydro_desc* d) {
+  if (!d) return fail(HYDRO_EINVAL, "null descriptor");
+  if (!(d->gamma > 1.0) || !std::isfinite(d->gamma)) return fail(HYDRO_EINVAL, "gamma must be > 1");
+  if (!(d->cfl > 0.0 && d->cfl <= 1.0)) return fail(HYDRO_EINVAL, "cfl must be in (0, 1]");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(d->grav[a])) return fail(HYDRO_EINVAL, "gravity must be finite");
+  for (int a = 0; a < 3; ++a) {
+    int lo = d->bc[2 * a], hi = d->bc[2 * a + 1];
+    if (lo < 0 || lo > 2 || hi < 0 || hi > 2) return fail(HYDRO_EINVAL, "unknown boundary condition");
+    if ((lo == HYDRO_BC_PERIODIC) != (hi == HYDRO_BC_PERIODIC))
+      return fail(HYDRO_EINVAL, "periodic boundary set on one side only");
+  }
+  if (d->precision != HYDRO_FP32 && d->precision != HYDRO_FP64)
+    return fail(HYDRO_EINVAL, "unknown precision");
+  return HYDRO_OK;
+}
+
+int check_extent(const int32_t n[3], int32_t ng, const double dx[3]) {
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 1) return fail(HYDRO_EINVAL, "cell counts must be >= 1");
+    if (n[a] == 1) continue;  // inactive axis
+    if (n[a] > (1 << 24)) return fail(HYDRO_EINVAL, "axis too long");
+  }
+  for (int a = 0; a < 3; ++a)
+    if (!finite_pos(dx[a])) return fail(HYDRO_EINVAL, "cell widths must be > 0");
+  if (ng < 0 || ng > 64) return fail(HYDRO_EINVAL, "ghost layers must be in [0, 64]");
+  return HYDRO_OK;
+}
+
+PatchDev make_patch(const int32_t n[3], int32_t ng, const double dx[3], int64_t offset) {
+  PatchDev P;
+  int64_t sx = n[0] + 2 * ng, sy = n[1] + 2 * ng, sz = n[2] + 2 * ng;
+  P.plane = sx * sy * sz;
+  P.sy = int32_t(sx);
+  P.sz = int32_t(sx * sy);
+  P.base0 = offset + ng + ng * sx + ng * sx * sy;
+  for (int a = 0; a < 3; ++a) {
+    P.n[a] = n[a];
+    P.dx[a] = dx[a];
+  }
+  return P;
+}
+
+// ------------------------------------------------------------------------
+// kernel configurations
+// ------------------------------------------------------------------------
+
+struct Config {
+  SweepCfg ax[3];
+  int32_t batch_blocks = 0;  // persistent launches: workgroups
+};
+
+bool x_cfg_ok(const SweepCfg& c, int nx, int fp64) {
+  if (c.kind != 0 || (c.v != 1 && c.v != 2 && c.v != 4)) return false;
+  if (nx % c.v) return false;
+  int lpp = nx / c.v;
+  if (c.block < 64 || c.block > kMaxBlock || c.block % 64 || c.block < lpp) return false;
+  if (x_lds_bytes(c, fp64) > 64 * 1024) return false;
+  return true;
+}
+
+bool col_cfg_ok(const SweepCfg& c) {
+  if (c.kind != 1 || c.q < 1 || c.s < 1) return false;
+  int b = c.q * c.s;
+  return b >= 64 && b <= kMaxBlock && b % 64 == 0 && c.q % 64 == 0 && c.s <= 16;
+}
+
+SweepCfg default_x(int nx, int fp64) {
+  SweepCfg c{};
+  c.kind = 0;
+  int v = 4;
+  while (nx % v) v /= 2;
+  c.v = v;
+  int lpp = nx / v;
+  c.block = lpp > 256 ? int(align_up(size_t(lpp), 64)) : 256;
+  if (!x_cfg_ok(c, nx, fp64)) {
+    c.v = 1;
+    c.block = int(align_up(size_t(nx), 64));
+  }
+  return c;
+}
+
+SweepCfg default_col(int n) {
+  SweepCfg c{};
+  c.kind = 1;
+  c.q = 64;
+  int s = (n + 63) / 64;
+  c.s = std::max(1, std::min(kMaxBlock / c.q, s));
+  return c;
+}
+
+std::string cfg_text(const Config& cf) {
+  std::ostringstream o;
+  o << "x:v=" << cf.ax[0].v << ",b=" << cf.ax[0].block;
+  o << ";y:q=" << cf.ax[1].q << ",s=" << cf.ax[1].s;
+  o << ";z:q=" << cf.ax[2].q << ",s=" << cf.ax[2].s;
+  if (cf.batch_blocks) o << ";p:g=" << cf.batch_blocks;
+  return o.str();
+}
+
+// parse "x:v=4,b=256;y:q=64,s=4;z:q=64,s=2;p:g=2048" (any subset) into cf
+bool parse_cfg(const std::string& text, Config& cf) {
+  std::stringstream ss(text);
+  std::string part;
+  while (std::getline(ss, part, ';')) {
+    if (part.empty()) continue;
+    if (part.size() < 3 || part[1] != ':') return false;
+    char ax = part[0];
+    std::stringstream kv(part.substr(2));
+    std::string item;
+    while (std::getline(kv, item, ',')) {
+      auto eq = item.find('=');
+      if (eq == std::string::npos) return false;
+      std::string k = item.substr(0, eq);
+      char* end = nullptr;
+      long v = std::strtol(item.c_str() + eq + 1, &end, 10);
+      if (!end || *end) return false;
+      if (ax == 'x') {
+        if (k == "v") cf.ax[0].v = int(v);
+        else if (k == "b") cf.ax[0].block = int(v);
+        else return false;
+      } else if (ax == 'y' || ax == 'z') {
+        SweepCfg& c = cf.ax[ax == 'y' ? 1 : 2];
+        if (k == "q") c.q = int(v);
+        else if (k == "s") c.s = int(v);
+        else return false;
+      } else if (ax == 'p') {
+        if (k == "g") cf.batch_blocks = int(v);
+        else return false;
+      } else {
+        return false;
+      }
+    }
+  }
+  return true;
+}
+
+// ------------------------------------------------------------------------
+// autotune cache (flat JSON object of string -> string)
+// ------------------------------------------------------------------------
+
+std::mutex g_cache_mu;
+
+std::string cache_path() {
+  const char* p = std::getenv("HYDRO_TUNE_CACHE");
+  if (p && *p) return p;
+  const char* home = std::getenv("HOME");
+  return std::string(home ? home : "/tmp") + "/.cache/hydro_mi355x_tune.json";
+}
+
+std::map<std::string, std::string> cache_read() {
+  std::map<std::string, std::string> m;
+  std::ifstream f(cache_path());
+  if (!f) return m;
+  std::stringstream buf;
+  buf << f.rdbuf();
+  std::string s = buf.str();
+  size_t i = 0;
+  auto str = [&](std::string& out) {
+    while (i < s.size() && s[i] != '"') ++i;
+    if (i >= s.size()) return false;
+    size_t j = s.find('"', i + 1);
+    if (j == std::string::npos) return false;
+    out = s.substr(i + 1, j - i - 1);
+    i = j + 1;
+    return true;
+  };
+  std::string k, v;
+  while (str(k) && str(v)) m[k] = v;
+  return m;
+}
+
+void cache_write(const std::map<std::string, std::string>& m) {
+  std::string path = cache_path();
+  size_t slash = path.find_last_of('/');
+  if (slash != std::string::npos && slash > 0) {
+    // create the cache directory if missing (best effort, one level)
+    ::mkdir(path.substr(0, slash).c_str(), 0755);
+  }
+  std::string tmp = path + ".tmp";
+  std::ofstream f(tmp);
+  if (!f) return;
+  f << "{\n";
+  size_t i = 0;
+  for (auto& kv : m) {
+    f << "  \"" << kv.first << "\": \"" << kv.second << "\"" << (++i < m.size() ? "," : "")
+      << "\n";
+  }
+  f << "}\n";
+  f.close();
+  std::rename(tmp.c_str(), path.c_str());
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------
+// context
+// ------------------------------------------------------------------------
+
+struct hydro_ctx {
+  hydro_desc desc{};
+  bool batch = false;
+  int fp64 = 0;
+  void* pool = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  DevScalars* scal = nullptr;
+  double* partials = nullptr;
+  PatchDev single{};
+  // batch
+  int32_t npatch = 0;
+  std::vector<PatchDev> patches;
+  PatchDev* d_patches = nullptr;
+  WorkItem* d_items[3] = {nullptr, nullptr, nullptr};
+  int32_t nitems[3] = {0, 0, 0};
+  int64_t max_patch_cells = 0;
+  // run state
+  int64_t step = 0;
+  double t_host = 0.0;
+  double t_end = 0.0;
+  bool dt_valid = false;
+  Config cfg;
+  bool active[3] = {false, false, false};
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  int cu_count = 0;
+  std::string arch;
+};
+
+namespace {
+
+LaunchSweep sweep_launch(const hydro_ctx* c, int axis, int do_cfl) {
+  LaunchSweep L{};
+  L.pool = c->pool;
+  L.patches = c->d_patches;
+  L.single = c->single;
+  L.items = c->d_items[axis];
+  L.nitems = c->nitems[axis];
+  L.nblocks = c->cfg.batch_blocks;
+  L.axis = axis;
+  L.bc_lo = c->desc.bc[2 * axis];
+  L.bc_hi = c->desc.bc[2 * axis + 1];
+  L.do_cfl = do_cfl;
+  L.grav = c->desc.grav[axis];
+  L.gamma = c->desc.gamma;
+  L.scal = c->scal;
+  L.cfg = c->cfg.ax[axis];
+  L.persistent = c->batch ? 1 : 0;
+  L.fp64 = c->fp64;
+  return L;
+}
+
+LaunchReduce reduce_launch(const hydro_ctx* c) {
+  LaunchReduce L{};
+  L.pool = c->pool;
+  L.patches = c->batch ? c->d_patches : nullptr;
+  L.single = c->single;
+  L.npatch = c->batch ? c->npatch : 1;
+  L.chunks = c->batch ? kBatchChunks
+                      : chunks_for(int64_t(c->single.n[0]) * c->single.n[1] * c->single.n[2]);
+  L.gamma = c->desc.gamma;
+  for (int a = 0; a < 3; ++a) L.grav[a] = c->desc.grav[a];
+  L.scal = c->scal;
+  L.partials = c->partials;
+  L.fp64 = c->fp64;
+  return L;
+}
+
+// The three sweeps of a step in Strang order, the last folding the CFL max,
+// then the step bookkeeping.
+hipError_t enqueue_step_kernels(const hydro_ctx* c, int parity, hipStream_t st) {
+  static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
+  const int* order = parity ? odd : even;
+  int last = -1;
+  for (int i = 0; i < 3; ++i)
+    if (c->active[order[i]]) last = i;
+  for (int i = 0; i < 3; ++i) {
+    int ax = order[i];
+    if (!c->active[ax]) continue;
+    if (c->batch && c->nitems[ax] == 0) continue;
+    hipError_t e = launch_sweep(sweep_launch(c, ax, i == last ? 1 : 0), st);
+    if (e != hipSuccess) return e;
+  }
+  if (last < 0) {
+    // nothing to sweep: still fold the CFL of the state so dt stays defined
+    hipError_t e = launch_cfl(reduce_launch(c), st);
+    if (e != hipSuccess) return e;
+    return launch_finish_step(c->scal, st);
+  }
+  return launch_finish_step(c->scal, st);
+}
+
+void destroy_graphs(hydro_ctx* c) {
+  for (int p = 0; p < 2; ++p) {
+    if (c->graph[p]) (void)hipGraphExecDestroy(c->graph[p]);
+    c->graph[p] = nullptr;
+  }
+}
+
+int capture_graphs(hydro_ctx* c) {
+  destroy_graphs(c);
+  if (c->desc.flags & HYDRO_FLAG_NO_GRAPH) return HYDRO_OK;
+  for (int p = 0; p < 2; ++p) {
+    HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_step_kernels(c, p, c->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(HYDRO_EDEVICE, std::string("graph capture: ") +
+                                     hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipError_t e3 = hipGraphInstantiate(&c->graph[p], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) return fail(HYDRO_EDEVICE, std::string("graph instantiate: ") +
+                                                        hipGetErrorString(e3));
+  }
+  return HYDRO_OK;
+}
+
+// Mean ms per launch of one sweep (dt on the device must already be 0).
+int time_sweep(hydro_ctx* c, int axis, int reps, double* ms) {
+  hipEvent_t a, b;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  LaunchSweep L = sweep_launch(c, axis, 1);
+  auto run = [&]() -> hipError_t {
+    hipError_t e = launch_sweep(L, c->stream);
+    if (e == hipSuccess && c->batch) e = launch_reset_tickets(c->scal, c->stream);
+    return e;
+  };
+  int rc = HYDRO_OK;
+  for (int i = 0; i < 2 && rc == HYDRO_OK; ++i)
+    if (run() != hipSuccess) rc = fail(HYDRO_EDEVICE, "sweep launch failed");
+  if (rc == HYDRO_OK && hipEventRecord(a, c->stream) != hipSuccess) rc = HYDRO_EDEVICE;
+  for (int i = 0; i < reps && rc == HYDRO_OK; ++i)
+    if (run() != hipSuccess) rc = fail(HYDRO_EDEVICE, "sweep launch failed");
+  if (rc == HYDRO_OK && hipEventRecord(b, c->stream) != hipSuccess) rc = HYDRO_EDEVICE;
+  if (rc == HYDRO_OK && hipEventSynchronize(b) != hipSuccess) rc = HYDRO_EDEVICE;
+  float t = 0.f;
+  if (rc == HYDRO_OK && hipEventElapsedTime(&t, a, b) != hipSuccess) rc = HYDRO_EDEVICE;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc == HYDRO_OK) *ms = double(t) / reps;
+  return rc == HYDRO_EDEVICE && g_last_error.empty() ? fail(rc, "timing failed") : rc;
+}
+
+std::string shape_key(const hydro_ctx* c, int axis) {
+  std::ostringstream o;
+  o << c->arch << ":cu" << c->cu_count << ":" << (c->fp64 ? "fp64" : "fp32") << ":ax" << axis
+    << ":k3";
+  if (c->batch) {
+    o << ":batch" << c->npatch << "x" << c->max_patch_cells;
+  } else {
+    o << ":" << c->single.n[0] << "x" << c->single.n[1] << "x" << c->single.n[2] << ":s"
+      << c->single.sy << "x" << c->single.sz;
+  }
+  return o.str();
+}
+
+std::vector<SweepCfg> candidates(const hydro_ctx* c, int axis) {
+  std::vector<SweepCfg> out;
+  if (axis == 0) {
+    std::vector<int> widths;
+    if (c->batch)
+      for (auto& P : c->patches) widths.push_back(P.n[0]);
+    else
+      widths.push_back(c->single.n[0]);
+    for (int v : {1, 2, 4})
+      for (int b : {64, 128, 256, 512}) {
+        SweepCfg s{};
+        s.kind = 0;
+        s.v = v;
+        s.block = b;
+        bool ok = true;
+        for (int w : widths) ok = ok && x_cfg_ok(s, w, c->fp64);
+        if (ok) out.push_back(s);
+      }
+  } else {
+    int n = c->batch ? 64 : c->single.n[axis];
+    for (int q : {64, 128, 256})
+      for (int s : {1, 2, 4, 8, 16}) {
+        SweepCfg k{};
+        k.kind = 1;
+        k.q = q;
+        k.s = s;
+        if (!col_cfg_ok(k)) continue;
+        if (s > 1 && (n + s - 1) / s < 8) continue;  // segments shorter than 8 cells
+        out.push_back(k);
+      }
+  }
+  return out;
+}
+
+int rebuild_items(hydro_ctx* c);
+
+// Pick each axis' configuration: HYDRO_FORCE_CONFIG, then the cache, then a
+// timing search (dt = 0 leaves the state unchanged bit for bit).
+int choose_config(hydro_ctx* c) {
+  Config cf = c->cfg;
+  const char* forced = std::getenv("HYDRO_FORCE_CONFIG");
+  if (forced && *forced) {
+    if (!parse_cfg(forced, cf)) return fail(HYDRO_EINVAL, "bad HYDRO_FORCE_CONFIG");
+    c->cfg = cf;
+    return HYDRO_OK;
+  }
+  if (c->desc.flags & HYDRO_FLAG_NO_TUNE) return HYDRO_OK;
+  std::map<std::string, std::string> cache;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    cache = cache_read();
+  }
+  bool dirty = false;
+  for (int axis = 0; axis < 3; ++axis) {
+    if (!c->active[axis]) continue;
+    std::string key = shape_key(c, axis);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      Config tmp = c->cfg;
+      if (parse_cfg(it->second, tmp)) {
+        bool ok = axis == 0 ? true : col_cfg_ok(tmp.ax[axis]);
+        if (axis == 0) {
+          if (c->batch)
+            for (auto& P : c->patches) ok = ok && x_cfg_ok(tmp.ax[0], P.n[0], c->fp64);
+          else
+            ok = x_cfg_ok(tmp.ax[0], c->single.n[0], c->fp64);
+        }
+        if (ok) {
+          c->cfg.ax[axis] = tmp.ax[axis];
+          continue;
+        }
+      }
+    }
+    // timing search
+    int rc = HYDRO_OK;
+    if (launch_timing_begin(c->scal, c->stream) != hipSuccess)
+      return fail(HYDRO_EDEVICE, "timing setup failed");
+    double best = 1e30;
+    SweepCfg best_cfg = c->cfg.ax[axis];
+    const int reps = 5;
+    for (const SweepCfg& s : candidates(c, axis)) {
+      c->cfg.ax[axis] = s;
+      if (c->batch && (rc = rebuild_items(c)) != HYDRO_OK) break;
+      double ms = 0;
+      if ((rc = time_sweep(c, axis, reps, &ms)) != HYDRO_OK) break;
+      if (ms < best) {
+        best = ms;
+        best_cfg = s;
+      }
+    }
+    c->cfg.ax[axis] = best_cfg;
+    if (launch_timing_end(c->scal, c->stream) != hipSuccess)
+      return fail(HYDRO_EDEVICE, "timing teardown failed");
+    if (rc != HYDRO_OK) return rc;
+    if (c->batch && (rc = rebuild_items(c)) != HYDRO_OK) return rc;
+    Config one{};
+    one.ax[axis] = best_cfg;
+    std::string txt = cfg_text(one);
+    // keep only this axis' part
+    std::string part;
+    {
+      std::stringstream ss(txt);
+      std::string p;
+      const char tag = "xyz"[axis];
+      while (std::getline(ss, p, ';'))
+        if (!p.empty() && p[0] == tag) part = p;
+    }
+    cache[key] = part;
+    dirty = true;
+  }
+  if (dirty) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto merged = cache_read();
+    for (auto& kv : cache) merged[kv.first] = kv.second;
+    cache_write(merged);
+  }
+  return HYDRO_OK;
+}
+
+int device_info(hydro_ctx* c) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  c->cu_count = prop.multiProcessorCount;
+  c->arch = prop.gcnArchName;
+  auto colon = c->arch.find(':');
+  if (colon != std::string::npos) c->arch = c->arch.substr(0, colon);
+  return HYDRO_OK;
+}
+
+int common_init(hydro_ctx* c) {
+  int rc = device_info(c);
+  if (rc) return rc;
+  HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  HIP_TRY(launch_init_scalars(c->scal, c->desc.cfl, 0.0, 0.0, c->stream));
+  rc = choose_config(c);
+  if (rc) return rc;
+  HIP_TRY(launch_init_scalars(c->scal, c->desc.cfl, 0.0, 0.0, c->stream));
+  rc = capture_graphs(c);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->step = 0;
+  c->t_host = 0.0;
+  c->dt_valid = false;
+  return HYDRO_OK;
+}
+
+int read_scalars(hydro_ctx* c, DevScalars* out) {
+  HIP_TRY(hipMemcpyAsync(out, c->scal, sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return HYDRO_OK;
+}
+
+size_t grid_workspace_bytes(int64_t cells) {
+  return kScalarBytes + align_up(size_t(chunks_for(cells)) * 6 * sizeof(double), 256);
+}
+
+// layout of a batch workspace
+struct BatchLayout {
+  size_t partials, patches, items[3], total;
+};
+
+BatchLayout batch_layout(int32_t n, const int32_t items[3]) {
+  BatchLayout L;
+  size_t o = kScalarBytes;
+  L.partials = o;
+  o += align_up(size_t(n) * kBatchChunks * 6 * sizeof(double), 256);
+  L.patches = o;
+  o += align_up(size_t(n) * sizeof(PatchDev), 256);
+  for (int a = 0; a < 3; ++a) {
+    L.items[a] = o;
+    o += align_up(size_t(std::max(1, items[a])) * sizeof(WorkItem), 256);
+  }
+  L.total = o;
+  return L;
+}
+
+// The most tiles a patch list can need per axis under any valid config
+// (x: v = 1 with one pencil per workgroup; columns: 64 columns per tile).
+void max_items(const std::vector<PatchDev>& ps, int32_t out[3]) {
+  int64_t acc[3] = {0, 0, 0};
+  for (auto& P : ps) {
+    acc[0] += int64_t(P.n[1]) * P.n[2];
+    acc[1] += (int64_t(P.n[0]) * P.n[2] + 63) / 64;
+    acc[2] += (int64_t(P.n[0]) * P.n[1] + 63) / 64;
+  }
+  for (int a = 0; a < 3; ++a) out[a] = int32_t(std::min<int64_t>(acc[a], INT32_MAX));
+}
+
+int rebuild_items(hydro_ctx* c) {
+  // work items per axis, largest patches first (longest-processing-time
+  // order keeps the persistent workgroups busy until the end)
+  std::vector<int32_t> order(c->npatch);
+  for (int32_t i = 0; i < c->npatch; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    const PatchDev &A = c->patches[a], &B = c->patches[b];
+    return int64_t(A.n[0]) * A.n[1] * A.n[2] > int64_t(B.n[0]) * B.n[1] * B.n[2];
+  });
+  int32_t cap[3];
+  max_items(c->patches, cap);
+  for (int axis = 0; axis < 3; ++axis) {
+    std::vector<WorkItem> items;
+    if (c->active[axis]) {
+      for (int32_t p : order) {
+        const PatchDev& P = c->patches[p];
+        if (P.n[axis] == 1) continue;
+        int64_t nt = axis == 0 ? x_tiles(P, c->cfg.ax[0]) : col_tiles(P, axis, c->cfg.ax[axis]);
+        for (int64_t t = 0; t < nt; ++t) items.push_back(WorkItem{p, int32_t(t)});
+      }
+    }
+    if (int64_t(items.size()) > cap[axis]) return fail(HYDRO_EINVAL, "work list overflow");
+    c->nitems[axis] = int32_t(items.size());
+    if (!items.empty())
+      HIP_TRY(hipMemcpyAsync(c->d_items[axis], items.data(), items.size() * sizeof(WorkItem),
+                             hipMemcpyHostToDevice, c->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return HYDRO_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------
+// exported API
+// ------------------------------------------------------------------------
+
+extern "C" {
+
+int hydro_abi_version(void) { return HYDRO_ABI_VERSION; }
+
+const char* hydro_strerror(int s) {
+  switch (s) {
+    case HYDRO_OK: return "HYDRO_OK";
+    case HYDRO_EINVAL: return "HYDRO_EINVAL: invalid argument";
+    case HYDRO_EDEVICE: return "HYDRO_EDEVICE: HIP runtime error";
+    case HYDRO_ENUMERIC: return "HYDRO_ENUMERIC: non-physical or non-finite state";
+    case HYDRO_ESTATE: return "HYDRO_ESTATE: call out of order";
+    default: return "unknown hydro status";
+  }
+}
+
+const char* hydro_last_error(void) { return g_last_error.c_str(); }
+
+int hydro_workspace_bytes(const hydro_desc* d, size_t* bytes) {
+  if (!d || !bytes) return fail(HYDRO_EINVAL, "null argument");
+  int rc = check_common(d);
+  if (rc) return rc;
+  int32_t n[3] = {d->nx, d->ny, d->nz};
+  double dx[3] = {d->dx, d->dy, d->dz};
+  rc = check_extent(n, d->ng, dx);
+  if (rc) return rc;
+  *bytes = grid_workspace_bytes(int64_t(n[0]) * n[1] * n[2]);
+  return HYDRO_OK;
+}
+
+int hydro_init(const hydro_desc* d, void* state, size_t state_bytes, void* workspace,
+               size_t ws_bytes, void* stream, hydro_ctx** out) {
+  g_last_error.clear();
+  if (!out) return fail(HYDRO_EINVAL, "null output pointer");
+  *out = nullptr;
+  size_t need = 0;
+  int rc = hydro_workspace_bytes(d, &need);
+  if (rc) return rc;
+  if (!state || !workspace) return fail(HYDRO_EINVAL, "null device pointer");
+  if ((reinterpret_cast<uintptr_t>(state) & 15) || (reinterpret_cast<uintptr_t>(workspace) & 15))
+    return fail(HYDRO_EINVAL, "device pointers must be 16-byte aligned");
+  if (ws_bytes < need) return fail(HYDRO_EINVAL, "workspace too small");
+  int32_t n[3] = {d->nx, d->ny, d->nz};
+  double dx[3] = {d->dx, d->dy, d->dz};
+  PatchDev P = make_patch(n, d->ng, dx, 0);
+  const size_t esz = d->precision == HYDRO_FP64 ? 8 : 4;
+  if (P.plane > (int64_t(1) << 31)) return fail(HYDRO_EINVAL, "grid plane too large");
+  if (state_bytes < size_t(P.plane) * 5 * esz) return fail(HYDRO_EINVAL, "state buffer too small");
+  hydro_ctx* c = new (std::nothrow) hydro_ctx();
+  if (!c) return fail(HYDRO_EINVAL, "out of host memory");
+  c->desc = *d;
+  c->fp64 = d->precision == HYDRO_FP64;
+  c->pool = state;
+  c->ws = static_cast<char*>(workspace);
+  c->ws_bytes = ws_bytes;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->scal = reinterpret_cast<DevScalars*>(c->ws);
+  c->partials = reinterpret_cast<double*>(c->ws + kScalarBytes);
+  c->single = P;
+  for (int a = 0; a < 3; ++a) c->active[a] = n[a] > 1;
+  c->cfg.ax[0] = default_x(n[0], c->fp64);
+  c->cfg.ax[1] = default_col(n[1]);
+  c->cfg.ax[2] = default_col(n[2]);
+  if (!x_cfg_ok(c->cfg.ax[0], n[0], c->fp64) && c->active[0]) {
+    delete c;
+    return fail(HYDRO_EINVAL, "no valid x-sweep configuration for this width");
+  }
+  rc = common_init(c);
+  if (rc) {
+    hydro_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return HYDRO_OK;
+}
+
+int hydro_batch_workspace_bytes(const hydro_patch* p, int32_t n, const hydro_desc* common,
+                                size_t* bytes) {
+  if (!p || !common || !bytes || n < 1) return fail(HYDRO_EINVAL, "bad batch arguments");
+  int rc = check_common(common);
+  if (rc) return rc;
+  std::vector<PatchDev> ps;
+  ps.reserve(n);
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t nn[3] = {p[i].nx, p[i].ny, p[i].nz};
+    double dx[3] = {p[i].dx, p[i].dy, p[i].dz};
+    rc = check_extent(nn, p[i].ng, dx);
+    if (rc) return rc;
+    ps.push_back(make_patch(nn, p[i].ng, dx, p[i].offset_elems));
+  }
+  int32_t cap[3];
+  max_items(ps, cap);
+  *bytes = batch_layout(n, cap).total;
+  return HYDRO_OK;
+}
+
+int hydro_batch_init(const hydro_patch* p, int32_t n, const hydro_desc* common, void* pool,
+                     size_t pool_bytes, void* workspace, size_t ws_bytes, void* stream,
+                     hydro_ctx** out) {
+  g_last_error.clear();
+  if (!out) return fail(HYDRO_EINVAL, "null output pointer");
+  *out = nullptr;
+  size_t need = 0;
+  int rc = hydro_batch_workspace_bytes(p, n, common, &need);
+  if (rc) return rc;
+  if (!pool || !workspace) return fail(HYDRO_EINVAL, "null device pointer");
+  if ((reinterpret_cast<uintptr_t>(pool) & 15) || (reinterpret_cast<uintptr_t>(workspace) & 15))
+    return fail(HYDRO_EINVAL, "device pointers must be 16-byte aligned");
+  if (ws_bytes < need) return fail(HYDRO_EINVAL, "workspace too small");
+  const size_t esz = common->precision == HYDRO_FP64 ? 8 : 4;
+  const int64_t pool_elems = int64_t(pool_bytes / esz);
+  hydro_ctx* c = new (std::nothrow) hydro_ctx();
+  if (!c) return fail(HYDRO_EINVAL, "out of host memory");
+  c->desc = *common;
+  c->batch = true;
+  c->fp64 = common->precision == HYDRO_FP64;
+  c->pool = pool;
+  c->npatch = n;
+  // patch extents: inside the pool, aligned, non-overlapping
+  std::vector<std::pair<int64_t, int64_t>> spans;
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t nn[3] = {p[i].nx, p[i].ny, p[i].nz};
+    double dx[3] = {p[i].dx, p[i].dy, p[i].dz};
+    PatchDev P = make_patch(nn, p[i].ng, dx, p[i].offset_elems);
+    int64_t len = P.plane * 5;
+    if (p[i].offset_elems < 0 || p[i].offset_elems + len > pool_elems) {
+      delete c;
+      return fail(HYDRO_EINVAL, "patch " + std::to_string(i) + " lies outside the pool");
+    }
+    if ((p[i].offset_elems * int64_t(esz)) % 16) {
+      delete c;
+      return fail(HYDRO_EINVAL, "patch offsets must be 16-byte aligned");
+    }
+    spans.push_back({p[i].offset_elems, p[i].offset_elems + len});
+    c->patches.push_back(P);
+    c->max_patch_cells = std::max<int64_t>(c->max_patch_cells, int64_t(nn[0]) * nn[1] * nn[2]);
+    for (int a = 0; a < 3; ++a) c->active[a] = c->active[a] || nn[a] > 1;
+  }
+  std::sort(spans.begin(), spans.end());
+  for (size_t i = 1; i < spans.size(); ++i)
+    if (spans[i].first < spans[i - 1].second) {
+      delete c;
+      return fail(HYDRO_EINVAL, "patches overlap in the pool");
+    }
+  c->ws = static_cast<char*>(workspace);
+  c->ws_bytes = ws_bytes;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->scal = reinterpret_cast<DevScalars*>(c->ws);
+  int32_t cap[3];
+  max_items(c->patches, cap);
+  BatchLayout L = batch_layout(n, cap);
+  c->partials = reinterpret_cast<double*>(c->ws + L.partials);
+  c->d_patches = reinterpret_cast<PatchDev*>(c->ws + L.patches);
+  for (int a = 0; a < 3; ++a) c->d_items[a] = reinterpret_cast<WorkItem*>(c->ws + L.items[a]);
+  c->single = c->patches[0];
+  // batch defaults: 4 cells per lane where every width allows, whole
+  // columns per thread (patches are short), 8 workgroups per CU
+  SweepCfg x{};
+  x.kind = 0;
+  x.block = 256;
+  for (int v : {4, 2, 1}) {
+    x.v = v;
+    bool ok = true;
+    for (auto& P : c->patches) ok = ok && x_cfg_ok(x, P.n[0], c->fp64);
+    if (ok) break;
+  }
+  bool xok = true;
+  for (auto& P : c->patches) xok = xok && x_cfg_ok(x, P.n[0], c->fp64);
+  if (!xok && c->active[0]) {
+    delete c;
+    return fail(HYDRO_EINVAL, "no x-sweep configuration fits every patch width");
+  }
+  c->cfg.ax[0] = x;
+  for (int a = 1; a < 3; ++a) {
+    SweepCfg s{};
+    s.kind = 1;
+    s.q = 256;
+    s.s = 1;
+    c->cfg.ax[a] = s;
+  }
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+      delete c;
+      return fail(HYDRO_EDEVICE, "device query failed");
+    }
+    c->cfg.batch_blocks = prop.multiProcessorCount * 8;
+  }
+  if (hipMemcpyAsync(c->d_patches, c->patches.data(), c->patches.size() * sizeof(PatchDev),
+                     hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+    delete c;
+    return fail(HYDRO_EDEVICE, "patch table upload failed");
+  }
+  rc = rebuild_items(c);
+  if (rc == HYDRO_OK) rc = common_init(c);
+  if (rc == HYDRO_OK) rc = rebuild_items(c);
+  if (rc) {
+    hydro_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return HYDRO_OK;
+}
+
+static int step_common(hydro_ctx* c, double dt, bool want_batch) {
+  if (!c) return fail(HYDRO_EINVAL, "null context");
+  if (c->batch != want_batch)
+    return fail(HYDRO_ESTATE, want_batch ? "not a batch context" : "batch context: use hydro_batch_step");
+  if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(HYDRO_EINVAL, "dt must be >= 0 and finite");
+  if (dt > 0.0) {
+    HIP_TRY(launch_set_dt(c->scal, dt, c->stream));
+  } else if (!c->dt_valid) {
+    HIP_TRY(launch_cfl(reduce_launch(c), c->stream));
+  }
+  const int parity = int(c->step & 1);
+  if (c->graph[parity]) {
+    HIP_TRY(hipGraphLaunch(c->graph[parity], c->stream));
+  } else {
+    HIP_TRY(enqueue_step_kernels(c, parity, c->stream));
+  }
+  c->step += 1;
+  c->dt_valid = true;
+  return HYDRO_OK;
+}
+
+int hydro_step(hydro_ctx* c, double dt) { return step_common(c, dt, false); }
+
+int hydro_batch_step(hydro_ctx* c, double dt) { return step_common(c, dt, true); }
+
+int hydro_sweep(hydro_ctx* c, int axis, double dt, int fold_cfl) {
+  if (!c) return fail(HYDRO_EINVAL, "null context");
+  if (axis < 0 || axis > 2) return fail(HYDRO_EINVAL, "axis must be 0, 1 or 2");
+  if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(HYDRO_EINVAL, "dt must be >= 0 and finite");
+  if (dt > 0.0) {
+    HIP_TRY(launch_set_dt(c->scal, dt, c->stream));
+  } else if (!c->dt_valid) {
+    HIP_TRY(launch_cfl(reduce_launch(c), c->stream));
+  }
+  if (c->active[axis] && (!c->batch || c->nitems[axis] > 0)) {
+    HIP_TRY(launch_sweep(sweep_launch(c, axis, fold_cfl ? 1 : 0), c->stream));
+  }
+  if (c->batch) HIP_TRY(launch_reset_tickets(c->scal, c->stream));
+  if (fold_cfl) {
+    // the device dt becomes the CFL dt of the swept state (t is left alone)
+    HIP_TRY(launch_finish_cfl(c->scal, c->stream));
+    c->dt_valid = true;
+  } else {
+    c->dt_valid = false;
+  }
+  return HYDRO_OK;
+}
+
+int hydro_cfl_dt(hydro_ctx* c, double* dt) {
+  if (!c || !dt) return fail(HYDRO_EINVAL, "null argument");
+  *dt = 0.0;
+  HIP_TRY(launch_cfl(reduce_launch(c), c->stream));
+  DevScalars s;
+  int rc = read_scalars(c, &s);
+  if (rc) return rc;
+  c->dt_valid = true;
+  if (s.error) return fail(HYDRO_ENUMERIC, "state holds rho <= 0, p <= 0 or a non-finite value");
+  *dt = s.dt;
+  return HYDRO_OK;
+}
+
+int hydro_totals(hydro_ctx* c, double out[6]) {
+  if (!c || !out) return fail(HYDRO_EINVAL, "null argument");
+  HIP_TRY(launch_totals(reduce_launch(c), c->stream));
+  DevScalars s;
+  int rc = read_scalars(c, &s);
+  if (rc) return rc;
+  for (int v = 0; v < 6; ++v) out[v] = s.totals[v];
+  return HYDRO_OK;
+}
+
+int hydro_get_time(hydro_ctx* c, double* t, int64_t* step) {
+  if (!c) return fail(HYDRO_EINVAL, "null context");
+  DevScalars s;
+  int rc = read_scalars(c, &s);
+  if (rc) return rc;
+  c->t_host = s.t;
+  if (t) *t = s.t;
+  if (step) *step = c->step;
+  return HYDRO_OK;
+}
+
+int hydro_set_time(hydro_ctx* c, double t, int64_t step) {
+  if (!c) return fail(HYDRO_EINVAL, "null context");
+  if (!std::isfinite(t) || step < 0) return fail(HYDRO_EINVAL, "bad time or step");
+  HIP_TRY(launch_set_time(c->scal, t, c->t_end, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->t_host = t;
+  c->step = step;
+  c->dt_valid = false;
+  return HYDRO_OK;
+}
+
+int hydro_set_t_end(hydro_ctx* c, double t_end) {
+  if (!c) return fail(HYDRO_EINVAL, "null context");
+  if (!std::isfinite(t_end)) return fail(HYDRO_EINVAL, "t_end must be finite");
+  double t = 0.0;
+  int rc = hydro_get_time(c, &t, nullptr);
+  if (rc) return rc;
+  c->t_end = t_end > 0.0 ? t_end : 0.0;
+  HIP_TRY(launch_set_time(c->scal, t, c->t_end, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->dt_valid = false;
+  return HYDRO_OK;
+}
+
+int hydro_state_changed(hydro_ctx* c) {
+  if (!c) return fail(HYDRO_EINVAL, "null context");
+  c->dt_valid = false;
+  return HYDRO_OK;
+}
+
+int hydro_get_error(hydro_ctx* c) {
+  if (!c) return fail(HYDRO_EINVAL, "null context");
+  DevScalars s;
+  int rc = read_scalars(c, &s);
+  if (rc) return rc;
+  return s.error ? fail(HYDRO_ENUMERIC, "sticky numeric error flag is set") : HYDRO_OK;
+}
+
+int hydro_clear_error(hydro_ctx* c) {
+  if (!c) return fail(HYDRO_EINVAL, "null context");
+  HIP_TRY(launch_clear_error(c->scal, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return HYDRO_OK;
+}
+
+int hydro_get_config(hydro_ctx* c, char* buf, size_t len) {
+  if (!c || !buf || len == 0) return fail(HYDRO_EINVAL, "bad argument");
+  std::string s = cfg_text(c->cfg);
+  if (s.size() + 1 > len) return fail(HYDRO_EINVAL, "buffer too small");
+  std::memcpy(buf, s.c_str(), s.size() + 1);
+  return HYDRO_OK;
+}
+
+int hydro_set_config(hydro_ctx* c, const char* text) {
+  if (!c || !text) return fail(HYDRO_EINVAL, "bad argument");
+  Config cf = c->cfg;
+  if (!parse_cfg(text, cf)) return fail(HYDRO_EINVAL, "cannot parse configuration");
+  if (c->active[0]) {
+    if (c->batch) {
+      for (auto& P : c->patches)
+        if (!x_cfg_ok(cf.ax[0], P.n[0], c->fp64)) return fail(HYDRO_EINVAL, "invalid x config");
+    } else if (!x_cfg_ok(cf.ax[0], c->single.n[0], c->fp64)) {
+      return fail(HYDRO_EINVAL, "invalid x config");
+    }
+  }
+  for (int a = 1; a < 3; ++a)
+    if (c->active[a] && !col_cfg_ok(cf.ax[a])) return fail(HYDRO_EINVAL, "invalid column config");
+  if (c->batch && (cf.batch_blocks < 1 || cf.batch_blocks > 65536))
+    return fail(HYDRO_EINVAL, "invalid persistent grid size");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->cfg = cf;
+  if (c->batch) {
+    int rc = rebuild_items(c);
+    if (rc) return rc;
+  }
+  return capture_graphs(c);
+}
+
+int hydro_time_sweeps(hydro_ctx* c, int reps, double ms[3]) {
+  if (!c || !ms || reps < 1) return fail(HYDRO_EINVAL, "bad argument");
+  HIP_TRY(launch_timing_begin(c->scal, c->stream));
+  int rc = HYDRO_OK;
+  for (int a = 0; a < 3; ++a) {
+    ms[a] = 0.0;
+    if (!c->active[a] || (c->batch && c->nitems[a] == 0)) continue;
+    rc = time_sweep(c, a, reps, &ms[a]);
+    if (rc) break;
+  }
+  HIP_TRY(launch_timing_end(c->scal, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return rc;
+}
+
+int hydro_profile_step(hydro_ctx* c, double dt, double ms[4]) {
+  if (!c || !ms) return fail(HYDRO_EINVAL, "bad argument");
+  if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(HYDRO_EINVAL, "dt must be >= 0 and finite");
+  for (int i = 0; i < 4; ++i) ms[i] = 0.0;
+  if (dt > 0.0) {
+    HIP_TRY(launch_set_dt(c->scal, dt, c->stream));
+  } else if (!c->dt_valid) {
+    HIP_TRY(launch_cfl(reduce_launch(c), c->stream));
+  }
+  static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
+  const int* order = (c->step & 1) ? odd : even;
+  int last = -1;
+  for (int i = 0; i < 3; ++i)
+    if (c->active[order[i]] && (!c->batch || c->nitems[order[i]] > 0)) last = i;
+  hipEvent_t ev[4];
+  for (int i = 0; i < 4; ++i) HIP_TRY(hipEventCreate(&ev[i]));
+  int rc = HYDRO_OK;
+  float t[3] = {0.f, 0.f, 0.f};
+  for (int i = 0; i < 3 && rc == HYDRO_OK; ++i) {
+    const int ax = order[i];
+    if (!c->active[ax] || (c->batch && c->nitems[ax] == 0)) continue;
+    if (hipEventRecord(ev[i], c->stream) != hipSuccess ||
+        launch_sweep(sweep_launch(c, ax, i == last ? 1 : 0), c->stream) != hipSuccess ||
+        hipEventRecord(ev[3], c->stream) != hipSuccess ||
+        hipEventSynchronize(ev[3]) != hipSuccess ||
+        hipEventElapsedTime(&t[i], ev[i], ev[3]) != hipSuccess)
+      rc = fail(HYDRO_EDEVICE, "profiled sweep failed");
+    else
+      ms[ax] = double(t[i]);
+  }
+  if (rc == HYDRO_OK) {
+    if (last < 0 && launch_cfl(reduce_launch(c), c->stream) != hipSuccess)
+      rc = fail(HYDRO_EDEVICE, "cfl launch failed");
+    else if (launch_finish_step(c->scal, c->stream) != hipSuccess)
+      rc = fail(HYDRO_EDEVICE, "step bookkeeping launch failed");
+  }
+  for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  ms[3] = ms[0] + ms[1] + ms[2];
+  c->step += 1;
+  c->dt_valid = true;
+  return HYDRO_OK;
+}
+
+int hydro_destroy(hydro_ctx* c) {
+  if (!c) return HYDRO_OK;
+  (void)hipStreamSynchronize(c->stream);
+  destroy_graphs(c);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  delete c;
+  return HYDRO_OK;
+}
+
+}  // extern "C"

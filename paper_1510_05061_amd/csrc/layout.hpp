@@ -1,0 +1,58 @@
+// layout.hpp -- structures shared by the host runtime and the kernels.
+#pragma once
+
+#include <stdint.h>
+
+namespace hydro {
+
+constexpr int kBcPeriodic = 0;
+constexpr int kBcOutflow = 1;
+constexpr int kBcReflect = 2;
+
+// Geometry of one grid or patch inside the caller's state buffer.  The
+// state is 5 planes (rho, mx, my, mz, E); plane v of the patch starts at
+// element base0 + v * plane, x is contiguous, y has stride sy, z stride sz.
+// base0 points at interior cell (0,0,0).
+struct PatchDev {
+  int64_t base0;   // element offset of interior cell (0,0,0) of plane 0
+  int64_t plane;   // elements per plane of this patch
+  int32_t n[3];    // interior cells along x, y, z
+  int32_t sy, sz;  // element strides along y and z
+  double dx[3];    // cell widths
+};
+
+// Device-resident scalars at the start of the workspace.
+struct DevScalars {
+  double dt;                     // dt of the next step
+  double t;                      // simulated time
+  double t_end;                  // final time (<= 0: none)
+  double cfl;                    // Courant number
+  unsigned long long smax_bits;  // running max of signal speed / dx (FP64 bits)
+  unsigned int error;            // sticky error bits (kErr*)
+  unsigned int pad0;
+  unsigned int tickets[4];       // persistent-sweep work tickets
+  double saved[2];               // dt, t saved around timing runs
+  double totals[6];              // last FP64 totals
+  double pad1[2];
+};
+
+constexpr unsigned kErrState = 1u;   // rho <= 0, p <= 0 or non-finite after an update
+constexpr unsigned kErrSpeed = 2u;   // max signal speed zero or non-finite
+
+// A unit of work of a persistent sweep: tile `tile` of patch `patch`.
+struct WorkItem {
+  int32_t patch;
+  int32_t tile;
+};
+
+// Kernel configuration of one sweep axis.
+struct SweepCfg {
+  int32_t kind;    // 0: lane runs along x, 1: column march
+  int32_t v;       // lane runs: cells per lane (1, 2, 4)
+  int32_t block;   // threads per workgroup
+  int32_t q;       // column march: columns per tile
+  int32_t s;       // column march: segments per column
+  int32_t pad;
+};
+
+}  // namespace hydro

@@ -1,0 +1,426 @@
+"""ctypes binding of libhydro (include/hydro.h): argument marshalling only.
+
+Every numerical step runs in the HIP kernels of libhydro.so.  PyTorch
+supplies device memory and the stream; nothing here computes on the state.
+If the library is missing this module raises on import of `lib()`: there is
+no CPU fallback.
+
+Two layers:
+  * functions with the C names (hydro_init, hydro_step, ...) that take and
+    return plain values and raise HydroError on a non-zero status;
+  * `Grid` and `Batch`, small owners of a context plus its workspace
+    tensor.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhydro.so")
+
+HYDRO_OK, HYDRO_EINVAL, HYDRO_EDEVICE, HYDRO_ENUMERIC, HYDRO_ESTATE = range(5)
+PERIODIC, OUTFLOW, REFLECT = 0, 1, 2
+FP32, FP64 = 0, 1
+FLAG_NO_GRAPH, FLAG_NO_TUNE = 0x1, 0x2
+DT_CFL = 0.0
+
+
+class HydroDesc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("ng", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
+        ("grav", ctypes.c_double * 3),
+        ("bc", ctypes.c_int32 * 6),
+        ("precision", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class HydroPatch(ctypes.Structure):
+    _fields_ = [
+        ("offset_elems", ctypes.c_int64),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("ng", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+    ]
+
+
+class HydroError(RuntimeError):
+    def __init__(self, status, where, detail):
+        self.status = status
+        super().__init__(f"{where}: status {status} ({detail})")
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+_dp = ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "hydro_abi_version": ([], ctypes.c_int),
+    "hydro_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "hydro_last_error": ([], ctypes.c_char_p),
+    "hydro_workspace_bytes": ([ctypes.POINTER(HydroDesc), ctypes.POINTER(_sz)], ctypes.c_int),
+    "hydro_init": ([ctypes.POINTER(HydroDesc), _vp, _sz, _vp, _sz, _vp,
+                    ctypes.POINTER(_vp)], ctypes.c_int),
+    "hydro_cfl_dt": ([_vp, _dp], ctypes.c_int),
+    "hydro_step": ([_vp, ctypes.c_double], ctypes.c_int),
+    "hydro_sweep": ([_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int], ctypes.c_int),
+    "hydro_batch_workspace_bytes": ([ctypes.POINTER(HydroPatch), ctypes.c_int32,
+                                     ctypes.POINTER(HydroDesc), ctypes.POINTER(_sz)],
+                                    ctypes.c_int),
+    "hydro_batch_init": ([ctypes.POINTER(HydroPatch), ctypes.c_int32,
+                          ctypes.POINTER(HydroDesc), _vp, _sz, _vp, _sz, _vp,
+                          ctypes.POINTER(_vp)], ctypes.c_int),
+    "hydro_batch_step": ([_vp, ctypes.c_double], ctypes.c_int),
+    "hydro_totals": ([_vp, _dp], ctypes.c_int),
+    "hydro_get_time": ([_vp, _dp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "hydro_set_time": ([_vp, ctypes.c_double, ctypes.c_int64], ctypes.c_int),
+    "hydro_set_t_end": ([_vp, ctypes.c_double], ctypes.c_int),
+    "hydro_state_changed": ([_vp], ctypes.c_int),
+    "hydro_get_error": ([_vp], ctypes.c_int),
+    "hydro_clear_error": ([_vp], ctypes.c_int),
+    "hydro_get_config": ([_vp, ctypes.c_char_p, _sz], ctypes.c_int),
+    "hydro_set_config": ([_vp, ctypes.c_char_p], ctypes.c_int),
+    "hydro_time_sweeps": ([_vp, ctypes.c_int, _dp], ctypes.c_int),
+    "hydro_profile_step": ([_vp, ctypes.c_double, _dp], ctypes.c_int),
+    "hydro_destroy": ([_vp], ctypes.c_int),
+}
+
+
+def lib():
+    """Load libhydro.so (built in-tree by __graft_entry__.build()).  Raises if
+    it is missing: there is no fallback."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(rc, where):
+    if rc != HYDRO_OK:
+        detail = lib().hydro_last_error().decode(errors="replace")
+        raise HydroError(rc, where, detail or lib().hydro_strerror(rc).decode())
+    return rc
+
+
+# --------------------------------------------------------------------------
+# C-named wrappers
+# --------------------------------------------------------------------------
+
+def hydro_abi_version():
+    return lib().hydro_abi_version()
+
+
+def hydro_workspace_bytes(desc):
+    n = _sz(0)
+    _check(lib().hydro_workspace_bytes(ctypes.byref(desc), ctypes.byref(n)),
+           "hydro_workspace_bytes")
+    return n.value
+
+
+def hydro_init(desc, state_ptr, state_bytes, ws_ptr, ws_bytes, stream_ptr):
+    ctx = _vp()
+    _check(lib().hydro_init(ctypes.byref(desc), state_ptr, state_bytes, ws_ptr, ws_bytes,
+                            stream_ptr, ctypes.byref(ctx)), "hydro_init")
+    return ctx
+
+
+def hydro_batch_workspace_bytes(patches, desc):
+    n = _sz(0)
+    _check(lib().hydro_batch_workspace_bytes(patches, len(patches), ctypes.byref(desc),
+                                             ctypes.byref(n)), "hydro_batch_workspace_bytes")
+    return n.value
+
+
+def hydro_batch_init(patches, desc, pool_ptr, pool_bytes, ws_ptr, ws_bytes, stream_ptr):
+    ctx = _vp()
+    _check(lib().hydro_batch_init(patches, len(patches), ctypes.byref(desc), pool_ptr,
+                                  pool_bytes, ws_ptr, ws_bytes, stream_ptr,
+                                  ctypes.byref(ctx)), "hydro_batch_init")
+    return ctx
+
+
+def hydro_cfl_dt(ctx):
+    dt = ctypes.c_double(0.0)
+    _check(lib().hydro_cfl_dt(ctx, ctypes.byref(dt)), "hydro_cfl_dt")
+    return dt.value
+
+
+def hydro_step(ctx, dt=DT_CFL):
+    _check(lib().hydro_step(ctx, float(dt)), "hydro_step")
+
+
+def hydro_batch_step(ctx, dt=DT_CFL):
+    _check(lib().hydro_batch_step(ctx, float(dt)), "hydro_batch_step")
+
+
+def hydro_sweep(ctx, axis, dt, fold_cfl=False):
+    _check(lib().hydro_sweep(ctx, int(axis), float(dt), int(bool(fold_cfl))), "hydro_sweep")
+
+
+def hydro_totals(ctx):
+    out = (ctypes.c_double * 6)()
+    _check(lib().hydro_totals(ctx, out), "hydro_totals")
+    return list(out)
+
+
+def hydro_get_time(ctx):
+    t = ctypes.c_double(0.0)
+    s = ctypes.c_int64(0)
+    _check(lib().hydro_get_time(ctx, ctypes.byref(t), ctypes.byref(s)), "hydro_get_time")
+    return t.value, s.value
+
+
+def hydro_set_time(ctx, t, step):
+    _check(lib().hydro_set_time(ctx, float(t), int(step)), "hydro_set_time")
+
+
+def hydro_set_t_end(ctx, t_end):
+    _check(lib().hydro_set_t_end(ctx, float(t_end)), "hydro_set_t_end")
+
+
+def hydro_state_changed(ctx):
+    _check(lib().hydro_state_changed(ctx), "hydro_state_changed")
+
+
+def hydro_get_error(ctx):
+    """HYDRO_OK or HYDRO_ENUMERIC (returned, not raised)."""
+    rc = lib().hydro_get_error(ctx)
+    if rc not in (HYDRO_OK, HYDRO_ENUMERIC):
+        _check(rc, "hydro_get_error")
+    return rc
+
+
+def hydro_clear_error(ctx):
+    _check(lib().hydro_clear_error(ctx), "hydro_clear_error")
+
+
+def hydro_get_config(ctx):
+    buf = ctypes.create_string_buffer(256)
+    _check(lib().hydro_get_config(ctx, buf, 256), "hydro_get_config")
+    return buf.value.decode()
+
+
+def hydro_set_config(ctx, text):
+    _check(lib().hydro_set_config(ctx, text.encode()), "hydro_set_config")
+
+
+def hydro_time_sweeps(ctx, reps=10):
+    ms = (ctypes.c_double * 3)()
+    _check(lib().hydro_time_sweeps(ctx, int(reps), ms), "hydro_time_sweeps")
+    return list(ms)
+
+
+def hydro_profile_step(ctx, dt=DT_CFL):
+    ms = (ctypes.c_double * 4)()
+    _check(lib().hydro_profile_step(ctx, float(dt), ms), "hydro_profile_step")
+    return list(ms)
+
+
+def hydro_destroy(ctx):
+    if ctx:
+        _check(lib().hydro_destroy(ctx), "hydro_destroy")
+
+
+# --------------------------------------------------------------------------
+# owners
+# --------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def make_desc(shape, dx, gamma, cfl=0.8, bc=(PERIODIC,) * 6, grav=(0.0, 0.0, 0.0),
+              precision=FP32, ng=0, flags=0):
+    nz, ny, nx = shape
+    d = HydroDesc()
+    d.nx, d.ny, d.nz, d.ng = nx, ny, nz, ng
+    if not hasattr(dx, "__len__"):
+        dx = (dx, dx, dx)
+    d.dx, d.dy, d.dz = (float(v) for v in dx)
+    d.gamma = float(gamma)
+    d.cfl = float(cfl)
+    d.grav[:] = [float(g) for g in grav]
+    d.bc[:] = [int(b) for b in bc]
+    d.precision = int(precision)
+    d.flags = int(flags)
+    return d
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream), stream
+
+
+class Grid:
+    """A grid stepped by libhydro.  `state` is a CUDA tensor of shape
+    (5, nz+2ng, ny+2ng, nx+2ng), float32 or float64, contiguous; it is
+    updated in place."""
+
+    def __init__(self, state, dx, gamma, cfl=0.8, bc=(PERIODIC,) * 6,
+                 grav=(0.0, 0.0, 0.0), ng=0, flags=0, stream=None):
+        torch = _torch()
+        if not state.is_cuda or not state.is_contiguous() or state.dim() != 4 \
+                or state.shape[0] != 5:
+            raise ValueError("state must be a contiguous CUDA tensor (5, nz, ny, nx)")
+        if state.dtype == torch.float32:
+            prec = FP32
+        elif state.dtype == torch.float64:
+            prec = FP64
+        else:
+            raise ValueError("state must be float32 or float64")
+        shape = tuple(int(s) - 2 * ng for s in state.shape[1:])
+        self.state = state
+        self.desc = make_desc(shape, dx, gamma, cfl, bc, grav, prec, ng, flags)
+        nbytes = hydro_workspace_bytes(self.desc)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=state.device)
+        sp, self.stream = _stream_ptr(stream)
+        self.ctx = hydro_init(self.desc, ctypes.c_void_p(state.data_ptr()),
+                              state.numel() * state.element_size(),
+                              ctypes.c_void_p(self.workspace.data_ptr()), nbytes, sp)
+
+    # thin method forms of the C calls
+    def step(self, dt=DT_CFL):
+        hydro_step(self.ctx, dt)
+
+    def sweep(self, axis, dt, fold_cfl=False):
+        hydro_sweep(self.ctx, axis, dt, fold_cfl)
+
+    def cfl_dt(self):
+        return hydro_cfl_dt(self.ctx)
+
+    def totals(self):
+        return hydro_totals(self.ctx)
+
+    def time(self):
+        return hydro_get_time(self.ctx)
+
+    def set_time(self, t, step):
+        hydro_set_time(self.ctx, t, step)
+
+    def set_t_end(self, t_end):
+        hydro_set_t_end(self.ctx, t_end)
+
+    def state_changed(self):
+        hydro_state_changed(self.ctx)
+
+    def error(self):
+        return hydro_get_error(self.ctx)
+
+    def clear_error(self):
+        hydro_clear_error(self.ctx)
+
+    @property
+    def config(self):
+        return hydro_get_config(self.ctx)
+
+    @config.setter
+    def config(self, text):
+        hydro_set_config(self.ctx, text)
+
+    def time_sweeps(self, reps=10):
+        return hydro_time_sweeps(self.ctx, reps)
+
+    def profile_step(self, dt=DT_CFL):
+        return hydro_profile_step(self.ctx, dt)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            hydro_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent patches in one pool tensor, stepped by one persistent
+    launch per sweep.  `patches` is a list of dicts or tuples
+    (offset_elems, nx, ny, nz, ng, dx, dy, dz)."""
+
+    def __init__(self, pool, patches, gamma, cfl=0.8, bc=(PERIODIC,) * 6,
+                 grav=(0.0, 0.0, 0.0), flags=0, stream=None):
+        torch = _torch()
+        if not pool.is_cuda or not pool.is_contiguous():
+            raise ValueError("pool must be a contiguous CUDA tensor")
+        prec = FP64 if pool.dtype == torch.float64 else FP32
+        if pool.dtype not in (torch.float32, torch.float64):
+            raise ValueError("pool must be float32 or float64")
+        arr = (HydroPatch * len(patches))()
+        for i, p in enumerate(patches):
+            (arr[i].offset_elems, arr[i].nx, arr[i].ny, arr[i].nz, arr[i].ng,
+             arr[i].dx, arr[i].dy, arr[i].dz) = p
+        self.patches = arr
+        self.pool = pool
+        self.desc = make_desc((1, 1, 1), 1.0, gamma, cfl, bc, grav, prec, 0, flags)
+        nbytes = hydro_batch_workspace_bytes(arr, self.desc)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=pool.device)
+        sp, self.stream = _stream_ptr(stream)
+        self.ctx = hydro_batch_init(arr, self.desc, ctypes.c_void_p(pool.data_ptr()),
+                                    pool.numel() * pool.element_size(),
+                                    ctypes.c_void_p(self.workspace.data_ptr()), nbytes, sp)
+
+    def step(self, dt=DT_CFL):
+        hydro_batch_step(self.ctx, dt)
+
+    def sweep(self, axis, dt, fold_cfl=False):
+        hydro_sweep(self.ctx, axis, dt, fold_cfl)
+
+    def cfl_dt(self):
+        return hydro_cfl_dt(self.ctx)
+
+    def totals(self):
+        return hydro_totals(self.ctx)
+
+    def time(self):
+        return hydro_get_time(self.ctx)
+
+    def set_time(self, t, step):
+        hydro_set_time(self.ctx, t, step)
+
+    def error(self):
+        return hydro_get_error(self.ctx)
+
+    @property
+    def config(self):
+        return hydro_get_config(self.ctx)
+
+    @config.setter
+    def config(self, text):
+        hydro_set_config(self.ctx, text)
+
+    def time_sweeps(self, reps=10):
+        return hydro_time_sweeps(self.ctx, reps)
+
+    def profile_step(self, dt=DT_CFL):
+        return hydro_profile_step(self.ctx, dt)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            hydro_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
