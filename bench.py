@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--config", default="", help="force a kernel configuration")
     ap.add_argument("--copy-only", action="store_true",
