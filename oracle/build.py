@@ -14,15 +14,15 @@ CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
           "-shared", "-std=c11", "-Wall", "-Wextra"]
 
 
-def build(force: bool = True) -> str:
-    if not force and os.path.exists(LIB) and \
-            os.path.getmtime(LIB) >= os.path.getmtime(SRC):
-        return LIB
-    tmp = LIB + ".tmp"
-    cmd = ["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"]
+def build(force: bool = True, src: str = SRC, lib: str = LIB) -> str:
+    if not force and os.path.exists(lib) and \
+            os.path.getmtime(lib) >= os.path.getmtime(src):
+        return lib
+    tmp = lib + ".tmp"
+    cmd = ["gcc", *CFLAGS, "-o", tmp, src, "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
