@@ -41,6 +41,7 @@ struct LaunchSweep {
   SweepCfg cfg;
   int32_t persistent;
   int32_t fp64;
+  int32_t xwave;
 };
 struct LaunchReduce {
   const void* pool;
@@ -70,6 +71,7 @@ hipError_t launch_reset_tickets(DevScalars* s, hipStream_t st);
 int64_t x_tiles(const PatchDev& P, const SweepCfg& c);
 int64_t col_tiles(const PatchDev& P, int axis, const SweepCfg& c);
 size_t x_lds_bytes(const SweepCfg& c, int fp64);
+bool x_wave_ok(int n, int v);
 }  // namespace hydro
 
 using namespace hydro;
@@ -162,12 +164,25 @@ struct Config {
   int32_t batch_blocks = 0;  // persistent launches: workgroups
 };
 
-bool x_cfg_ok(const SweepCfg& c, int nx, int fp64) {
+// A lane run of v cells is loaded and stored as one vector access, so every
+// row of the patch must start on a multiple of the vector's element count
+// (the pool itself is 16-byte aligned).
+bool x_cfg_ok(const SweepCfg& c, const PatchDev& P, int fp64) {
   if (c.kind != 0 || (c.v != 1 && c.v != 2 && c.v != 4)) return false;
+  const int nx = P.n[0];
   if (nx % c.v) return false;
   int lpp = nx / c.v;
   if (c.block < 64 || c.block > kMaxBlock || c.block % 64 || c.block < lpp) return false;
   if (x_lds_bytes(c, fp64) > 64 * 1024) return false;
+  const int esz = fp64 ? 8 : 4;
+  const int a = std::min(c.v, 16 / esz);
+  if (P.base0 % a || P.sy % a || P.sz % a || P.plane % a) return false;
+  return true;
+}
+
+bool x_cfg_ok_all(const SweepCfg& c, const std::vector<PatchDev>& ps, int fp64) {
+  for (auto& P : ps)
+    if (!x_cfg_ok(c, P, fp64)) return false;
   return true;
 }
 
@@ -177,18 +192,17 @@ bool col_cfg_ok(const SweepCfg& c) {
   return b >= 64 && b <= kMaxBlock && b % 64 == 0 && c.q % 64 == 0 && c.s <= 16;
 }
 
-SweepCfg default_x(int nx, int fp64) {
+SweepCfg default_x(const std::vector<PatchDev>& ps, int fp64) {
   SweepCfg c{};
   c.kind = 0;
-  int v = 4;
-  while (nx % v) v /= 2;
-  c.v = v;
-  int lpp = nx / v;
-  c.block = lpp > 256 ? int(align_up(size_t(lpp), 64)) : 256;
-  if (!x_cfg_ok(c, nx, fp64)) {
-    c.v = 1;
-    c.block = int(align_up(size_t(nx), 64));
+  for (int v : {4, 2, 1}) {
+    c.v = v;
+    int lpp = 1;
+    for (auto& P : ps) lpp = std::max(lpp, P.n[0] / v);
+    c.block = lpp > 256 ? int(align_up(size_t(lpp), 64)) : 256;
+    if (x_cfg_ok_all(c, ps, fp64)) return c;
   }
+  c.v = 0;  // none fits
   return c;
 }
 
@@ -360,6 +374,12 @@ LaunchSweep sweep_launch(const hydro_ctx* c, int axis, int do_cfl) {
   L.cfg = c->cfg.ax[axis];
   L.persistent = c->batch ? 1 : 0;
   L.fp64 = c->fp64;
+  L.xwave = 1;
+  if (c->batch) {
+    for (auto& P : c->patches) L.xwave = L.xwave && x_wave_ok(P.n[0], c->cfg.ax[0].v);
+  } else {
+    L.xwave = x_wave_ok(c->single.n[0], c->cfg.ax[0].v);
+  }
   return L;
 }
 
@@ -474,20 +494,14 @@ std::string shape_key(const hydro_ctx* c, int axis) {
 std::vector<SweepCfg> candidates(const hydro_ctx* c, int axis) {
   std::vector<SweepCfg> out;
   if (axis == 0) {
-    std::vector<int> widths;
-    if (c->batch)
-      for (auto& P : c->patches) widths.push_back(P.n[0]);
-    else
-      widths.push_back(c->single.n[0]);
+    const std::vector<PatchDev> ps = c->batch ? c->patches : std::vector<PatchDev>{c->single};
     for (int v : {1, 2, 4})
       for (int b : {64, 128, 256, 512}) {
         SweepCfg s{};
         s.kind = 0;
         s.v = v;
         s.block = b;
-        bool ok = true;
-        for (int w : widths) ok = ok && x_cfg_ok(s, w, c->fp64);
-        if (ok) out.push_back(s);
+        if (x_cfg_ok_all(s, ps, c->fp64)) out.push_back(s);
       }
   } else {
     int n = c->batch ? 64 : c->single.n[axis];
@@ -532,12 +546,9 @@ int choose_config(hydro_ctx* c) {
       Config tmp = c->cfg;
       if (parse_cfg(it->second, tmp)) {
         bool ok = axis == 0 ? true : col_cfg_ok(tmp.ax[axis]);
-        if (axis == 0) {
-          if (c->batch)
-            for (auto& P : c->patches) ok = ok && x_cfg_ok(tmp.ax[0], P.n[0], c->fp64);
-          else
-            ok = x_cfg_ok(tmp.ax[0], c->single.n[0], c->fp64);
-        }
+        if (axis == 0)
+          ok = x_cfg_ok_all(tmp.ax[0],
+                            c->batch ? c->patches : std::vector<PatchDev>{c->single}, c->fp64);
         if (ok) {
           c->cfg.ax[axis] = tmp.ax[axis];
           continue;
@@ -742,9 +753,11 @@ int hydro_init(const hydro_desc* d, void* state, size_t state_bytes, void* works
   int32_t n[3] = {d->nx, d->ny, d->nz};
   double dx[3] = {d->dx, d->dy, d->dz};
   PatchDev P = make_patch(n, d->ng, dx, 0);
-  const size_t esz = d->precision == HYDRO_FP64 ? 8 : 4;
-  if (P.plane > (int64_t(1) << 31)) return fail(HYDRO_EINVAL, "grid plane too large");
-  if (state_bytes < size_t(P.plane) * 5 * esz) return fail(HYDRO_EINVAL, "state buffer too small");
+  const int64_t esz = d->precision == HYDRO_FP64 ? 8 : 4;
+  if (P.plane * int64_t(esz) >= (int64_t(1) << 32))
+    return fail(HYDRO_EINVAL, "a state plane must be smaller than 4 GiB");
+  if (state_bytes < size_t(P.plane) * 5 * size_t(esz))
+    return fail(HYDRO_EINVAL, "state buffer too small");
   hydro_ctx* c = new (std::nothrow) hydro_ctx();
   if (!c) return fail(HYDRO_EINVAL, "out of host memory");
   c->desc = *d;
@@ -757,10 +770,10 @@ int hydro_init(const hydro_desc* d, void* state, size_t state_bytes, void* works
   c->partials = reinterpret_cast<double*>(c->ws + kScalarBytes);
   c->single = P;
   for (int a = 0; a < 3; ++a) c->active[a] = n[a] > 1;
-  c->cfg.ax[0] = default_x(n[0], c->fp64);
+  c->cfg.ax[0] = default_x({P}, c->fp64);
   c->cfg.ax[1] = default_col(n[1]);
   c->cfg.ax[2] = default_col(n[2]);
-  if (!x_cfg_ok(c->cfg.ax[0], n[0], c->fp64) && c->active[0]) {
+  if (c->cfg.ax[0].v == 0 && c->active[0]) {
     delete c;
     return fail(HYDRO_EINVAL, "no valid x-sweep configuration for this width");
   }
@@ -854,18 +867,8 @@ int hydro_batch_init(const hydro_patch* p, int32_t n, const hydro_desc* common, 
   c->single = c->patches[0];
   // batch defaults: 4 cells per lane where every width allows, whole
   // columns per thread (patches are short), 8 workgroups per CU
-  SweepCfg x{};
-  x.kind = 0;
-  x.block = 256;
-  for (int v : {4, 2, 1}) {
-    x.v = v;
-    bool ok = true;
-    for (auto& P : c->patches) ok = ok && x_cfg_ok(x, P.n[0], c->fp64);
-    if (ok) break;
-  }
-  bool xok = true;
-  for (auto& P : c->patches) xok = xok && x_cfg_ok(x, P.n[0], c->fp64);
-  if (!xok && c->active[0]) {
+  SweepCfg x = default_x(c->patches, c->fp64);
+  if (x.v == 0 && c->active[0]) {
     delete c;
     return fail(HYDRO_EINVAL, "no x-sweep configuration fits every patch width");
   }
@@ -1041,14 +1044,10 @@ int hydro_set_config(hydro_ctx* c, const char* text) {
   if (!c || !text) return fail(HYDRO_EINVAL, "bad argument");
   Config cf = c->cfg;
   if (!parse_cfg(text, cf)) return fail(HYDRO_EINVAL, "cannot parse configuration");
-  if (c->active[0]) {
-    if (c->batch) {
-      for (auto& P : c->patches)
-        if (!x_cfg_ok(cf.ax[0], P.n[0], c->fp64)) return fail(HYDRO_EINVAL, "invalid x config");
-    } else if (!x_cfg_ok(cf.ax[0], c->single.n[0], c->fp64)) {
-      return fail(HYDRO_EINVAL, "invalid x config");
-    }
-  }
+  if (c->active[0] &&
+      !x_cfg_ok_all(cf.ax[0], c->batch ? c->patches : std::vector<PatchDev>{c->single},
+                    c->fp64))
+    return fail(HYDRO_EINVAL, "invalid x config");
   for (int a = 1; a < 3; ++a)
     if (c->active[a] && !col_cfg_ok(cf.ax[a])) return fail(HYDRO_EINVAL, "invalid column config");
   if (c->batch && (cf.batch_blocks < 1 || cf.batch_blocks > 65536))

@@ -31,6 +31,7 @@ namespace hydro {
 template <class T>
 struct Prim {
   T r, u, t1, t2, p;
+  T ri;  // 1 / rho of a cell-centred state (unused on face states)
 };
 
 template <class T>
@@ -38,17 +39,33 @@ struct Cons {
   T r, mn, mt1, mt2, e;
 };
 
-// Reciprocal, division and square root policies.  FP64 keeps IEEE division
-// and square root.  FP32 uses the hardware reciprocal and square root (about
-// 1 ulp) and divides by multiplying with the reciprocal; the FP32 path is checked against the FP64 oracle through an L1
-// bound, and the instructions are deterministic, so every kernel that calls
-// these still agrees bit for bit.
-__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+// Reciprocal, division and square-root policies.
+//  * FP32: the hardware reciprocal and reciprocal square root (about 1 ulp).
+//  * FP64: the hardware estimates refined by two Newton steps (about 1 ulp
+//    in double), instead of the longer IEEE-exact division and square-root
+//    sequences.
+// Both are deterministic instruction sequences, so every kernel that calls
+// them produces the same bits; both stay far inside the FP64 parity bound
+// and the FP32 L1 bound against the oracle.
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
-__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double div_(double a, double b) { return a / b; }
-__device__ __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double rsqrt_(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x;
+  double e = __builtin_fma(-(h * y), y, 0.5);
+  y = __builtin_fma(y, e, y);
+  e = __builtin_fma(-(h * y), y, 0.5);
+  return __builtin_fma(y, e, y);
+}
+__device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double div_(double a, double b) { return a * rcp(b); }
+__device__ __forceinline__ float div_(float a, float b) { return a * rcp(b); }
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmin_(double a, double b) { return __builtin_fmin(a, b); }
@@ -58,13 +75,20 @@ __device__ __forceinline__ float fmax_(float a, float b) { return __builtin_fmax
 __device__ __forceinline__ double fabs_(double a) { return __builtin_fabs(a); }
 __device__ __forceinline__ float fabs_(float a) { return __builtin_fabsf(a); }
 
+// Sound speed sqrt(gamma p / rho) written as gamma p / sqrt(gamma p rho):
+// one reciprocal square root, no division.
+template <class T>
+__device__ __forceinline__ T sound(T gamma, T p, T rho) {
+  T gp = gamma * p;
+  return gp * rsqrt_(gp * rho);
+}
+
 // Constants of one sweep, in the arithmetic type.
 template <class T>
 struct SweepConst {
   T gamma;        // ratio of specific heats
   T gm1;          // gamma - 1
   T inv_gm1;      // 1 / (gamma - 1)
-  T half_dtdx;    // dt / dx / 2
   T dtdx;         // dt / dx
   T kick;         // dt g / 2 along the sweep axis (gravity half kick)
   T dtg;          // dt g along the sweep axis
@@ -76,6 +100,7 @@ template <class T>
 __device__ __forceinline__ Prim<T> to_prim(const Cons<T>& U, const SweepConst<T>& k) {
   Prim<T> W;
   T ri = rcp(U.r);
+  W.ri = ri;
   W.r = U.r;
   W.u = U.mn * ri;
   W.t1 = U.mt1 * ri;
@@ -93,49 +118,60 @@ __device__ __forceinline__ Prim<T> mirror(const Prim<T>& W) {
   return M;
 }
 
+// minmod(x, y) = median(x, y, 0): the smaller magnitude when x and y share a
+// strict sign, else 0.  One v_med3 in FP32.
+__device__ __forceinline__ float minmod(float x, float y) {
+  return __builtin_amdgcn_fmed3f(x, y, 0.0f);
+}
+__device__ __forceinline__ double minmod(double x, double y) {
+  return __builtin_fmax(__builtin_fmin(x, y), __builtin_fmin(__builtin_fmax(x, y), 0.0));
+}
+
+// Half of the MC limited slope from the left difference a and the right
+// difference b.  MC = sign(a) min(2|a|, 2|b|, |a+b|/2) when a and b share a
+// strict sign, else 0 (van Leer 1977); equivalently
+// MC = minmod((a+b)/2, 2 minmod(a, b)), so MC/2 = minmod((a+b)/4, minmod(a, b))
+// (scaling by a power of two is exact).
 template <class T>
-__device__ __forceinline__ T mc_slope(T a, T b) {
-  T m = fmin_(T(2) * fmin_(fabs_(a), fabs_(b)), T(0.5) * fabs_(a + b));
-  bool pos = (a > T(0)) & (b > T(0));
-  bool neg = (a < T(0)) & (b < T(0));
-  return pos ? m : (neg ? -m : T(0));
+__device__ __forceinline__ T half_mc(T a, T b) {
+  return minmod(T(0.25) * (a + b), minmod(a, b));
 }
 
 // Face states (W-, W+) of the cell W with left and right neighbours Wl, Wr.
 // `kick` is the gravity half kick of this cell (negated for a mirrored ghost
-// behind a reflecting wall, whose gravity is mirrored too).
+// behind a reflecting wall, whose gravity is mirrored too).  With d = D/2:
+// W-/+ = W - (dt/dx) A(W) d -/+ d.
 template <class T>
 __device__ __forceinline__ void face_states(const Prim<T>& Wl, const Prim<T>& W,
                                             const Prim<T>& Wr, const SweepConst<T>& k,
                                             T kick, Prim<T>& Wm, Prim<T>& Wp) {
-  Prim<T> D;
-  D.r = mc_slope(W.r - Wl.r, Wr.r - W.r);
-  D.u = mc_slope(W.u - Wl.u, Wr.u - W.u);
-  D.t1 = mc_slope(W.t1 - Wl.t1, Wr.t1 - W.t1);
-  D.t2 = mc_slope(W.t2 - Wl.t2, Wr.t2 - W.t2);
-  D.p = mc_slope(W.p - Wl.p, Wr.p - W.p);
-  // A(W) D for the primitive Euler system
-  T ri = rcp(W.r);
-  T ar = fma_(W.u, D.r, W.r * D.u);
-  T au = fma_(W.u, D.u, D.p * ri);
-  T at1 = W.u * D.t1;
-  T at2 = W.u * D.t2;
-  T ap = fma_(k.gamma * W.p, D.u, W.u * D.p);
-  T h = k.half_dtdx;
+  Prim<T> d;
+  d.r = half_mc(W.r - Wl.r, Wr.r - W.r);
+  d.u = half_mc(W.u - Wl.u, Wr.u - W.u);
+  d.t1 = half_mc(W.t1 - Wl.t1, Wr.t1 - W.t1);
+  d.t2 = half_mc(W.t2 - Wl.t2, Wr.t2 - W.t2);
+  d.p = half_mc(W.p - Wl.p, Wr.p - W.p);
+  // A(W) d for the primitive Euler system
+  T ar = fma_(W.u, d.r, W.r * d.u);
+  T au = fma_(W.u, d.u, d.p * W.ri);
+  T at1 = W.u * d.t1;
+  T at2 = W.u * d.t2;
+  T ap = fma_(k.gamma * W.p, d.u, W.u * d.p);
+  T h = k.dtdx;
   T br = fma_(-h, ar, W.r), bu = fma_(-h, au, W.u), bt1 = fma_(-h, at1, W.t1);
   T bt2 = fma_(-h, at2, W.t2), bp = fma_(-h, ap, W.p);
-  Wm.r = fma_(T(-0.5), D.r, br);
-  Wp.r = fma_(T(0.5), D.r, br);
-  Wm.u = fma_(T(-0.5), D.u, bu);
-  Wp.u = fma_(T(0.5), D.u, bu);
-  Wm.t1 = fma_(T(-0.5), D.t1, bt1);
-  Wp.t1 = fma_(T(0.5), D.t1, bt1);
-  Wm.t2 = fma_(T(-0.5), D.t2, bt2);
-  Wp.t2 = fma_(T(0.5), D.t2, bt2);
-  Wm.p = fma_(T(-0.5), D.p, bp);
-  Wp.p = fma_(T(0.5), D.p, bp);
-  bool bad = (Wm.r <= T(0)) | (Wm.p <= T(0)) | (Wp.r <= T(0)) | (Wp.p <= T(0));
-  if (bad) {  // first order for this cell
+  Wm.r = br - d.r;
+  Wp.r = br + d.r;
+  Wm.u = bu - d.u;
+  Wp.u = bu + d.u;
+  Wm.t1 = bt1 - d.t1;
+  Wp.t1 = bt1 + d.t1;
+  Wm.t2 = bt2 - d.t2;
+  Wp.t2 = bt2 + d.t2;
+  Wm.p = bp - d.p;
+  Wp.p = bp + d.p;
+  T lo = fmin_(fmin_(Wm.r, Wp.r), fmin_(Wm.p, Wp.p));
+  if (lo <= T(0)) {  // first order for this cell
     Wm = W;
     Wp = W;
   }
@@ -151,8 +187,8 @@ __device__ __forceinline__ void face_states(const Prim<T>& Wl, const Prim<T>& W,
 template <class T>
 __device__ __forceinline__ Cons<T> hllc(const Prim<T>& L, const Prim<T>& R,
                                         const SweepConst<T>& k) {
-  T cL = sqrt_(k.gamma * L.p * rcp(L.r));
-  T cR = sqrt_(k.gamma * R.p * rcp(R.r));
+  T cL = sound(k.gamma, L.p, L.r);
+  T cR = sound(k.gamma, R.p, R.r);
   T SL = fmin_(L.u - cL, R.u - cR);
   T SR = fmax_(L.u + cL, R.u + cR);
   T aL = L.r * (SL - L.u);
@@ -216,14 +252,11 @@ __device__ __forceinline__ void update(Cons<T>& U, const Cons<T>& Fl, const Cons
   }
 }
 
-// Health of an updated cell: rho > 0 and p > 0 (2 rho E > |m|^2), finite.
+// Health of an updated cell from its primitives: rho > 0, p > 0 and a finite
+// energy (a NaN fails every comparison).
 template <class T>
-__device__ __forceinline__ bool cell_ok(const Cons<T>& U) {
-  T mm = fma_(U.mn, U.mn, fma_(U.mt1, U.mt1, U.mt2 * U.mt2));
-  bool ok = (U.r > T(0)) & (T(2) * U.r * U.e > mm);
-  // a NaN fails the comparisons above; an infinity makes 2 rho E or mm inf
-  ok = ok && (fabs_(U.e) < T(__builtin_huge_val())) && (fabs_(U.r) < T(__builtin_huge_val()));
-  return ok;
+__device__ __forceinline__ bool cell_ok(const Cons<T>& U, const Prim<T>& W) {
+  return (W.r > T(0)) && (W.p > T(0)) && (fabs_(U.e) < T(__builtin_huge_val()));
 }
 
 }  // namespace hydro

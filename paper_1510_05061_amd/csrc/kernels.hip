@@ -54,7 +54,6 @@ __device__ __forceinline__ SweepConst<T> make_const(double dt, double dx, double
   k.inv_gm1 = T(1.0 / (gamma - 1.0));
   double dtdx = dt / dx;
   k.dtdx = T(dtdx);
-  k.half_dtdx = T(0.5 * dtdx);
   k.kick = T(0.5 * dt * g);
   k.dtg = T(dt * g);
   k.has_g = (g != 0.0);
@@ -67,34 +66,98 @@ template <> struct Rot<0> { static constexpr int n = 1, t1 = 2, t2 = 3; };
 template <> struct Rot<1> { static constexpr int n = 2, t1 = 1, t2 = 3; };
 template <> struct Rot<2> { static constexpr int n = 3, t1 = 1, t2 = 2; };
 
+// The five planes of a grid or patch as uniform base pointers, addressed by
+// a 32-bit byte offset inside a plane (one address VGPR shared by the five
+// loads or stores of a cell; the runtime guarantees planes below 4 GiB).
 template <class T, int AXIS>
-__device__ __forceinline__ Cons<T> load_cell(const T* __restrict__ p, int64_t pl) {
-  Cons<T> U;
-  U.r = p[0];
-  U.mn = p[Rot<AXIS>::n * pl];
-  U.mt1 = p[Rot<AXIS>::t1 * pl];
-  U.mt2 = p[Rot<AXIS>::t2 * pl];
-  U.e = p[4 * pl];
-  return U;
+struct Planes {
+  char* r;
+  char* n;
+  char* t1;
+  char* t2;
+  char* e;
+  __device__ __forceinline__ Planes(T* pool, const PatchDev& P) {
+    T* p0 = pool + P.base0;
+    const int64_t pl = P.plane;
+    r = reinterpret_cast<char*>(p0);
+    n = reinterpret_cast<char*>(p0 + Rot<AXIS>::n * pl);
+    t1 = reinterpret_cast<char*>(p0 + Rot<AXIS>::t1 * pl);
+    t2 = reinterpret_cast<char*>(p0 + Rot<AXIS>::t2 * pl);
+    e = reinterpret_cast<char*>(p0 + 4 * pl);
+  }
+  __device__ __forceinline__ Cons<T> load(uint32_t b) const {
+    Cons<T> U;
+    U.r = *reinterpret_cast<const T*>(r + b);
+    U.mn = *reinterpret_cast<const T*>(n + b);
+    U.mt1 = *reinterpret_cast<const T*>(t1 + b);
+    U.mt2 = *reinterpret_cast<const T*>(t2 + b);
+    U.e = *reinterpret_cast<const T*>(e + b);
+    return U;
+  }
+  __device__ __forceinline__ void store(uint32_t b, const Cons<T>& U) const {
+    *reinterpret_cast<T*>(r + b) = U.r;
+    *reinterpret_cast<T*>(n + b) = U.mn;
+    *reinterpret_cast<T*>(t1 + b) = U.mt1;
+    *reinterpret_cast<T*>(t2 + b) = U.mt2;
+    *reinterpret_cast<T*>(e + b) = U.e;
+  }
+};
+
+// V consecutive elements of one plane at byte offset b (aligned to the
+// vector width; the runtime only picks V > 1 where rows are aligned).
+template <class T, int V>
+__device__ __forceinline__ void load_run(const char* base, uint32_t b, T (&o)[V]) {
+  if constexpr (V == 1) {
+    o[0] = *reinterpret_cast<const T*>(base + b);
+  } else if constexpr (sizeof(T) * V <= 16) {
+    typedef T vec __attribute__((ext_vector_type(V)));
+    vec t = *reinterpret_cast<const vec*>(base + b);
+#pragma unroll
+    for (int i = 0; i < V; ++i) o[i] = t[i];
+  } else {
+    constexpr int H = 16 / sizeof(T);
+    typedef T vec __attribute__((ext_vector_type(H)));
+#pragma unroll
+    for (int h = 0; h < V / H; ++h) {
+      vec t = *reinterpret_cast<const vec*>(base + b + h * 16);
+#pragma unroll
+      for (int i = 0; i < H; ++i) o[h * H + i] = t[i];
+    }
+  }
 }
 
-template <class T, int AXIS>
-__device__ __forceinline__ void store_cell(T* __restrict__ p, int64_t pl, const Cons<T>& U) {
-  p[0] = U.r;
-  p[Rot<AXIS>::n * pl] = U.mn;
-  p[Rot<AXIS>::t1 * pl] = U.mt1;
-  p[Rot<AXIS>::t2 * pl] = U.mt2;
-  p[4 * pl] = U.e;
+template <class T, int V>
+__device__ __forceinline__ void store_run(char* base, uint32_t b, const T (&o)[V]) {
+  if constexpr (V == 1) {
+    *reinterpret_cast<T*>(base + b) = o[0];
+  } else if constexpr (sizeof(T) * V <= 16) {
+    typedef T vec __attribute__((ext_vector_type(V)));
+    vec t;
+#pragma unroll
+    for (int i = 0; i < V; ++i) t[i] = o[i];
+    *reinterpret_cast<vec*>(base + b) = t;
+  } else {
+    constexpr int H = 16 / sizeof(T);
+    typedef T vec __attribute__((ext_vector_type(H)));
+#pragma unroll
+    for (int h = 0; h < V / H; ++h) {
+      vec t;
+#pragma unroll
+      for (int i = 0; i < H; ++i) t[i] = o[h * H + i];
+      *reinterpret_cast<vec*>(base + b + h * 16) = t;
+    }
+  }
 }
 
 // Signal speed over the cell width, maxed over the active axes, of an
-// updated cell.  U is rotated back to the physical frame (rho, mx, my, mz,
-// E) first so that the result does not depend on which sweep computed it:
-// the folded maximum of a step and a standalone reduction of the same state
-// give the same bits.  id* are 1/dx per physical axis, zero when inactive.
+// updated cell, and its health.  U is rotated back to the physical frame
+// (rho, mx, my, mz, E) first so that the result does not depend on which
+// sweep computed it: the folded maximum of a step and a standalone
+// reduction of the same state give the same bits.  id[] is 1/dx per
+// physical axis, zero for an inactive axis.
 template <class T, int AXIS>
 __device__ __forceinline__ T cell_speed(const Cons<T>& S, const SweepConst<T>& k,
-                                        const T id[3]) {
+                                        const T id[3], bool& bad) {
   Cons<T> U;  // physical frame: mn holds mx, mt1 my, mt2 mz
   U.r = S.r;
   U.e = S.e;
@@ -102,7 +165,8 @@ __device__ __forceinline__ T cell_speed(const Cons<T>& S, const SweepConst<T>& k
   if (AXIS == 1) { U.mn = S.mt1; U.mt1 = S.mn; U.mt2 = S.mt2; }
   if (AXIS == 2) { U.mn = S.mt1; U.mt1 = S.mt2; U.mt2 = S.mn; }
   Prim<T> W = to_prim(U, k);
-  T c = sqrt_(k.gamma * W.p * rcp(W.r));
+  bad |= !cell_ok(U, W);
+  T c = sound(k.gamma, W.p, W.r);
   T s = (fabs_(W.u) + c) * id[0];
   s = fmax_(s, (fabs_(W.t1) + c) * id[1]);
   s = fmax_(s, (fabs_(W.t2) + c) * id[2]);
@@ -140,16 +204,39 @@ __device__ void finish_block(DevScalars* scal, T smax, bool bad, bool do_cfl, T*
   }
 }
 
+template <class T>
+__device__ __forceinline__ Prim<T> shfl_prim(const Prim<T>& W, int src) {
+  Prim<T> r;
+  r.r = __shfl(W.r, src);
+  r.u = __shfl(W.u, src);
+  r.t1 = __shfl(W.t1, src);
+  r.t2 = __shfl(W.t2, src);
+  r.p = __shfl(W.p, src);
+  r.ri = __shfl(W.ri, src);
+  return r;
+}
+
+template <class T>
+__device__ __forceinline__ Cons<T> shfl_cons(const Cons<T>& F, int src) {
+  Cons<T> r;
+  r.r = __shfl(F.r, src);
+  r.mn = __shfl(F.mn, src);
+  r.mt1 = __shfl(F.mt1, src);
+  r.mt2 = __shfl(F.mt2, src);
+  r.e = __shfl(F.e, src);
+  return r;
+}
+
 // --------------------------------------------------------------------------
 // Lane runs along x
 // --------------------------------------------------------------------------
 
-// LDS use per workgroup: 15 values per thread (edge primitives, last face
-// state; the first face flux reuses the primitive slots).
-template <class T>
-constexpr int xlds_values() { return 15; }
-
-template <class T, int V>
+// LDS use per workgroup of the LDS-exchange variant: 15 values per thread
+// (edge primitives, last face state; the first face flux reuses the
+// primitive slots).  The wave variant (a pencil never straddles a wave)
+// trades the same values with cross-lane shuffles and needs no LDS and no
+// barrier.
+template <class T, int V, bool WAVE>
 __device__ void xsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t tile,
                             const SweepConst<T>& k, T* lds, T& smax, bool& bad) {
   const int N = P.n[0];
@@ -162,133 +249,179 @@ __device__ void xsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t ti
   const int64_t npen = int64_t(P.n[1]) * P.n[2];
   const int64_t q = tile * PPW + pw;
   const bool act = (pw < PPW) && (q < npen);
-  const int64_t pl = P.plane;
-  T* base = a.pool + P.base0 + lane * V;
-  if (act) base += (q % P.n[1]) * int64_t(P.sy) + (q / P.n[1]) * int64_t(P.sz);
-
-  T* lw = lds;            // [10][B]: W first (0..4), W last (5..9); later F first
-  T* lp = lds + 10 * B;   // [5][B]: Wp of the last cell
+  const Planes<T, 0> pl(a.pool, P);
+  uint32_t off = 0;  // byte offset of this lane's first cell inside a plane
+  if (act)
+    off = uint32_t(((q % P.n[1]) * int64_t(P.sy) + (q / P.n[1]) * int64_t(P.sz) + lane * V) *
+                   int64_t(sizeof(T)));
 
   Cons<T> U[V];
   Prim<T> W[V];
-  if (act) {
+  {
+    T r[V], mn[V], mt1[V], mt2[V], e[V];
+    if (act) {
+      load_run<T, V>(pl.r, off, r);
+      load_run<T, V>(pl.n, off, mn);
+      load_run<T, V>(pl.t1, off, mt1);
+      load_run<T, V>(pl.t2, off, mt2);
+      load_run<T, V>(pl.e, off, e);
+    } else {
+#pragma unroll
+      for (int c = 0; c < V; ++c) {  // a benign state for idle lanes
+        r[c] = T(1); mn[c] = mt1[c] = mt2[c] = T(0); e[c] = T(1);
+      }
+    }
 #pragma unroll
     for (int c = 0; c < V; ++c) {
-      U[c] = load_cell<T, 0>(base + c, pl);
+      U[c] = Cons<T>{r[c], mn[c], mt1[c], mt2[c], e[c]};
       W[c] = to_prim(U[c], k);
     }
-    lw[0 * B + tid] = W[0].r; lw[1 * B + tid] = W[0].u; lw[2 * B + tid] = W[0].t1;
-    lw[3 * B + tid] = W[0].t2; lw[4 * B + tid] = W[0].p;
-    lw[5 * B + tid] = W[V - 1].r; lw[6 * B + tid] = W[V - 1].u; lw[7 * B + tid] = W[V - 1].t1;
-    lw[8 * B + tid] = W[V - 1].t2; lw[9 * B + tid] = W[V - 1].p;
   }
-  __syncthreads();
-
-  auto read_w = [&](int slot, int t) {
-    Prim<T> r;
-    r.r = lw[(slot + 0) * B + t]; r.u = lw[(slot + 1) * B + t]; r.t1 = lw[(slot + 2) * B + t];
-    r.t2 = lw[(slot + 3) * B + t]; r.p = lw[(slot + 4) * B + t];
-    return r;
-  };
 
   Prim<T> Wl, Wr;  // cell left of the first, right of the last
-  Prim<T> Wm[V], Wp[V];
-  if (act) {
-    if (lane > 0) {
-      Wl = read_w(5, tid - 1);
-    } else if (a.bc_lo == kBcPeriodic) {
-      Wl = read_w(5, tid + LPP - 1);
-    } else if (a.bc_lo == kBcOutflow) {
-      Wl = W[0];
-    } else {
-      Wl = mirror(W[0]);
+  if (WAVE) {
+    const int lw = tid & 63;
+    const int srcL = lane > 0 ? lw - 1 : lw + LPP - 1;
+    const int srcR = lane < LPP - 1 ? lw + 1 : lw - (LPP - 1);
+    Wl = shfl_prim(W[V - 1], srcL);
+    Wr = shfl_prim(W[0], srcR);
+  } else {
+    T* lw = lds;  // [10][B]: W first (0..4), W last (5..9)
+    if (act) {
+      lw[0 * B + tid] = W[0].r; lw[1 * B + tid] = W[0].u; lw[2 * B + tid] = W[0].t1;
+      lw[3 * B + tid] = W[0].t2; lw[4 * B + tid] = W[0].p;
+      lw[5 * B + tid] = W[V - 1].r; lw[6 * B + tid] = W[V - 1].u;
+      lw[7 * B + tid] = W[V - 1].t1; lw[8 * B + tid] = W[V - 1].t2;
+      lw[9 * B + tid] = W[V - 1].p;
     }
-    if (lane < LPP - 1) {
-      Wr = read_w(0, tid + 1);
-    } else if (a.bc_hi == kBcPeriodic) {
-      Wr = read_w(0, tid - (LPP - 1));
-    } else if (a.bc_hi == kBcOutflow) {
-      Wr = W[V - 1];
-    } else {
-      Wr = mirror(W[V - 1]);
+    __syncthreads();
+    if (act) {
+      auto read_w = [&](int slot, int t) {
+        Prim<T> r;
+        r.r = lw[(slot + 0) * B + t]; r.u = lw[(slot + 1) * B + t];
+        r.t1 = lw[(slot + 2) * B + t]; r.t2 = lw[(slot + 3) * B + t];
+        r.p = lw[(slot + 4) * B + t];
+        r.ri = rcp(r.r);
+        return r;
+      };
+      Wl = read_w(5, lane > 0 ? tid - 1 : tid + LPP - 1);
+      Wr = read_w(0, lane < LPP - 1 ? tid + 1 : tid - (LPP - 1));
     }
-#pragma unroll
-    for (int c = 0; c < V; ++c) {
-      const Prim<T>& L = c == 0 ? Wl : W[c - 1];
-      const Prim<T>& R = c == V - 1 ? Wr : W[c + 1];
-      face_states(L, W[c], R, k, k.kick, Wm[c], Wp[c]);
-    }
-    lp[0 * B + tid] = Wp[V - 1].r; lp[1 * B + tid] = Wp[V - 1].u; lp[2 * B + tid] = Wp[V - 1].t1;
-    lp[3 * B + tid] = Wp[V - 1].t2; lp[4 * B + tid] = Wp[V - 1].p;
   }
-  __syncthreads();
+  if (lane == 0 && a.bc_lo != kBcPeriodic) Wl = a.bc_lo == kBcOutflow ? W[0] : mirror(W[0]);
+  if (lane == LPP - 1 && a.bc_hi != kBcPeriodic)
+    Wr = a.bc_hi == kBcOutflow ? W[V - 1] : mirror(W[V - 1]);
 
-  Cons<T> F[V];
-  if (act) {
-    Prim<T> WpL;  // face state W+ of the cell left of the first
-    if (lane > 0 || a.bc_lo == kBcPeriodic) {
+  Prim<T> Wm[V], Wp[V];
+#pragma unroll
+  for (int c = 0; c < V; ++c) {
+    const Prim<T>& L = c == 0 ? Wl : W[c - 1];
+    const Prim<T>& R = c == V - 1 ? Wr : W[c + 1];
+    face_states(L, W[c], R, k, k.kick, Wm[c], Wp[c]);
+  }
+
+  Prim<T> WpL;  // face state W+ of the cell left of the first
+  if (WAVE) {
+    const int lw = tid & 63;
+    WpL = shfl_prim(Wp[V - 1], lane > 0 ? lw - 1 : lw + LPP - 1);
+  } else {
+    T* lp = lds + 10 * B;  // [5][B]: Wp of the last cell
+    if (act) {
+      lp[0 * B + tid] = Wp[V - 1].r; lp[1 * B + tid] = Wp[V - 1].u;
+      lp[2 * B + tid] = Wp[V - 1].t1; lp[3 * B + tid] = Wp[V - 1].t2;
+      lp[4 * B + tid] = Wp[V - 1].p;
+    }
+    __syncthreads();
+    if (act) {
       int t = lane > 0 ? tid - 1 : tid + LPP - 1;
       WpL.r = lp[0 * B + t]; WpL.u = lp[1 * B + t]; WpL.t1 = lp[2 * B + t];
       WpL.t2 = lp[3 * B + t]; WpL.p = lp[4 * B + t];
-    } else {
-      // ghost cell -1 with ghost -2 behind it
-      Prim<T> g1, g2, dummy;
-      T kick = k.kick;
-      if (a.bc_lo == kBcOutflow) {
-        g1 = W[0];
-        g2 = W[0];
-      } else {
-        const Prim<T>& W1 = V >= 2 ? W[V >= 2 ? 1 : 0] : Wr;
-        g1 = mirror(W[0]);
-        g2 = mirror(W1);
-        kick = -k.kick;
-      }
-      face_states(g2, g1, W[0], k, kick, dummy, WpL);
     }
+  }
+  if (lane == 0 && a.bc_lo != kBcPeriodic) {
+    // ghost cell -1 with ghost -2 behind it
+    Prim<T> g1, g2, dummy;
+    T kick = k.kick;
+    if (a.bc_lo == kBcOutflow) {
+      g1 = W[0];
+      g2 = W[0];
+    } else {
+      const Prim<T>& W1 = V >= 2 ? W[V >= 2 ? 1 : 0] : Wr;
+      g1 = mirror(W[0]);
+      g2 = mirror(W1);
+      kick = -k.kick;
+    }
+    face_states(g2, g1, W[0], k, kick, dummy, WpL);
+  }
+
+  Cons<T> F[V];
 #pragma unroll
-    for (int c = 0; c < V; ++c) F[c] = hllc(c == 0 ? WpL : Wp[c - 1], Wm[c], k);
-  }
-  __syncthreads();  // every lane has read the primitive slots
-  if (act) {
-    lw[0 * B + tid] = F[0].r; lw[1 * B + tid] = F[0].mn; lw[2 * B + tid] = F[0].mt1;
-    lw[3 * B + tid] = F[0].mt2; lw[4 * B + tid] = F[0].e;
-  }
-  __syncthreads();
-  if (act) {
-    Cons<T> FR;  // flux at the right face of the last cell
-    if (lane < LPP - 1 || a.bc_hi == kBcPeriodic) {
-      int t = lane < LPP - 1 ? tid + 1 : tid - (LPP - 1);
-      FR.r = lw[0 * B + t]; FR.mn = lw[1 * B + t]; FR.mt1 = lw[2 * B + t];
-      FR.mt2 = lw[3 * B + t]; FR.e = lw[4 * B + t];
-    } else {
-      // ghost cell N with ghost N+1 beyond it
-      Prim<T> g1, g2, WmR, dummy;
-      T kick = k.kick;
-      if (a.bc_hi == kBcOutflow) {
-        g1 = W[V - 1];
-        g2 = W[V - 1];
-      } else {
-        const Prim<T>& Wn2 = V >= 2 ? W[V >= 2 ? V - 2 : 0] : Wl;
-        g1 = mirror(W[V - 1]);
-        g2 = mirror(Wn2);
-        kick = -k.kick;
-      }
-      face_states(W[V - 1], g1, g2, k, kick, WmR, dummy);
-      FR = hllc(Wp[V - 1], WmR, k);
+  for (int c = 0; c < V; ++c) F[c] = hllc(c == 0 ? WpL : Wp[c - 1], Wm[c], k);
+
+  Cons<T> FR;  // flux at the right face of the last cell
+  if (WAVE) {
+    const int lw = tid & 63;
+    FR = shfl_cons(F[0], lane < LPP - 1 ? lw + 1 : lw - (LPP - 1));
+  } else {
+    T* lf = lds;  // the primitive slots are free once every lane passed barrier 2
+    __syncthreads();
+    if (act) {
+      lf[0 * B + tid] = F[0].r; lf[1 * B + tid] = F[0].mn; lf[2 * B + tid] = F[0].mt1;
+      lf[3 * B + tid] = F[0].mt2; lf[4 * B + tid] = F[0].e;
     }
+    __syncthreads();
+    if (act) {
+      int t = lane < LPP - 1 ? tid + 1 : tid - (LPP - 1);
+      FR.r = lf[0 * B + t]; FR.mn = lf[1 * B + t]; FR.mt1 = lf[2 * B + t];
+      FR.mt2 = lf[3 * B + t]; FR.e = lf[4 * B + t];
+    }
+  }
+  if (lane == LPP - 1 && a.bc_hi != kBcPeriodic) {
+    // ghost cell N with ghost N+1 beyond it
+    Prim<T> g1, g2, WmR, dummy;
+    T kick = k.kick;
+    if (a.bc_hi == kBcOutflow) {
+      g1 = W[V - 1];
+      g2 = W[V - 1];
+    } else {
+      const Prim<T>& Wn2 = V >= 2 ? W[V >= 2 ? V - 2 : 0] : Wl;
+      g1 = mirror(W[V - 1]);
+      g2 = mirror(Wn2);
+      kick = -k.kick;
+    }
+    face_states(W[V - 1], g1, g2, k, kick, WmR, dummy);
+    FR = hllc(Wp[V - 1], WmR, k);
+  }
+
+  if (act) {
     T id[3];
     inv_widths<T>(P, id);
+    T r[V], mn[V], mt1[V], mt2[V], e[V];
 #pragma unroll
     for (int c = 0; c < V; ++c) {
       update(U[c], F[c], c == V - 1 ? FR : F[c + 1], k);
-      store_cell<T, 0>(base + c, pl, U[c]);
-      bad |= !cell_ok(U[c]);
-      if (a.do_cfl) smax = fmax_(smax, cell_speed<T, 0>(U[c], k, id));
+      r[c] = U[c].r; mn[c] = U[c].mn; mt1[c] = U[c].mt1; mt2[c] = U[c].mt2; e[c] = U[c].e;
+      if (a.do_cfl) smax = fmax_(smax, cell_speed<T, 0>(U[c], k, id, bad));
     }
+    store_run<T, V>(pl.r, off, r);
+    store_run<T, V>(pl.n, off, mn);
+    store_run<T, V>(pl.t1, off, mt1);
+    store_run<T, V>(pl.t2, off, mt2);
+    store_run<T, V>(pl.e, off, e);
   }
 }
 
-template <class T, int V, bool PERSIST>
+// Work item of a persistent launch, made wave-uniform so that the item,
+// the patch record and the plane pointers live in scalar registers.
+__device__ __forceinline__ int next_item(unsigned int* ticket, int* slot) {
+  if (threadIdx.x == 0) *slot = int(atomicAdd(ticket, 1u));
+  __syncthreads();
+  const int it = __builtin_amdgcn_readfirstlane(*slot);
+  __syncthreads();
+  return it;
+}
+
+template <class T, int V, bool WAVE, bool PERSIST>
 __global__ void __launch_bounds__(512) sweep_x_kernel(SweepArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
@@ -299,19 +432,16 @@ __global__ void __launch_bounds__(512) sweep_x_kernel(SweepArgs<T> a) {
   bool bad = false;
   if (!PERSIST) {
     SweepConst<T> k = make_const<T>(dt, a.single.dx[0], a.gamma, a.grav);
-    xsweep_tile<T, V>(a, a.single, blockIdx.x, k, lds, smax, bad);
+    xsweep_tile<T, V, WAVE>(a, a.single, blockIdx.x, k, lds, smax, bad);
   } else {
     for (;;) {
-      if (threadIdx.x == 0) item_s = int(atomicAdd(&a.scal->tickets[0], 1u));
-      __syncthreads();
-      const int it = item_s;
-      __syncthreads();
+      const int it = next_item(&a.scal->tickets[0], &item_s);
       if (it >= a.nitems) break;
       const WorkItem w = a.items[it];
       const PatchDev P = a.patches[w.patch];
       SweepConst<T> k = make_const<T>(dt, P.dx[0], a.gamma, a.grav);
-      xsweep_tile<T, V>(a, P, w.tile, k, lds, smax, bad);
-      __syncthreads();
+      xsweep_tile<T, V, WAVE>(a, P, w.tile, k, lds, smax, bad);
+      if (!WAVE) __syncthreads();
     }
   }
   finish_block(a.scal, smax, bad, a.do_cfl != 0, red);
@@ -328,7 +458,7 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
   const int N = P.n[AXIS];
   const int nx = P.n[0];
   const int64_t ncol = int64_t(nx) * P.n[TA];
-  const int64_t sd = AXIS == 1 ? P.sy : P.sz;
+  const uint32_t sd = uint32_t((AXIS == 1 ? P.sy : P.sz) * int64_t(sizeof(T)));  // bytes
   const int64_t st = AXIS == 1 ? P.sz : P.sy;
   const int Q = a.q, S = a.s;
   const int l = threadIdx.x % Q;
@@ -338,9 +468,9 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
   const int ja = seg * L;
   const int jb = min(N, ja + L);
   const bool act = (seg < S) && (col < ncol) && (ja < jb);
-  const int64_t pl = P.plane;
-  T* cbase = a.pool + P.base0;
-  if (act) cbase += (col % nx) + (col / nx) * st;
+  const Planes<T, AXIS> pl(a.pool, P);
+  uint32_t cb = 0;  // byte offset of the column's cell 0 inside a plane
+  if (act) cb = uint32_t(((col % nx) + (col / nx) * st) * int64_t(sizeof(T)));
 
   // halo cells ja-2, ja-1, jb, jb+1 with the boundary conditions applied
   Prim<T> H[4];
@@ -358,7 +488,7 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
         else if (a.bc_hi == kBcOutflow) j = N - 1;
         else { j = 2 * N - 1 - j; mir = true; }
       }
-      Prim<T> W = to_prim(load_cell<T, AXIS>(cbase + j * sd, pl), k);
+      Prim<T> W = to_prim(pl.load(cb + uint32_t(j) * sd), k);
       H[h] = mir ? mirror(W) : W;
     }
   }
@@ -370,12 +500,21 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
   const T kick_lo = (ja == 0 && a.bc_lo == kBcReflect) ? -k.kick : k.kick;
   const T kick_hi = (jb == N && a.bc_hi == kBcReflect) ? -k.kick : k.kick;
 
-  Cons<T> U0 = load_cell<T, AXIS>(cbase + ja * sd, pl);
+  // March: cell j is updated from the flux on its left face (carried) and
+  // the flux on its right face, which needs the face states of cell j+1,
+  // hence the primitives of j, j+1, j+2.  The body of the main loop has no
+  // branch on the position: cell j+3 is prefetched one iteration ahead,
+  // clamped to the last own cell (an own cell ahead of the march, not yet
+  // written), and the last two cells, whose j+2 neighbour is a halo copy,
+  // run in the tail loop.
+  uint32_t b = cb + uint32_t(ja) * sd;    // byte offset of cell j
+  const uint32_t blast = cb + uint32_t(jb - 1) * sd;
+  Cons<T> U0 = pl.load(b);
   Prim<T> W0 = to_prim(U0, k);
   Cons<T> U1;
   Prim<T> W1;
   if (ja + 1 < jb) {
-    U1 = load_cell<T, AXIS>(cbase + (ja + 1) * sd, pl);
+    U1 = pl.load(b + sd);
     W1 = to_prim(U1, k);
   } else {
     W1 = H[2];
@@ -386,24 +525,40 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
   Cons<T> Fl = hllc(WpPrev, WmC, k);
   WpPrev = WpC;
 
-  for (int j = ja; j < jb; ++j) {
-    Cons<T> U2;
-    Prim<T> W2;
-    if (j + 2 < jb) {
-      U2 = load_cell<T, AXIS>(cbase + int64_t(j + 2) * sd, pl);
-      W2 = to_prim(U2, k);
-    } else {
-      W2 = (j + 2 == jb) ? H[2] : H[3];
+  int j = ja;
+  if (jb - ja > 2) {
+    Cons<T> Upre = pl.load(b + 2 * sd);
+#pragma unroll 2
+    for (; j < jb - 2; ++j) {
+      const Cons<T> U2 = Upre;
+      const uint32_t bn = b + 3 * sd;
+      Upre = pl.load(bn < blast ? bn : blast);
+      const Prim<T> W2 = to_prim(U2, k);
+      Prim<T> Wm1, Wp1;
+      face_states(W0, W1, W2, k, k.kick, Wm1, Wp1);  // cell j+1
+      const Cons<T> Fr = hllc(WpPrev, Wm1, k);
+      update(U0, Fl, Fr, k);
+      pl.store(b, U0);
+      if (a.do_cfl) smax = fmax_(smax, cell_speed<T, AXIS>(U0, k, id, bad));
+      b += sd;
+      U0 = U1;
+      U1 = U2;
+      W0 = W1;
+      W1 = W2;
+      WpPrev = Wp1;
+      Fl = Fr;
     }
+  }
+  for (; j < jb; ++j) {
+    const Prim<T> W2 = (j + 2 == jb) ? H[2] : H[3];
     Prim<T> Wm1, Wp1;
     face_states(W0, W1, W2, k, (j + 1 == jb) ? kick_hi : k.kick, Wm1, Wp1);  // cell j+1
-    Cons<T> Fr = hllc(WpPrev, Wm1, k);
+    const Cons<T> Fr = hllc(WpPrev, Wm1, k);
     update(U0, Fl, Fr, k);
-    store_cell<T, AXIS>(cbase + int64_t(j) * sd, pl, U0);
-    bad |= !cell_ok(U0);
-    if (a.do_cfl) smax = fmax_(smax, cell_speed<T, AXIS>(U0, k, id));
+    pl.store(b, U0);
+    if (a.do_cfl) smax = fmax_(smax, cell_speed<T, AXIS>(U0, k, id, bad));
+    b += sd;
     U0 = U1;
-    U1 = U2;
     W0 = W1;
     W1 = W2;
     WpPrev = Wp1;
@@ -423,10 +578,7 @@ __global__ void __launch_bounds__(512) sweep_col_kernel(SweepArgs<T> a) {
     colsweep_tile<T, AXIS>(a, a.single, blockIdx.x, k, smax, bad);
   } else {
     for (;;) {
-      if (threadIdx.x == 0) item_s = int(atomicAdd(&a.scal->tickets[AXIS], 1u));
-      __syncthreads();
-      const int it = item_s;
-      __syncthreads();
+      const int it = next_item(&a.scal->tickets[AXIS], &item_s);
       if (it >= a.nitems) break;
       const WorkItem w = a.items[it];
       const PatchDev P = a.patches[w.patch];
@@ -461,6 +613,7 @@ __global__ void __launch_bounds__(256) cfl_kernel(ReduceArgs<T> a) {
   SweepConst<T> k = make_const<T>(0.0, 1.0, a.gamma, 0.0);
   T id[3];
   inv_widths<T>(P, id);
+  const Planes<T, 0> pl(const_cast<T*>(a.pool), P);
   T smax = T(0);
   bool bad = false;
   for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < cells;
@@ -469,10 +622,9 @@ __global__ void __launch_bounds__(256) cfl_kernel(ReduceArgs<T> a) {
     int64_t r = c / P.n[0];
     int y = int(r % P.n[1]);
     int z = int(r / P.n[1]);
-    const T* p = a.pool + P.base0 + x + int64_t(y) * P.sy + int64_t(z) * P.sz;
-    Cons<T> U = load_cell<T, 0>(p, P.plane);
-    bad |= !cell_ok(U);
-    smax = fmax_(smax, cell_speed<T, 0>(U, k, id));
+    uint32_t off = uint32_t((x + int64_t(y) * P.sy + int64_t(z) * P.sz) * int64_t(sizeof(T)));
+    Cons<T> U = pl.load(off);
+    smax = fmax_(smax, cell_speed<T, 0>(U, k, id, bad));
   }
   finish_block(a.scal, smax, bad, true, red);
 }
@@ -632,6 +784,7 @@ struct LaunchSweep {
   SweepCfg cfg;
   int32_t persistent;
   int32_t fp64;
+  int32_t xwave;       // x sweep: every pencil fits inside one wave
 };
 
 template <class T>
@@ -665,12 +818,18 @@ int64_t col_tiles(const PatchDev& P, int axis, const SweepCfg& c) {
   return (ncol + c.q - 1) / c.q;
 }
 
-template <class T, int V, bool PERSIST>
-static hipError_t launch_x_v(const LaunchSweep& L, hipStream_t st, dim3 grid) {
-  size_t lds = size_t(xlds_values<T>()) * L.cfg.block * sizeof(T);
-  hipLaunchKernelGGL((sweep_x_kernel<T, V, PERSIST>), grid, dim3(L.cfg.block), lds, st,
+template <class T, int V, bool WAVE, bool PERSIST>
+static hipError_t launch_x_vw(const LaunchSweep& L, hipStream_t st, dim3 grid) {
+  size_t lds = WAVE ? 0 : size_t(15) * L.cfg.block * sizeof(T);
+  hipLaunchKernelGGL((sweep_x_kernel<T, V, WAVE, PERSIST>), grid, dim3(L.cfg.block), lds, st,
                      to_args<T>(L));
   return hipGetLastError();
+}
+
+template <class T, int V, bool PERSIST>
+static hipError_t launch_x_v(const LaunchSweep& L, hipStream_t st, dim3 grid) {
+  return L.xwave ? launch_x_vw<T, V, true, PERSIST>(L, st, grid)
+                 : launch_x_vw<T, V, false, PERSIST>(L, st, grid);
 }
 
 template <class T, bool PERSIST>
@@ -798,6 +957,14 @@ hipError_t launch_reset_tickets(DevScalars* s, hipStream_t st) {
 
 size_t x_lds_bytes(const SweepCfg& c, int fp64) {
   return size_t(15) * c.block * (fp64 ? 8 : 4);
+}
+
+// the x sweep can trade values by cross-lane shuffles when every pencil of
+// n cells split into runs of v sits inside one wave
+bool x_wave_ok(int n, int v) {
+  if (n % v) return false;
+  int lpp = n / v;
+  return lpp <= 64 && 64 % lpp == 0;
 }
 
 }  // namespace hydro
