@@ -47,8 +47,9 @@ WORKLOADS = {
     "turb": "3D decaying turbulence, 768^3 periodic, gamma 5/3, rho=p=1, solenoidal "
             "random-phase velocity in shells k=1..8, E(k)~k^-5/3, rms Mach 0.3",
     "batch": "4096 independent periodic KH patches, edges from {16,32,48,64} (seeded), "
-             "4 stored ghost layers, gamma 5/3, shear 0.1-1.0, density ratio 1-4; one "
-             "persistent launch per sweep, hipGraph step, one global dt",
+             "4 stored ghost layers, rows padded so each interior row starts on a 128-byte "
+             "boundary, gamma 5/3, shear 0.1-1.0, density ratio 1-4; one persistent launch "
+             "per sweep, hipGraph step, one global dt",
 }
 
 
@@ -131,7 +132,8 @@ def run_gpu(W, prec, args, torch, hydro):
         U = torch.from_numpy(np.ascontiguousarray(P.U.astype(dtype, copy=False))).to("cuda:0")
         obj = hydro.Grid(U, P.dx, P.gamma, P.cfl, P.bc, P.grav, flags=flags)
     else:
-        pool, patches = ic.batch_pool(W["specs"], ng=4, dtype=dtype)
+        # interior rows start on 128-byte boundaries (ghost layers kept)
+        pool, patches = ic.batch_pool(W["specs"], ng=4, dtype=dtype, pad_rows=32)
         U = torch.from_numpy(pool).to("cuda:0")
         del pool
         obj = hydro.Batch(U, patches, 5.0 / 3.0, flags=flags)

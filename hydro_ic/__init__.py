@@ -364,34 +364,60 @@ def turbulence(n=768, seed=4, kmax=8, mach=0.3, gamma=5.0 / 3.0,
                    meta={"seed": seed, "mach": mach})
 
 
-def batch_pool(specs, ng=4, dtype=np.float64, align=64, gamma=5.0 / 3.0):
-    """Pack the interior states of `specs` into one flat pool: patch p holds 5
-    planes of (n+2ng)^3 elements (x fastest) starting at a multiple of
-    `align` elements; ghost layers hold the periodic wrap of the interior.
-    Returns (pool, patches) with patches[p] = (offset_elems, nx, ny, nz, ng,
-    dx, dy, dz)."""
-    offsets = []
+def batch_pool(specs, ng=4, dtype=np.float64, align=64, gamma=5.0 / 3.0, pad_rows=0):
+    """Pack the interior states of `specs` into one flat pool.  Patch p holds
+    5 planes with its interior and `ng` ghost layers on every side (the ghost
+    layers hold the periodic wrap of the interior), starting at a multiple of
+    `align` elements.  pad_rows = 0 stores rows of n + 2 ng elements back to
+    back; pad_rows = A > 0 places interior cell x = 0 of every row on a
+    multiple of A elements (A = 32 puts it on a 128-byte boundary in FP32)
+    and pads the row pitch to a multiple of A.  Returns (pool, patches) with
+    patches[p] = (offset_elems, nx, ny, nz, ng, dx, dy, dz, row_pitch,
+    slab_pitch, plane_pitch, interior_offset)."""
+    layout = []
     off = 0
     for s in specs:
         m = s.n + 2 * ng
-        offsets.append(off)
-        off += 5 * m ** 3
+        if pad_rows:
+            A = pad_rows
+            rp = -(-(A + s.n + ng) // A) * A
+            x0 = A - ng                     # element of ghost x = -ng in its row
+        else:
+            rp = m
+            x0 = 0
+        sp = rp * m
+        pp = sp * m
+        io = x0 + ng + ng * rp + ng * sp
+        layout.append((off, rp, sp, pp, io, x0))
+        off += 5 * pp
         off = (off + align - 1) // align * align
     pool = np.zeros(off, dtype=dtype)
     patches = []
-    for s, o in zip(specs, offsets):
+    for s, (o, rp, sp, pp, io, x0) in zip(specs, layout):
         m = s.n + 2 * ng
         U = kh_patch(s, gamma)
         if ng:
             U = np.pad(U, ((0, 0), (ng, ng), (ng, ng), (ng, ng)), mode="wrap")
-        pool[o:o + 5 * m ** 3] = U.astype(dtype).ravel()
+        blk = pool[o:o + 5 * pp].reshape(5, m, m, rp)[:, :, :, x0:x0 + m]
+        blk[...] = U.astype(dtype)
         d = 1.0 / s.n
-        patches.append((o, s.n, s.n, s.n, ng, d, d, d))
+        patches.append((o, s.n, s.n, s.n, ng, d, d, d, rp, sp, pp, io))
     return pool, patches
 
 
 def patch_view(pool, patch):
-    """(5, n+2ng, n+2ng, n+2ng) view of one patch of a pool."""
+    """(5, nz+2ng, ny+2ng, nx+2ng) view (ghosts included) of one patch of a
+    pool, for either layout of batch_pool."""
     o, nx, ny, nz, ng = patch[:5]
-    return pool[o:o + 5 * (nx + 2 * ng) * (ny + 2 * ng) * (nz + 2 * ng)].reshape(
-        5, nz + 2 * ng, ny + 2 * ng, nx + 2 * ng)
+    if len(patch) > 8 and patch[8]:
+        rp, sp, pp, io = patch[8:12]
+    else:
+        rp = nx + 2 * ng
+        sp = rp * (ny + 2 * ng)
+        pp = sp * (nz + 2 * ng)
+        io = ng * (1 + rp + sp)
+    start = o + io - ng * (1 + rp + sp)
+    it = pool.itemsize
+    return np.lib.stride_tricks.as_strided(
+        pool[start:], shape=(5, nz + 2 * ng, ny + 2 * ng, nx + 2 * ng),
+        strides=(pp * it, sp * it, rp * it, it), writeable=False)

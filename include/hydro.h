@@ -100,12 +100,21 @@ typedef struct hydro_desc {
 } hydro_desc;
 
 /* One patch of a batch.  The patch's 5 planes start at element
- * offset_elems of the pool, each plane (nz+2ng)(ny+2ng)(nx+2ng) elements,
- * x fastest.  offset_elems must keep the patch 16-byte aligned. */
+ * offset_elems of the pool (16-byte aligned), x fastest.  By default a plane
+ * holds (nz+2ng)(ny+2ng)(nx+2ng) elements and interior cell (0,0,0) sits at
+ * stored index (ng, ng, ng).  The four pitches below (in elements, 0 = that
+ * default) describe a padded layout instead, e.g. rows whose interior starts
+ * on a 128-byte boundary so that every row access is whole cache lines:
+ *   row_pitch        elements between y-neighbours (>= nx + 2ng)
+ *   slab_pitch       elements between z-neighbours (>= row_pitch (ny + 2ng))
+ *   plane_pitch      elements between variables    (>= slab_pitch (nz + 2ng))
+ *   interior_offset  elements from offset_elems to interior cell (0,0,0)
+ *                    (>= ng (1 + row_pitch + slab_pitch)) */
 typedef struct hydro_patch {
   int64_t offset_elems;
   int32_t nx, ny, nz, ng;
   double dx, dy, dz;
+  int64_t row_pitch, slab_pitch, plane_pitch, interior_offset;
 } hydro_patch;
 
 typedef struct hydro_ctx hydro_ctx;

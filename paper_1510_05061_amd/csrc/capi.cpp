@@ -70,8 +70,8 @@ hipError_t launch_timing_end(DevScalars* s, hipStream_t st);
 hipError_t launch_reset_tickets(DevScalars* s, hipStream_t st);
 int64_t x_tiles(const PatchDev& P, const SweepCfg& c);
 int64_t col_tiles(const PatchDev& P, int axis, const SweepCfg& c);
-size_t x_lds_bytes(const SweepCfg& c, int fp64);
 bool x_wave_ok(int n, int v);
+int64_t x_pencils_per_tile(const PatchDev& P, const SweepCfg& c);
 }  // namespace hydro
 
 using namespace hydro;
@@ -155,6 +155,38 @@ PatchDev make_patch(const int32_t n[3], int32_t ng, const double dx[3], int64_t 
   return P;
 }
 
+// Patch geometry from a hydro_patch (defaults or explicit pitches); returns
+// false on an inconsistent layout.  *len receives the elements the patch
+// spans in the pool (5 planes).
+bool patch_from(const hydro_patch& p, PatchDev* out, int64_t* len) {
+  const int32_t n[3] = {p.nx, p.ny, p.nz};
+  const double dx[3] = {p.dx, p.dy, p.dz};
+  const int64_t ng = p.ng;
+  const int64_t rp = p.row_pitch ? p.row_pitch : n[0] + 2 * ng;
+  const int64_t sp = p.slab_pitch ? p.slab_pitch : rp * (n[1] + 2 * ng);
+  const int64_t pp = p.plane_pitch ? p.plane_pitch : sp * (n[2] + 2 * ng);
+  const int64_t io = p.interior_offset ? p.interior_offset : ng * (1 + rp + sp);
+  if (rp < n[0] + 2 * ng || sp < rp * (n[1] + 2 * ng) || pp < sp * (n[2] + 2 * ng))
+    return false;
+  if (io < ng * (1 + rp + sp)) return false;
+  // the last stored cell of a plane (interior plus ng beyond) inside the plane
+  const int64_t lastc = io + (n[0] - 1 + ng) + (n[1] - 1 + ng) * rp + (n[2] - 1 + ng) * sp;
+  if (lastc >= pp) return false;
+  if (rp > INT32_MAX || sp > INT32_MAX) return false;
+  PatchDev P;
+  P.plane = pp;
+  P.sy = int32_t(rp);
+  P.sz = int32_t(sp);
+  P.base0 = p.offset_elems + io;
+  for (int a = 0; a < 3; ++a) {
+    P.n[a] = n[a];
+    P.dx[a] = dx[a];
+  }
+  *out = P;
+  *len = 5 * pp;
+  return true;
+}
+
 // ------------------------------------------------------------------------
 // kernel configurations
 // ------------------------------------------------------------------------
@@ -172,8 +204,9 @@ bool x_cfg_ok(const SweepCfg& c, const PatchDev& P, int fp64) {
   const int nx = P.n[0];
   if (nx % c.v) return false;
   int lpp = nx / c.v;
-  if (c.block < 64 || c.block > kMaxBlock || c.block % 64 || c.block < lpp) return false;
-  if (x_lds_bytes(c, fp64) > 64 * 1024) return false;
+  if (c.block < 64 || c.block > kMaxBlock || c.block % 64) return false;
+  if (lpp > 64 && c.block % (64 * ((lpp + 63) / 64))) return false;  // whole pencils per WG
+  if (x_pencils_per_tile(P, c) < 1) return false;
   const int esz = fp64 ? 8 : 4;
   const int a = std::min(c.v, 16 / esz);
   if (P.base0 % a || P.sy % a || P.sz % a || P.plane % a) return false;
@@ -199,7 +232,9 @@ SweepCfg default_x(const std::vector<PatchDev>& ps, int fp64) {
     c.v = v;
     int lpp = 1;
     for (auto& P : ps) lpp = std::max(lpp, P.n[0] / v);
-    c.block = lpp > 256 ? int(align_up(size_t(lpp), 64)) : 256;
+    const int wpp = (lpp + 63) / 64;      // waves per pencil
+    c.block = 64 * wpp * std::max(1, 4 / wpp);
+    if (c.block > kMaxBlock) c.block = 64 * wpp;
     if (x_cfg_ok_all(c, ps, fp64)) return c;
   }
   c.v = 0;  // none fits
@@ -348,6 +383,7 @@ struct hydro_ctx {
   double t_end = 0.0;
   bool dt_valid = false;
   Config cfg;
+  Config items_cfg;          // configuration the batch work lists were built for
   bool active[3] = {false, false, false};
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   int cu_count = 0;
@@ -355,6 +391,15 @@ struct hydro_ctx {
 };
 
 namespace {
+
+int rebuild_items(hydro_ctx* c);
+
+// The persistent sweeps read (patch, tile) lists whose tiles depend on the
+// configuration; launching with lists built for another configuration would
+// silently skip or repeat work, so every batched launch path checks this.
+bool items_current(const hydro_ctx* c) {
+  return !c->batch || std::memcmp(c->items_cfg.ax, c->cfg.ax, sizeof(c->cfg.ax)) == 0;
+}
 
 LaunchSweep sweep_launch(const hydro_ctx* c, int axis, int do_cfl) {
   LaunchSweep L{};
@@ -402,6 +447,7 @@ LaunchReduce reduce_launch(const hydro_ctx* c) {
 // The three sweeps of a step in Strang order, the last folding the CFL max,
 // then the step bookkeeping.
 hipError_t enqueue_step_kernels(const hydro_ctx* c, int parity, hipStream_t st) {
+  if (!items_current(c)) return hipErrorInvalidValue;
   static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
   const int* order = parity ? odd : even;
   int last = -1;
@@ -432,6 +478,12 @@ void destroy_graphs(hydro_ctx* c) {
 
 int capture_graphs(hydro_ctx* c) {
   destroy_graphs(c);
+  // a graph freezes the work-list lengths: rebuild the lists for the current
+  // configuration first, so the captured counts and the lists always agree
+  if (c->batch) {
+    int rc = rebuild_items(c);
+    if (rc) return rc;
+  }
   if (c->desc.flags & HYDRO_FLAG_NO_GRAPH) return HYDRO_OK;
   for (int p = 0; p < 2; ++p) {
     HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
@@ -453,6 +505,7 @@ int capture_graphs(hydro_ctx* c) {
 
 // Mean ms per launch of one sweep (dt on the device must already be 0).
 int time_sweep(hydro_ctx* c, int axis, int reps, double* ms) {
+  if (!items_current(c)) return fail(HYDRO_ESTATE, "batch work lists out of date");
   hipEvent_t a, b;
   HIP_TRY(hipEventCreate(&a));
   HIP_TRY(hipEventCreate(&b));
@@ -496,7 +549,7 @@ std::vector<SweepCfg> candidates(const hydro_ctx* c, int axis) {
   if (axis == 0) {
     const std::vector<PatchDev> ps = c->batch ? c->patches : std::vector<PatchDev>{c->single};
     for (int v : {1, 2, 4})
-      for (int b : {64, 128, 256, 512}) {
+      for (int b : {64, 128, 192, 256, 384, 448, 512}) {
         SweepCfg s{};
         s.kind = 0;
         s.v = v;
@@ -551,6 +604,10 @@ int choose_config(hydro_ctx* c) {
                             c->batch ? c->patches : std::vector<PatchDev>{c->single}, c->fp64);
         if (ok) {
           c->cfg.ax[axis] = tmp.ax[axis];
+          if (c->batch) {
+            int rc = rebuild_items(c);
+            if (rc) return rc;
+          }
           continue;
         }
       }
@@ -591,6 +648,43 @@ int choose_config(hydro_ctx* c) {
     }
     cache[key] = part;
     dirty = true;
+  }
+  if (c->batch) {
+    // persistent grid size: workgroups per CU, timed over the three sweeps
+    const std::string key = shape_key(c, 3);
+    auto it = cache.find(key);
+    Config tmp = c->cfg;
+    if (it != cache.end() && parse_cfg(it->second, tmp) && tmp.batch_blocks > 0 &&
+        tmp.batch_blocks <= 65536) {
+      c->cfg.batch_blocks = tmp.batch_blocks;
+    } else {
+      if (launch_timing_begin(c->scal, c->stream) != hipSuccess)
+        return fail(HYDRO_EDEVICE, "timing setup failed");
+      double best = 1e30;
+      int best_g = c->cfg.batch_blocks;
+      int rc = HYDRO_OK;
+      for (int per_cu : {2, 4, 8, 16}) {
+        c->cfg.batch_blocks = per_cu * c->cu_count;
+        double tot = 0.0;
+        for (int axis = 0; axis < 3 && rc == HYDRO_OK; ++axis) {
+          if (!c->active[axis] || c->nitems[axis] == 0) continue;
+          double ms = 0.0;
+          rc = time_sweep(c, axis, 3, &ms);
+          tot += ms;
+        }
+        if (rc) break;
+        if (tot < best) {
+          best = tot;
+          best_g = c->cfg.batch_blocks;
+        }
+      }
+      c->cfg.batch_blocks = best_g;
+      if (launch_timing_end(c->scal, c->stream) != hipSuccess)
+        return fail(HYDRO_EDEVICE, "timing teardown failed");
+      if (rc) return rc;
+      cache[key] = "p:g=" + std::to_string(best_g);
+      dirty = true;
+    }
   }
   if (dirty) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
@@ -700,6 +794,7 @@ int rebuild_items(hydro_ctx* c) {
                              hipMemcpyHostToDevice, c->stream));
   }
   HIP_TRY(hipStreamSynchronize(c->stream));
+  std::memcpy(&c->items_cfg, &c->cfg, sizeof(Config));
   return HYDRO_OK;
 }
 
@@ -798,7 +893,11 @@ int hydro_batch_workspace_bytes(const hydro_patch* p, int32_t n, const hydro_des
     double dx[3] = {p[i].dx, p[i].dy, p[i].dz};
     rc = check_extent(nn, p[i].ng, dx);
     if (rc) return rc;
-    ps.push_back(make_patch(nn, p[i].ng, dx, p[i].offset_elems));
+    PatchDev P;
+    int64_t len = 0;
+    if (!patch_from(p[i], &P, &len))
+      return fail(HYDRO_EINVAL, "patch " + std::to_string(i) + " has an inconsistent layout");
+    ps.push_back(P);
   }
   int32_t cap[3];
   max_items(ps, cap);
@@ -832,9 +931,13 @@ int hydro_batch_init(const hydro_patch* p, int32_t n, const hydro_desc* common, 
   std::vector<std::pair<int64_t, int64_t>> spans;
   for (int32_t i = 0; i < n; ++i) {
     int32_t nn[3] = {p[i].nx, p[i].ny, p[i].nz};
-    double dx[3] = {p[i].dx, p[i].dy, p[i].dz};
-    PatchDev P = make_patch(nn, p[i].ng, dx, p[i].offset_elems);
-    int64_t len = P.plane * 5;
+    PatchDev P;
+    int64_t len = 0;
+    (void)patch_from(p[i], &P, &len);  // validated by hydro_batch_workspace_bytes
+    if (P.plane * int64_t(esz) >= (int64_t(1) << 32)) {
+      delete c;
+      return fail(HYDRO_EINVAL, "a patch plane must be smaller than 4 GiB");
+    }
     if (p[i].offset_elems < 0 || p[i].offset_elems + len > pool_elems) {
       delete c;
       return fail(HYDRO_EINVAL, "patch " + std::to_string(i) + " lies outside the pool");
@@ -907,6 +1010,7 @@ int hydro_batch_init(const hydro_patch* p, int32_t n, const hydro_desc* common, 
 
 static int step_common(hydro_ctx* c, double dt, bool want_batch) {
   if (!c) return fail(HYDRO_EINVAL, "null context");
+  if (!items_current(c)) return fail(HYDRO_ESTATE, "batch work lists out of date");
   if (c->batch != want_batch)
     return fail(HYDRO_ESTATE, want_batch ? "not a batch context" : "batch context: use hydro_batch_step");
   if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(HYDRO_EINVAL, "dt must be >= 0 and finite");
@@ -932,6 +1036,7 @@ int hydro_batch_step(hydro_ctx* c, double dt) { return step_common(c, dt, true);
 
 int hydro_sweep(hydro_ctx* c, int axis, double dt, int fold_cfl) {
   if (!c) return fail(HYDRO_EINVAL, "null context");
+  if (!items_current(c)) return fail(HYDRO_ESTATE, "batch work lists out of date");
   if (axis < 0 || axis > 2) return fail(HYDRO_EINVAL, "axis must be 0, 1 or 2");
   if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(HYDRO_EINVAL, "dt must be >= 0 and finite");
   if (dt > 0.0) {
@@ -1078,6 +1183,7 @@ int hydro_time_sweeps(hydro_ctx* c, int reps, double ms[3]) {
 
 int hydro_profile_step(hydro_ctx* c, double dt, double ms[4]) {
   if (!c || !ms) return fail(HYDRO_EINVAL, "bad argument");
+  if (!items_current(c)) return fail(HYDRO_ESTATE, "batch work lists out of date");
   if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(HYDRO_EINVAL, "dt must be >= 0 and finite");
   for (int i = 0; i < 4; ++i) ms[i] = 0.0;
   if (dt > 0.0) {

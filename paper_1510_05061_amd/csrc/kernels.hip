@@ -231,28 +231,76 @@ __device__ __forceinline__ Cons<T> shfl_cons(const Cons<T>& F, int src) {
 // Lane runs along x
 // --------------------------------------------------------------------------
 
-// LDS use per workgroup of the LDS-exchange variant: 15 values per thread
-// (edge primitives, last face state; the first face flux reuses the
-// primitive slots).  The wave variant (a pencil never straddles a wave)
-// trades the same values with cross-lane shuffles and needs no LDS and no
-// barrier.
-template <class T, int V, bool WAVE>
+// Values a wave hands to its neighbour waves of the same pencil (MULTI
+// variant): the edge primitives, the last face state and the first flux.
+template <class T>
+struct EdgeSlots {
+  T wf[6];   // W of the wave's first cell
+  T wl[6];   // W of the wave's last active cell
+  T wp[6];   // W+ face state of the last active cell
+  T f[5];    // flux on the left face of the first cell
+};
+
+template <class T>
+__device__ __forceinline__ void put_prim(T* s, const Prim<T>& W) {
+  s[0] = W.r; s[1] = W.u; s[2] = W.t1; s[3] = W.t2; s[4] = W.p; s[5] = W.ri;
+}
+template <class T>
+__device__ __forceinline__ Prim<T> get_prim(const T* s) {
+  Prim<T> W;
+  W.r = s[0]; W.u = s[1]; W.t1 = s[2]; W.t2 = s[3]; W.p = s[4]; W.ri = s[5];
+  return W;
+}
+
+// One tile of x-pencils.  Lane l of a pencil holds cells [lV, lV+V).  Values
+// cross lane boundaries by cross-lane shuffles.
+//  * MULTI = false: a pencil has at most 64 lanes (n/V <= 64); floor(64/(n/V))
+//    pencils share a wave and a pencil's periodic neighbour is its own far
+//    end, also a shuffle.  No LDS, no barrier: every load of a pencil comes
+//    before its first shuffle and every store after its last.
+//  * MULTI = true: a pencil spans S = ceil((n/V)/64) consecutive waves of the
+//    workgroup.  Inside a wave values move by shuffles; across a wave edge
+//    the edge lanes pass them through small LDS slots between barriers.  All
+//    loads precede the first barrier and all stores follow the last, so the
+//    in-place update is race-free.
+// Outflow and reflecting ends build their ghost cells from the edge lanes'
+// own cells.
+template <class T, int V, bool MULTI>
 __device__ void xsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t tile,
-                            const SweepConst<T>& k, T* lds, T& smax, bool& bad) {
+                            const SweepConst<T>& k, EdgeSlots<T>* slots, T& smax,
+                            bool& bad) {
   const int N = P.n[0];
-  const int LPP = N / V;           // lanes per pencil
-  const int B = blockDim.x;
-  const int PPW = B / LPP;         // pencils per workgroup
+  const int LPP = N / V;                 // lanes per pencil
   const int tid = threadIdx.x;
-  const int lane = tid % LPP;
-  const int pw = tid / LPP;
+  const int wave = tid >> 6;
+  const int l = tid & 63;
+  const int nwaves = blockDim.x >> 6;
+  int gl, last, pw, seg = 0, S = 1;      // lane in pencil, its last lane, pencil in tile
+  bool act;
+  int64_t q;
+  if (!MULTI) {
+    const int gpw = 64 / LPP;            // pencils per wave
+    const int grp = l / LPP;
+    gl = l - grp * LPP;
+    last = LPP - 1;
+    pw = wave * gpw + grp;
+    q = tile * int64_t(nwaves * gpw) + pw;
+    act = grp < gpw;
+  } else {
+    S = (LPP + 63) >> 6;
+    pw = wave / S;
+    seg = wave - pw * S;
+    gl = seg * 64 + l;
+    last = LPP - 1;
+    q = tile * int64_t(nwaves / S) + pw;
+    act = pw < nwaves / S && gl < LPP;
+  }
   const int64_t npen = int64_t(P.n[1]) * P.n[2];
-  const int64_t q = tile * PPW + pw;
-  const bool act = (pw < PPW) && (q < npen);
+  act = act && q < npen;
   const Planes<T, 0> pl(a.pool, P);
   uint32_t off = 0;  // byte offset of this lane's first cell inside a plane
   if (act)
-    off = uint32_t(((q % P.n[1]) * int64_t(P.sy) + (q / P.n[1]) * int64_t(P.sz) + lane * V) *
+    off = uint32_t(((q % P.n[1]) * int64_t(P.sy) + (q / P.n[1]) * int64_t(P.sz) + gl * V) *
                    int64_t(sizeof(T)));
 
   Cons<T> U[V];
@@ -278,38 +326,32 @@ __device__ void xsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t ti
     }
   }
 
-  Prim<T> Wl, Wr;  // cell left of the first, right of the last
-  if (WAVE) {
-    const int lw = tid & 63;
-    const int srcL = lane > 0 ? lw - 1 : lw + LPP - 1;
-    const int srcR = lane < LPP - 1 ? lw + 1 : lw - (LPP - 1);
-    Wl = shfl_prim(W[V - 1], srcL);
-    Wr = shfl_prim(W[0], srcR);
-  } else {
-    T* lw = lds;  // [10][B]: W first (0..4), W last (5..9)
-    if (act) {
-      lw[0 * B + tid] = W[0].r; lw[1 * B + tid] = W[0].u; lw[2 * B + tid] = W[0].t1;
-      lw[3 * B + tid] = W[0].t2; lw[4 * B + tid] = W[0].p;
-      lw[5 * B + tid] = W[V - 1].r; lw[6 * B + tid] = W[V - 1].u;
-      lw[7 * B + tid] = W[V - 1].t1; lw[8 * B + tid] = W[V - 1].t2;
-      lw[9 * B + tid] = W[V - 1].p;
-    }
+  // lane-level neighbours inside a wave (a wave-edge lane takes the value it
+  // gets here only when the neighbour lives in the same wave)
+  const int srcL = MULTI ? ((l + 63) & 63) : (gl > 0 ? l - 1 : l + last);
+  const int srcR = MULTI ? ((l + 1) & 63) : (gl < last ? l + 1 : l - last);
+  const bool firstw = MULTI && l == 0;                               // left neighbour in LDS
+  const bool lastw = MULTI && (l == 63 || gl == last) && gl <= last;  // right neighbour in LDS
+  const int wfirst = wave - seg;          // first wave of this pencil (MULTI)
+  const int wlast = wfirst + S - 1;
+
+  Prim<T> Wl = shfl_prim(W[V - 1], srcL);
+  Prim<T> Wr = shfl_prim(W[0], srcR);
+  if (MULTI) {
+    if (act && firstw) put_prim(slots[wave].wf, W[0]);
+    if (act && lastw) put_prim(slots[wave].wl, W[V - 1]);
     __syncthreads();
-    if (act) {
-      auto read_w = [&](int slot, int t) {
-        Prim<T> r;
-        r.r = lw[(slot + 0) * B + t]; r.u = lw[(slot + 1) * B + t];
-        r.t1 = lw[(slot + 2) * B + t]; r.t2 = lw[(slot + 3) * B + t];
-        r.p = lw[(slot + 4) * B + t];
-        r.ri = rcp(r.r);
-        return r;
-      };
-      Wl = read_w(5, lane > 0 ? tid - 1 : tid + LPP - 1);
-      Wr = read_w(0, lane < LPP - 1 ? tid + 1 : tid - (LPP - 1));
+    if (act && firstw) {
+      if (gl > 0) Wl = get_prim(slots[wave - 1].wl);
+      else if (a.bc_lo == kBcPeriodic) Wl = get_prim(slots[wlast].wl);
+    }
+    if (act && lastw) {
+      if (gl < last) Wr = get_prim(slots[wave + 1].wf);
+      else if (a.bc_hi == kBcPeriodic) Wr = get_prim(slots[wfirst].wf);
     }
   }
-  if (lane == 0 && a.bc_lo != kBcPeriodic) Wl = a.bc_lo == kBcOutflow ? W[0] : mirror(W[0]);
-  if (lane == LPP - 1 && a.bc_hi != kBcPeriodic)
+  if (gl == 0 && a.bc_lo != kBcPeriodic) Wl = a.bc_lo == kBcOutflow ? W[0] : mirror(W[0]);
+  if (gl == last && a.bc_hi != kBcPeriodic)
     Wr = a.bc_hi == kBcOutflow ? W[V - 1] : mirror(W[V - 1]);
 
   Prim<T> Wm[V], Wp[V];
@@ -320,25 +362,16 @@ __device__ void xsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t ti
     face_states(L, W[c], R, k, k.kick, Wm[c], Wp[c]);
   }
 
-  Prim<T> WpL;  // face state W+ of the cell left of the first
-  if (WAVE) {
-    const int lw = tid & 63;
-    WpL = shfl_prim(Wp[V - 1], lane > 0 ? lw - 1 : lw + LPP - 1);
-  } else {
-    T* lp = lds + 10 * B;  // [5][B]: Wp of the last cell
-    if (act) {
-      lp[0 * B + tid] = Wp[V - 1].r; lp[1 * B + tid] = Wp[V - 1].u;
-      lp[2 * B + tid] = Wp[V - 1].t1; lp[3 * B + tid] = Wp[V - 1].t2;
-      lp[4 * B + tid] = Wp[V - 1].p;
-    }
+  Prim<T> WpL = shfl_prim(Wp[V - 1], srcL);  // face state W+ of the cell left of the first
+  if (MULTI) {
+    if (act && lastw) put_prim(slots[wave].wp, Wp[V - 1]);
     __syncthreads();
-    if (act) {
-      int t = lane > 0 ? tid - 1 : tid + LPP - 1;
-      WpL.r = lp[0 * B + t]; WpL.u = lp[1 * B + t]; WpL.t1 = lp[2 * B + t];
-      WpL.t2 = lp[3 * B + t]; WpL.p = lp[4 * B + t];
+    if (act && firstw) {
+      if (gl > 0) WpL = get_prim(slots[wave - 1].wp);
+      else if (a.bc_lo == kBcPeriodic) WpL = get_prim(slots[wlast].wp);
     }
   }
-  if (lane == 0 && a.bc_lo != kBcPeriodic) {
+  if (gl == 0 && a.bc_lo != kBcPeriodic) {
     // ghost cell -1 with ghost -2 behind it
     Prim<T> g1, g2, dummy;
     T kick = k.kick;
@@ -358,25 +391,21 @@ __device__ void xsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t ti
 #pragma unroll
   for (int c = 0; c < V; ++c) F[c] = hllc(c == 0 ? WpL : Wp[c - 1], Wm[c], k);
 
-  Cons<T> FR;  // flux at the right face of the last cell
-  if (WAVE) {
-    const int lw = tid & 63;
-    FR = shfl_cons(F[0], lane < LPP - 1 ? lw + 1 : lw - (LPP - 1));
-  } else {
-    T* lf = lds;  // the primitive slots are free once every lane passed barrier 2
-    __syncthreads();
-    if (act) {
-      lf[0 * B + tid] = F[0].r; lf[1 * B + tid] = F[0].mn; lf[2 * B + tid] = F[0].mt1;
-      lf[3 * B + tid] = F[0].mt2; lf[4 * B + tid] = F[0].e;
+  Cons<T> FR = shfl_cons(F[0], srcR);  // flux at the right face of the last cell
+  if (MULTI) {
+    if (act && firstw) {
+      T* s = slots[wave].f;
+      s[0] = F[0].r; s[1] = F[0].mn; s[2] = F[0].mt1; s[3] = F[0].mt2; s[4] = F[0].e;
     }
     __syncthreads();
-    if (act) {
-      int t = lane < LPP - 1 ? tid + 1 : tid - (LPP - 1);
-      FR.r = lf[0 * B + t]; FR.mn = lf[1 * B + t]; FR.mt1 = lf[2 * B + t];
-      FR.mt2 = lf[3 * B + t]; FR.e = lf[4 * B + t];
+    if (act && lastw) {
+      const T* s = nullptr;
+      if (gl < last) s = slots[wave + 1].f;
+      else if (a.bc_hi == kBcPeriodic) s = slots[wfirst].f;
+      if (s) FR = Cons<T>{s[0], s[1], s[2], s[3], s[4]};
     }
   }
-  if (lane == LPP - 1 && a.bc_hi != kBcPeriodic) {
+  if (gl == last && a.bc_hi != kBcPeriodic) {
     // ghost cell N with ghost N+1 beyond it
     Prim<T> g1, g2, WmR, dummy;
     T kick = k.kick;
@@ -421,10 +450,9 @@ __device__ __forceinline__ int next_item(unsigned int* ticket, int* slot) {
   return it;
 }
 
-template <class T, int V, bool WAVE, bool PERSIST>
+template <class T, int V, bool MULTI, bool PERSIST>
 __global__ void __launch_bounds__(512) sweep_x_kernel(SweepArgs<T> a) {
-  extern __shared__ unsigned char smem_raw[];
-  T* lds = reinterpret_cast<T*>(smem_raw);
+  __shared__ EdgeSlots<T> slots[MULTI ? 8 : 1];
   __shared__ int item_s;
   __shared__ T red[8];
   const double dt = a.scal->dt;
@@ -432,7 +460,7 @@ __global__ void __launch_bounds__(512) sweep_x_kernel(SweepArgs<T> a) {
   bool bad = false;
   if (!PERSIST) {
     SweepConst<T> k = make_const<T>(dt, a.single.dx[0], a.gamma, a.grav);
-    xsweep_tile<T, V, WAVE>(a, a.single, blockIdx.x, k, lds, smax, bad);
+    xsweep_tile<T, V, MULTI>(a, a.single, blockIdx.x, k, slots, smax, bad);
   } else {
     for (;;) {
       const int it = next_item(&a.scal->tickets[0], &item_s);
@@ -440,8 +468,8 @@ __global__ void __launch_bounds__(512) sweep_x_kernel(SweepArgs<T> a) {
       const WorkItem w = a.items[it];
       const PatchDev P = a.patches[w.patch];
       SweepConst<T> k = make_const<T>(dt, P.dx[0], a.gamma, a.grav);
-      xsweep_tile<T, V, WAVE>(a, P, w.tile, k, lds, smax, bad);
-      if (!WAVE) __syncthreads();
+      xsweep_tile<T, V, MULTI>(a, P, w.tile, k, slots, smax, bad);
+      if (MULTI) __syncthreads();
     }
   }
   finish_block(a.scal, smax, bad, a.do_cfl != 0, red);
@@ -806,10 +834,18 @@ static SweepArgs<T> to_args(const LaunchSweep& L) {
   return a;
 }
 
+// pencils of a patch processed by one workgroup of the x sweep
+int64_t x_pencils_per_tile(const PatchDev& P, const SweepCfg& c) {
+  const int lpp = P.n[0] / c.v;
+  const int nw = c.block / 64;
+  if (lpp <= 64) return int64_t(nw) * (64 / lpp);
+  const int s = (lpp + 63) / 64;
+  return nw / s;
+}
+
 int64_t x_tiles(const PatchDev& P, const SweepCfg& c) {
-  int lpp = P.n[0] / c.v;
-  int ppw = c.block / lpp;
-  int64_t npen = int64_t(P.n[1]) * P.n[2];
+  const int64_t ppw = x_pencils_per_tile(P, c);
+  const int64_t npen = int64_t(P.n[1]) * P.n[2];
   return (npen + ppw - 1) / ppw;
 }
 
@@ -818,18 +854,17 @@ int64_t col_tiles(const PatchDev& P, int axis, const SweepCfg& c) {
   return (ncol + c.q - 1) / c.q;
 }
 
-template <class T, int V, bool WAVE, bool PERSIST>
+template <class T, int V, bool MULTI, bool PERSIST>
 static hipError_t launch_x_vw(const LaunchSweep& L, hipStream_t st, dim3 grid) {
-  size_t lds = WAVE ? 0 : size_t(15) * L.cfg.block * sizeof(T);
-  hipLaunchKernelGGL((sweep_x_kernel<T, V, WAVE, PERSIST>), grid, dim3(L.cfg.block), lds, st,
+  hipLaunchKernelGGL((sweep_x_kernel<T, V, MULTI, PERSIST>), grid, dim3(L.cfg.block), 0, st,
                      to_args<T>(L));
   return hipGetLastError();
 }
 
 template <class T, int V, bool PERSIST>
 static hipError_t launch_x_v(const LaunchSweep& L, hipStream_t st, dim3 grid) {
-  return L.xwave ? launch_x_vw<T, V, true, PERSIST>(L, st, grid)
-                 : launch_x_vw<T, V, false, PERSIST>(L, st, grid);
+  return L.xwave ? launch_x_vw<T, V, false, PERSIST>(L, st, grid)
+                 : launch_x_vw<T, V, true, PERSIST>(L, st, grid);
 }
 
 template <class T, bool PERSIST>
@@ -955,16 +990,8 @@ hipError_t launch_reset_tickets(DevScalars* s, hipStream_t st) {
   return hipGetLastError();
 }
 
-size_t x_lds_bytes(const SweepCfg& c, int fp64) {
-  return size_t(15) * c.block * (fp64 ? 8 : 4);
-}
-
-// the x sweep can trade values by cross-lane shuffles when every pencil of
-// n cells split into runs of v sits inside one wave
-bool x_wave_ok(int n, int v) {
-  if (n % v) return false;
-  int lpp = n / v;
-  return lpp <= 64 && 64 % lpp == 0;
-}
+// the x sweep packs whole pencils into waves when a pencil has at most 64
+// lanes; longer pencils span several waves of one workgroup
+bool x_wave_ok(int n, int v) { return n % v == 0 && n / v <= 64; }
 
 }  // namespace hydro

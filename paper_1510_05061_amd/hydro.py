@@ -43,6 +43,8 @@ class HydroPatch(ctypes.Structure):
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("ng", ctypes.c_int32),
         ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+        ("row_pitch", ctypes.c_int64), ("slab_pitch", ctypes.c_int64),
+        ("plane_pitch", ctypes.c_int64), ("interior_offset", ctypes.c_int64),
     ]
 
 
@@ -354,8 +356,9 @@ class Grid:
 
 class Batch:
     """Independent patches in one pool tensor, stepped by one persistent
-    launch per sweep.  `patches` is a list of dicts or tuples
-    (offset_elems, nx, ny, nz, ng, dx, dy, dz)."""
+    launch per sweep.  `patches` is a list of tuples (offset_elems, nx, ny,
+    nz, ng, dx, dy, dz[, row_pitch, slab_pitch, plane_pitch,
+    interior_offset]); omitted or zero pitches mean the unpadded layout."""
 
     def __init__(self, pool, patches, gamma, cfl=0.8, bc=(PERIODIC,) * 6,
                  grav=(0.0, 0.0, 0.0), flags=0, stream=None):
@@ -367,8 +370,10 @@ class Batch:
             raise ValueError("pool must be float32 or float64")
         arr = (HydroPatch * len(patches))()
         for i, p in enumerate(patches):
+            p = tuple(p) + (0,) * (12 - len(p))
             (arr[i].offset_elems, arr[i].nx, arr[i].ny, arr[i].nz, arr[i].ng,
-             arr[i].dx, arr[i].dy, arr[i].dz) = p
+             arr[i].dx, arr[i].dy, arr[i].dz, arr[i].row_pitch, arr[i].slab_pitch,
+             arr[i].plane_pitch, arr[i].interior_offset) = p
         self.patches = arr
         self.pool = pool
         self.desc = make_desc((1, 1, 1), 1.0, gamma, cfl, bc, grav, prec, 0, flags)

@@ -36,7 +36,7 @@ def test_status_strings_and_struct_layout():
     L = hydro.lib()
     assert b"EINVAL" in L.hydro_strerror(1)
     assert ctypes.sizeof(hydro.HydroDesc) == 4 * 4 + 8 * 5 + 8 * 3 + 4 * 6 + 4 + 4
-    assert ctypes.sizeof(hydro.HydroPatch) == 8 + 4 * 4 + 8 * 3
+    assert ctypes.sizeof(hydro.HydroPatch) == 8 + 4 * 4 + 8 * 3 + 8 * 4
 
 
 def test_workspace_size_and_descriptor_validation_on_host():

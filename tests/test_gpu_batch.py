@@ -15,27 +15,28 @@ pytestmark = pytest.mark.gpu
 GAMMA = 5.0 / 3.0
 
 
-def _batch(count, prec, seed=3, ng=4, flags=hydro.FLAG_NO_TUNE):
+def _batch(count, prec, seed=3, ng=4, flags=hydro.FLAG_NO_TUNE, pad_rows=0):
     specs = ic.batch_specs(count, seed=seed)
     dt = np.float64 if prec == hydro.FP64 else np.float32
-    pool, patches = ic.batch_pool(specs, ng=ng, dtype=dt)
+    pool, patches = ic.batch_pool(specs, ng=ng, dtype=dt, pad_rows=pad_rows)
     dev = torch().from_numpy(pool).to("cuda:0")
     b = hydro.Batch(dev, patches, GAMMA, flags=flags)
     return b, dev, pool, patches
 
 
 def _single(pool, patch, prec):
-    view = ic.patch_view(pool, patch).copy()
+    view = np.ascontiguousarray(ic.patch_view(pool, patch))
     dev = torch().from_numpy(view).to("cuda:0")
     d = patch[5]
     g = hydro.Grid(dev, (d, d, d), GAMMA, ng=patch[4], flags=hydro.FLAG_NO_TUNE)
     return g, dev
 
 
+@pytest.mark.parametrize("pad_rows", [0, 32])
 @pytest.mark.parametrize("prec", [hydro.FP32, hydro.FP64])
-def test_batch_equals_single_grids_bitwise(prec):
-    say(f"batch vs single {prec}")
-    b, dev, pool, patches = _batch(12, prec)
+def test_batch_equals_single_grids_bitwise(prec, pad_rows):
+    say(f"batch vs single {prec} pad {pad_rows}")
+    b, dev, pool, patches = _batch(12, prec, pad_rows=pad_rows)
     dts = [1.3e-3, 1.1e-3, 0.9e-3]
     for dt in dts:
         b.step(dt)
@@ -51,7 +52,7 @@ def test_batch_equals_single_grids_bitwise(prec):
 
 def test_batch_dt_is_min_over_patches():
     say("batch dt")
-    b, dev, pool, patches = _batch(10, hydro.FP64)
+    b, dev, pool, patches = _batch(10, hydro.FP64, pad_rows=32)
     dt = b.cfl_dt()
     singles = []
     for p in patches:
@@ -62,9 +63,10 @@ def test_batch_dt_is_min_over_patches():
     b.close()
 
 
-def test_batch_fp64_matches_oracle_and_keeps_ghosts():
-    say("batch oracle")
-    b, dev, pool, patches = _batch(8, hydro.FP64)
+@pytest.mark.parametrize("pad_rows", [0, 32])
+def test_batch_fp64_matches_oracle_and_keeps_ghosts(pad_rows):
+    say(f"batch oracle pad {pad_rows}")
+    b, dev, pool, patches = _batch(8, hydro.FP64, pad_rows=pad_rows)
     dt = b.cfl_dt()
     b.step(dt)
     out = host(dev)
@@ -81,13 +83,19 @@ def test_batch_fp64_matches_oracle_and_keeps_ghosts():
         mask = np.ones(full.shape[1:], bool)
         mask[ng:-ng, ng:-ng, ng:-ng] = False
         np.testing.assert_array_equal(got_full[:, mask], full[:, mask])
+    # padding outside every patch block is untouched too
+    touched = np.zeros(pool.size, bool)
+    for p in patches:
+        o = p[0]
+        touched[o:o + 5 * (p[10] if len(p) > 10 and p[10] else (p[1] + 2 * p[4]) ** 3)] = True
+    np.testing.assert_array_equal(out[~touched], pool[~touched])
     b.close()
 
 
 def test_batch_graph_equals_eager_and_totals():
     say("batch graph/totals")
-    a, deva, pool, patches = _batch(9, hydro.FP32, seed=5)
-    e, deve, _, _ = _batch(9, hydro.FP32, seed=5,
+    a, deva, pool, patches = _batch(9, hydro.FP32, seed=5, pad_rows=32)
+    e, deve, _, _ = _batch(9, hydro.FP32, seed=5, pad_rows=32,
                           flags=hydro.FLAG_NO_TUNE | hydro.FLAG_NO_GRAPH)
     for _ in range(3):
         a.step()
@@ -105,3 +113,26 @@ def test_batch_graph_equals_eager_and_totals():
     np.testing.assert_allclose(tot, want, rtol=1e-12, atol=1e-12)
     a.close()
     e.close()
+
+
+def test_cached_autotune_config_runs_the_whole_batch(tmp_path):
+    """A second context on the same batch shape takes its kernel
+    configuration from the autotune cache; its steps must still cover every
+    patch (same bits as a context with the built-in configuration)."""
+    import os
+    say("batch cached config")
+    os.environ["HYDRO_TUNE_CACHE"] = str(tmp_path / "tune.json")
+    try:
+        outs = []
+        for flags in (0, 0, hydro.FLAG_NO_TUNE):
+            b, dev, pool, patches = _batch(40, hydro.FP32, seed=7, pad_rows=32, flags=flags)
+            for _ in range(2):
+                b.step(1e-3)
+            outs.append((host(dev), b.config))
+            b.close()
+        assert (tmp_path / "tune.json").exists()
+        assert outs[0][1] == outs[1][1]
+        np.testing.assert_array_equal(outs[0][0], outs[2][0])
+        np.testing.assert_array_equal(outs[1][0], outs[2][0])
+    finally:
+        del os.environ["HYDRO_TUNE_CACHE"]

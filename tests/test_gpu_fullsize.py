@@ -140,7 +140,7 @@ def test_turbulence768_fp32_sampled_blocks():
 def test_batch4096_fp32_sampled_patches():
     say("batch 4096 fp32")
     specs = ic.batch_specs(4096, seed=3)
-    pool, patches = ic.batch_pool(specs, ng=4, dtype=np.float32)
+    pool, patches = ic.batch_pool(specs, ng=4, dtype=np.float32, pad_rows=32)
     t = torch()
     dev = t.from_numpy(pool).to("cuda:0")
     b = hydro.Batch(dev, patches, 5.0 / 3.0)
