@@ -233,6 +233,13 @@ int hydro_time_sweeps(hydro_ctx* c, int reps, double ms[3]);
  * Synchronous. */
 int hydro_profile_step(hydro_ctx* c, double dt, double ms[4]);
 
+/* Mean device time in milliseconds of one in-place streaming pass over the
+ * context's whole state (or pool) buffer: every 16-byte word read and
+ * written back unchanged, with no arithmetic.  The memory-only ceiling a
+ * sweep kernel over the same bytes can approach.  The state is unchanged.
+ * Synchronous. */
+int hydro_stream_ceiling(hydro_ctx* c, int reps, double* ms);
+
 /* Release the host objects of a context (device buffers stay with the
  * caller).  Waits for the context's stream. */
 int hydro_destroy(hydro_ctx* c);

@@ -68,6 +68,7 @@ hipError_t launch_clear_error(DevScalars* s, hipStream_t st);
 hipError_t launch_timing_begin(DevScalars* s, hipStream_t st);
 hipError_t launch_timing_end(DevScalars* s, hipStream_t st);
 hipError_t launch_reset_tickets(DevScalars* s, hipStream_t st);
+hipError_t launch_stream(void* p, int64_t bytes, hipStream_t st);
 int64_t x_tiles(const PatchDev& P, const SweepCfg& c);
 int64_t col_tiles(const PatchDev& P, int axis, const SweepCfg& c);
 bool x_wave_ok(int n, int v);
@@ -363,6 +364,7 @@ struct hydro_ctx {
   bool batch = false;
   int fp64 = 0;
   void* pool = nullptr;
+  size_t pool_bytes = 0;     // size of the state (grid) or pool (batch) buffer
   char* ws = nullptr;
   size_t ws_bytes = 0;
   hipStream_t stream = nullptr;
@@ -858,6 +860,7 @@ int hydro_init(const hydro_desc* d, void* state, size_t state_bytes, void* works
   c->desc = *d;
   c->fp64 = d->precision == HYDRO_FP64;
   c->pool = state;
+  c->pool_bytes = size_t(P.plane) * 5 * size_t(esz);
   c->ws = static_cast<char*>(workspace);
   c->ws_bytes = ws_bytes;
   c->stream = static_cast<hipStream_t>(stream);
@@ -926,6 +929,7 @@ int hydro_batch_init(const hydro_patch* p, int32_t n, const hydro_desc* common, 
   c->batch = true;
   c->fp64 = common->precision == HYDRO_FP64;
   c->pool = pool;
+  c->pool_bytes = pool_bytes;
   c->npatch = n;
   // patch extents: inside the pool, aligned, non-overlapping
   std::vector<std::pair<int64_t, int64_t>> spans;
@@ -1225,6 +1229,30 @@ int hydro_profile_step(hydro_ctx* c, double dt, double ms[4]) {
   c->step += 1;
   c->dt_valid = true;
   return HYDRO_OK;
+}
+
+int hydro_stream_ceiling(hydro_ctx* c, int reps, double* ms) {
+  if (!c || !ms || reps < 1) return fail(HYDRO_EINVAL, "bad argument");
+  hipEvent_t a, b;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  int rc = HYDRO_OK;
+  const int64_t bytes = int64_t(c->pool_bytes) & ~int64_t(15);
+  if (launch_stream(c->pool, bytes, c->stream) != hipSuccess ||
+      hipEventRecord(a, c->stream) != hipSuccess)
+    rc = fail(HYDRO_EDEVICE, "stream launch failed");
+  for (int i = 0; i < reps && rc == HYDRO_OK; ++i)
+    if (launch_stream(c->pool, bytes, c->stream) != hipSuccess)
+      rc = fail(HYDRO_EDEVICE, "stream launch failed");
+  float t = 0.f;
+  if (rc == HYDRO_OK && (hipEventRecord(b, c->stream) != hipSuccess ||
+                         hipEventSynchronize(b) != hipSuccess ||
+                         hipEventElapsedTime(&t, a, b) != hipSuccess))
+    rc = fail(HYDRO_EDEVICE, "stream timing failed");
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc == HYDRO_OK) *ms = double(t) / reps;
+  return rc;
 }
 
 int hydro_destroy(hydro_ctx* c) {

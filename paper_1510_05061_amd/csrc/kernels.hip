@@ -952,6 +952,28 @@ hipError_t launch_totals(const LaunchReduce& L, hipStream_t st) {
   return hipGetLastError();
 }
 
+// In-place streaming pass over a buffer of n16 16-byte words: every word is
+// read and written back unchanged (xor with a runtime zero keeps the
+// compiler from dropping the pair).  The memory-only ceiling of a sweep.
+__global__ void __launch_bounds__(256) stream_kernel(uint4* p, int64_t n16, unsigned zero) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n16;
+       i += int64_t(gridDim.x) * 256) {
+    uint4 v = p[i];
+    v.x ^= zero;
+    p[i] = v;
+  }
+}
+
+hipError_t launch_stream(void* p, int64_t bytes, hipStream_t st) {
+  const int64_t n16 = bytes / 16;
+  int64_t blocks = (n16 + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) return hipSuccess;
+  hipLaunchKernelGGL(stream_kernel, dim3(unsigned(blocks)), dim3(256), 0, st,
+                     static_cast<uint4*>(p), n16, 0u);
+  return hipGetLastError();
+}
+
 hipError_t launch_finish_step(DevScalars* s, hipStream_t st) {
   hipLaunchKernelGGL(finish_step_kernel, dim3(1), dim3(1), 0, st, s);
   return hipGetLastError();

@@ -87,6 +87,7 @@ _SIGS = {
     "hydro_set_config": ([_vp, ctypes.c_char_p], ctypes.c_int),
     "hydro_time_sweeps": ([_vp, ctypes.c_int, _dp], ctypes.c_int),
     "hydro_profile_step": ([_vp, ctypes.c_double, _dp], ctypes.c_int),
+    "hydro_stream_ceiling": ([_vp, ctypes.c_int, _dp], ctypes.c_int),
     "hydro_destroy": ([_vp], ctypes.c_int),
 }
 
@@ -232,6 +233,12 @@ def hydro_profile_step(ctx, dt=DT_CFL):
     return list(ms)
 
 
+def hydro_stream_ceiling(ctx, reps=10):
+    ms = ctypes.c_double(0.0)
+    _check(lib().hydro_stream_ceiling(ctx, int(reps), ctypes.byref(ms)), "hydro_stream_ceiling")
+    return ms.value
+
+
 def hydro_destroy(ctx):
     if ctx:
         _check(lib().hydro_destroy(ctx), "hydro_destroy")
@@ -342,6 +349,9 @@ class Grid:
     def profile_step(self, dt=DT_CFL):
         return hydro_profile_step(self.ctx, dt)
 
+    def stream_ceiling(self, reps=10):
+        return hydro_stream_ceiling(self.ctx, reps)
+
     def close(self):
         if getattr(self, "ctx", None):
             hydro_destroy(self.ctx)
@@ -418,6 +428,9 @@ class Batch:
 
     def profile_step(self, dt=DT_CFL):
         return hydro_profile_step(self.ctx, dt)
+
+    def stream_ceiling(self, reps=10):
+        return hydro_stream_ceiling(self.ctx, reps)
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -109,6 +109,8 @@ def test_time_sweeps_leaves_state_unchanged():
     ms = g.time_sweeps(3)
     assert all(m > 0 for m in ms)
     np.testing.assert_array_equal(host(dev), before)
+    assert g.stream_ceiling(2) > 0
+    np.testing.assert_array_equal(host(dev), before)
     # stepping afterwards matches a fresh grid
     g.step(1e-4)
     h, dev2 = gpu_grid(P, prec=hydro.FP64)
