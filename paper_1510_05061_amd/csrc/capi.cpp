@@ -41,7 +41,7 @@ struct LaunchSweep {
   SweepCfg cfg;
   int32_t persistent;
   int32_t fp64;
-  int32_t xwave;
+  int32_t xmode;
 };
 struct LaunchReduce {
   const void* pool;
@@ -201,12 +201,17 @@ struct Config {
 // row of the patch must start on a multiple of the vector's element count
 // (the pool itself is 16-byte aligned).
 bool x_cfg_ok(const SweepCfg& c, const PatchDev& P, int fp64) {
-  if (c.kind != 0 || (c.v != 1 && c.v != 2 && c.v != 4)) return false;
+  if (c.kind != kLaneRunKind && c.kind != kXMarchKind) return false;
+  if (c.v != 1 && c.v != 2 && c.v != 4) return false;
   const int nx = P.n[0];
   if (nx % c.v) return false;
   int lpp = nx / c.v;
   if (c.block < 64 || c.block > kMaxBlock || c.block % 64) return false;
-  if (lpp > 64 && c.block % (64 * ((lpp + 63) / 64))) return false;  // whole pencils per WG
+  if (c.kind == kLaneRunKind && lpp > 64 && c.block % (64 * ((lpp + 63) / 64)))
+    return false;  // whole pencils per workgroup
+  if (c.kind == kXMarchKind && fp64 && c.v == 4) return false;  // not built (spills)
+  if (c.kind == kLaneRunKind && c.q != 0) return false;            // no grid cap
+  if (c.q < 0) return false;
   if (x_pencils_per_tile(P, c) < 1) return false;
   const int esz = fp64 ? 8 : 4;
   const int a = std::min(c.v, 16 / esz);
@@ -221,14 +226,14 @@ bool x_cfg_ok_all(const SweepCfg& c, const std::vector<PatchDev>& ps, int fp64) 
 }
 
 bool col_cfg_ok(const SweepCfg& c) {
-  if (c.kind != 1 || c.q < 1 || c.s < 1) return false;
+  if (c.kind != kColumnKind || c.q < 1 || c.s < 1) return false;
   int b = c.q * c.s;
   return b >= 64 && b <= kMaxBlock && b % 64 == 0 && c.q % 64 == 0 && c.s <= 16;
 }
 
 SweepCfg default_x(const std::vector<PatchDev>& ps, int fp64) {
   SweepCfg c{};
-  c.kind = 0;
+  c.kind = kLaneRunKind;
   for (int v : {4, 2, 1}) {
     c.v = v;
     int lpp = 1;
@@ -244,7 +249,7 @@ SweepCfg default_x(const std::vector<PatchDev>& ps, int fp64) {
 
 SweepCfg default_col(int n) {
   SweepCfg c{};
-  c.kind = 1;
+  c.kind = kColumnKind;
   c.q = 64;
   int s = (n + 63) / 64;
   c.s = std::max(1, std::min(kMaxBlock / c.q, s));
@@ -254,13 +259,18 @@ SweepCfg default_col(int n) {
 std::string cfg_text(const Config& cf) {
   std::ostringstream o;
   o << "x:v=" << cf.ax[0].v << ",b=" << cf.ax[0].block;
+  if (cf.ax[0].kind == kXMarchKind) {
+    o << ",m=1";
+    if (cf.ax[0].q) o << ",g=" << cf.ax[0].q;
+  }
   o << ";y:q=" << cf.ax[1].q << ",s=" << cf.ax[1].s;
   o << ";z:q=" << cf.ax[2].q << ",s=" << cf.ax[2].s;
   if (cf.batch_blocks) o << ";p:g=" << cf.batch_blocks;
   return o.str();
 }
 
-// parse "x:v=4,b=256;y:q=64,s=4;z:q=64,s=2;p:g=2048" (any subset) into cf
+// parse "x:v=4,b=256[,m=1];y:q=64,s=4;z:q=64,s=2;p:g=2048" (any subset) into
+// cf; m=1 selects the chunked x march, m=0 (or no m) the lane-run x sweep
 bool parse_cfg(const std::string& text, Config& cf) {
   std::stringstream ss(text);
   std::string part;
@@ -268,6 +278,10 @@ bool parse_cfg(const std::string& text, Config& cf) {
     if (part.empty()) continue;
     if (part.size() < 3 || part[1] != ':') return false;
     char ax = part[0];
+    if (ax == 'x') {
+      cf.ax[0].kind = kLaneRunKind;
+      cf.ax[0].q = 0;
+    }
     std::stringstream kv(part.substr(2));
     std::string item;
     while (std::getline(kv, item, ',')) {
@@ -280,6 +294,8 @@ bool parse_cfg(const std::string& text, Config& cf) {
       if (ax == 'x') {
         if (k == "v") cf.ax[0].v = int(v);
         else if (k == "b") cf.ax[0].block = int(v);
+        else if (k == "m" && (v == 0 || v == 1)) cf.ax[0].kind = v ? kXMarchKind : kLaneRunKind;
+        else if (k == "g" && v >= 0 && v <= (1 << 24)) cf.ax[0].q = int(v);
         else return false;
       } else if (ax == 'y' || ax == 'z') {
         SweepCfg& c = cf.ax[ax == 'y' ? 1 : 2];
@@ -421,11 +437,16 @@ LaunchSweep sweep_launch(const hydro_ctx* c, int axis, int do_cfl) {
   L.cfg = c->cfg.ax[axis];
   L.persistent = c->batch ? 1 : 0;
   L.fp64 = c->fp64;
-  L.xwave = 1;
-  if (c->batch) {
-    for (auto& P : c->patches) L.xwave = L.xwave && x_wave_ok(P.n[0], c->cfg.ax[0].v);
+  if (c->cfg.ax[0].kind == kXMarchKind) {
+    L.xmode = kXMarch;
   } else {
-    L.xwave = x_wave_ok(c->single.n[0], c->cfg.ax[0].v);
+    bool wave = true;
+    if (c->batch) {
+      for (auto& P : c->patches) wave = wave && x_wave_ok(P.n[0], c->cfg.ax[0].v);
+    } else {
+      wave = x_wave_ok(c->single.n[0], c->cfg.ax[0].v);
+    }
+    L.xmode = wave ? kXPacked : kXMulti;
   }
   return L;
 }
@@ -536,7 +557,7 @@ int time_sweep(hydro_ctx* c, int axis, int reps, double* ms) {
 std::string shape_key(const hydro_ctx* c, int axis) {
   std::ostringstream o;
   o << c->arch << ":cu" << c->cu_count << ":" << (c->fp64 ? "fp64" : "fp32") << ":ax" << axis
-    << ":k3";
+    << ":k4";
   if (c->batch) {
     o << ":batch" << c->npatch << "x" << c->max_patch_cells;
   } else {
@@ -550,20 +571,35 @@ std::vector<SweepCfg> candidates(const hydro_ctx* c, int axis) {
   std::vector<SweepCfg> out;
   if (axis == 0) {
     const std::vector<PatchDev> ps = c->batch ? c->patches : std::vector<PatchDev>{c->single};
+    int nx_min = 1 << 30;
+    for (auto& P : ps) nx_min = std::min(nx_min, P.n[0]);
     for (int v : {1, 2, 4})
       for (int b : {64, 128, 192, 256, 384, 448, 512}) {
         SweepCfg s{};
-        s.kind = 0;
+        s.kind = kLaneRunKind;
         s.v = v;
         s.block = b;
         if (x_cfg_ok_all(s, ps, c->fp64)) out.push_back(s);
+        // the march only pays where every pencil spans more than one wave;
+        // direct launches also try capped grids (a wave then marches
+        // several pencils, prefetching the next one's first chunk)
+        s.kind = kXMarchKind;
+        if (nx_min / v > 64 && x_cfg_ok_all(s, ps, c->fp64)) {
+          out.push_back(s);
+          if (!c->batch)
+            for (int g : {2, 4, 8}) {
+              s.q = g * c->cu_count;
+              out.push_back(s);
+            }
+          s.q = 0;
+        }
       }
   } else {
     int n = c->batch ? 64 : c->single.n[axis];
     for (int q : {64, 128, 256})
       for (int s : {1, 2, 4, 8, 16}) {
         SweepCfg k{};
-        k.kind = 1;
+        k.kind = kColumnKind;
         k.q = q;
         k.s = s;
         if (!col_cfg_ok(k)) continue;
@@ -982,7 +1018,7 @@ int hydro_batch_init(const hydro_patch* p, int32_t n, const hydro_desc* common, 
   c->cfg.ax[0] = x;
   for (int a = 1; a < 3; ++a) {
     SweepCfg s{};
-    s.kind = 1;
+    s.kind = kColumnKind;
     s.q = 256;
     s.s = 1;
     c->cfg.ax[a] = s;

@@ -476,6 +476,286 @@ __global__ void __launch_bounds__(512) sweep_x_kernel(SweepArgs<T> a) {
 }
 
 // --------------------------------------------------------------------------
+// Chunked x march: one pencil per wave
+// --------------------------------------------------------------------------
+
+// Value of lane `lane` (wave-uniform) of x, as a wave-uniform value.
+__device__ __forceinline__ float lane_val(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+__device__ __forceinline__ double lane_val(double x, int lane) {
+  const long long b = __double_as_longlong(x);
+  const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(b), lane));
+  const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(b >> 32), lane));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <class T>
+__device__ __forceinline__ Prim<T> lane_prim(const Prim<T>& W, int lane) {
+  Prim<T> r;
+  r.r = lane_val(W.r, lane); r.u = lane_val(W.u, lane); r.t1 = lane_val(W.t1, lane);
+  r.t2 = lane_val(W.t2, lane); r.p = lane_val(W.p, lane); r.ri = lane_val(W.ri, lane);
+  return r;
+}
+template <class T>
+__device__ __forceinline__ Cons<T> lane_cons(const Cons<T>& U, int lane) {
+  return Cons<T>{lane_val(U.r, lane), lane_val(U.mn, lane), lane_val(U.mt1, lane),
+                 lane_val(U.mt2, lane), lane_val(U.e, lane)};
+}
+
+// The five planes of one lane run.
+template <class T, int V>
+struct Run {
+  T r[V], n[V], t1[V], t2[V], e[V];
+};
+
+template <class T, int V>
+__device__ __forceinline__ void load_runs(const Planes<T, 0>& pl, uint32_t off, bool act,
+                                          Run<T, V>& R) {
+  if (act) {
+    load_run<T, V>(pl.r, off, R.r);
+    load_run<T, V>(pl.n, off, R.n);
+    load_run<T, V>(pl.t1, off, R.t1);
+    load_run<T, V>(pl.t2, off, R.t2);
+    load_run<T, V>(pl.e, off, R.e);
+  } else {
+#pragma unroll
+    for (int c = 0; c < V; ++c) {  // a benign state for idle lanes
+      R.r[c] = T(1); R.n[c] = R.t1[c] = R.t2[c] = T(0); R.e[c] = T(1);
+    }
+  }
+}
+
+// First M cells of a run, stored element by element.
+template <class T, int V, int M>
+__device__ __forceinline__ void store_head(const Planes<T, 0>& pl, uint32_t off,
+                                           const Cons<T> (&U)[V]) {
+#pragma unroll
+  for (int c = 0; c < M; ++c) pl.store(off + uint32_t(c * sizeof(T)), U[c]);
+}
+
+// x-pencils q0, q0 + qs, ... (below qend) marched one after another by one
+// wave, each in chunks of 64 lane runs (64 V cells); lane l of chunk j holds
+// cells [(64 j + l) V, (64 j + l + 1) V).  Inside a chunk values cross lanes
+// by shuffles.  Across a chunk edge:
+//  * the next chunk is loaded (prefetched) before the current one is
+//    stored, so its first cell is still the original state; lane 63 takes
+//    that cell's primitives as its right neighbour;
+//  * the flux through the chunk edge needs the next chunk's face states, so
+//    the update of the chunk's last cell waits one chunk: lane 63 stores
+//    its first V-1 cells, and lane 0 of the next chunk finishes the held
+//    cell from the carried (original) state, its left flux and the edge
+//    flux, which that lane computes anyway as its own left-face flux;
+//  * the carried values (primitives and W+ face state of the held cell, its
+//    state and left flux) are wave-uniform.
+// The last chunk of a pencil prefetches the first chunk of the next one.
+// A periodic pencil reads its last two cells before anything is stored (for
+// the wrap face at the low end) and keeps the first cell's primitives and
+// the wrap flux of the first chunk for its high end.  Every value of a
+// pencil is loaded before the wave stores over it, and no other wave touches
+// the pencil, so the update is in place without barriers.
+template <class T, int V>
+__device__ void xmarch_pencils(const SweepArgs<T>& a, const PatchDev& P, int q0, int qs,
+                               int qend, const SweepConst<T>& k, const T id[3], T& smax,
+                               bool& bad) {
+  if (q0 >= qend) return;
+  const int N = P.n[0];
+  const int LPP = N / V;
+  const int C = (LPP + 63) >> 6;
+  const int l = threadIdx.x & 63;
+  const Planes<T, 0> pl(a.pool, P);
+  const uint32_t runb = uint32_t(V * sizeof(T));
+  const bool per = a.bc_lo == kBcPeriodic;  // periodic is set on both ends or neither
+  const unsigned ny = unsigned(P.n[1]);
+  auto row_of = [&](int q) {
+    const unsigned z = unsigned(q) / ny, y = unsigned(q) - z * ny;
+    return uint32_t((int64_t(y) * P.sy + int64_t(z) * P.sz) * int64_t(sizeof(T)));
+  };
+
+  Run<T, V> nxt;
+  load_runs<T, V>(pl, row_of(q0) + uint32_t(l) * runb, l < LPP, nxt);
+  for (int q = q0; q < qend; q += qs) {
+    const uint32_t row = row_of(q);
+    const int qn = q + qs;  // next pencil of this wave
+    Prim<T> Wt1, Wt2;  // original cells N-1 and N-2 (periodic low end)
+    if (per) {
+      Wt1 = to_prim(pl.load(row + uint32_t((N - 1) * sizeof(T))), k);
+      Wt2 = to_prim(pl.load(row + uint32_t((N - 2) * sizeof(T))), k);
+    }
+
+    Prim<T> W0, Wprev, WpPrev;  // carried, wave-uniform
+    Cons<T> Fwrap, Uheld, Fheld;
+    for (int j = 0; j < C; ++j) {
+      const int gl = j * 64 + l;
+      const bool act = gl < LPP;
+      const bool lastc = j == C - 1;
+      const int hi = lastc ? LPP - 1 - j * 64 : 63;  // last active lane of the chunk
+      const uint32_t off = row + uint32_t(gl) * runb;
+      Cons<T> U[V];
+      Prim<T> W[V];
+#pragma unroll
+      for (int c = 0; c < V; ++c) {
+        U[c] = Cons<T>{nxt.r[c], nxt.n[c], nxt.t1[c], nxt.t2[c], nxt.e[c]};
+        W[c] = to_prim(U[c], k);
+      }
+      if (!lastc) load_runs<T, V>(pl, off + 64 * runb, gl + 64 < LPP, nxt);
+      else if (qn < qend) load_runs<T, V>(pl, row_of(qn) + uint32_t(l) * runb, l < LPP, nxt);
+      if (j == 0 && per) W0 = lane_prim(W[0], 0);
+
+      const int srcL = (l + 63) & 63, srcR = (l + 1) & 63;
+      Prim<T> Wl = shfl_prim(W[V - 1], srcL);
+      Prim<T> Wr = shfl_prim(W[0], srcR);
+      if (l == 0) {
+        if (j > 0) Wl = Wprev;
+        else if (per) Wl = Wt1;
+        else Wl = a.bc_lo == kBcOutflow ? W[0] : mirror(W[0]);
+      }
+      if (!lastc) {
+        const Cons<T> un{lane_val(nxt.r[0], 0), lane_val(nxt.n[0], 0), lane_val(nxt.t1[0], 0),
+                         lane_val(nxt.t2[0], 0), lane_val(nxt.e[0], 0)};
+        const Prim<T> Wn = to_prim(un, k);
+        if (l == 63) Wr = Wn;
+      } else if (l == hi) {
+        if (per) Wr = W0;
+        else Wr = a.bc_hi == kBcOutflow ? W[V - 1] : mirror(W[V - 1]);
+      }
+
+      Prim<T> Wm[V], Wp[V];
+#pragma unroll
+      for (int c = 0; c < V; ++c) {
+        const Prim<T>& L = c == 0 ? Wl : W[c - 1];
+        const Prim<T>& R = c == V - 1 ? Wr : W[c + 1];
+        face_states(L, W[c], R, k, k.kick, Wm[c], Wp[c]);
+      }
+
+      Prim<T> WpL = shfl_prim(Wp[V - 1], srcL);
+      if (l == 0) {
+        if (j > 0) {
+          WpL = WpPrev;
+        } else if (per) {
+          Prim<T> dummy;
+          face_states(Wt2, Wt1, W[0], k, k.kick, dummy, WpL);
+        } else {
+          // ghost cell -1 with ghost -2 behind it
+          Prim<T> g1, g2, dummy;
+          T kick = k.kick;
+          if (a.bc_lo == kBcOutflow) {
+            g1 = W[0];
+            g2 = W[0];
+          } else {
+            const Prim<T>& W1 = V >= 2 ? W[V >= 2 ? 1 : 0] : Wr;
+            g1 = mirror(W[0]);
+            g2 = mirror(W1);
+            kick = -k.kick;
+          }
+          face_states(g2, g1, W[0], k, kick, dummy, WpL);
+        }
+      }
+
+      Cons<T> F[V];
+#pragma unroll
+      for (int c = 0; c < V; ++c) F[c] = hllc(c == 0 ? WpL : Wp[c - 1], Wm[c], k);
+      if (j == 0 && per) Fwrap = lane_cons(F[0], 0);
+
+      Cons<T> FR = shfl_cons(F[0], srcR);  // flux at the right face of the lane's last cell
+      if (lastc && l == hi) {
+        if (per) {
+          FR = Fwrap;
+        } else {
+          // ghost cell N with ghost N+1 beyond it
+          Prim<T> g1, g2, WmR, dummy;
+          T kick = k.kick;
+          if (a.bc_hi == kBcOutflow) {
+            g1 = W[V - 1];
+            g2 = W[V - 1];
+          } else {
+            const Prim<T>& Wn2 = V >= 2 ? W[V >= 2 ? V - 2 : 0] : Wl;
+            g1 = mirror(W[V - 1]);
+            g2 = mirror(Wn2);
+            kick = -k.kick;
+          }
+          face_states(W[V - 1], g1, g2, k, kick, WmR, dummy);
+          FR = hllc(Wp[V - 1], WmR, k);
+        }
+      }
+
+      // the cell held back by the previous chunk: lane 0's left-face flux is
+      // its right-face flux
+      if (j > 0 && l == 0) {
+        Cons<T> Ud = Uheld;
+        update(Ud, Fheld, F[0], k);
+        pl.store(off - uint32_t(sizeof(T)), Ud);
+        if (a.do_cfl) smax = fmax_(smax, cell_speed<T, 0>(Ud, k, id, bad));
+      }
+      const bool hold = !lastc && l == 63;
+      if (!lastc) {
+        Wprev = lane_prim(W[V - 1], 63);
+        WpPrev = lane_prim(Wp[V - 1], 63);
+        Uheld = lane_cons(U[V - 1], 63);
+        Fheld = lane_cons(F[V - 1], 63);
+      }
+
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+          update(U[c], F[c], c == V - 1 ? FR : F[c + 1], k);
+          if (a.do_cfl && !(hold && c == V - 1))
+            smax = fmax_(smax, cell_speed<T, 0>(U[c], k, id, bad));
+        }
+        if (!hold) {
+          Run<T, V> o;
+#pragma unroll
+          for (int c = 0; c < V; ++c) {
+            o.r[c] = U[c].r; o.n[c] = U[c].mn; o.t1[c] = U[c].mt1; o.t2[c] = U[c].mt2;
+            o.e[c] = U[c].e;
+          }
+          store_run<T, V>(pl.r, off, o.r);
+          store_run<T, V>(pl.n, off, o.n);
+          store_run<T, V>(pl.t1, off, o.t1);
+          store_run<T, V>(pl.t2, off, o.t2);
+          store_run<T, V>(pl.e, off, o.e);
+        } else {
+          store_head<T, V, V - 1>(pl, off, U);
+        }
+      }
+    }
+  }
+}
+
+template <class T, int V, bool PERSIST>
+__global__ void __launch_bounds__(512) sweep_xm_kernel(SweepArgs<T> a) {
+  __shared__ int item_s;
+  __shared__ T red[8];
+  const double dt = a.scal->dt;
+  const int nw = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  T smax = T(0);
+  bool bad = false;
+  if (!PERSIST) {
+    const PatchDev& P = a.single;
+    SweepConst<T> k = make_const<T>(dt, P.dx[0], a.gamma, a.grav);
+    T id[3];
+    inv_widths<T>(P, id);
+    // grid-stride over pencils: wave w of workgroup b takes pencils
+    // b nw + w, (b + G) nw + w, ... for a grid of G workgroups
+    xmarch_pencils<T, V>(a, P, int(blockIdx.x) * nw + wave, int(gridDim.x) * nw,
+                         P.n[1] * P.n[2], k, id, smax, bad);
+  } else {
+    for (;;) {
+      const int it = next_item(&a.scal->tickets[0], &item_s);
+      if (it >= a.nitems) break;
+      const WorkItem w = a.items[it];
+      const PatchDev P = a.patches[w.patch];
+      SweepConst<T> k = make_const<T>(dt, P.dx[0], a.gamma, a.grav);
+      T id[3];
+      inv_widths<T>(P, id);
+      const int npen = P.n[1] * P.n[2];
+      xmarch_pencils<T, V>(a, P, w.tile * nw + wave, npen, npen, k, id, smax, bad);
+    }
+  }
+  finish_block(a.scal, smax, bad, a.do_cfl != 0, red);
+}
+
+// --------------------------------------------------------------------------
 // Column marches along y (AXIS 1) or z (AXIS 2)
 // --------------------------------------------------------------------------
 
@@ -812,7 +1092,7 @@ struct LaunchSweep {
   SweepCfg cfg;
   int32_t persistent;
   int32_t fp64;
-  int32_t xwave;       // x sweep: every pencil fits inside one wave
+  int32_t xmode;       // x sweep: kXPacked, kXMulti or kXMarch
 };
 
 template <class T>
@@ -838,6 +1118,7 @@ static SweepArgs<T> to_args(const LaunchSweep& L) {
 int64_t x_pencils_per_tile(const PatchDev& P, const SweepCfg& c) {
   const int lpp = P.n[0] / c.v;
   const int nw = c.block / 64;
+  if (c.kind == kXMarchKind) return nw;  // one pencil per wave
   if (lpp <= 64) return int64_t(nw) * (64 / lpp);
   const int s = (lpp + 63) / 64;
   return nw / s;
@@ -847,6 +1128,13 @@ int64_t x_tiles(const PatchDev& P, const SweepCfg& c) {
   const int64_t ppw = x_pencils_per_tile(P, c);
   const int64_t npen = int64_t(P.n[1]) * P.n[2];
   return (npen + ppw - 1) / ppw;
+}
+
+// workgroups of a direct x launch: one per tile, or for the march at most
+// c.q (its grid-stride cap; 0 = no cap)
+int64_t x_grid(const PatchDev& P, const SweepCfg& c) {
+  const int64_t t = x_tiles(P, c);
+  return c.kind == kXMarchKind && c.q > 0 ? std::min<int64_t>(t, c.q) : t;
 }
 
 int64_t col_tiles(const PatchDev& P, int axis, const SweepCfg& c) {
@@ -863,8 +1151,17 @@ static hipError_t launch_x_vw(const LaunchSweep& L, hipStream_t st, dim3 grid) {
 
 template <class T, int V, bool PERSIST>
 static hipError_t launch_x_v(const LaunchSweep& L, hipStream_t st, dim3 grid) {
-  return L.xwave ? launch_x_vw<T, V, false, PERSIST>(L, st, grid)
-                 : launch_x_vw<T, V, true, PERSIST>(L, st, grid);
+  if (L.xmode == kXMarch) {
+    if constexpr (sizeof(T) == 8 && V == 4) {
+      return hipErrorInvalidValue;  // not built: the FP64 V=4 march spills registers
+    } else {
+      hipLaunchKernelGGL((sweep_xm_kernel<T, V, PERSIST>), grid, dim3(L.cfg.block), 0, st,
+                         to_args<T>(L));
+      return hipGetLastError();
+    }
+  }
+  return L.xmode == kXPacked ? launch_x_vw<T, V, false, PERSIST>(L, st, grid)
+                             : launch_x_vw<T, V, true, PERSIST>(L, st, grid);
 }
 
 template <class T, bool PERSIST>
@@ -893,7 +1190,7 @@ static hipError_t launch_sweep_t(const LaunchSweep& L, hipStream_t st) {
     dim3 grid(L.nblocks);
     return L.axis == 0 ? launch_x<T, true>(L, st, grid) : launch_col<T, true>(L, st, grid);
   }
-  if (L.axis == 0) return launch_x<T, false>(L, st, dim3(unsigned(x_tiles(L.single, L.cfg))));
+  if (L.axis == 0) return launch_x<T, false>(L, st, dim3(unsigned(x_grid(L.single, L.cfg))));
   return launch_col<T, false>(L, st, dim3(unsigned(col_tiles(L.single, L.axis, L.cfg))));
 }
 

@@ -45,12 +45,22 @@ struct WorkItem {
   int32_t tile;
 };
 
+// Kinds of sweep kernel (SweepCfg::kind).
+constexpr int kLaneRunKind = 0;   // x: lane runs, whole pencils per workgroup
+constexpr int kColumnKind = 1;    // y, z: column march
+constexpr int kXMarchKind = 2;    // x: one pencil per wave, marched in chunks
+
+// Shapes of the x lane-run launch.
+constexpr int kXPacked = 0;  // every pencil inside one wave
+constexpr int kXMulti = 1;   // a pencil spans several waves of a workgroup
+constexpr int kXMarch = 2;   // chunked march (kXMarchKind)
+
 // Kernel configuration of one sweep axis.
 struct SweepCfg {
-  int32_t kind;    // 0: lane runs along x, 1: column march
+  int32_t kind;    // kLaneRunKind, kColumnKind or kXMarchKind
   int32_t v;       // lane runs: cells per lane (1, 2, 4)
   int32_t block;   // threads per workgroup
-  int32_t q;       // column march: columns per tile
+  int32_t q;       // column march: columns per tile; x march: workgroup cap (0: none)
   int32_t s;       // column march: segments per column
   int32_t pad;
 };

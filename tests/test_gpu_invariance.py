@@ -17,6 +17,8 @@ CONFIGS = [
     "x:v=2,b=256;y:q=64,s=2;z:q=128,s=2",
     "x:v=4,b=64;y:q=128,s=4;z:q=64,s=4",
     "x:v=4,b=512;y:q=64,s=8;z:q=256,s=2",
+    "x:v=1,b=192,m=1;y:q=128,s=2;z:q=128,s=1",   # chunked x march: 72 = 64 + 8 lanes
+    "x:v=2,b=64,m=1;y:q=64,s=1;z:q=64,s=1",
 ]
 
 
