@@ -21,7 +21,15 @@ Prints ONE JSON line.  Fields beyond the driver's contract:
                  zone-update);
   fp64           the FP64 path on the same workload and the FP32 speedup;
   copy_ceiling   a plain device copy of the same bytes, for context;
-  cpu_baseline   the FP64 CPU oracle timed on the host (OpenMP threads).
+  stream_ceiling an in-place read+write pass over the state with no
+                 arithmetic (hydro_stream_ceiling): the memory-only ceiling;
+  cpu_baseline   the FP64 CPU oracle timed on the host (OpenMP threads) over
+                 a bounded sample of the workload;
+  accuracy       fp32_vs_fp64_gpu: per-variable L1 (and max-norm) error of
+                 the FP32 path against the FP64 path after the workload's
+                 step count, both on the GPU with the same dt sequence;
+                 vs_oracle: both GPU paths against the oracle's end state of
+                 the CPU sample, replaying the oracle's dt sequence.
 """
 import argparse
 import hashlib
@@ -53,6 +61,11 @@ WORKLOADS = {
 }
 
 
+# steps of the FP32-vs-FP64 side-by-side run per workload (KH and turbulence
+# as their workload definitions state; RT and the batch as a matching length)
+ACCURACY_STEPS = {"kh": 100, "turb": 50, "rt": 100, "batch": 20}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,7 +77,11 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--cpu-steps", type=int, default=0,
+                    help="oracle steps of the CPU sample (0: about 4e8 zone-updates)")
+    ap.add_argument("--skip-accuracy", action="store_true")
+    ap.add_argument("--accuracy-steps", type=int, default=0,
+                    help="steps of the FP32-vs-FP64 comparison (0: the workload's own)")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--config", default="", help="force a kernel configuration")
     ap.add_argument("--copy-only", action="store_true",
@@ -75,6 +92,11 @@ def parse():
 # --------------------------------------------------------------------------
 # workloads (host-side initial data)
 # --------------------------------------------------------------------------
+
+def log(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
 
 def make_workload(args):
     import numpy as np
@@ -122,15 +144,19 @@ def profile(obj, steps):
     return [t / max(1, steps) for t in tot]
 
 
-def run_gpu(W, prec, args, torch, hydro):
+def build_obj(W, prec, args, torch, hydro, flags=None):
+    """The workload's initial state on the GPU in `prec`, wrapped in a Grid or
+    Batch.  Returns (obj, state tensor, patch tuples or None)."""
     import numpy as np
     import hydro_ic as ic
     dtype = np.float32 if prec == hydro.FP32 else np.float64
-    flags = hydro.FLAG_NO_TUNE if args.no_tune else 0
+    if flags is None:
+        flags = hydro.FLAG_NO_TUNE if args.no_tune else 0
     if W["kind"] == "grid":
         P = W["P"]
         U = torch.from_numpy(np.ascontiguousarray(P.U.astype(dtype, copy=False))).to("cuda:0")
         obj = hydro.Grid(U, P.dx, P.gamma, P.cfl, P.bc, P.grav, flags=flags)
+        patches = None
     else:
         # interior rows start on 128-byte boundaries (ghost layers kept)
         pool, patches = ic.batch_pool(W["specs"], ng=4, dtype=dtype, pad_rows=32)
@@ -139,16 +165,117 @@ def run_gpu(W, prec, args, torch, hydro):
         obj = hydro.Batch(U, patches, 5.0 / 3.0, flags=flags)
     if args.config:
         obj.config = args.config
+    return obj, U, patches
+
+
+def run_gpu(W, prec, args, torch, hydro):
+    log(f"precision {prec}: build and tune")
+    obj, U, _ = build_obj(W, prec, args, torch, hydro)
+    log(f"precision {prec}: timing with {obj.config}")
     sec = timed_steps(obj, args.steps, args.warmup, torch)
     if obj.error() != hydro.HYDRO_OK:
         raise RuntimeError("numeric error flag set during the benchmark")
     kms = profile(obj, args.profile_steps)
     cfg = obj.config
-    obj.close()
     state_bytes = U.numel() * U.element_size()
+    sms = obj.stream_ceiling(10)
+    stream = {"bytes_per_pass": 2 * state_bytes, "mean_ms": sms,
+              "gbs": 2 * state_bytes / (sms * 1e-3) / 1e9}
+    obj.close()
     del U
     torch.cuda.empty_cache()
-    return sec, kms, cfg, state_bytes
+    return sec, kms, cfg, state_bytes, stream
+
+
+# --------------------------------------------------------------------------
+# accuracy: L1 errors of a result against a reference of the same workload
+# --------------------------------------------------------------------------
+
+VARS = ("rho", "mx", "my", "mz", "E")
+
+
+def interiors(U, patches):
+    """(5, nz, ny, nx) interior views of a grid state or of every patch of a
+    pool (ghost layers and row padding excluded)."""
+    if patches is None:
+        yield U
+        return
+    for o, nx, ny, nz, ng, _, _, _, rp, sp, pp, io in patches:
+        yield U.as_strided((5, nz, ny, nx), (pp, sp, rp, 1), o + io)
+
+
+class L1:
+    """Accumulates sum |q - q_ref| and sum |q_ref| per conserved variable, plus
+    the momentum vector measure (component differences summed over the three
+    axes over sum |m|_1, meaningful where one component is nearly zero) and
+    the max-norm relative error."""
+
+    def __init__(self, torch):
+        self.t = torch
+        self.num = torch.zeros(5, dtype=torch.float64, device="cuda:0")
+        self.den = torch.zeros(5, dtype=torch.float64, device="cuda:0")
+        self.dmax = torch.zeros(5, dtype=torch.float64, device="cuda:0")
+        self.rmax = torch.zeros(5, dtype=torch.float64, device="cuda:0")
+
+    def add(self, got, ref):
+        for v in range(5):
+            d = (got[v].to(self.t.float64) - ref[v]).abs_()
+            self.num[v] += d.sum()
+            self.dmax[v] = self.t.maximum(self.dmax[v], d.max())
+            del d
+            a = ref[v].abs()
+            self.den[v] += a.sum()
+            self.rmax[v] = self.t.maximum(self.rmax[v], a.max())
+            del a
+
+    def result(self):
+        num = self.num.cpu().tolist()
+        den = self.den.cpu().tolist()
+        dmax = self.dmax.cpu().tolist()
+        rmax = self.rmax.cpu().tolist()
+        out = {"l1": {VARS[v]: num[v] / max(den[v], 1e-300) for v in range(5)},
+               "max_rel": {VARS[v]: dmax[v] / max(rmax[v], 1e-300) for v in range(5)}}
+        out["l1"]["m"] = sum(num[1:4]) / max(sum(den[1:4]), 1e-300)
+        return out
+
+
+def replay(W, prec, dts, args, torch, hydro):
+    """The workload stepped in `prec` with the given dt sequence (Strang
+    parity from step 0).  Returns (state tensor, patches)."""
+    obj, U, patches = build_obj(W, prec, args, torch, hydro, flags=hydro.FLAG_NO_TUNE)
+    for dt in dts:
+        obj.step(dt)
+    torch.cuda.synchronize()
+    if obj.error() != hydro.HYDRO_OK:
+        raise RuntimeError("numeric error flag set during a replay")
+    obj.close()
+    return U, patches
+
+
+def side_by_side(W, steps, args, torch, hydro):
+    """FP32 against FP64 on the GPU: the FP64 path takes `steps` CFL steps
+    (dt from hydro_cfl_dt before each), the FP32 path replays the same dt
+    sequence, and the per-variable L1 error of FP32 against FP64 is
+    reported."""
+    log(f"FP32 vs FP64 side by side, {steps} steps")
+    obj, U64, patches = build_obj(W, hydro.FP64, args, torch, hydro,
+                                  flags=hydro.FLAG_NO_TUNE)
+    dts = []
+    for _ in range(steps):
+        dt = obj.cfl_dt()
+        obj.step(dt)
+        dts.append(dt)
+    torch.cuda.synchronize()
+    obj.close()
+    U32, _ = replay(W, hydro.FP32, dts, args, torch, hydro)
+    acc = L1(torch)
+    for a, b in zip(interiors(U32, patches), interiors(U64, patches)):
+        acc.add(a, b)
+    out = {"steps": steps, "t": float(sum(dts)), "dt": "CFL of the FP64 path, replayed "
+           "in FP32", **acc.result()}
+    del U32, U64
+    torch.cuda.empty_cache()
+    return out
 
 
 def copy_ceiling(torch, nbytes_state, reps=20):
@@ -178,36 +305,84 @@ def copy_ceiling(torch, nbytes_state, reps=20):
 # CPU baseline (the oracle as it stands)
 # --------------------------------------------------------------------------
 
-def cpu_baseline(W, steps):
+def default_cpu_steps(W):
+    """Oracle steps of the CPU sample: about 4e8 zone-updates (10-20 s on 16
+    host threads), at least one step."""
+    if W["kind"] != "grid":
+        return 1
+    return max(1, min(24, int(4e8 // W["P"].zones)))
+
+
+def cpu_baseline(W, steps, args, torch, hydro):
+    """The FP64 oracle timed on the host over a bounded sample of the
+    workload.  Its end state is also the reference of the `vs_oracle`
+    accuracy figures: the GPU paths replay the oracle's dt sequence from the
+    same initial state and their interiors are compared with it."""
     import numpy as np
     import hydro_ic as ic
     import oracle
     threads = min(16, os.cpu_count() or 1)
+    log(f"oracle on {threads} host threads, {steps} step(s)")
+    acc32, acc64 = L1(torch), L1(torch)
     if W["kind"] == "grid":
         P = W["P"]
         p = oracle.make_params(P.shape, P.dx, P.gamma, P.cfl, P.bc, P.grav, nthreads=threads)
-        U = np.ascontiguousarray(P.U, dtype=np.float64)
+        U = np.array(P.U, dtype=np.float64, order="C", copy=True)  # P.U stays the input
+        dts = []
         t0 = time.perf_counter()
-        oracle.run(p, U, steps)
+        for k in range(steps):
+            dt = oracle.cfl_dt(p, U)
+            oracle.step(p, U, dt, k)
+            dts.append(dt)
         sec = time.perf_counter() - t0
         zu = P.zones * steps
         sample = (f"{steps} full steps of the same {W['grid'][0]}x{W['grid'][1]}x"
                   f"{W['grid'][2]} grid in FP64, CFL dt each step, {sec:.1f} s wall")
+        ref = torch.from_numpy(U).to("cuda:0")
+        del U
+        for prec, acc in ((hydro.FP32, acc32), (hydro.FP64, acc64)):
+            G, _ = replay(W, prec, dts, args, torch, hydro)
+            acc.add(G, ref)
+            del G
+            torch.cuda.empty_cache()
+        del ref
     else:
-        specs = W["specs"][:256]
-        zu = 0
+        specs = W["specs"]
+        dx = [1.0 / s.n for s in specs]
+        params = [oracle.make_params((s.n,) * 3, d, 5.0 / 3.0, 0.8, nthreads=threads)
+                  for s, d in zip(specs, dx)]
         sec = 0.0
-        for s in specs:
+        dt = float("inf")
+        for s, p in zip(specs, params):       # one global dt, as the batch uses
             U = ic.kh_patch(s)
-            p = oracle.make_params(U.shape[1:], 1.0 / s.n, 5.0 / 3.0, 0.8, nthreads=threads)
             t0 = time.perf_counter()
-            oracle.run(p, U, 1)
+            dt = min(dt, oracle.cfl_dt(p, U))
+            sec += time.perf_counter() - t0
+        dts = [dt]
+        G32, patches = replay(W, hydro.FP32, dts, args, torch, hydro)
+        G64, _ = replay(W, hydro.FP64, dts, args, torch, hydro)
+        views = zip(interiors(G32, patches), interiors(G64, patches))
+        zu = 0
+        for s, p, (v32, v64) in zip(specs, params, views):
+            U = ic.kh_patch(s)
+            t0 = time.perf_counter()
+            oracle.step(p, U, dt, 0)
             sec += time.perf_counter() - t0
             zu += s.n ** 3
-        sample = (f"one step of each of the first {len(specs)} patches of the batch in FP64 "
-                  f"(patch by patch), {sec:.1f} s wall")
-    return {"value": zu / sec, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
+            ref = torch.from_numpy(U).to("cuda:0")
+            acc32.add(v32, ref)
+            acc64.add(v64, ref)
+        del G32, G64
+        torch.cuda.empty_cache()
+        sample = (f"one step of all {len(specs)} patches of the batch in FP64 (patch by "
+                  f"patch) at one dt, the smallest oracle CFL dt over the patches; CFL "
+                  f"pass and step timed, {sec:.1f} s wall")
+    base = {"value": zu / sec, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
             "sample": sample}
+    vs = {"steps": len(dts), "t": float(sum(dts)),
+          "dt": "the oracle's CFL dt sequence, replayed by both GPU paths",
+          "fp32": acc32.result(), "fp64": acc64.result()}
+    return base, vs
 
 
 # --------------------------------------------------------------------------
@@ -256,10 +431,10 @@ def main():
 
     W = make_workload(args)
     zones = interior_zones(W)
-    sec32, k32, cfg32, bytes32 = run_gpu(W, hydro.FP32, args, torch, hydro)
+    sec32, k32, cfg32, bytes32, stream32 = run_gpu(W, hydro.FP32, args, torch, hydro)
     fp64 = None
     if not args.skip_fp64:
-        sec64, k64, cfg64, _ = run_gpu(W, hydro.FP64, args, torch, hydro)
+        sec64, k64, cfg64, _, stream64 = run_gpu(W, hydro.FP64, args, torch, hydro)
         fp64 = {"value": zones / sec64, "unit": "zone-updates/s",
                 "ms_per_step": sec64 * 1e3,
                 "step_roofline_frac": zones / sec64 * 240 / (HBM_PEAK_GBS * 1e9),
@@ -267,6 +442,7 @@ def main():
                 "kernel_gbs": {ax: (zones * 80 / (k64[i] * 1e-3) / 1e9 if k64[i] else 0.0)
                                for i, ax in enumerate("xyz")},
                 "config": cfg64,
+                "stream_ceiling": stream64,
                 "fp32_speedup": sec64 / sec32}
 
     value = zones / sec32
@@ -303,10 +479,17 @@ def main():
         "kernel_ms": {"x": k32[0], "y": k32[1], "z": k32[2]},
         "fp64": fp64,
         "copy_ceiling": copy_ceiling(torch, bytes32),
+        "stream_ceiling": stream32,
         "kernel_source": kernel_source_hash(),
     }
+    acc = {}
+    if not args.skip_accuracy:
+        steps = args.accuracy_steps or ACCURACY_STEPS[args.workload]
+        acc["fp32_vs_fp64_gpu"] = side_by_side(W, steps, args, torch, hydro)
     if not args.skip_cpu:
-        out["cpu_baseline"] = cpu_baseline(W, args.cpu_steps if W["kind"] == "grid" else 1)
+        steps = args.cpu_steps or default_cpu_steps(W)
+        out["cpu_baseline"], acc["vs_oracle"] = cpu_baseline(W, steps, args, torch, hydro)
+    out["accuracy"] = acc or None
     print(json.dumps(out))
 
 
