@@ -525,12 +525,42 @@ __device__ __forceinline__ void load_runs(const Planes<T, 0>& pl, uint32_t off, 
   }
 }
 
-// First M cells of a run, stored element by element.
-template <class T, int V, int M>
-__device__ __forceinline__ void store_head(const Planes<T, 0>& pl, uint32_t off,
-                                           const Cons<T> (&U)[V]) {
+// The last 128-byte line of a chunk's runs is written to memory by the next
+// chunk, in one piece, rather than in two pieces at different times (the
+// line holds the run whose last cell waits for the next chunk).  Until then
+// it waits in a per-wave LDS buffer of kLineBytes per plane: slot i, plane v
+// at elements [v kLineBytes/sizeof(T) + i V, + V).
+constexpr int kLineBytes = 128;
+
+// Orders this wave's LDS accesses across lanes: the hardware runs a wave's
+// LDS instructions in order, and the fences keep the compiler from moving
+// them across this point.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class T, int V>
+__device__ __forceinline__ void put_run(T* line, int slot, const Run<T, V>& R) {
+  constexpr int PL = kLineBytes / int(sizeof(T));
+  T* b = line + slot * V;
 #pragma unroll
-  for (int c = 0; c < M; ++c) pl.store(off + uint32_t(c * sizeof(T)), U[c]);
+  for (int c = 0; c < V; ++c) {
+    b[c] = R.r[c]; b[PL + c] = R.n[c]; b[2 * PL + c] = R.t1[c]; b[3 * PL + c] = R.t2[c];
+    b[4 * PL + c] = R.e[c];
+  }
+}
+
+template <class T, int V>
+__device__ __forceinline__ void get_run(const T* line, int slot, Run<T, V>& R) {
+  constexpr int PL = kLineBytes / int(sizeof(T));
+  const T* b = line + slot * V;
+#pragma unroll
+  for (int c = 0; c < V; ++c) {
+    R.r[c] = b[c]; R.n[c] = b[PL + c]; R.t1[c] = b[2 * PL + c]; R.t2[c] = b[3 * PL + c];
+    R.e[c] = b[4 * PL + c];
+  }
 }
 
 // x-pencils q0, q0 + qs, ... (below qend) marched one after another by one
@@ -541,12 +571,13 @@ __device__ __forceinline__ void store_head(const Planes<T, 0>& pl, uint32_t off,
 //    stored, so its first cell is still the original state; lane 63 takes
 //    that cell's primitives as its right neighbour;
 //  * the flux through the chunk edge needs the next chunk's face states, so
-//    the update of the chunk's last cell waits one chunk: lane 63 stores
-//    its first V-1 cells, and lane 0 of the next chunk finishes the held
-//    cell from the carried (original) state, its left flux and the edge
-//    flux, which that lane computes anyway as its own left-face flux;
+//    the update of the chunk's last cell waits one chunk: lane 63 keeps its
+//    run, and lane 0 of the next chunk finishes the held cell from the
+//    carried (original) state, its left flux and the edge flux (which that
+//    lane computes anyway as its own left-face flux), then stores the whole
+//    run, so that no run is ever written in pieces;
 //  * the carried values (primitives and W+ face state of the held cell, its
-//    state and left flux) are wave-uniform.
+//    state and left flux, the updated head of the run) are wave-uniform.
 // The last chunk of a pencil prefetches the first chunk of the next one.
 // A periodic pencil reads its last two cells before anything is stored (for
 // the wrap face at the low end) and keeps the first cell's primitives and
@@ -555,8 +586,8 @@ __device__ __forceinline__ void store_head(const Planes<T, 0>& pl, uint32_t off,
 // the pencil, so the update is in place without barriers.
 template <class T, int V>
 __device__ void xmarch_pencils(const SweepArgs<T>& a, const PatchDev& P, int q0, int qs,
-                               int qend, const SweepConst<T>& k, const T id[3], T& smax,
-                               bool& bad) {
+                               int qend, const SweepConst<T>& k, const T id[3], T* line,
+                               T& smax, bool& bad) {
   if (q0 >= qend) return;
   const int N = P.n[0];
   const int LPP = N / V;
@@ -564,6 +595,7 @@ __device__ void xmarch_pencils(const SweepArgs<T>& a, const PatchDev& P, int q0,
   const int l = threadIdx.x & 63;
   const Planes<T, 0> pl(a.pool, P);
   const uint32_t runb = uint32_t(V * sizeof(T));
+  constexpr int LPL = int(kLineBytes / (V * sizeof(T)));  // lane runs per 128-byte line
   const bool per = a.bc_lo == kBcPeriodic;  // periodic is set on both ends or neither
   const unsigned ny = unsigned(P.n[1]);
   auto row_of = [&](int q) {
@@ -678,15 +710,31 @@ __device__ void xmarch_pencils(const SweepArgs<T>& a, const PatchDev& P, int q0,
         }
       }
 
-      // the cell held back by the previous chunk: lane 0's left-face flux is
-      // its right-face flux
-      if (j > 0 && l == 0) {
+      // the last line of the previous chunk: its held cell takes lane 0's
+      // left-face flux as its right-face flux; lanes 0..LPL-1 store the
+      // line's runs, kept in LDS since that chunk, as whole vectors
+      wave_sync();  // the line written by other lanes of this wave
+      if (j > 0) {
         Cons<T> Ud = Uheld;
-        update(Ud, Fheld, F[0], k);
-        pl.store(off - uint32_t(sizeof(T)), Ud);
-        if (a.do_cfl) smax = fmax_(smax, cell_speed<T, 0>(Ud, k, id, bad));
+        update(Ud, Fheld, lane_cons(F[0], 0), k);
+        if (a.do_cfl && l == 0) smax = fmax_(smax, cell_speed<T, 0>(Ud, k, id, bad));
+        if (l < LPL) {
+          Run<T, V> o;
+          get_run<T, V>(line, l, o);
+          if (l == LPL - 1) {
+            o.r[V - 1] = Ud.r; o.n[V - 1] = Ud.mn; o.t1[V - 1] = Ud.mt1;
+            o.t2[V - 1] = Ud.mt2; o.e[V - 1] = Ud.e;
+          }
+          const uint32_t ho = off - uint32_t(LPL) * runb;
+          store_run<T, V>(pl.r, ho, o.r);
+          store_run<T, V>(pl.n, ho, o.n);
+          store_run<T, V>(pl.t1, ho, o.t1);
+          store_run<T, V>(pl.t2, ho, o.t2);
+          store_run<T, V>(pl.e, ho, o.e);
+        }
       }
-      const bool hold = !lastc && l == 63;
+      wave_sync();  // every lane has read the line before it is refilled
+      const bool hold = !lastc && l == 63;  // its last cell waits for the next chunk
       if (!lastc) {
         Wprev = lane_prim(W[V - 1], 63);
         WpPrev = lane_prim(Wp[V - 1], 63);
@@ -701,20 +749,20 @@ __device__ void xmarch_pencils(const SweepArgs<T>& a, const PatchDev& P, int q0,
           if (a.do_cfl && !(hold && c == V - 1))
             smax = fmax_(smax, cell_speed<T, 0>(U[c], k, id, bad));
         }
-        if (!hold) {
-          Run<T, V> o;
+        Run<T, V> o;
 #pragma unroll
-          for (int c = 0; c < V; ++c) {
-            o.r[c] = U[c].r; o.n[c] = U[c].mn; o.t1[c] = U[c].mt1; o.t2[c] = U[c].mt2;
-            o.e[c] = U[c].e;
-          }
+        for (int c = 0; c < V; ++c) {
+          o.r[c] = U[c].r; o.n[c] = U[c].mn; o.t1[c] = U[c].mt1; o.t2[c] = U[c].mt2;
+          o.e[c] = U[c].e;
+        }
+        if (lastc || l < 64 - LPL) {
           store_run<T, V>(pl.r, off, o.r);
           store_run<T, V>(pl.n, off, o.n);
           store_run<T, V>(pl.t1, off, o.t1);
           store_run<T, V>(pl.t2, off, o.t2);
           store_run<T, V>(pl.e, off, o.e);
         } else {
-          store_head<T, V, V - 1>(pl, off, U);
+          put_run<T, V>(line, l - (64 - LPL), o);  // the next chunk stores it
         }
       }
     }
@@ -725,6 +773,7 @@ template <class T, int V, bool PERSIST>
 __global__ void __launch_bounds__(512) sweep_xm_kernel(SweepArgs<T> a) {
   __shared__ int item_s;
   __shared__ T red[8];
+  __shared__ T lines[8][5 * kLineBytes / sizeof(T)];  // per wave
   const double dt = a.scal->dt;
   const int nw = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -738,7 +787,7 @@ __global__ void __launch_bounds__(512) sweep_xm_kernel(SweepArgs<T> a) {
     // grid-stride over pencils: wave w of workgroup b takes pencils
     // b nw + w, (b + G) nw + w, ... for a grid of G workgroups
     xmarch_pencils<T, V>(a, P, int(blockIdx.x) * nw + wave, int(gridDim.x) * nw,
-                         P.n[1] * P.n[2], k, id, smax, bad);
+                         P.n[1] * P.n[2], k, id, lines[wave], smax, bad);
   } else {
     for (;;) {
       const int it = next_item(&a.scal->tickets[0], &item_s);
@@ -749,7 +798,8 @@ __global__ void __launch_bounds__(512) sweep_xm_kernel(SweepArgs<T> a) {
       T id[3];
       inv_widths<T>(P, id);
       const int npen = P.n[1] * P.n[2];
-      xmarch_pencils<T, V>(a, P, w.tile * nw + wave, npen, npen, k, id, smax, bad);
+      xmarch_pencils<T, V>(a, P, w.tile * nw + wave, npen, npen, k, id, lines[wave], smax,
+                           bad);
     }
   }
   finish_block(a.scal, smax, bad, a.do_cfl != 0, red);
