@@ -42,6 +42,7 @@ struct LaunchSweep {
   int32_t persistent;
   int32_t fp64;
   int32_t xmode;
+  int32_t dyn;
 };
 struct LaunchReduce {
   const void* pool;
@@ -195,6 +196,7 @@ bool patch_from(const hydro_patch& p, PatchDev* out, int64_t* len) {
 struct Config {
   SweepCfg ax[3];
   int32_t batch_blocks = 0;  // persistent launches: workgroups
+  int32_t batch_dyn = 1;     // persistent launches: ticket (1) or static (0) items
 };
 
 // A lane run of v cells is loaded and stored as one vector access, so every
@@ -265,7 +267,7 @@ std::string cfg_text(const Config& cf) {
   }
   o << ";y:q=" << cf.ax[1].q << ",s=" << cf.ax[1].s;
   o << ";z:q=" << cf.ax[2].q << ",s=" << cf.ax[2].s;
-  if (cf.batch_blocks) o << ";p:g=" << cf.batch_blocks;
+  if (cf.batch_blocks) o << ";p:g=" << cf.batch_blocks << ",d=" << cf.batch_dyn;
   return o.str();
 }
 
@@ -304,6 +306,7 @@ bool parse_cfg(const std::string& text, Config& cf) {
         else return false;
       } else if (ax == 'p') {
         if (k == "g") cf.batch_blocks = int(v);
+        else if (k == "d" && (v == 0 || v == 1)) cf.batch_dyn = int(v);
         else return false;
       } else {
         return false;
@@ -427,6 +430,7 @@ LaunchSweep sweep_launch(const hydro_ctx* c, int axis, int do_cfl) {
   L.items = c->d_items[axis];
   L.nitems = c->nitems[axis];
   L.nblocks = c->cfg.batch_blocks;
+  L.dyn = c->cfg.batch_dyn;
   L.axis = axis;
   L.bc_lo = c->desc.bc[2 * axis];
   L.bc_hi = c->desc.bc[2 * axis + 1];
@@ -557,7 +561,7 @@ int time_sweep(hydro_ctx* c, int axis, int reps, double* ms) {
 std::string shape_key(const hydro_ctx* c, int axis) {
   std::ostringstream o;
   o << c->arch << ":cu" << c->cu_count << ":" << (c->fp64 ? "fp64" : "fp32") << ":ax" << axis
-    << ":k4";
+    << ":k5";
   if (c->batch) {
     o << ":batch" << c->npatch << "x" << c->max_patch_cells;
   } else {
@@ -695,14 +699,16 @@ int choose_config(hydro_ctx* c) {
     if (it != cache.end() && parse_cfg(it->second, tmp) && tmp.batch_blocks > 0 &&
         tmp.batch_blocks <= 65536) {
       c->cfg.batch_blocks = tmp.batch_blocks;
+      c->cfg.batch_dyn = tmp.batch_dyn;
     } else {
       if (launch_timing_begin(c->scal, c->stream) != hipSuccess)
         return fail(HYDRO_EDEVICE, "timing setup failed");
       double best = 1e30;
-      int best_g = c->cfg.batch_blocks;
+      int best_g = c->cfg.batch_blocks, best_d = c->cfg.batch_dyn;
       int rc = HYDRO_OK;
-      for (int per_cu : {2, 4, 8, 16}) {
-        c->cfg.batch_blocks = per_cu * c->cu_count;
+      for (int trial = 0; trial < 8 && rc == HYDRO_OK; ++trial) {
+        c->cfg.batch_blocks = (2 << (trial % 4)) * c->cu_count;  // 2, 4, 8, 16 per CU
+        c->cfg.batch_dyn = trial < 4 ? 1 : 0;
         double tot = 0.0;
         for (int axis = 0; axis < 3 && rc == HYDRO_OK; ++axis) {
           if (!c->active[axis] || c->nitems[axis] == 0) continue;
@@ -714,13 +720,15 @@ int choose_config(hydro_ctx* c) {
         if (tot < best) {
           best = tot;
           best_g = c->cfg.batch_blocks;
+          best_d = c->cfg.batch_dyn;
         }
       }
       c->cfg.batch_blocks = best_g;
+      c->cfg.batch_dyn = best_d;
       if (launch_timing_end(c->scal, c->stream) != hipSuccess)
         return fail(HYDRO_EDEVICE, "timing teardown failed");
       if (rc) return rc;
-      cache[key] = "p:g=" + std::to_string(best_g);
+      cache[key] = "p:g=" + std::to_string(best_g) + ",d=" + std::to_string(best_d);
       dirty = true;
     }
   }

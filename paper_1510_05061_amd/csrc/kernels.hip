@@ -40,6 +40,7 @@ struct SweepArgs {
   int32_t bc_lo, bc_hi;      // boundary conditions along the sweep axis
   int32_t do_cfl;            // fold the CFL maximum of the updated cells
   int32_t q, s;              // column march: columns per tile, segments
+  int32_t dyn;               // persistent launches: 1 ticket scheduling, 0 static
   double grav;               // gravity along the sweep axis
   double gamma;
   DevScalars* scal;
@@ -450,6 +451,16 @@ __device__ __forceinline__ int next_item(unsigned int* ticket, int* slot) {
   return it;
 }
 
+// The i-th work item of this workgroup: pulled from the ticket (dynamic
+// scheduling), or item blockIdx.x + i gridDim.x (static round robin over the
+// largest-first list: no atomic and no barrier per item).
+template <class T>
+__device__ __forceinline__ int item_at(const SweepArgs<T>& a, int i, unsigned int* ticket,
+                                       int* slot) {
+  if (a.dyn) return next_item(ticket, slot);
+  return int(blockIdx.x) + i * int(gridDim.x);
+}
+
 template <class T, int V, bool MULTI, bool PERSIST>
 __global__ void __launch_bounds__(512) sweep_x_kernel(SweepArgs<T> a) {
   __shared__ EdgeSlots<T> slots[MULTI ? 8 : 1];
@@ -462,8 +473,8 @@ __global__ void __launch_bounds__(512) sweep_x_kernel(SweepArgs<T> a) {
     SweepConst<T> k = make_const<T>(dt, a.single.dx[0], a.gamma, a.grav);
     xsweep_tile<T, V, MULTI>(a, a.single, blockIdx.x, k, slots, smax, bad);
   } else {
-    for (;;) {
-      const int it = next_item(&a.scal->tickets[0], &item_s);
+    for (int i = 0;; ++i) {
+      const int it = item_at(a, i, &a.scal->tickets[0], &item_s);
       if (it >= a.nitems) break;
       const WorkItem w = a.items[it];
       const PatchDev P = a.patches[w.patch];
@@ -789,8 +800,8 @@ __global__ void __launch_bounds__(512) sweep_xm_kernel(SweepArgs<T> a) {
     xmarch_pencils<T, V>(a, P, int(blockIdx.x) * nw + wave, int(gridDim.x) * nw,
                          P.n[1] * P.n[2], k, id, lines[wave], smax, bad);
   } else {
-    for (;;) {
-      const int it = next_item(&a.scal->tickets[0], &item_s);
+    for (int i = 0;; ++i) {
+      const int it = item_at(a, i, &a.scal->tickets[0], &item_s);
       if (it >= a.nitems) break;
       const WorkItem w = a.items[it];
       const PatchDev P = a.patches[w.patch];
@@ -809,9 +820,30 @@ __global__ void __launch_bounds__(512) sweep_xm_kernel(SweepArgs<T> a) {
 // Column marches along y (AXIS 1) or z (AXIS 2)
 // --------------------------------------------------------------------------
 
-template <class T, int AXIS>
+// Cell c of a column, as (a) the owning segment's index s' = c / L and
+// (b) that segment's edge slot: its first two cells are slots 0, 1 and its
+// last two slots 2, 3 (a segment shorter than four cells repeats cells).
+// Only cells within two of a segment edge are ever looked up.
+__device__ __forceinline__ int edge_slot(int c, int L, int N, int* seg) {
+  const int s = c / L;
+  const int ja = s * L, jb = min(N, ja + L);
+  *seg = s;
+  return c - ja < 2 ? c - ja : 2 + (c - (jb - 2));
+}
+
+// One tile of a column march: Q consecutive columns, each cut into S
+// segments of L cells owned by S threads.
+//  * LDSH = true (halos through LDS): every thread loads its segment's
+//    first two and last two cells once, writes their primitives to an LDS
+//    table (tab: [segment][slot][component][Q]) and keeps the last two
+//    states in registers for the end of its march; after the barrier each
+//    thread reads its four halo cells from the table.  Every cell is then
+//    read from memory once.
+//  * LDSH = false: each thread loads its halo cells from memory before the
+//    barrier (the owner loads them again when it marches there).
+template <class T, int AXIS, bool LDSH>
 __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t tile,
-                              const SweepConst<T>& k, T& smax, bool& bad) {
+                              const SweepConst<T>& k, T* tab, T& smax, bool& bad) {
   constexpr int TA = AXIS == 1 ? 2 : 1;   // the other transverse axis
   const int N = P.n[AXIS];
   const int nx = P.n[0];
@@ -830,28 +862,62 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
   uint32_t cb = 0;  // byte offset of the column's cell 0 inside a plane
   if (act) cb = uint32_t(((col % nx) + (col / nx) * st) * int64_t(sizeof(T)));
 
-  // halo cells ja-2, ja-1, jb, jb+1 with the boundary conditions applied
+  // halo cell h (ja-2, ja-1, jb, jb+1) after the boundary conditions: the
+  // interior cell it copies, and whether it is mirrored
+  auto halo_cell = [&](int h, bool& mir) {
+    int j = h < 2 ? ja - 2 + h : jb + h - 2;
+    mir = false;
+    if (j < 0) {
+      if (a.bc_lo == kBcPeriodic) j += N;
+      else if (a.bc_lo == kBcOutflow) j = 0;
+      else { j = -j - 1; mir = true; }
+    } else if (j >= N) {
+      if (a.bc_hi == kBcPeriodic) j -= N;
+      else if (a.bc_hi == kBcOutflow) j = N - 1;
+      else { j = 2 * N - 1 - j; mir = true; }
+    }
+    return j;
+  };
+
   Prim<T> H[4];
-  if (act) {
+  Cons<T> E[4];  // LDSH: own cells ja, ja+1, jb-2, jb-1 (clamped into the segment)
+  if (LDSH) {
+    if (act) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = e < 2 ? min(ja + e, jb - 1) : max(jb - 4 + e, ja);
+        E[e] = pl.load(cb + uint32_t(c) * sd);
+        const Prim<T> W = to_prim(E[e], k);
+        T* t = tab + ((seg * 4 + e) * 5) * Q + l;
+        t[0] = W.r; t[Q] = W.u; t[2 * Q] = W.t1; t[3 * Q] = W.t2; t[4 * Q] = W.p;
+      }
+    }
+    __syncthreads();  // the table is full, and no cell has been written
+    if (!act) return;
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
-      int j = h < 2 ? ja - 2 + h : jb + h - 2;
-      bool mir = false;
-      if (j < 0) {
-        if (a.bc_lo == kBcPeriodic) j += N;
-        else if (a.bc_lo == kBcOutflow) j = 0;
-        else { j = -j - 1; mir = true; }
-      } else if (j >= N) {
-        if (a.bc_hi == kBcPeriodic) j -= N;
-        else if (a.bc_hi == kBcOutflow) j = N - 1;
-        else { j = 2 * N - 1 - j; mir = true; }
-      }
-      Prim<T> W = to_prim(pl.load(cb + uint32_t(j) * sd), k);
+      bool mir;
+      int os;
+      const int e = edge_slot(halo_cell(h, mir), L, N, &os);
+      const T* t = tab + ((os * 4 + e) * 5) * Q + l;
+      Prim<T> W;
+      W.r = t[0]; W.u = t[Q]; W.t1 = t[2 * Q]; W.t2 = t[3 * Q]; W.p = t[4 * Q];
+      W.ri = rcp(W.r);  // as to_prim computes it
       H[h] = mir ? mirror(W) : W;
     }
+  } else {
+    if (act) {
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        bool mir;
+        const int j = halo_cell(h, mir);
+        Prim<T> W = to_prim(pl.load(cb + uint32_t(j) * sd), k);
+        H[h] = mir ? mirror(W) : W;
+      }
+    }
+    __syncthreads();  // every halo copy is taken before any cell is written
+    if (!act) return;
   }
-  __syncthreads();  // every halo copy is taken before any cell is written
-  if (!act) return;
 
   T id[3];
   inv_widths<T>(P, id);
@@ -862,17 +928,17 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
   // the flux on its right face, which needs the face states of cell j+1,
   // hence the primitives of j, j+1, j+2.  The body of the main loop has no
   // branch on the position: cell j+3 is prefetched one iteration ahead,
-  // clamped to the last own cell (an own cell ahead of the march, not yet
-  // written), and the last two cells, whose j+2 neighbour is a halo copy,
+  // clamped to the last cell read from memory (an own cell ahead of the
+  // march, not yet written); with LDSH the last two cells come from
+  // registers; the last two updates, whose j+2 neighbour is a halo copy,
   // run in the tail loop.
   uint32_t b = cb + uint32_t(ja) * sd;    // byte offset of cell j
-  const uint32_t blast = cb + uint32_t(jb - 1) * sd;
-  Cons<T> U0 = pl.load(b);
+  Cons<T> U0 = LDSH ? E[0] : pl.load(b);
   Prim<T> W0 = to_prim(U0, k);
   Cons<T> U1;
   Prim<T> W1;
   if (ja + 1 < jb) {
-    U1 = pl.load(b + sd);
+    U1 = LDSH ? E[1] : pl.load(b + sd);
     W1 = to_prim(U1, k);
   } else {
     W1 = H[2];
@@ -883,29 +949,39 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
   Cons<T> Fl = hllc(WpPrev, WmC, k);
   WpPrev = WpC;
 
+  // one step of the march with cell j+2 in U2
+  auto advance = [&](const Cons<T>& U2) {
+    const Prim<T> W2 = to_prim(U2, k);
+    Prim<T> Wm1, Wp1;
+    face_states(W0, W1, W2, k, k.kick, Wm1, Wp1);  // cell j+1
+    const Cons<T> Fr = hllc(WpPrev, Wm1, k);
+    update(U0, Fl, Fr, k);
+    pl.store(b, U0);
+    if (a.do_cfl) smax = fmax_(smax, cell_speed<T, AXIS>(U0, k, id, bad));
+    b += sd;
+    U0 = U1;
+    U1 = U2;
+    W0 = W1;
+    W1 = W2;
+    WpPrev = Wp1;
+    Fl = Fr;
+  };
+
   int j = ja;
-  if (jb - ja > 2) {
+  const int jm = LDSH ? jb - 4 : jb - 2;  // main loop: cell j+2 read from memory
+  if (jm > ja) {
+    const uint32_t bmax = cb + uint32_t(jm + 1) * sd;  // last cell read from memory
     Cons<T> Upre = pl.load(b + 2 * sd);
 #pragma unroll 2
-    for (; j < jb - 2; ++j) {
+    for (; j < jm; ++j) {
       const Cons<T> U2 = Upre;
       const uint32_t bn = b + 3 * sd;
-      Upre = pl.load(bn < blast ? bn : blast);
-      const Prim<T> W2 = to_prim(U2, k);
-      Prim<T> Wm1, Wp1;
-      face_states(W0, W1, W2, k, k.kick, Wm1, Wp1);  // cell j+1
-      const Cons<T> Fr = hllc(WpPrev, Wm1, k);
-      update(U0, Fl, Fr, k);
-      pl.store(b, U0);
-      if (a.do_cfl) smax = fmax_(smax, cell_speed<T, AXIS>(U0, k, id, bad));
-      b += sd;
-      U0 = U1;
-      U1 = U2;
-      W0 = W1;
-      W1 = W2;
-      WpPrev = Wp1;
-      Fl = Fr;
+      Upre = pl.load(bn < bmax ? bn : bmax);
+      advance(U2);
     }
+  }
+  if (LDSH) {
+    for (; j < jb - 2; ++j) advance(j + 2 == jb - 2 ? E[2] : E[3]);
   }
   for (; j < jb; ++j) {
     const Prim<T> W2 = (j + 2 == jb) ? H[2] : H[3];
@@ -924,24 +1000,28 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
   }
 }
 
-template <class T, int AXIS, bool PERSIST>
-__global__ void __launch_bounds__(512) sweep_col_kernel(SweepArgs<T> a) {
+// FP32: at least 4 waves per SIMD (at most 128 VGPRs), the occupancy the
+// march needs to cover memory latency.
+template <class T, int AXIS, bool PERSIST, bool LDSH>
+__global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 1) sweep_col_kernel(SweepArgs<T> a) {
   __shared__ int item_s;
   __shared__ T red[8];
+  extern __shared__ __align__(16) unsigned char dyn_lds[];  // halo table (LDSH)
+  T* tab = reinterpret_cast<T*>(dyn_lds);
   const double dt = a.scal->dt;
   T smax = T(0);
   bool bad = false;
   if (!PERSIST) {
     SweepConst<T> k = make_const<T>(dt, a.single.dx[AXIS], a.gamma, a.grav);
-    colsweep_tile<T, AXIS>(a, a.single, blockIdx.x, k, smax, bad);
+    colsweep_tile<T, AXIS, LDSH>(a, a.single, blockIdx.x, k, tab, smax, bad);
   } else {
-    for (;;) {
-      const int it = next_item(&a.scal->tickets[AXIS], &item_s);
+    for (int i = 0;; ++i) {
+      const int it = item_at(a, i, &a.scal->tickets[AXIS], &item_s);
       if (it >= a.nitems) break;
       const WorkItem w = a.items[it];
       const PatchDev P = a.patches[w.patch];
       SweepConst<T> k = make_const<T>(dt, P.dx[AXIS], a.gamma, a.grav);
-      colsweep_tile<T, AXIS>(a, P, w.tile, k, smax, bad);
+      colsweep_tile<T, AXIS, LDSH>(a, P, w.tile, k, tab, smax, bad);
       __syncthreads();
     }
   }
@@ -1143,6 +1223,7 @@ struct LaunchSweep {
   int32_t persistent;
   int32_t fp64;
   int32_t xmode;       // x sweep: kXPacked, kXMulti or kXMarch
+  int32_t dyn;         // persistent: ticket (1) or static round-robin (0) items
 };
 
 template <class T>
@@ -1158,6 +1239,7 @@ static SweepArgs<T> to_args(const LaunchSweep& L) {
   a.do_cfl = L.do_cfl;
   a.q = L.cfg.q;
   a.s = L.cfg.s;
+  a.dyn = L.dyn;
   a.grav = L.grav;
   a.gamma = L.gamma;
   a.scal = L.scal;
@@ -1226,11 +1308,23 @@ static hipError_t launch_x(const LaunchSweep& L, hipStream_t st, dim3 grid) {
 
 template <class T, bool PERSIST>
 static hipError_t launch_col(const LaunchSweep& L, hipStream_t st, dim3 grid) {
-  dim3 block(L.cfg.q * L.cfg.s);
-  if (L.axis == 1)
-    hipLaunchKernelGGL((sweep_col_kernel<T, 1, PERSIST>), grid, block, 0, st, to_args<T>(L));
-  else
-    hipLaunchKernelGGL((sweep_col_kernel<T, 2, PERSIST>), grid, block, 0, st, to_args<T>(L));
+  const int threads = L.cfg.q * L.cfg.s;
+  dim3 block(threads);
+  // halos through LDS while the table (20 values per thread) fits in 64 KiB
+  const size_t tab = size_t(threads) * 20 * sizeof(T);
+  const bool ldsh = tab <= 65536;
+  const SweepArgs<T> a = to_args<T>(L);
+  if (L.axis == 1) {
+    if (ldsh)
+      hipLaunchKernelGGL((sweep_col_kernel<T, 1, PERSIST, true>), grid, block, tab, st, a);
+    else
+      hipLaunchKernelGGL((sweep_col_kernel<T, 1, PERSIST, false>), grid, block, 0, st, a);
+  } else {
+    if (ldsh)
+      hipLaunchKernelGGL((sweep_col_kernel<T, 2, PERSIST, true>), grid, block, tab, st, a);
+    else
+      hipLaunchKernelGGL((sweep_col_kernel<T, 2, PERSIST, false>), grid, block, 0, st, a);
+  }
   return hipGetLastError();
 }
 
