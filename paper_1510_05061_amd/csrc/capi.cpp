@@ -153,6 +153,7 @@ PatchDev make_patch(const int32_t n[3], int32_t ng, const double dx[3], int64_t 
   for (int a = 0; a < 3; ++a) {
     P.n[a] = n[a];
     P.dx[a] = dx[a];
+    P.idx[a] = n[a] > 1 ? 1.0 / dx[a] : 0.0;
   }
   return P;
 }
@@ -183,6 +184,7 @@ bool patch_from(const hydro_patch& p, PatchDev* out, int64_t* len) {
   for (int a = 0; a < 3; ++a) {
     P.n[a] = n[a];
     P.dx[a] = dx[a];
+    P.idx[a] = n[a] > 1 ? 1.0 / dx[a] : 0.0;
   }
   *out = P;
   *len = 5 * pp;
@@ -660,7 +662,7 @@ int choose_config(hydro_ctx* c) {
       return fail(HYDRO_EDEVICE, "timing setup failed");
     double best = 1e30;
     SweepCfg best_cfg = c->cfg.ax[axis];
-    const int reps = 5;
+    const int reps = 10;
     for (const SweepCfg& s : candidates(c, axis)) {
       c->cfg.ax[axis] = s;
       if (c->batch && (rc = rebuild_items(c)) != HYDRO_OK) break;
@@ -713,7 +715,7 @@ int choose_config(hydro_ctx* c) {
         for (int axis = 0; axis < 3 && rc == HYDRO_OK; ++axis) {
           if (!c->active[axis] || c->nitems[axis] == 0) continue;
           double ms = 0.0;
-          rc = time_sweep(c, axis, 3, &ms);
+          rc = time_sweep(c, axis, 5, &ms);
           tot += ms;
         }
         if (rc) break;

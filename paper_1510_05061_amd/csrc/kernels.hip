@@ -176,7 +176,7 @@ __device__ __forceinline__ T cell_speed(const Cons<T>& S, const SweepConst<T>& k
 
 template <class T>
 __device__ __forceinline__ void inv_widths(const PatchDev& P, T id[3]) {
-  for (int a = 0; a < 3; ++a) id[a] = P.n[a] > 1 ? T(1.0 / P.dx[a]) : T(0);
+  for (int a = 0; a < 3; ++a) id[a] = T(P.idx[a]);  // 1/dx, made on the host
 }
 
 template <class T>
@@ -300,9 +300,10 @@ __device__ void xsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t ti
   act = act && q < npen;
   const Planes<T, 0> pl(a.pool, P);
   uint32_t off = 0;  // byte offset of this lane's first cell inside a plane
-  if (act)
-    off = uint32_t(((q % P.n[1]) * int64_t(P.sy) + (q / P.n[1]) * int64_t(P.sz) + gl * V) *
-                   int64_t(sizeof(T)));
+  if (act) {
+    const unsigned z = unsigned(q) / unsigned(P.n[1]), y = unsigned(q) - z * unsigned(P.n[1]);
+    off = uint32_t((int64_t(y) * P.sy + int64_t(z) * P.sz + gl * V) * int64_t(sizeof(T)));
+  }
 
   Cons<T> U[V];
   Prim<T> W[V];
@@ -847,20 +848,23 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
   constexpr int TA = AXIS == 1 ? 2 : 1;   // the other transverse axis
   const int N = P.n[AXIS];
   const int nx = P.n[0];
-  const int64_t ncol = int64_t(nx) * P.n[TA];
+  const int ncol = nx * P.n[TA];
   const uint32_t sd = uint32_t((AXIS == 1 ? P.sy : P.sz) * int64_t(sizeof(T)));  // bytes
   const int64_t st = AXIS == 1 ? P.sz : P.sy;
   const int Q = a.q, S = a.s;
   const int l = threadIdx.x % Q;
   const int seg = threadIdx.x / Q;
-  const int64_t col = tile * Q + l;
+  const int col = int(tile) * Q + l;
   const int L = (N + S - 1) / S;
   const int ja = seg * L;
   const int jb = min(N, ja + L);
   const bool act = (seg < S) && (col < ncol) && (ja < jb);
   const Planes<T, AXIS> pl(a.pool, P);
   uint32_t cb = 0;  // byte offset of the column's cell 0 inside a plane
-  if (act) cb = uint32_t(((col % nx) + (col / nx) * st) * int64_t(sizeof(T)));
+  if (act) {
+    const unsigned t = unsigned(col) / unsigned(nx), x = unsigned(col) - t * unsigned(nx);
+    cb = uint32_t((int64_t(x) + int64_t(t) * st) * int64_t(sizeof(T)));
+  }
 
   // halo cell h (ja-2, ja-1, jb, jb+1) after the boundary conditions: the
   // interior cell it copies, and whether it is mirrored
@@ -927,7 +931,7 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
   // March: cell j is updated from the flux on its left face (carried) and
   // the flux on its right face, which needs the face states of cell j+1,
   // hence the primitives of j, j+1, j+2.  The body of the main loop has no
-  // branch on the position: cell j+3 is prefetched one iteration ahead,
+  // branch on the position: cells are prefetched three iterations ahead,
   // clamped to the last cell read from memory (an own cell ahead of the
   // march, not yet written); with LDSH the last two cells come from
   // registers; the last two updates, whose j+2 neighbour is a halo copy,
@@ -970,13 +974,25 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
   int j = ja;
   const int jm = LDSH ? jb - 4 : jb - 2;  // main loop: cell j+2 read from memory
   if (jm > ja) {
-    const uint32_t bmax = cb + uint32_t(jm + 1) * sd;  // last cell read from memory
-    Cons<T> Upre = pl.load(b + 2 * sd);
-#pragma unroll 2
+    // cells j+3, j+4, j+5 are in flight while cell j is updated (clamped to
+    // the last cell read from memory)
+    const uint64_t bmax = cb + uint64_t(jm + 1) * sd;
+    auto ahead = [&](int d) {
+      const uint64_t o = uint64_t(b) + uint64_t(d) * sd;
+      return pl.load(uint32_t(o < bmax ? o : bmax));
+    };
+    Cons<T> P0 = pl.load(b + 2 * sd);  // cell ja+2 <= jm+1
+    Cons<T> P1 = ahead(3);
+    Cons<T> P2 = ahead(4);
+    // unrolled 6 times: the carried cells and the prefetch queue rotate
+    // with period 3 and the carried face state and flux with period 2, so
+    // the copies vanish
+#pragma unroll 6
     for (; j < jm; ++j) {
-      const Cons<T> U2 = Upre;
-      const uint32_t bn = b + 3 * sd;
-      Upre = pl.load(bn < bmax ? bn : bmax);
+      const Cons<T> U2 = P0;
+      P0 = P1;
+      P1 = P2;
+      P2 = ahead(5);
       advance(U2);
     }
   }

@@ -19,6 +19,7 @@ struct PatchDev {
   int32_t n[3];    // interior cells along x, y, z
   int32_t sy, sz;  // element strides along y and z
   double dx[3];    // cell widths
+  double idx[3];   // 1 / dx per axis, 0 along an axis with one cell
 };
 
 // Device-resident scalars at the start of the workspace.
