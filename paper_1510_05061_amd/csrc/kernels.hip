@@ -821,6 +821,12 @@ __global__ void __launch_bounds__(512) sweep_xm_kernel(SweepArgs<T> a) {
 // Column marches along y (AXIS 1) or z (AXIS 2)
 // --------------------------------------------------------------------------
 
+// Column march prefetch depth (cells in flight ahead of the update).
+#ifndef HYDRO_MARCH_AHEAD
+#define HYDRO_MARCH_AHEAD 3
+#endif
+constexpr int kMarchAhead = HYDRO_MARCH_AHEAD;
+
 // Cell c of a column, as (a) the owning segment's index s' = c / L and
 // (b) that segment's edge slot: its first two cells are slots 0, 1 and its
 // last two slots 2, 3 (a segment shorter than four cells repeats cells).
@@ -974,25 +980,27 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
   int j = ja;
   const int jm = LDSH ? jb - 4 : jb - 2;  // main loop: cell j+2 read from memory
   if (jm > ja) {
-    // cells j+3, j+4, j+5 are in flight while cell j is updated (clamped to
+    // cells j+3 .. j+2+D are in flight while cell j is updated (clamped to
     // the last cell read from memory)
+    constexpr int D = kMarchAhead;
     const uint64_t bmax = cb + uint64_t(jm + 1) * sd;
     auto ahead = [&](int d) {
       const uint64_t o = uint64_t(b) + uint64_t(d) * sd;
       return pl.load(uint32_t(o < bmax ? o : bmax));
     };
-    Cons<T> P0 = pl.load(b + 2 * sd);  // cell ja+2 <= jm+1
-    Cons<T> P1 = ahead(3);
-    Cons<T> P2 = ahead(4);
-    // unrolled 6 times: the carried cells and the prefetch queue rotate
-    // with period 3 and the carried face state and flux with period 2, so
-    // the copies vanish
+    Cons<T> Pq[D];
+    Pq[0] = pl.load(b + 2 * sd);  // cell ja+2 <= jm+1
+#pragma unroll
+    for (int d = 1; d < D; ++d) Pq[d] = ahead(2 + d);
+    // unrolled 6 times: the carried cells rotate with period 3, the carried
+    // face state and flux with period 2 and the prefetch queue with period
+    // D (a divisor of 6), so the copies vanish
 #pragma unroll 6
     for (; j < jm; ++j) {
-      const Cons<T> U2 = P0;
-      P0 = P1;
-      P1 = P2;
-      P2 = ahead(5);
+      const Cons<T> U2 = Pq[0];
+#pragma unroll
+      for (int d = 0; d + 1 < D; ++d) Pq[d] = Pq[d + 1];
+      Pq[D - 1] = ahead(2 + D);
       advance(U2);
     }
   }
@@ -1016,10 +1024,15 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
   }
 }
 
-// FP32: at least 4 waves per SIMD (at most 128 VGPRs), the occupancy the
-// march needs to cover memory latency.
+// FP32: at least kColWaves waves per SIMD, the occupancy the march needs to
+// cover memory latency.
+#ifndef HYDRO_COL_WAVES
+#define HYDRO_COL_WAVES 4
+#endif
+constexpr int kColWaves = HYDRO_COL_WAVES;
 template <class T, int AXIS, bool PERSIST, bool LDSH>
-__global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 1) sweep_col_kernel(SweepArgs<T> a) {
+__global__ void __launch_bounds__(512, sizeof(T) == 4 ? kColWaves : 1)
+    sweep_col_kernel(SweepArgs<T> a) {
   __shared__ int item_s;
   __shared__ T red[8];
   extern __shared__ __align__(16) unsigned char dyn_lds[];  // halo table (LDSH)

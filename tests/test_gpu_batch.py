@@ -67,14 +67,19 @@ def test_batch_dt_is_min_over_patches():
 def test_batch_fp64_matches_oracle_and_keeps_ghosts(pad_rows):
     say(f"batch oracle pad {pad_rows}")
     b, dev, pool, patches = _batch(8, hydro.FP64, pad_rows=pad_rows)
-    dt = b.cfl_dt()
+    # one global dt: the smallest oracle CFL dt over the patches
+    interiors, params = [], []
+    for p in patches:
+        ng = p[4]
+        interiors.append(np.ascontiguousarray(ic.patch_view(pool, p)[:, ng:-ng, ng:-ng, ng:-ng]))
+        params.append(oracle.make_params(interiors[-1].shape[1:], p[5], GAMMA, 0.8))
+    dt = min(oracle.cfl_dt(prm, u) for prm, u in zip(params, interiors))
+    assert abs(b.cfl_dt() - dt) <= 1e-14 * dt
     b.step(dt)
     out = host(dev)
-    for p in patches:
-        o, n, _, _, ng = p[:5]
+    for p, interior, prm in zip(patches, interiors, params):
+        ng = p[4]
         full = ic.patch_view(pool, p)
-        interior = np.ascontiguousarray(full[:, ng:-ng, ng:-ng, ng:-ng])
-        prm = oracle.make_params(interior.shape[1:], p[5], GAMMA, 0.8)
         ref = interior.copy()
         oracle.step(prm, ref, dt, 0)
         got_full = ic.patch_view(out, p)
