@@ -25,6 +25,8 @@ Prints ONE JSON line.  Fields beyond the driver's contract:
                  arithmetic (hydro_stream_ceiling): the memory-only ceiling;
   cpu_baseline   the FP64 CPU oracle timed on the host (OpenMP threads) over
                  a bounded sample of the workload;
+  per_patch_loop batch only: the same patches stepped one grid at a time
+                 (FP32 and FP64), and the batch's speedup over that loop;
   accuracy       fp32_vs_fp64_gpu: per-variable L1 (and max-norm) error of
                  the FP32 path against the FP64 path after the workload's
                  step count, both on the GPU with the same dt sequence;
@@ -74,12 +76,17 @@ def parse():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="kh")
     ap.add_argument("--n", type=int, default=0, help="grid edge (kh, turb)")
     ap.add_argument("--patches", type=int, default=4096)
+    ap.add_argument("--pad-rows", type=int, default=32,
+                    help="batch: interior rows start on multiples of this many elements "
+                         "(0: rows of n + 8 stored back to back)")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0,
                     help="oracle steps of the CPU sample (0: about 4e8 zone-updates)")
     ap.add_argument("--skip-accuracy", action="store_true")
+    ap.add_argument("--skip-loop", action="store_true",
+                    help="batch: skip the per-patch loop baseline")
     ap.add_argument("--accuracy-steps", type=int, default=0,
                     help="steps of the FP32-vs-FP64 comparison (0: the workload's own)")
     ap.add_argument("--no-tune", action="store_true")
@@ -159,7 +166,7 @@ def build_obj(W, prec, args, torch, hydro, flags=None):
         patches = None
     else:
         # interior rows start on 128-byte boundaries (ghost layers kept)
-        pool, patches = ic.batch_pool(W["specs"], ng=4, dtype=dtype, pad_rows=32)
+        pool, patches = ic.batch_pool(W["specs"], ng=4, dtype=dtype, pad_rows=args.pad_rows)
         U = torch.from_numpy(pool).to("cuda:0")
         del pool
         obj = hydro.Batch(U, patches, 5.0 / 3.0, flags=flags)
@@ -185,6 +192,34 @@ def run_gpu(W, prec, args, torch, hydro):
     del U
     torch.cuda.empty_cache()
     return sec, kms, cfg, state_bytes, stream
+
+
+def per_patch_loop(W, prec, npatch, steps, torch, hydro):
+    """The batch's first `npatch` patches stepped one by one, each as its own
+    grid (hydro_step, one graph launch per patch per step): the baseline that
+    the single persistent launch per sweep replaces.  Returns zone-updates/s."""
+    import numpy as np
+    import hydro_ic as ic
+    dtype = np.float32 if prec == hydro.FP32 else np.float64
+    grids, zones = [], 0
+    for s in W["specs"][:npatch]:
+        U = torch.from_numpy(ic.kh_patch(s).astype(dtype)).to("cuda:0")
+        grids.append(hydro.Grid(U, 1.0 / s.n, 5.0 / 3.0, flags=hydro.FLAG_NO_TUNE))
+        zones += s.n ** 3
+    for g in grids:          # warm-up step (first-step CFL, graph upload)
+        g.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for g in grids:
+            g.step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    for g in grids:
+        g.close()
+    del grids
+    torch.cuda.empty_cache()
+    return zones / sec
 
 
 # --------------------------------------------------------------------------
@@ -482,6 +517,17 @@ def main():
         "stream_ceiling": stream32,
         "kernel_source": kernel_source_hash(),
     }
+    if W["kind"] == "batch" and not args.skip_loop:
+        npl = min(len(W["specs"]), 1024)
+        log(f"per-patch loop over {npl} patches")
+        l32 = per_patch_loop(W, hydro.FP32, npl, 5, torch, hydro)
+        l64 = per_patch_loop(W, hydro.FP64, npl, 5, torch, hydro)
+        out["per_patch_loop"] = {
+            "sample": f"the first {npl} patches, each its own grid stepped by hydro_step "
+                      "(one graph launch per patch per step), 5 timed steps",
+            "fp32": l32, "fp64": l64, "unit": "zone-updates/s",
+            "batch_fp32_over_loop_fp32": value / l32,
+            "batch_fp32_over_loop_fp64": value / l64}
     acc = {}
     if not args.skip_accuracy:
         steps = args.accuracy_steps or ACCURACY_STEPS[args.workload]
