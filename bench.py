@@ -18,7 +18,10 @@ Prints ONE JSON line.  Fields beyond the driver's contract:
                  8 TB/s HBM peak; `traffic` from rocprofv3 counters when the
                  committed counter summary matches the current kernel source;
   step_roofline  the whole step against the same peak (120 B per FP32
-                 zone-update);
+                 zone-update, the three-sweep method's algorithmic bytes);
+                 when a batch step fuses the x and y sweeps it moves 80 B per
+                 zone-update, given as hbm_bytes_per_zone_update and
+                 hbm_achieved;
   fp64           the FP64 path on the same workload and the FP32 speedup;
   copy_ceiling   a plain device copy of the same bytes, for context;
   stream_ceiling an in-place read+write pass over the state with no
@@ -485,9 +488,13 @@ def main():
     bytes_launch = zones * 40                      # 5 words read + 5 written, FP32
     achieved = bytes_launch / (k32[dom] * 1e-3) / 1e9 if k32[dom] > 0 else 0.0
     pers = W["kind"] == "batch"
+    fused = "f=1" in cfg32
     names = {0: "sweep_x_kernel<float>", 1: "sweep_col_kernel<float,1>",
              2: "sweep_col_kernel<float,2>"}
+    if fused:   # one launch does the x and y sweeps of every patch z-plane
+        names[0] = "sweep_plane_kernel<float> (x and y sweeps fused)"
     kname = names[dom] + (" (persistent)" if pers else "")
+    hbm_per_zu = 80 if fused else 120
     traffic = counter_traffic(args.workload, names[dom], "fp32")
     out = {
         "metric": METRIC,
@@ -510,7 +517,9 @@ def main():
                      "kernel": kname, "mean_ms": k32[dom], "bytes_per_launch": bytes_launch},
         "step_roofline": {"achieved": value * 120 / 1e9, "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": value * 120 / (HBM_PEAK_GBS * 1e9),
-                          "bytes_per_zone_update": 120},
+                          "bytes_per_zone_update": 120,
+                          "hbm_bytes_per_zone_update": hbm_per_zu,
+                          "hbm_achieved": value * hbm_per_zu / 1e9},
         "kernel_ms": {"x": k32[0], "y": k32[1], "z": k32[2]},
         "fp64": fp64,
         "copy_ceiling": copy_ceiling(torch, bytes32),

@@ -21,60 +21,8 @@
 #include <vector>
 
 #include "../../include/hydro.h"
+#include "launch.hpp"
 #include "layout.hpp"
-
-namespace hydro {
-// kernels.hip
-struct LaunchSweep {
-  void* pool;
-  const PatchDev* patches;
-  PatchDev single;
-  const WorkItem* items;
-  int32_t nitems;
-  int32_t nblocks;
-  int32_t axis;
-  int32_t bc_lo, bc_hi;
-  int32_t do_cfl;
-  double grav;
-  double gamma;
-  DevScalars* scal;
-  SweepCfg cfg;
-  int32_t persistent;
-  int32_t fp64;
-  int32_t xmode;
-  int32_t dyn;
-};
-struct LaunchReduce {
-  const void* pool;
-  const PatchDev* patches;
-  PatchDev single;
-  int32_t npatch;
-  int32_t chunks;
-  double gamma;
-  double grav[3];
-  DevScalars* scal;
-  double* partials;
-  int32_t fp64;
-};
-hipError_t launch_sweep(const LaunchSweep& L, hipStream_t st);
-hipError_t launch_cfl(const LaunchReduce& L, hipStream_t st);
-hipError_t launch_totals(const LaunchReduce& L, hipStream_t st);
-hipError_t launch_finish_step(DevScalars* s, hipStream_t st);
-hipError_t launch_finish_cfl(DevScalars* s, hipStream_t st);
-hipError_t launch_init_scalars(DevScalars* s, double cfl, double t, double t_end,
-                               hipStream_t st);
-hipError_t launch_set_dt(DevScalars* s, double dt, hipStream_t st);
-hipError_t launch_set_time(DevScalars* s, double t, double t_end, hipStream_t st);
-hipError_t launch_clear_error(DevScalars* s, hipStream_t st);
-hipError_t launch_timing_begin(DevScalars* s, hipStream_t st);
-hipError_t launch_timing_end(DevScalars* s, hipStream_t st);
-hipError_t launch_reset_tickets(DevScalars* s, hipStream_t st);
-hipError_t launch_stream(void* p, int64_t bytes, hipStream_t st);
-int64_t x_tiles(const PatchDev& P, const SweepCfg& c);
-int64_t col_tiles(const PatchDev& P, int axis, const SweepCfg& c);
-bool x_wave_ok(int n, int v);
-int64_t x_pencils_per_tile(const PatchDev& P, const SweepCfg& c);
-}  // namespace hydro
 
 using namespace hydro;
 
@@ -199,6 +147,8 @@ struct Config {
   SweepCfg ax[3];
   int32_t batch_blocks = 0;  // persistent launches: workgroups
   int32_t batch_dyn = 1;     // persistent launches: ticket (1) or static (0) items
+  int32_t batch_fuse = 0;    // batches: x and y sweeps fused per patch z-plane (1)
+  SweepCfg plane{kLaneRunKind, 4, 512, 0, 0, 0};  // fused plane kernel: V, threads
 };
 
 // A lane run of v cells is loaded and stored as one vector access, so every
@@ -269,7 +219,10 @@ std::string cfg_text(const Config& cf) {
   }
   o << ";y:q=" << cf.ax[1].q << ",s=" << cf.ax[1].s;
   o << ";z:q=" << cf.ax[2].q << ",s=" << cf.ax[2].s;
-  if (cf.batch_blocks) o << ";p:g=" << cf.batch_blocks << ",d=" << cf.batch_dyn;
+  if (cf.batch_blocks) {
+    o << ";p:g=" << cf.batch_blocks << ",d=" << cf.batch_dyn << ",f=" << cf.batch_fuse;
+    if (cf.batch_fuse) o << ";w:v=" << cf.plane.v << ",b=" << cf.plane.block;
+  }
   return o.str();
 }
 
@@ -306,9 +259,14 @@ bool parse_cfg(const std::string& text, Config& cf) {
         if (k == "q") c.q = int(v);
         else if (k == "s") c.s = int(v);
         else return false;
+      } else if (ax == 'w') {
+        if (k == "v") cf.plane.v = int(v);
+        else if (k == "b") cf.plane.block = int(v);
+        else return false;
       } else if (ax == 'p') {
         if (k == "g") cf.batch_blocks = int(v);
         else if (k == "d" && (v == 0 || v == 1)) cf.batch_dyn = int(v);
+        else if (k == "f" && (v == 0 || v == 1)) cf.batch_fuse = int(v);
         else return false;
       } else {
         return false;
@@ -397,8 +355,8 @@ struct hydro_ctx {
   int32_t npatch = 0;
   std::vector<PatchDev> patches;
   PatchDev* d_patches = nullptr;
-  WorkItem* d_items[3] = {nullptr, nullptr, nullptr};
-  int32_t nitems[3] = {0, 0, 0};
+  WorkItem* d_items[4] = {nullptr, nullptr, nullptr, nullptr};  // x, y, z, planes
+  int32_t nitems[4] = {0, 0, 0, 0};
   int64_t max_patch_cells = 0;
   // run state
   int64_t step = 0;
@@ -473,27 +431,89 @@ LaunchReduce reduce_launch(const hydro_ctx* c) {
   return L;
 }
 
-// The three sweeps of a step in Strang order, the last folding the CFL max,
-// then the step bookkeeping.
-hipError_t enqueue_step_kernels(const hydro_ctx* c, int parity, hipStream_t st) {
-  if (!items_current(c)) return hipErrorInvalidValue;
+// Fused plane sweeps apply to a batch whose x and y axes are both active
+// and whose every z-plane fits the kernel: an LDS share of at most
+// kPlaneLdsBytes, lane runs of the x configuration's V along x and along y
+// (n / V <= 64), and rows aligned for its vector copies.
+bool plane_ok(const hydro_ctx* c, const Config& cf) {
+  if (!c->batch || !c->active[0] || !c->active[1]) return false;
+  const int v = cf.plane.v;
+  if (v != 1 && v != 2 && v != 4) return false;
+  if (cf.plane.block < 64 || cf.plane.block > kMaxBlock || cf.plane.block % 64) return false;
+  const int esz = c->fp64 ? 8 : 4;
+  const int a = std::min(v, 16 / esz);
+  for (auto& P : c->patches) {
+    if (P.n[0] == 1 || P.n[1] == 1) return false;
+    if (P.n[0] % v || P.n[1] % v || P.n[0] / v > 64 || P.n[1] / v > 64) return false;
+    if (plane_lds_bytes(P, c->fp64) == 0) return false;
+    if (P.base0 % a || P.sy % a || P.sz % a || P.plane % a) return false;
+  }
+  return true;
+}
+
+// The fused x and y sweeps of every patch z-plane (x first on even steps).
+LaunchSweep plane_launch(const hydro_ctx* c, bool xfirst, int do_cfl) {
+  LaunchSweep L = sweep_launch(c, 0, do_cfl);
+  L.plane = xfirst ? kPlaneXY : kPlaneYX;
+  L.cfg = c->cfg.plane;
+  L.items = c->d_items[3];
+  L.nitems = c->nitems[3];
+  L.bc_lo_y = c->desc.bc[2];
+  L.bc_hi_y = c->desc.bc[3];
+  L.grav_y = c->desc.grav[1];
+  int lds = 0;
+  for (auto& P : c->patches) lds = std::max(lds, plane_lds_bytes(P, c->fp64));
+  L.plane_lds = lds;
+  return L;
+}
+
+// One launch of a step and the profile slot it reports in (0: x, or x and y
+// fused; 1: y; 2: z).
+struct StepOp {
+  LaunchSweep L;
+  int slot;
+};
+
+// The launches of a step in Strang order (x, y, z on even steps, z, y, x on
+// odd ones; with fusion the x and y sweeps are one launch), the last folding
+// the CFL maximum.
+std::vector<StepOp> step_ops(const hydro_ctx* c, int parity) {
   static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
   const int* order = parity ? odd : even;
-  int last = -1;
-  for (int i = 0; i < 3; ++i)
-    if (c->active[order[i]]) last = i;
+  const bool fuse = c->cfg.batch_fuse && c->nitems[3] > 0 && plane_ok(c, c->cfg);
+  std::vector<int> seq;  // axes; -1 for the fused plane sweeps
   for (int i = 0; i < 3; ++i) {
-    int ax = order[i];
-    if (!c->active[ax]) continue;
-    if (c->batch && c->nitems[ax] == 0) continue;
-    hipError_t e = launch_sweep(sweep_launch(c, ax, i == last ? 1 : 0), st);
+    const int ax = order[i];
+    if (!c->active[ax] || (c->batch && c->nitems[ax] == 0)) continue;
+    if (fuse && ax < 2) {
+      if (std::find(seq.begin(), seq.end(), -1) == seq.end()) seq.push_back(-1);
+      continue;
+    }
+    seq.push_back(ax);
+  }
+  std::vector<StepOp> ops;
+  for (size_t i = 0; i < seq.size(); ++i) {
+    const int cfl = i + 1 == seq.size() ? 1 : 0;
+    if (seq[i] < 0)
+      ops.push_back(StepOp{plane_launch(c, parity == 0, cfl), 0});
+    else
+      ops.push_back(StepOp{sweep_launch(c, seq[i], cfl), seq[i]});
+  }
+  return ops;
+}
+
+// The launches of a step, then the step bookkeeping.
+hipError_t enqueue_step_kernels(const hydro_ctx* c, int parity, hipStream_t st) {
+  if (!items_current(c)) return hipErrorInvalidValue;
+  const std::vector<StepOp> ops = step_ops(c, parity);
+  for (const StepOp& op : ops) {
+    hipError_t e = launch_sweep(op.L, st);
     if (e != hipSuccess) return e;
   }
-  if (last < 0) {
+  if (ops.empty()) {
     // nothing to sweep: still fold the CFL of the state so dt stays defined
     hipError_t e = launch_cfl(reduce_launch(c), st);
     if (e != hipSuccess) return e;
-    return launch_finish_step(c->scal, st);
   }
   return launch_finish_step(c->scal, st);
 }
@@ -533,12 +553,16 @@ int capture_graphs(hydro_ctx* c) {
 }
 
 // Mean ms per launch of one sweep (dt on the device must already be 0).
+int time_launch(hydro_ctx* c, const LaunchSweep& L, int reps, double* ms);
 int time_sweep(hydro_ctx* c, int axis, int reps, double* ms) {
+  return time_launch(c, sweep_launch(c, axis, 1), reps, ms);
+}
+
+int time_launch(hydro_ctx* c, const LaunchSweep& L, int reps, double* ms) {
   if (!items_current(c)) return fail(HYDRO_ESTATE, "batch work lists out of date");
   hipEvent_t a, b;
   HIP_TRY(hipEventCreate(&a));
   HIP_TRY(hipEventCreate(&b));
-  LaunchSweep L = sweep_launch(c, axis, 1);
   auto run = [&]() -> hipError_t {
     hipError_t e = launch_sweep(L, c->stream);
     if (e == hipSuccess && c->batch) e = launch_reset_tickets(c->scal, c->stream);
@@ -734,6 +758,49 @@ int choose_config(hydro_ctx* c) {
       dirty = true;
     }
   }
+  if (c->batch) {
+    // fuse the x and y sweeps per patch z-plane when that is faster than the
+    // two sweeps (the tuner compares the x-first plane launch with x + y)
+    const std::string key = shape_key(c, 4);
+    auto it = cache.find(key);
+    Config tmp = c->cfg;
+    if (it != cache.end() && parse_cfg(it->second, tmp) && (!tmp.batch_fuse || plane_ok(c, tmp))) {
+      c->cfg.batch_fuse = tmp.batch_fuse;
+      c->cfg.plane = tmp.plane;
+    } else {
+      // the fastest valid plane configuration, then fused or not
+      if (launch_timing_begin(c->scal, c->stream) != hipSuccess)
+        return fail(HYDRO_EDEVICE, "timing setup failed");
+      double tx = 0.0, ty = 0.0, best = 1e30;
+      SweepCfg best_p = c->cfg.plane;
+      int rc = time_sweep(c, 0, 5, &tx);
+      if (rc == HYDRO_OK) rc = time_sweep(c, 1, 5, &ty);
+      for (int v : {1, 2, 4})
+        for (int b : {256, 512}) {
+          if (rc != HYDRO_OK) break;
+          Config trial = c->cfg;
+          trial.plane.v = v;
+          trial.plane.block = b;
+          if (!plane_ok(c, trial)) continue;
+          c->cfg.plane = trial.plane;
+          double tp = 0.0;
+          rc = time_launch(c, plane_launch(c, true, 1), 5, &tp);
+          if (rc == HYDRO_OK && tp < best) {
+            best = tp;
+            best_p = trial.plane;
+          }
+        }
+      if (launch_timing_end(c->scal, c->stream) != hipSuccess)
+        return fail(HYDRO_EDEVICE, "timing teardown failed");
+      if (rc) return rc;
+      c->cfg.plane = best_p;
+      c->cfg.batch_fuse = best < tx + ty ? 1 : 0;
+      std::ostringstream o;
+      o << "p:f=" << c->cfg.batch_fuse << ";w:v=" << best_p.v << ",b=" << best_p.block;
+      cache[key] = o.str();
+      dirty = true;
+    }
+  }
   if (dirty) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto merged = cache_read();
@@ -784,17 +851,17 @@ size_t grid_workspace_bytes(int64_t cells) {
 
 // layout of a batch workspace
 struct BatchLayout {
-  size_t partials, patches, items[3], total;
+  size_t partials, patches, items[4], total;
 };
 
-BatchLayout batch_layout(int32_t n, const int32_t items[3]) {
+BatchLayout batch_layout(int32_t n, const int32_t items[4]) {
   BatchLayout L;
   size_t o = kScalarBytes;
   L.partials = o;
   o += align_up(size_t(n) * kBatchChunks * 6 * sizeof(double), 256);
   L.patches = o;
   o += align_up(size_t(n) * sizeof(PatchDev), 256);
-  for (int a = 0; a < 3; ++a) {
+  for (int a = 0; a < 4; ++a) {
     L.items[a] = o;
     o += align_up(size_t(std::max(1, items[a])) * sizeof(WorkItem), 256);
   }
@@ -803,15 +870,17 @@ BatchLayout batch_layout(int32_t n, const int32_t items[3]) {
 }
 
 // The most tiles a patch list can need per axis under any valid config
-// (x: v = 1 with one pencil per workgroup; columns: 64 columns per tile).
-void max_items(const std::vector<PatchDev>& ps, int32_t out[3]) {
-  int64_t acc[3] = {0, 0, 0};
+// (x: v = 1 with one pencil per workgroup; columns: 64 columns per tile),
+// and its z-planes (fused plane sweeps).
+void max_items(const std::vector<PatchDev>& ps, int32_t out[4]) {
+  int64_t acc[4] = {0, 0, 0, 0};
   for (auto& P : ps) {
     acc[0] += int64_t(P.n[1]) * P.n[2];
     acc[1] += (int64_t(P.n[0]) * P.n[2] + 63) / 64;
     acc[2] += (int64_t(P.n[0]) * P.n[1] + 63) / 64;
+    acc[3] += P.n[2];
   }
-  for (int a = 0; a < 3; ++a) out[a] = int32_t(std::min<int64_t>(acc[a], INT32_MAX));
+  for (int a = 0; a < 4; ++a) out[a] = int32_t(std::min<int64_t>(acc[a], INT32_MAX));
 }
 
 int rebuild_items(hydro_ctx* c) {
@@ -823,11 +892,19 @@ int rebuild_items(hydro_ctx* c) {
     const PatchDev &A = c->patches[a], &B = c->patches[b];
     return int64_t(A.n[0]) * A.n[1] * A.n[2] > int64_t(B.n[0]) * B.n[1] * B.n[2];
   });
-  int32_t cap[3];
+  int32_t cap[4];
   max_items(c->patches, cap);
-  for (int axis = 0; axis < 3; ++axis) {
+  for (int axis = 0; axis < 4; ++axis) {
     std::vector<WorkItem> items;
-    if (c->active[axis]) {
+    if (axis == 3) {
+      // z-planes of the fused plane sweeps (patches with both x and y active)
+      if (c->active[0] && c->active[1])
+        for (int32_t p : order) {
+          const PatchDev& P = c->patches[p];
+          if (P.n[0] == 1 || P.n[1] == 1) continue;
+          for (int32_t z = 0; z < P.n[2]; ++z) items.push_back(WorkItem{p, z});
+        }
+    } else if (c->active[axis]) {
       for (int32_t p : order) {
         const PatchDev& P = c->patches[p];
         if (P.n[axis] == 1) continue;
@@ -948,7 +1025,7 @@ int hydro_batch_workspace_bytes(const hydro_patch* p, int32_t n, const hydro_des
       return fail(HYDRO_EINVAL, "patch " + std::to_string(i) + " has an inconsistent layout");
     ps.push_back(P);
   }
-  int32_t cap[3];
+  int32_t cap[4];
   max_items(ps, cap);
   *bytes = batch_layout(n, cap).total;
   return HYDRO_OK;
@@ -1011,12 +1088,12 @@ int hydro_batch_init(const hydro_patch* p, int32_t n, const hydro_desc* common, 
   c->ws_bytes = ws_bytes;
   c->stream = static_cast<hipStream_t>(stream);
   c->scal = reinterpret_cast<DevScalars*>(c->ws);
-  int32_t cap[3];
+  int32_t cap[4];
   max_items(c->patches, cap);
   BatchLayout L = batch_layout(n, cap);
   c->partials = reinterpret_cast<double*>(c->ws + L.partials);
   c->d_patches = reinterpret_cast<PatchDev*>(c->ws + L.patches);
-  for (int a = 0; a < 3; ++a) c->d_items[a] = reinterpret_cast<WorkItem*>(c->ws + L.items[a]);
+  for (int a = 0; a < 4; ++a) c->d_items[a] = reinterpret_cast<WorkItem*>(c->ws + L.items[a]);
   c->single = c->patches[0];
   // batch defaults: 4 cells per lane where every width allows, whole
   // columns per thread (patches are short), 8 workgroups per CU
@@ -1207,6 +1284,8 @@ int hydro_set_config(hydro_ctx* c, const char* text) {
     if (c->active[a] && !col_cfg_ok(cf.ax[a])) return fail(HYDRO_EINVAL, "invalid column config");
   if (c->batch && (cf.batch_blocks < 1 || cf.batch_blocks > 65536))
     return fail(HYDRO_EINVAL, "invalid persistent grid size");
+  if (cf.batch_fuse && !plane_ok(c, cf))
+    return fail(HYDRO_EINVAL, "fused plane sweeps do not apply to these patches");
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->cfg = cf;
   if (c->batch) {
@@ -1241,34 +1320,29 @@ int hydro_profile_step(hydro_ctx* c, double dt, double ms[4]) {
   } else if (!c->dt_valid) {
     HIP_TRY(launch_cfl(reduce_launch(c), c->stream));
   }
-  static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
-  const int* order = (c->step & 1) ? odd : even;
-  int last = -1;
-  for (int i = 0; i < 3; ++i)
-    if (c->active[order[i]] && (!c->batch || c->nitems[order[i]] > 0)) last = i;
-  hipEvent_t ev[4];
-  for (int i = 0; i < 4; ++i) HIP_TRY(hipEventCreate(&ev[i]));
+  const std::vector<StepOp> ops = step_ops(c, int(c->step & 1));
+  hipEvent_t ev[2];
+  for (int i = 0; i < 2; ++i) HIP_TRY(hipEventCreate(&ev[i]));
   int rc = HYDRO_OK;
-  float t[3] = {0.f, 0.f, 0.f};
-  for (int i = 0; i < 3 && rc == HYDRO_OK; ++i) {
-    const int ax = order[i];
-    if (!c->active[ax] || (c->batch && c->nitems[ax] == 0)) continue;
-    if (hipEventRecord(ev[i], c->stream) != hipSuccess ||
-        launch_sweep(sweep_launch(c, ax, i == last ? 1 : 0), c->stream) != hipSuccess ||
-        hipEventRecord(ev[3], c->stream) != hipSuccess ||
-        hipEventSynchronize(ev[3]) != hipSuccess ||
-        hipEventElapsedTime(&t[i], ev[i], ev[3]) != hipSuccess)
+  for (const StepOp& op : ops) {
+    float t = 0.f;
+    if (hipEventRecord(ev[0], c->stream) != hipSuccess ||
+        launch_sweep(op.L, c->stream) != hipSuccess ||
+        hipEventRecord(ev[1], c->stream) != hipSuccess ||
+        hipEventSynchronize(ev[1]) != hipSuccess ||
+        hipEventElapsedTime(&t, ev[0], ev[1]) != hipSuccess) {
       rc = fail(HYDRO_EDEVICE, "profiled sweep failed");
-    else
-      ms[ax] = double(t[i]);
+      break;
+    }
+    ms[op.slot] = double(t);
   }
   if (rc == HYDRO_OK) {
-    if (last < 0 && launch_cfl(reduce_launch(c), c->stream) != hipSuccess)
+    if (ops.empty() && launch_cfl(reduce_launch(c), c->stream) != hipSuccess)
       rc = fail(HYDRO_EDEVICE, "cfl launch failed");
     else if (launch_finish_step(c->scal, c->stream) != hipSuccess)
       rc = fail(HYDRO_EDEVICE, "step bookkeeping launch failed");
   }
-  for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
+  for (int i = 0; i < 2; ++i) (void)hipEventDestroy(ev[i]);
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(c->stream));
   ms[3] = ms[0] + ms[1] + ms[2];

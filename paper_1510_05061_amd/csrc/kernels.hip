@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include "euler.hpp"
+#include "launch.hpp"
 #include "layout.hpp"
 
 namespace hydro {
@@ -41,7 +42,9 @@ struct SweepArgs {
   int32_t do_cfl;            // fold the CFL maximum of the updated cells
   int32_t q, s;              // column march: columns per tile, segments
   int32_t dyn;               // persistent launches: 1 ticket scheduling, 0 static
-  double grav;               // gravity along the sweep axis
+  int32_t bc_lo_y, bc_hi_y;  // fused plane sweeps: boundary conditions along y
+  double grav;               // gravity along the sweep axis (plane sweeps: x)
+  double grav_y;             // fused plane sweeps: gravity along y
   double gamma;
   DevScalars* scal;
 };
@@ -185,10 +188,13 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
-// Workgroup max of smax folded into the FP64 atomic, and the sticky error.
+// Workgroup max of smax folded into the FP64 atomic, and the sticky error
+// (one atomic per wave that saw a bad cell: a wave vote, no LDS).  `red`
+// holds one T per wave.
 template <class T>
 __device__ void finish_block(DevScalars* scal, T smax, bool bad, bool do_cfl, T* red) {
-  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(&scal->error, kErrState);
+  const bool wbad = __any(bad);
+  if (wbad && (threadIdx.x & 63) == 0) atomicOr(&scal->error, kErrState);
   if (!do_cfl) return;
   T m = wave_max(smax);
   const int wid = threadIdx.x >> 6;
@@ -253,6 +259,82 @@ __device__ __forceinline__ Prim<T> get_prim(const T* s) {
   return W;
 }
 
+// Lane-run update of a pencil that lies inside one wave.  This lane holds V
+// consecutive cells U (rotated frame: mn is the momentum along the sweep
+// axis, AXIS); gl is its place in the pencil (0 .. last), srcL and srcR the
+// lanes holding the neighbouring runs (a periodic pencil's ends are each
+// other's neighbours).  Values cross lanes by shuffles only; the ends of a
+// non-periodic pencil build their ghost cells from their own cells.  U is
+// replaced by the updated state; lanes with `act` fold their cells into the
+// CFL maximum when do_cfl.  Every lane of the wave must call this together.
+template <class T, int V, int AXIS>
+__device__ __forceinline__ void lanerun_update(Cons<T> (&U)[V], int gl, int last, int srcL,
+                                               int srcR, int bc_lo, int bc_hi,
+                                               const SweepConst<T>& k, const T id[3], bool act,
+                                               bool do_cfl, T& smax, bool& bad) {
+  Prim<T> W[V];
+#pragma unroll
+  for (int c = 0; c < V; ++c) W[c] = to_prim(U[c], k);
+
+  Prim<T> Wl = shfl_prim(W[V - 1], srcL);
+  Prim<T> Wr = shfl_prim(W[0], srcR);
+  if (gl == 0 && bc_lo != kBcPeriodic) Wl = bc_lo == kBcOutflow ? W[0] : mirror(W[0]);
+  if (gl == last && bc_hi != kBcPeriodic) Wr = bc_hi == kBcOutflow ? W[V - 1] : mirror(W[V - 1]);
+
+  Prim<T> Wm[V], Wp[V];
+#pragma unroll
+  for (int c = 0; c < V; ++c) {
+    const Prim<T>& L = c == 0 ? Wl : W[c - 1];
+    const Prim<T>& R = c == V - 1 ? Wr : W[c + 1];
+    face_states(L, W[c], R, k, k.kick, Wm[c], Wp[c]);
+  }
+
+  Prim<T> WpL = shfl_prim(Wp[V - 1], srcL);  // face state W+ of the cell left of the first
+  if (gl == 0 && bc_lo != kBcPeriodic) {
+    // ghost cell -1 with ghost -2 behind it
+    Prim<T> g1, g2, dummy;
+    T kick = k.kick;
+    if (bc_lo == kBcOutflow) {
+      g1 = W[0];
+      g2 = W[0];
+    } else {
+      const Prim<T>& W1 = V >= 2 ? W[V >= 2 ? 1 : 0] : Wr;
+      g1 = mirror(W[0]);
+      g2 = mirror(W1);
+      kick = -k.kick;
+    }
+    face_states(g2, g1, W[0], k, kick, dummy, WpL);
+  }
+
+  Cons<T> F[V];
+#pragma unroll
+  for (int c = 0; c < V; ++c) F[c] = hllc(c == 0 ? WpL : Wp[c - 1], Wm[c], k);
+
+  Cons<T> FR = shfl_cons(F[0], srcR);  // flux at the right face of the last cell
+  if (gl == last && bc_hi != kBcPeriodic) {
+    // ghost cell N with ghost N+1 beyond it
+    Prim<T> g1, g2, WmR, dummy;
+    T kick = k.kick;
+    if (bc_hi == kBcOutflow) {
+      g1 = W[V - 1];
+      g2 = W[V - 1];
+    } else {
+      const Prim<T>& Wn2 = V >= 2 ? W[V >= 2 ? V - 2 : 0] : Wl;
+      g1 = mirror(W[V - 1]);
+      g2 = mirror(Wn2);
+      kick = -k.kick;
+    }
+    face_states(W[V - 1], g1, g2, k, kick, WmR, dummy);
+    FR = hllc(Wp[V - 1], WmR, k);
+  }
+
+#pragma unroll
+  for (int c = 0; c < V; ++c) {
+    update(U[c], F[c], c == V - 1 ? FR : F[c + 1], k);
+    if (act && do_cfl) smax = fmax_(smax, cell_speed<T, AXIS>(U[c], k, id, bad));
+  }
+}
+
 // One tile of x-pencils.  Lane l of a pencil holds cells [lV, lV+V).  Values
 // cross lane boundaries by cross-lane shuffles.
 //  * MULTI = false: a pencil has at most 64 lanes (n/V <= 64); floor(64/(n/V))
@@ -306,7 +388,6 @@ __device__ void xsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t ti
   }
 
   Cons<T> U[V];
-  Prim<T> W[V];
   {
     T r[V], mn[V], mt1[V], mt2[V], e[V];
     if (act) {
@@ -322,11 +403,34 @@ __device__ void xsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t ti
       }
     }
 #pragma unroll
-    for (int c = 0; c < V; ++c) {
-      U[c] = Cons<T>{r[c], mn[c], mt1[c], mt2[c], e[c]};
-      W[c] = to_prim(U[c], k);
-    }
+    for (int c = 0; c < V; ++c) U[c] = Cons<T>{r[c], mn[c], mt1[c], mt2[c], e[c]};
   }
+
+  if constexpr (!MULTI) {
+    const int srcL = gl > 0 ? l - 1 : l + last;
+    const int srcR = gl < last ? l + 1 : l - last;
+    T id[3];
+    inv_widths<T>(P, id);
+    lanerun_update<T, V, 0>(U, gl, last, srcL, srcR, a.bc_lo, a.bc_hi, k, id, act,
+                            a.do_cfl != 0, smax, bad);
+    if (act) {
+      T r[V], mn[V], mt1[V], mt2[V], e[V];
+#pragma unroll
+      for (int c = 0; c < V; ++c) {
+        r[c] = U[c].r; mn[c] = U[c].mn; mt1[c] = U[c].mt1; mt2[c] = U[c].mt2; e[c] = U[c].e;
+      }
+      store_run<T, V>(pl.r, off, r);
+      store_run<T, V>(pl.n, off, mn);
+      store_run<T, V>(pl.t1, off, mt1);
+      store_run<T, V>(pl.t2, off, mt2);
+      store_run<T, V>(pl.e, off, e);
+    }
+    return;
+  }
+
+  Prim<T> W[V];
+#pragma unroll
+  for (int c = 0; c < V; ++c) W[c] = to_prim(U[c], k);
 
   // lane-level neighbours inside a wave (a wave-edge lane takes the value it
   // gets here only when the neighbour lives in the same wave)
@@ -818,6 +922,159 @@ __global__ void __launch_bounds__(512) sweep_xm_kernel(SweepArgs<T> a) {
 }
 
 // --------------------------------------------------------------------------
+// Fused x and y sweeps of one z-plane of a patch, held in LDS (batches)
+// --------------------------------------------------------------------------
+//
+// A work item is one z-plane of one patch.  The workgroup copies the plane
+// (5 variables) into LDS, runs the first sweep, then the second, on the
+// plane in LDS, and copies it back: one pass over HBM for two sweeps.  The x
+// and y sweeps of a plane touch no other plane, so planes are independent
+// and the update is in place.  Both sweeps are lane runs (lanerun_update):
+// along x a lane holds V consecutive cells of a row, along y V consecutive
+// cells of a column, and a pencil's lanes trade values by shuffles.
+//
+// LDS layout: variable v (physical order) of cell (x, y) at
+//   v nx ny + y nx + ((x + s(y)) mod nx),  s(y) = (V floor(y / V)) mod nx.
+// The rotation keeps every aligned run of V cells of a row contiguous and
+// aligned, and spreads the V-cell column runs that the lanes of one y
+// access read over different LDS banks.
+
+// Largest plane (5 variables) a workgroup holds: two such workgroups fit in
+// the 160 KiB LDS of a CU.
+constexpr int kPlaneLdsBytes = 81920;
+
+template <class T, int V>
+__device__ __forceinline__ int plane_rot(int y, int nx) {
+  return (V * (y / V)) % nx;
+}
+
+// V consecutive elements between memory and LDS (both aligned to the run).
+template <class T, int V>
+__device__ __forceinline__ void copy_run(T* dst, const T* src) {
+  constexpr int H = (sizeof(T) * V <= 16) ? V : int(16 / sizeof(T));
+  typedef T vec __attribute__((ext_vector_type(H)));
+#pragma unroll
+  for (int h = 0; h < V / H; ++h)
+    *reinterpret_cast<vec*>(dst + h * H) = *reinterpret_cast<const vec*>(src + h * H);
+}
+
+// Plane z of patch P between the pool and LDS (LOAD: pool -> LDS).
+template <class T, int V, bool LOAD>
+__device__ void plane_copy(const SweepArgs<T>& a, const PatchDev& P, int z, T* lds) {
+  const int nx = P.n[0], ny = P.n[1];
+  const int nq = nx / V;   // runs per row (<= 64)
+  const int rpw = 64 / nq;  // rows per wave
+  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int r = l / nq, q = l - r * nq;
+  if (r >= rpw) return;
+  T* g = a.pool + P.base0 + int64_t(z) * P.sz;
+  for (int row = wave * rpw + r; row < 5 * ny; row += nw * rpw) {
+    const int v = row / ny, y = row - v * ny;
+    int x = q * V + plane_rot<T, V>(y, nx);
+    if (x >= nx) x -= nx;
+    T* gp = g + int64_t(v) * P.plane + int64_t(y) * P.sy + q * V;
+    T* lp = lds + (v * ny + y) * nx + x;
+    if (LOAD) copy_run<T, V>(lp, gp);
+    else copy_run<T, V>(gp, lp);
+  }
+}
+
+// Reads (write = false) or writes the V cells of a run in LDS: the cells at
+// (x0 + c dx, y0 + c dy), c < V, of the five variables, rotated into the
+// frame of the sweep axis (AXIS 0: x, 1: y).
+template <class T, int V, int AXIS, bool WRITE>
+__device__ __forceinline__ void plane_run(T* lds, int nx, int ny, int x0, int y0,
+                                          Cons<T> (&U)[V]) {
+  constexpr int vn = AXIS == 0 ? 1 : 2, vt1 = AXIS == 0 ? 2 : 1;
+  const int pl = nx * ny;
+  // x0 and y0 are multiples of V, so the whole run shares one rotation and
+  // a run of a row stays contiguous
+  int xr0 = x0 + plane_rot<T, V>(y0, nx);
+  if (xr0 >= nx) xr0 -= nx;
+#pragma unroll
+  for (int c = 0; c < V; ++c) {
+    T* p = AXIS == 0 ? lds + y0 * nx + xr0 + c : lds + (y0 + c) * nx + xr0;
+    if (WRITE) {
+      p[0] = U[c].r; p[vn * pl] = U[c].mn; p[vt1 * pl] = U[c].mt1; p[3 * pl] = U[c].mt2;
+      p[4 * pl] = U[c].e;
+    } else {
+      U[c] = Cons<T>{p[0], p[vn * pl], p[vt1 * pl], p[3 * pl], p[4 * pl]};
+    }
+  }
+}
+
+// One sweep along AXIS (0: x, 1: y) of the plane in LDS.  Pencils of n
+// cells take n/V lanes; a wave holds 64/(n/V) pencils, laid out so that the
+// lanes of equal place in their pencils sit together (for AXIS 1 they then
+// read consecutive x).
+template <class T, int V, int AXIS>
+__device__ void plane_sweep(const SweepArgs<T>& a, const PatchDev& P, T* lds, bool do_cfl,
+                            double dt, T& smax, bool& bad) {
+  const int nx = P.n[0], ny = P.n[1];
+  const int n = AXIS == 0 ? nx : ny;      // pencil length
+  const int m = AXIS == 0 ? ny : nx;      // pencils
+  const int LPP = n / V, ppw = 64 / LPP;  // lanes per pencil, pencils per wave
+  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int gl = l / ppw, col = l - gl * ppw, last = LPP - 1;
+  const int srcL = gl > 0 ? l - ppw : l + last * ppw;
+  const int srcR = gl < last ? l + ppw : l - last * ppw;
+  const SweepConst<T> k = make_const<T>(dt, P.dx[AXIS], a.gamma, AXIS == 0 ? a.grav : a.grav_y);
+  T id[3];
+  inv_widths<T>(P, id);
+  const int blo = AXIS == 0 ? a.bc_lo : a.bc_lo_y, bhi = AXIS == 0 ? a.bc_hi : a.bc_hi_y;
+  for (int m0 = wave * ppw; m0 < m; m0 += nw * ppw) {  // wave-uniform
+    const int pen = m0 + col;
+    const bool act = gl < LPP && pen < m;
+    Cons<T> U[V];
+    if (act) {
+      plane_run<T, V, AXIS, false>(lds, nx, ny, AXIS == 0 ? gl * V : pen,
+                                   AXIS == 0 ? pen : gl * V, U);
+    } else {
+#pragma unroll
+      for (int c = 0; c < V; ++c) U[c] = Cons<T>{T(1), T(0), T(0), T(0), T(1)};
+    }
+    lanerun_update<T, V, AXIS>(U, act ? gl : 0, last, srcL, srcR, blo, bhi, k, id, act, do_cfl,
+                               smax, bad);
+    if (act)
+      plane_run<T, V, AXIS, true>(lds, nx, ny, AXIS == 0 ? gl * V : pen,
+                                  AXIS == 0 ? pen : gl * V, U);
+  }
+}
+
+// XFIRST: x then y (even steps); else y then x (odd steps), where the x
+// sweep is the last of the step and folds the CFL maximum.
+template <class T, int V, bool XFIRST>
+__global__ void __launch_bounds__(512) sweep_plane_kernel(SweepArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  T* lds = reinterpret_cast<T*>(dyn_lds);
+  int* slot = reinterpret_cast<int*>(dyn_lds);  // free between items
+  const double dt = a.scal->dt;
+  T smax = T(0);
+  bool bad = false;
+  for (int i = 0;; ++i) {
+    const int it = item_at(a, i, &a.scal->tickets[3], slot);
+    if (it >= a.nitems) break;
+    const WorkItem w = a.items[it];
+    const PatchDev P = a.patches[w.patch];
+    plane_copy<T, V, true>(a, P, w.tile, lds);
+    __syncthreads();
+    if (XFIRST) {
+      plane_sweep<T, V, 0>(a, P, lds, false, dt, smax, bad);
+      __syncthreads();
+      plane_sweep<T, V, 1>(a, P, lds, a.do_cfl != 0, dt, smax, bad);
+    } else {
+      plane_sweep<T, V, 1>(a, P, lds, false, dt, smax, bad);
+      __syncthreads();
+      plane_sweep<T, V, 0>(a, P, lds, a.do_cfl != 0, dt, smax, bad);
+    }
+    __syncthreads();
+    plane_copy<T, V, false>(a, P, w.tile, lds);
+    __syncthreads();  // the LDS is free again (the next ticket lands in it)
+  }
+  finish_block(a.scal, smax, bad, a.do_cfl != 0, lds);
+}
+
+// --------------------------------------------------------------------------
 // Column marches along y (AXIS 1) or z (AXIS 2)
 // --------------------------------------------------------------------------
 
@@ -1234,26 +1491,6 @@ __global__ void reset_tickets_kernel(DevScalars* s) {
 // Host-side launchers
 // --------------------------------------------------------------------------
 
-struct LaunchSweep {
-  // pool: state or patch pool; patches/items: device tables (persistent)
-  void* pool;
-  const PatchDev* patches;
-  PatchDev single;
-  const WorkItem* items;
-  int32_t nitems;
-  int32_t nblocks;     // persistent: workgroups launched
-  int32_t axis;
-  int32_t bc_lo, bc_hi;
-  int32_t do_cfl;
-  double grav;
-  double gamma;
-  DevScalars* scal;
-  SweepCfg cfg;
-  int32_t persistent;
-  int32_t fp64;
-  int32_t xmode;       // x sweep: kXPacked, kXMulti or kXMarch
-  int32_t dyn;         // persistent: ticket (1) or static round-robin (0) items
-};
 
 template <class T>
 static SweepArgs<T> to_args(const LaunchSweep& L) {
@@ -1269,7 +1506,10 @@ static SweepArgs<T> to_args(const LaunchSweep& L) {
   a.q = L.cfg.q;
   a.s = L.cfg.s;
   a.dyn = L.dyn;
+  a.bc_lo_y = L.bc_lo_y;
+  a.bc_hi_y = L.bc_hi_y;
   a.grav = L.grav;
+  a.grav_y = L.grav_y;
   a.gamma = L.gamma;
   a.scal = L.scal;
   return a;
@@ -1357,8 +1597,34 @@ static hipError_t launch_col(const LaunchSweep& L, hipStream_t st, dim3 grid) {
   return hipGetLastError();
 }
 
+template <class T, int V>
+static hipError_t launch_plane_v(const LaunchSweep& L, hipStream_t st) {
+  const SweepArgs<T> a = to_args<T>(L);
+  const size_t lds = size_t(L.plane_lds);
+  if (L.plane == kPlaneXY)
+    hipLaunchKernelGGL((sweep_plane_kernel<T, V, true>), dim3(L.nblocks), dim3(L.cfg.block),
+                       lds, st, a);
+  else
+    hipLaunchKernelGGL((sweep_plane_kernel<T, V, false>), dim3(L.nblocks), dim3(L.cfg.block),
+                       lds, st, a);
+  return hipGetLastError();
+}
+
+template <class T>
+static hipError_t launch_plane(const LaunchSweep& L, hipStream_t st) {
+  if (L.plane_lds <= 0 || L.plane_lds > kPlaneLdsBytes || !L.persistent)
+    return hipErrorInvalidValue;
+  switch (L.cfg.v) {
+    case 1: return launch_plane_v<T, 1>(L, st);
+    case 2: return launch_plane_v<T, 2>(L, st);
+    case 4: return launch_plane_v<T, 4>(L, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <class T>
 static hipError_t launch_sweep_t(const LaunchSweep& L, hipStream_t st) {
+  if (L.plane != kPlaneNone) return launch_plane<T>(L, st);
   if (L.persistent) {
     dim3 grid(L.nblocks);
     return L.axis == 0 ? launch_x<T, true>(L, st, grid) : launch_col<T, true>(L, st, grid);
@@ -1371,18 +1637,6 @@ hipError_t launch_sweep(const LaunchSweep& L, hipStream_t st) {
   return L.fp64 ? launch_sweep_t<double>(L, st) : launch_sweep_t<float>(L, st);
 }
 
-struct LaunchReduce {
-  const void* pool;
-  const PatchDev* patches;
-  PatchDev single;
-  int32_t npatch;
-  int32_t chunks;
-  double gamma;
-  double grav[3];
-  DevScalars* scal;
-  double* partials;
-  int32_t fp64;
-};
 
 template <class T>
 static ReduceArgs<T> to_rargs(const LaunchReduce& L) {
@@ -1485,5 +1739,12 @@ hipError_t launch_reset_tickets(DevScalars* s, hipStream_t st) {
 // the x sweep packs whole pencils into waves when a pencil has at most 64
 // lanes; longer pencils span several waves of one workgroup
 bool x_wave_ok(int n, int v) { return n % v == 0 && n / v <= 64; }
+
+// LDS bytes of one z-plane of a patch in the fused plane sweeps (0 if it does
+// not fit in a workgroup's share)
+int plane_lds_bytes(const PatchDev& P, int fp64) {
+  const int64_t b = int64_t(5) * P.n[0] * P.n[1] * (fp64 ? 8 : 4);
+  return b <= kPlaneLdsBytes ? int(b) : 0;
+}
 
 }  // namespace hydro

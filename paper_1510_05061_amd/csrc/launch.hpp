@@ -1,0 +1,76 @@
+// launch.hpp -- launch descriptors passed from the host runtime (capi.cpp)
+// to the kernel launchers (kernels.hip), and the launcher entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "layout.hpp"
+
+namespace hydro {
+
+// Which kernel a sweep launch runs.
+constexpr int kPlaneNone = 0;  // one sweep along `axis`
+constexpr int kPlaneXY = 1;    // fused x then y sweeps of patch z-planes
+constexpr int kPlaneYX = 2;    // fused y then x sweeps of patch z-planes
+
+struct LaunchSweep {
+  // pool: state or patch pool; patches/items: device tables (persistent)
+  void* pool;
+  const PatchDev* patches;
+  PatchDev single;
+  const WorkItem* items;
+  int32_t nitems;
+  int32_t nblocks;     // persistent: workgroups launched
+  int32_t axis;
+  int32_t bc_lo, bc_hi;
+  int32_t do_cfl;
+  double grav;
+  double gamma;
+  DevScalars* scal;
+  SweepCfg cfg;
+  int32_t persistent;
+  int32_t fp64;
+  int32_t xmode;       // x sweep: kXPacked, kXMulti or kXMarch
+  int32_t dyn;         // persistent: ticket (1) or static round-robin (0) items
+  int32_t plane;       // kPlaneNone, kPlaneXY or kPlaneYX
+  int32_t plane_lds;   // fused plane sweeps: LDS bytes of the largest plane
+  int32_t bc_lo_y, bc_hi_y;  // fused plane sweeps: boundary conditions along y
+  double grav_y;             // fused plane sweeps: gravity along y
+};
+
+struct LaunchReduce {
+  const void* pool;
+  const PatchDev* patches;
+  PatchDev single;
+  int32_t npatch;
+  int32_t chunks;
+  double gamma;
+  double grav[3];
+  DevScalars* scal;
+  double* partials;
+  int32_t fp64;
+};
+
+hipError_t launch_sweep(const LaunchSweep& L, hipStream_t st);
+hipError_t launch_cfl(const LaunchReduce& L, hipStream_t st);
+hipError_t launch_totals(const LaunchReduce& L, hipStream_t st);
+hipError_t launch_finish_step(DevScalars* s, hipStream_t st);
+hipError_t launch_finish_cfl(DevScalars* s, hipStream_t st);
+hipError_t launch_init_scalars(DevScalars* s, double cfl, double t, double t_end,
+                               hipStream_t st);
+hipError_t launch_set_dt(DevScalars* s, double dt, hipStream_t st);
+hipError_t launch_set_time(DevScalars* s, double t, double t_end, hipStream_t st);
+hipError_t launch_clear_error(DevScalars* s, hipStream_t st);
+hipError_t launch_timing_begin(DevScalars* s, hipStream_t st);
+hipError_t launch_timing_end(DevScalars* s, hipStream_t st);
+hipError_t launch_reset_tickets(DevScalars* s, hipStream_t st);
+hipError_t launch_stream(void* p, int64_t bytes, hipStream_t st);
+int64_t x_tiles(const PatchDev& P, const SweepCfg& c);
+int64_t x_grid(const PatchDev& P, const SweepCfg& c);
+int64_t col_tiles(const PatchDev& P, int axis, const SweepCfg& c);
+bool x_wave_ok(int n, int v);
+int64_t x_pencils_per_tile(const PatchDev& P, const SweepCfg& c);
+int plane_lds_bytes(const PatchDev& P, int fp64);
+
+}  // namespace hydro
