@@ -968,14 +968,32 @@ __device__ void plane_copy(const SweepArgs<T>& a, const PatchDev& P, int z, T* l
   const int r = l / nq, q = l - r * nq;
   if (r >= rpw) return;
   T* g = a.pool + P.base0 + int64_t(z) * P.sz;
-  for (int row = wave * rpw + r; row < 5 * ny; row += nw * rpw) {
+  const int rows = 5 * ny, step = nw * rpw;
+  auto gaddr = [&](int row) {
+    const int v = row / ny, y = row - v * ny;
+    return g + int64_t(v) * P.plane + int64_t(y) * P.sy + q * V;
+  };
+  auto laddr = [&](int row) {
     const int v = row / ny, y = row - v * ny;
     int x = q * V + plane_rot<T, V>(y, nx);
     if (x >= nx) x -= nx;
-    T* gp = g + int64_t(v) * P.plane + int64_t(y) * P.sy + q * V;
-    T* lp = lds + (v * ny + y) * nx + x;
-    if (LOAD) copy_run<T, V>(lp, gp);
-    else copy_run<T, V>(gp, lp);
+    return lds + (v * ny + y) * nx + x;
+  };
+  if (LOAD) {
+    // B runs in flight per lane before the first LDS write
+    constexpr int B = int(128 / (V * sizeof(T))) < 8 ? int(128 / (V * sizeof(T))) : 8;
+    for (int row0 = wave * rpw + r; row0 < rows; row0 += B * step) {
+      T buf[B][V];
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+        if (row0 + b * step < rows) copy_run<T, V>(buf[b], gaddr(row0 + b * step));
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+        if (row0 + b * step < rows) copy_run<T, V>(laddr(row0 + b * step), buf[b]);
+    }
+  } else {
+    for (int row = wave * rpw + r; row < rows; row += step)
+      copy_run<T, V>(gaddr(row), laddr(row));
   }
 }
 
@@ -1003,13 +1021,41 @@ __device__ __forceinline__ void plane_run(T* lds, int nx, int ny, int x0, int y0
   }
 }
 
-// One sweep along AXIS (0: x, 1: y) of the plane in LDS.  Pencils of n
-// cells take n/V lanes; a wave holds 64/(n/V) pencils, laid out so that the
-// lanes of equal place in their pencils sit together (for AXIS 1 they then
-// read consecutive x).
-template <class T, int V, int AXIS>
-__device__ void plane_sweep(const SweepArgs<T>& a, const PatchDev& P, T* lds, bool do_cfl,
-                            double dt, T& smax, bool& bad) {
+// A row run (V cells from (x0, y) of plane z, rotated into the x frame)
+// between registers and the pool.
+template <class T, int V, bool WRITE>
+__device__ __forceinline__ void pool_run(const SweepArgs<T>& a, const PatchDev& P, int z, int x0,
+                                         int y, Cons<T> (&U)[V]) {
+  T* g = a.pool + P.base0 + int64_t(z) * P.sz + int64_t(y) * P.sy + x0;
+  T* p[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) p[v] = g + int64_t(v) * P.plane;
+  T r[V], mn[V], mt1[V], mt2[V], e[V];
+  if (WRITE) {
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+      r[c] = U[c].r; mn[c] = U[c].mn; mt1[c] = U[c].mt1; mt2[c] = U[c].mt2; e[c] = U[c].e;
+    }
+    copy_run<T, V>(p[0], r); copy_run<T, V>(p[1], mn); copy_run<T, V>(p[2], mt1);
+    copy_run<T, V>(p[3], mt2); copy_run<T, V>(p[4], e);
+  } else {
+    copy_run<T, V>(r, p[0]); copy_run<T, V>(mn, p[1]); copy_run<T, V>(mt1, p[2]);
+    copy_run<T, V>(mt2, p[3]); copy_run<T, V>(e, p[4]);
+#pragma unroll
+    for (int c = 0; c < V; ++c) U[c] = Cons<T>{r[c], mn[c], mt1[c], mt2[c], e[c]};
+  }
+}
+
+// One sweep along AXIS (0: x, 1: y) of the plane.  Pencils of n cells take
+// n/V lanes; a wave holds 64/(n/V) pencils, laid out so that the lanes of
+// equal place in their pencils sit together (for AXIS 1 they then read
+// consecutive x).  The input comes from LDS, or for the x sweep of an
+// x-first step straight from the pool (GSRC); the result goes to LDS, or
+// for the x sweep of a y-first step straight to the pool (GDST): a row run
+// is a coalesced vector access, so those two sweeps skip a copy through LDS.
+template <class T, int V, int AXIS, bool GSRC, bool GDST>
+__device__ void plane_sweep(const SweepArgs<T>& a, const PatchDev& P, int z, T* lds,
+                            bool do_cfl, double dt, T& smax, bool& bad) {
   const int nx = P.n[0], ny = P.n[1];
   const int n = AXIS == 0 ? nx : ny;      // pencil length
   const int m = AXIS == 0 ? ny : nx;      // pencils
@@ -1022,22 +1068,37 @@ __device__ void plane_sweep(const SweepArgs<T>& a, const PatchDev& P, T* lds, bo
   T id[3];
   inv_widths<T>(P, id);
   const int blo = AXIS == 0 ? a.bc_lo : a.bc_lo_y, bhi = AXIS == 0 ? a.bc_hi : a.bc_hi_y;
-  for (int m0 = wave * ppw; m0 < m; m0 += nw * ppw) {  // wave-uniform
+  const int mstep = nw * ppw;
+  Cons<T> Un[V];  // GSRC: the next pass's runs, loaded one pass ahead
+  if (GSRC && gl < LPP && wave * ppw + col < m)
+    pool_run<T, V, false>(a, P, z, gl * V, wave * ppw + col, Un);
+  for (int m0 = wave * ppw; m0 < m; m0 += mstep) {  // wave-uniform
     const int pen = m0 + col;
     const bool act = gl < LPP && pen < m;
     Cons<T> U[V];
     if (act) {
-      plane_run<T, V, AXIS, false>(lds, nx, ny, AXIS == 0 ? gl * V : pen,
-                                   AXIS == 0 ? pen : gl * V, U);
+      if (GSRC) {
+#pragma unroll
+        for (int c = 0; c < V; ++c) U[c] = Un[c];
+      } else {
+        plane_run<T, V, AXIS, false>(lds, nx, ny, AXIS == 0 ? gl * V : pen,
+                                     AXIS == 0 ? pen : gl * V, U);
+      }
     } else {
 #pragma unroll
       for (int c = 0; c < V; ++c) U[c] = Cons<T>{T(1), T(0), T(0), T(0), T(1)};
     }
+    if (GSRC && gl < LPP && pen + mstep < m)
+      pool_run<T, V, false>(a, P, z, gl * V, pen + mstep, Un);
     lanerun_update<T, V, AXIS>(U, act ? gl : 0, last, srcL, srcR, blo, bhi, k, id, act, do_cfl,
                                smax, bad);
-    if (act)
-      plane_run<T, V, AXIS, true>(lds, nx, ny, AXIS == 0 ? gl * V : pen,
-                                  AXIS == 0 ? pen : gl * V, U);
+    if (act) {
+      if (GDST)
+        pool_run<T, V, true>(a, P, z, gl * V, pen, U);
+      else
+        plane_run<T, V, AXIS, true>(lds, nx, ny, AXIS == 0 ? gl * V : pen,
+                                    AXIS == 0 ? pen : gl * V, U);
+    }
   }
 }
 
@@ -1056,19 +1117,22 @@ __global__ void __launch_bounds__(512) sweep_plane_kernel(SweepArgs<T> a) {
     if (it >= a.nitems) break;
     const WorkItem w = a.items[it];
     const PatchDev P = a.patches[w.patch];
-    plane_copy<T, V, true>(a, P, w.tile, lds);
-    __syncthreads();
+    const int z = w.tile;
     if (XFIRST) {
-      plane_sweep<T, V, 0>(a, P, lds, false, dt, smax, bad);
+      // x: pool -> registers -> LDS; y: LDS -> LDS; then LDS -> pool
+      plane_sweep<T, V, 0, true, false>(a, P, z, lds, false, dt, smax, bad);
       __syncthreads();
-      plane_sweep<T, V, 1>(a, P, lds, a.do_cfl != 0, dt, smax, bad);
+      plane_sweep<T, V, 1, false, false>(a, P, z, lds, a.do_cfl != 0, dt, smax, bad);
+      __syncthreads();
+      plane_copy<T, V, false>(a, P, z, lds);
     } else {
-      plane_sweep<T, V, 1>(a, P, lds, false, dt, smax, bad);
+      // pool -> LDS; y: LDS -> LDS; x: LDS -> registers -> pool
+      plane_copy<T, V, true>(a, P, z, lds);
       __syncthreads();
-      plane_sweep<T, V, 0>(a, P, lds, a.do_cfl != 0, dt, smax, bad);
+      plane_sweep<T, V, 1, false, false>(a, P, z, lds, false, dt, smax, bad);
+      __syncthreads();
+      plane_sweep<T, V, 0, false, true>(a, P, z, lds, a.do_cfl != 0, dt, smax, bad);
     }
-    __syncthreads();
-    plane_copy<T, V, false>(a, P, w.tile, lds);
     __syncthreads();  // the LDS is free again (the next ticket lands in it)
   }
   finish_block(a.scal, smax, bad, a.do_cfl != 0, lds);
