@@ -213,9 +213,23 @@ int hydro_state_changed(hydro_ctx* c);
 int hydro_get_error(hydro_ctx* c);
 int hydro_clear_error(hydro_ctx* c);
 
-/* Kernel configuration as text, "x:v=4,b=256;y:q=64,s=4;z:q=64,s=4"
- * (hydro_get_config writes at most len bytes including the NUL).
- * hydro_set_config replaces it (validated; graphs are re-captured). */
+/* Kernel configuration as text, parts separated by ';' (any subset may be
+ * given to hydro_set_config; the rest keeps its value):
+ *   x:v=V,b=B[,m=1[,g=G]]  x sweep: V cells per lane (1, 2, 4), B threads
+ *                          per workgroup; m=1 selects the chunked march (one
+ *                          pencil per wave), G caps its grid (0: none);
+ *                          without m the lane-run sweep;
+ *   y:q=Q,s=S  z:q=Q,s=S   column marches: Q columns per tile, S segments;
+ *   p:g=G,d=D,f=F          batch: G persistent workgroups, D = 1 ticket or
+ *                          0 round-robin work items, F = 1 fuses the x and
+ *                          y sweeps per patch z-plane;
+ *   w:v=V,b=B              batch, fused plane kernel: V cells per lane, B
+ *                          threads per workgroup.
+ * hydro_get_config writes at most len bytes including the NUL.
+ * hydro_set_config replaces it (validated: HYDRO_EINVAL for a shape the
+ * kernels do not support, e.g. f=1 when a patch plane exceeds 80 KiB; work
+ * lists are rebuilt and graphs re-captured).  Every valid configuration
+ * gives the same bits. */
 int hydro_get_config(hydro_ctx* c, char* buf, size_t len);
 int hydro_set_config(hydro_ctx* c, const char* cfg);
 
@@ -228,9 +242,10 @@ int hydro_time_sweeps(hydro_ctx* c, int reps, double ms[3]);
 /* One full split step like hydro_step / hydro_batch_step, launched kernel
  * by kernel with a hipEvent pair around each sweep on the context's stream;
  * ms[0..2] receive the device time of the x, y and z sweep kernels (0 for
- * an inactive axis) and ms[3] their sum.  For measurement; it waits after
- * each sweep, so the step as a whole runs slower than hydro_step.
- * Synchronous. */
+ * an inactive axis; with the fused batch plane sweeps ms[0] holds the fused
+ * x and y launch and ms[1] is 0) and ms[3] their sum.  For measurement; it
+ * waits after each sweep, so the step as a whole runs slower than
+ * hydro_step.  Synchronous. */
 int hydro_profile_step(hydro_ctx* c, double dt, double ms[4]);
 
 /* Mean device time in milliseconds of one in-place streaming pass over the
