@@ -109,7 +109,10 @@ typedef struct hydro_desc {
  *   slab_pitch       elements between z-neighbours (>= row_pitch (ny + 2ng))
  *   plane_pitch      elements between variables    (>= slab_pitch (nz + 2ng))
  *   interior_offset  elements from offset_elems to interior cell (0,0,0)
- *                    (>= ng (1 + row_pitch + slab_pitch)) */
+ *                    (>= ng (1 + row_pitch + slab_pitch))
+ * The kernels address a plane with 32-bit byte offsets: (plane_pitch +
+ * slab_pitch) elements must span less than 4 GiB (HYDRO_EINVAL otherwise);
+ * the same bound holds for the plane of a single grid. */
 typedef struct hydro_patch {
   int64_t offset_elems;
   int32_t nx, ny, nz, ng;

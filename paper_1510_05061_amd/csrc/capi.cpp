@@ -106,6 +106,13 @@ PatchDev make_patch(const int32_t n[3], int32_t ng, const double dx[3], int64_t 
   return P;
 }
 
+// The sweep kernels address a plane with 32-bit byte offsets from its
+// interior origin, up to one z layer past the last cell (a column march's
+// clamped prefetch steps there before clamping).
+bool plane_fits(const PatchDev& P, int64_t esz) {
+  return (P.plane + int64_t(P.sz)) * esz < (int64_t(1) << 32);
+}
+
 // Patch geometry from a hydro_patch (defaults or explicit pitches); returns
 // false on an inconsistent layout.  *len receives the elements the patch
 // spans in the pool (5 planes).
@@ -974,8 +981,7 @@ int hydro_init(const hydro_desc* d, void* state, size_t state_bytes, void* works
   double dx[3] = {d->dx, d->dy, d->dz};
   PatchDev P = make_patch(n, d->ng, dx, 0);
   const int64_t esz = d->precision == HYDRO_FP64 ? 8 : 4;
-  if (P.plane * int64_t(esz) >= (int64_t(1) << 32))
-    return fail(HYDRO_EINVAL, "a state plane must be smaller than 4 GiB");
+  if (!plane_fits(P, esz)) return fail(HYDRO_EINVAL, "a state plane must be smaller than 4 GiB");
   if (state_bytes < size_t(P.plane) * 5 * size_t(esz))
     return fail(HYDRO_EINVAL, "state buffer too small");
   hydro_ctx* c = new (std::nothrow) hydro_ctx();
@@ -1023,6 +1029,8 @@ int hydro_batch_workspace_bytes(const hydro_patch* p, int32_t n, const hydro_des
     int64_t len = 0;
     if (!patch_from(p[i], &P, &len))
       return fail(HYDRO_EINVAL, "patch " + std::to_string(i) + " has an inconsistent layout");
+    if (!plane_fits(P, common->precision == HYDRO_FP64 ? 8 : 4))
+      return fail(HYDRO_EINVAL, "patch " + std::to_string(i) + ": a plane must be smaller than 4 GiB");
     ps.push_back(P);
   }
   int32_t cap[4];

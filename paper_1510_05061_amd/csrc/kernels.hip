@@ -1303,16 +1303,20 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
   if (jm > ja) {
     // cells j+3 .. j+2+D are in flight while cell j is updated (clamped to
     // the last cell read from memory)
+    // The offset of the newest prefetched cell runs in 32 bits, clamped to
+    // bmax, so every access is a scalar base plus one 32-bit offset (the
+    // host keeps every offset up to one layer past a plane's last cell
+    // below 4 GiB, so oa + sd cannot wrap).
     constexpr int D = kMarchAhead;
-    const uint64_t bmax = cb + uint64_t(jm + 1) * sd;
-    auto ahead = [&](int d) {
-      const uint64_t o = uint64_t(b) + uint64_t(d) * sd;
-      return pl.load(uint32_t(o < bmax ? o : bmax));
-    };
+    const uint32_t bmax = cb + uint32_t(jm + 1) * sd;
+    uint32_t oa = b + 2 * sd;  // cell ja+2 <= jm+1
     Cons<T> Pq[D];
-    Pq[0] = pl.load(b + 2 * sd);  // cell ja+2 <= jm+1
+    Pq[0] = pl.load(oa);
 #pragma unroll
-    for (int d = 1; d < D; ++d) Pq[d] = ahead(2 + d);
+    for (int d = 1; d < D; ++d) {
+      oa = min(oa + sd, bmax);
+      Pq[d] = pl.load(oa);
+    }
     // unrolled 6 times: the carried cells rotate with period 3, the carried
     // face state and flux with period 2 and the prefetch queue with period
     // D (a divisor of 6), so the copies vanish
@@ -1321,7 +1325,8 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
       const Cons<T> U2 = Pq[0];
 #pragma unroll
       for (int d = 0; d + 1 < D; ++d) Pq[d] = Pq[d + 1];
-      Pq[D - 1] = ahead(2 + D);
+      oa = min(oa + sd, bmax);  // cell j+2+D, clamped
+      Pq[D - 1] = pl.load(oa);
       advance(U2);
     }
   }
