@@ -591,10 +591,42 @@ int time_launch(hydro_ctx* c, const LaunchSweep& L, int reps, double* ms) {
   return rc == HYDRO_EDEVICE && g_last_error.empty() ? fail(rc, "timing failed") : rc;
 }
 
+// Mean time of one even plus one odd step's sweep launches, run back to back
+// in step order as a captured step runs them (one step pair of warm-up).
+int time_steps(hydro_ctx* c, int reps, double* ms) {
+  if (!items_current(c)) return fail(HYDRO_ESTATE, "batch work lists out of date");
+  std::vector<StepOp> ops = step_ops(c, 0);
+  for (const StepOp& op : step_ops(c, 1)) ops.push_back(op);
+  hipEvent_t a, b;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  auto run = [&]() -> hipError_t {
+    for (const StepOp& op : ops) {
+      hipError_t e = launch_sweep(op.L, c->stream);
+      if (e == hipSuccess && c->batch) e = launch_reset_tickets(c->scal, c->stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  int rc = HYDRO_OK;
+  if (run() != hipSuccess) rc = fail(HYDRO_EDEVICE, "sweep launch failed");
+  if (rc == HYDRO_OK && hipEventRecord(a, c->stream) != hipSuccess) rc = HYDRO_EDEVICE;
+  for (int i = 0; i < reps && rc == HYDRO_OK; ++i)
+    if (run() != hipSuccess) rc = fail(HYDRO_EDEVICE, "sweep launch failed");
+  if (rc == HYDRO_OK && hipEventRecord(b, c->stream) != hipSuccess) rc = HYDRO_EDEVICE;
+  if (rc == HYDRO_OK && hipEventSynchronize(b) != hipSuccess) rc = HYDRO_EDEVICE;
+  float t = 0.f;
+  if (rc == HYDRO_OK && hipEventElapsedTime(&t, a, b) != hipSuccess) rc = HYDRO_EDEVICE;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc == HYDRO_OK) *ms = double(t) / reps;
+  return rc == HYDRO_EDEVICE && g_last_error.empty() ? fail(rc, "timing failed") : rc;
+}
+
 std::string shape_key(const hydro_ctx* c, int axis) {
   std::ostringstream o;
   o << c->arch << ":cu" << c->cu_count << ":" << (c->fp64 ? "fp64" : "fp32") << ":ax" << axis
-    << ":k5";
+    << ":k6";
   if (c->batch) {
     o << ":batch" << c->npatch << "x" << c->max_patch_cells;
   } else {
@@ -649,6 +681,32 @@ std::vector<SweepCfg> candidates(const hydro_ctx* c, int axis) {
 
 int rebuild_items(hydro_ctx* c);
 
+// Index of the fastest of n candidates.  Every candidate is timed once per
+// round, in forward order on even rounds and reverse order on odd ones, and
+// keeps its fastest round: a slow stretch of the device (clock or power
+// transients) then costs every candidate alike instead of whichever ran
+// during it.  apply(i) selects candidate i; measure(&ms) times it.
+// With HYDRO_TUNE_LOG set, every timing goes to stderr as
+// "tune <what> <candidate> <round> <ms>".
+template <class Apply, class Measure>
+int fastest_of(const char* what, int n, int rounds, Apply apply, Measure measure, int* best) {
+  const char* lg = std::getenv("HYDRO_TUNE_LOG");
+  const bool log = lg && *lg && std::strcmp(lg, "0") != 0;
+  std::vector<double> t(size_t(n), 1e30);
+  for (int r = 0; r < rounds; ++r)
+    for (int k = 0; k < n; ++k) {
+      const int i = (r & 1) ? n - 1 - k : k;
+      int rc = apply(i);
+      double ms = 0.0;
+      if (rc == HYDRO_OK) rc = measure(&ms);
+      if (rc != HYDRO_OK) return rc;
+      t[size_t(i)] = std::min(t[size_t(i)], ms);
+      if (log) std::fprintf(stderr, "tune %s %d %d %.4f\n", what, i, r, ms);
+    }
+  *best = int(std::min_element(t.begin(), t.end()) - t.begin());
+  return HYDRO_OK;
+}
+
 // Pick each axis' configuration: HYDRO_FORCE_CONFIG, then the cache, then a
 // timing search (dt = 0 leaves the state unchanged bit for bit).
 int choose_config(hydro_ctx* c) {
@@ -691,18 +749,19 @@ int choose_config(hydro_ctx* c) {
     int rc = HYDRO_OK;
     if (launch_timing_begin(c->scal, c->stream) != hipSuccess)
       return fail(HYDRO_EDEVICE, "timing setup failed");
-    double best = 1e30;
     SweepCfg best_cfg = c->cfg.ax[axis];
-    const int reps = 10;
-    for (const SweepCfg& s : candidates(c, axis)) {
-      c->cfg.ax[axis] = s;
-      if (c->batch && (rc = rebuild_items(c)) != HYDRO_OK) break;
-      double ms = 0;
-      if ((rc = time_sweep(c, axis, reps, &ms)) != HYDRO_OK) break;
-      if (ms < best) {
-        best = ms;
-        best_cfg = s;
-      }
+    const std::vector<SweepCfg> cands = candidates(c, axis);
+    int bi = 0;
+    if (!cands.empty()) {
+      static const char* const names[3] = {"x", "y", "z"};
+      rc = fastest_of(
+          names[axis], int(cands.size()), 2,
+          [&](int i) {
+            c->cfg.ax[axis] = cands[size_t(i)];
+            return c->batch ? rebuild_items(c) : HYDRO_OK;
+          },
+          [&](double* ms) { return time_sweep(c, axis, 5, ms); }, &bi);
+      if (rc == HYDRO_OK) best_cfg = cands[size_t(bi)];
     }
     c->cfg.ax[axis] = best_cfg;
     if (launch_timing_end(c->scal, c->stream) != hipSuccess)
@@ -725,7 +784,63 @@ int choose_config(hydro_ctx* c) {
     dirty = true;
   }
   if (c->batch) {
-    // persistent grid size: workgroups per CU, timed over the three sweeps
+    // fuse the x and y sweeps per patch z-plane when that is faster than the
+    // two sweeps: the fastest valid plane configuration (both Strang orders
+    // timed) against x + y
+    const std::string key = shape_key(c, 4);
+    auto it = cache.find(key);
+    Config tmp = c->cfg;
+    if (it != cache.end() && parse_cfg(it->second, tmp) && (!tmp.batch_fuse || plane_ok(c, tmp))) {
+      c->cfg.batch_fuse = tmp.batch_fuse;
+      c->cfg.plane = tmp.plane;
+    } else {
+      if (launch_timing_begin(c->scal, c->stream) != hipSuccess)
+        return fail(HYDRO_EDEVICE, "timing setup failed");
+      // candidate 0: the separate sweeps (x + y); candidate i > 0: plane
+      // configuration i - 1 (mean of its x-first and y-first launches)
+      std::vector<SweepCfg> planes;
+      for (int v : {1, 2, 4})
+        for (int b : {256, 512}) {
+          Config trial = c->cfg;
+          trial.plane.v = v;
+          trial.plane.block = b;
+          if (plane_ok(c, trial)) planes.push_back(trial.plane);
+        }
+      const SweepCfg keep = c->cfg.plane;
+      int sel = 0, bi = 0;
+      int rc = fastest_of(
+          "plane", int(planes.size()) + 1, 3,
+          [&](int i) {
+            sel = i;
+            if (i > 0) c->cfg.plane = planes[size_t(i - 1)];
+            return HYDRO_OK;
+          },
+          [&](double* ms) {
+            double t0 = 0.0, t1 = 0.0;
+            int r = sel ? time_launch(c, plane_launch(c, true, 1), 5, &t0)
+                        : time_sweep(c, 0, 5, &t0);
+            if (r == HYDRO_OK)
+              r = sel ? time_launch(c, plane_launch(c, false, 1), 5, &t1)
+                      : time_sweep(c, 1, 5, &t1);
+            *ms = sel ? 0.5 * (t0 + t1) : t0 + t1;
+            return r;
+          },
+          &bi);
+      if (launch_timing_end(c->scal, c->stream) != hipSuccess)
+        return fail(HYDRO_EDEVICE, "timing teardown failed");
+      if (rc) return rc;
+      c->cfg.plane = bi > 0 ? planes[size_t(bi - 1)] : keep;
+      c->cfg.batch_fuse = bi > 0 ? 1 : 0;
+      std::ostringstream o;
+      o << "p:f=" << c->cfg.batch_fuse << ";w:v=" << c->cfg.plane.v << ",b="
+        << c->cfg.plane.block;
+      cache[key] = o.str();
+      dirty = true;
+    }
+  }
+  if (c->batch) {
+    // persistent grid size (workgroups per CU) and scheduling, timed over
+    // the launches of one even and one odd step as they will run
     const std::string key = shape_key(c, 3);
     auto it = cache.find(key);
     Config tmp = c->cfg;
@@ -736,75 +851,20 @@ int choose_config(hydro_ctx* c) {
     } else {
       if (launch_timing_begin(c->scal, c->stream) != hipSuccess)
         return fail(HYDRO_EDEVICE, "timing setup failed");
-      double best = 1e30;
-      int best_g = c->cfg.batch_blocks, best_d = c->cfg.batch_dyn;
-      int rc = HYDRO_OK;
-      for (int trial = 0; trial < 8 && rc == HYDRO_OK; ++trial) {
-        c->cfg.batch_blocks = (2 << (trial % 4)) * c->cu_count;  // 2, 4, 8, 16 per CU
-        c->cfg.batch_dyn = trial < 4 ? 1 : 0;
-        double tot = 0.0;
-        for (int axis = 0; axis < 3 && rc == HYDRO_OK; ++axis) {
-          if (!c->active[axis] || c->nitems[axis] == 0) continue;
-          double ms = 0.0;
-          rc = time_sweep(c, axis, 5, &ms);
-          tot += ms;
-        }
-        if (rc) break;
-        if (tot < best) {
-          best = tot;
-          best_g = c->cfg.batch_blocks;
-          best_d = c->cfg.batch_dyn;
-        }
-      }
-      c->cfg.batch_blocks = best_g;
-      c->cfg.batch_dyn = best_d;
+      // 2, 4, 8, 16 workgroups per CU, each with the ticket and round robin
+      auto apply = [&](int i) {
+        c->cfg.batch_blocks = (2 << (i % 4)) * c->cu_count;
+        c->cfg.batch_dyn = i < 4 ? 1 : 0;
+        return HYDRO_OK;
+      };
+      int bi = 0;
+      int rc = fastest_of("grid", 8, 3, apply, [&](double* ms) { return time_steps(c, 2, ms); }, &bi);
+      if (rc == HYDRO_OK) apply(bi);
+      const int best_g = c->cfg.batch_blocks, best_d = c->cfg.batch_dyn;
       if (launch_timing_end(c->scal, c->stream) != hipSuccess)
         return fail(HYDRO_EDEVICE, "timing teardown failed");
       if (rc) return rc;
       cache[key] = "p:g=" + std::to_string(best_g) + ",d=" + std::to_string(best_d);
-      dirty = true;
-    }
-  }
-  if (c->batch) {
-    // fuse the x and y sweeps per patch z-plane when that is faster than the
-    // two sweeps (the tuner compares the x-first plane launch with x + y)
-    const std::string key = shape_key(c, 4);
-    auto it = cache.find(key);
-    Config tmp = c->cfg;
-    if (it != cache.end() && parse_cfg(it->second, tmp) && (!tmp.batch_fuse || plane_ok(c, tmp))) {
-      c->cfg.batch_fuse = tmp.batch_fuse;
-      c->cfg.plane = tmp.plane;
-    } else {
-      // the fastest valid plane configuration, then fused or not
-      if (launch_timing_begin(c->scal, c->stream) != hipSuccess)
-        return fail(HYDRO_EDEVICE, "timing setup failed");
-      double tx = 0.0, ty = 0.0, best = 1e30;
-      SweepCfg best_p = c->cfg.plane;
-      int rc = time_sweep(c, 0, 5, &tx);
-      if (rc == HYDRO_OK) rc = time_sweep(c, 1, 5, &ty);
-      for (int v : {1, 2, 4})
-        for (int b : {256, 512}) {
-          if (rc != HYDRO_OK) break;
-          Config trial = c->cfg;
-          trial.plane.v = v;
-          trial.plane.block = b;
-          if (!plane_ok(c, trial)) continue;
-          c->cfg.plane = trial.plane;
-          double tp = 0.0;
-          rc = time_launch(c, plane_launch(c, true, 1), 5, &tp);
-          if (rc == HYDRO_OK && tp < best) {
-            best = tp;
-            best_p = trial.plane;
-          }
-        }
-      if (launch_timing_end(c->scal, c->stream) != hipSuccess)
-        return fail(HYDRO_EDEVICE, "timing teardown failed");
-      if (rc) return rc;
-      c->cfg.plane = best_p;
-      c->cfg.batch_fuse = best < tx + ty ? 1 : 0;
-      std::ostringstream o;
-      o << "p:f=" << c->cfg.batch_fuse << ";w:v=" << best_p.v << ",b=" << best_p.block;
-      cache[key] = o.str();
       dirty = true;
     }
   }

@@ -933,19 +933,25 @@ __global__ void __launch_bounds__(512) sweep_xm_kernel(SweepArgs<T> a) {
 // along x a lane holds V consecutive cells of a row, along y V consecutive
 // cells of a column, and a pencil's lanes trade values by shuffles.
 //
-// LDS layout: variable v (physical order) of cell (x, y) at
-//   v nx ny + y nx + ((x + s(y)) mod nx),  s(y) = (V floor(y / V)) mod nx.
-// The rotation keeps every aligned run of V cells of a row contiguous and
-// aligned, and spreads the V-cell column runs that the lanes of one y
-// access read over different LDS banks.
+// LDS layout: rows of a fixed pitch of kPlanePitch elements, the five
+// variables of one y interleaved row by row.  Variable v (physical order) of
+// cell (x, y) sits at
+//   (5 y + v) kPlanePitch + ((x + s(y)) mod kPlanePitch),  s(y) = V floor(y / V).
+// With the pitch a compile-time power of two, every access of a run (V cells
+// of the five variables) is one base address plus immediate offsets, and
+// the rotation is a mask.  The rotation keeps every aligned run of V cells
+// of a row contiguous and aligned, and spreads the V-cell column runs that
+// the lanes of one y access read over different LDS banks.
 
-// Largest plane (5 variables) a workgroup holds: two such workgroups fit in
-// the 160 KiB LDS of a CU.
+// Row pitch (elements) of a plane in LDS, and the largest plane a
+// workgroup holds: two such workgroups fit in the 160 KiB LDS of a CU.
+constexpr int kPlanePitch = 64;
 constexpr int kPlaneLdsBytes = 81920;
 
-template <class T, int V>
-__device__ __forceinline__ int plane_rot(int y, int nx) {
-  return (V * (y / V)) % nx;
+// Element offset of run start x (a multiple of V) in LDS row y.
+template <int V>
+__device__ __forceinline__ int plane_col(int x, int y) {
+  return (x + (y & ~(V - 1))) & (kPlanePitch - 1);
 }
 
 // V consecutive elements between memory and LDS (both aligned to the run).
@@ -958,7 +964,8 @@ __device__ __forceinline__ void copy_run(T* dst, const T* src) {
     *reinterpret_cast<vec*>(dst + h * H) = *reinterpret_cast<const vec*>(src + h * H);
 }
 
-// Plane z of patch P between the pool and LDS (LOAD: pool -> LDS).
+// Plane z of patch P between the pool and LDS (LOAD: pool -> LDS).  LDS row
+// r holds variable r mod 5 of y = r / 5.
 template <class T, int V, bool LOAD>
 __device__ void plane_copy(const SweepArgs<T>& a, const PatchDev& P, int z, T* lds) {
   const int nx = P.n[0], ny = P.n[1];
@@ -967,18 +974,13 @@ __device__ void plane_copy(const SweepArgs<T>& a, const PatchDev& P, int z, T* l
   const int l = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int r = l / nq, q = l - r * nq;
   if (r >= rpw) return;
-  T* g = a.pool + P.base0 + int64_t(z) * P.sz;
+  T* g = a.pool + P.base0 + int64_t(z) * P.sz + q * V;
   const int rows = 5 * ny, step = nw * rpw;
   auto gaddr = [&](int row) {
-    const int v = row / ny, y = row - v * ny;
-    return g + int64_t(v) * P.plane + int64_t(y) * P.sy + q * V;
+    const int y = row / 5, v = row - 5 * y;
+    return g + int64_t(v) * P.plane + int64_t(y) * P.sy;
   };
-  auto laddr = [&](int row) {
-    const int v = row / ny, y = row - v * ny;
-    int x = q * V + plane_rot<T, V>(y, nx);
-    if (x >= nx) x -= nx;
-    return lds + (v * ny + y) * nx + x;
-  };
+  auto laddr = [&](int row) { return lds + row * kPlanePitch + plane_col<V>(q * V, row / 5); };
   if (LOAD) {
     // B runs in flight per lane before the first LDS write
     constexpr int B = int(128 / (V * sizeof(T))) < 8 ? int(128 / (V * sizeof(T))) : 8;
@@ -1001,22 +1003,20 @@ __device__ void plane_copy(const SweepArgs<T>& a, const PatchDev& P, int z, T* l
 // (x0 + c dx, y0 + c dy), c < V, of the five variables, rotated into the
 // frame of the sweep axis (AXIS 0: x, 1: y).
 template <class T, int V, int AXIS, bool WRITE>
-__device__ __forceinline__ void plane_run(T* lds, int nx, int ny, int x0, int y0,
-                                          Cons<T> (&U)[V]) {
+__device__ __forceinline__ void plane_run(T* lds, int x0, int y0, Cons<T> (&U)[V]) {
   constexpr int vn = AXIS == 0 ? 1 : 2, vt1 = AXIS == 0 ? 2 : 1;
-  const int pl = nx * ny;
+  constexpr int P = kPlanePitch;
   // x0 and y0 are multiples of V, so the whole run shares one rotation and
   // a run of a row stays contiguous
-  int xr0 = x0 + plane_rot<T, V>(y0, nx);
-  if (xr0 >= nx) xr0 -= nx;
+  T* base = lds + 5 * y0 * P + plane_col<V>(x0, y0);
 #pragma unroll
   for (int c = 0; c < V; ++c) {
-    T* p = AXIS == 0 ? lds + y0 * nx + xr0 + c : lds + (y0 + c) * nx + xr0;
+    T* p = AXIS == 0 ? base + c : base + 5 * c * P;
     if (WRITE) {
-      p[0] = U[c].r; p[vn * pl] = U[c].mn; p[vt1 * pl] = U[c].mt1; p[3 * pl] = U[c].mt2;
-      p[4 * pl] = U[c].e;
+      p[0] = U[c].r; p[vn * P] = U[c].mn; p[vt1 * P] = U[c].mt1; p[3 * P] = U[c].mt2;
+      p[4 * P] = U[c].e;
     } else {
-      U[c] = Cons<T>{p[0], p[vn * pl], p[vt1 * pl], p[3 * pl], p[4 * pl]};
+      U[c] = Cons<T>{p[0], p[vn * P], p[vt1 * P], p[3 * P], p[4 * P]};
     }
   }
 }
@@ -1081,8 +1081,7 @@ __device__ void plane_sweep(const SweepArgs<T>& a, const PatchDev& P, int z, T* 
 #pragma unroll
         for (int c = 0; c < V; ++c) U[c] = Un[c];
       } else {
-        plane_run<T, V, AXIS, false>(lds, nx, ny, AXIS == 0 ? gl * V : pen,
-                                     AXIS == 0 ? pen : gl * V, U);
+        plane_run<T, V, AXIS, false>(lds, AXIS == 0 ? gl * V : pen, AXIS == 0 ? pen : gl * V, U);
       }
     } else {
 #pragma unroll
@@ -1096,8 +1095,7 @@ __device__ void plane_sweep(const SweepArgs<T>& a, const PatchDev& P, int z, T* 
       if (GDST)
         pool_run<T, V, true>(a, P, z, gl * V, pen, U);
       else
-        plane_run<T, V, AXIS, true>(lds, nx, ny, AXIS == 0 ? gl * V : pen,
-                                    AXIS == 0 ? pen : gl * V, U);
+        plane_run<T, V, AXIS, true>(lds, AXIS == 0 ? gl * V : pen, AXIS == 0 ? pen : gl * V, U);
     }
   }
 }
@@ -1812,7 +1810,8 @@ bool x_wave_ok(int n, int v) { return n % v == 0 && n / v <= 64; }
 // LDS bytes of one z-plane of a patch in the fused plane sweeps (0 if it does
 // not fit in a workgroup's share)
 int plane_lds_bytes(const PatchDev& P, int fp64) {
-  const int64_t b = int64_t(5) * P.n[0] * P.n[1] * (fp64 ? 8 : 4);
+  if (P.n[0] > kPlanePitch) return 0;
+  const int64_t b = int64_t(5) * kPlanePitch * P.n[1] * (fp64 ? 8 : 4);
   return b <= kPlaneLdsBytes ? int(b) : 0;
 }
 
