@@ -1,0 +1,103 @@
+"""FP64 oracle of the in-situ diagnostics.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/ and by bench.py's cpu_baseline
+leg, never by the product package.  It shares no code with the HIP path.
+
+The paper names in-situ analysis of the flow as a capability large runs
+need (its discussion of the capabilities needed at the exascale) but fixes
+no diagnostic.  These are the definitions the library implements, written
+out plainly with numpy, on states of shape (5, nz, ny, nx) holding
+(rho, mx, my, mz, E) (interior cells only).
+
+Cell quantities, in FP64 with IEEE operations in exactly this order (an
+FP32 state is widened to FP64 first, which is exact):
+    m2    = mx*mx + my*my + mz*mz
+    ke    = (0.5 * m2) / rho                 kinetic energy density
+    p     = (gamma - 1) * (E - ke)           pressure
+    speed = sqrt(m2) / rho                   |v|
+    mach  = speed / sqrt((gamma * p) / rho)  |v| / c
+
+PDF of a quantity q over [lo, hi) in nbins bins, with w = nbins / (hi - lo):
+    counts[0]          cells with not (q >= lo)  (below range, or NaN)
+    counts[1 + b]      cells with b = floor((q - lo) * w) in [0, nbins)
+    counts[nbins + 1]  the rest (at or above hi)
+The bin decision is taken in FP64 on both sides, so the counts are exact.
+
+Slab profiles along an axis: for every slab i (cells with equal index along
+the axis) the means of rho, p, ke, f and f (1 - f), with the heavy-fluid
+fraction f = clip((rho - rho_lo) / (rho_hi - rho_lo), 0, 1) of a layer
+between densities rho_lo and rho_hi.  From them:
+    mixing width  W     = sum_i 4 <f>_i (1 - <f>_i) dx_axis
+    mixedness     Theta = sum_i <f (1-f)>_i / sum_i <f>_i (1 - <f>_i)
+                          (0 when the denominator is 0)
+"""
+import numpy as np
+
+RHO, PRESSURE, SPEED, MACH = 0, 1, 2, 3
+QUANTITIES = (RHO, PRESSURE, SPEED, MACH)
+PROFILE_FIELDS = ("rho", "p", "ke", "f", "f1mf")
+
+
+def quantity(U, gamma, q):
+    """Cell values of quantity q (RHO, PRESSURE, SPEED, MACH), FP64."""
+    U = np.asarray(U, dtype=np.float64)
+    r, mx, my, mz, e = U[0], U[1], U[2], U[3], U[4]
+    if q == RHO:
+        return r.copy()
+    with np.errstate(all="ignore"):
+        m2 = mx * mx + my * my + mz * mz
+        ke = (0.5 * m2) / r
+        p = (gamma - 1.0) * (e - ke)
+        if q == PRESSURE:
+            return p
+        speed = np.sqrt(m2) / r
+        if q == SPEED:
+            return speed
+        if q == MACH:
+            return speed / np.sqrt((gamma * p) / r)
+    raise ValueError(f"unknown quantity {q}")
+
+
+def pdf(states, gamma, q, lo, hi, nbins):
+    """Counts (int64, nbins + 2) of quantity q over every cell of the given
+    states (one state, or a list of patch interiors)."""
+    if isinstance(states, np.ndarray):
+        states = [states]
+    w = nbins / (hi - lo)
+    counts = np.zeros(nbins + 2, dtype=np.int64)
+    for U in states:
+        v = quantity(U, gamma, q).ravel()
+        below = ~(v >= lo)
+        with np.errstate(invalid="ignore"):
+            t = (v - lo) * w
+        inside = ~below & (t < nbins)
+        b = np.floor(t[inside]).astype(np.int64)
+        counts[0] += int(below.sum())
+        counts[1:nbins + 1] += np.bincount(b, minlength=nbins)[:nbins]
+        counts[nbins + 1] += int((~below & ~inside).sum())
+    return counts
+
+
+def profile(U, gamma, axis, rho_lo, rho_hi):
+    """(n_axis, 5) slab means of (rho, p, ke, f, f (1 - f)) along axis
+    (0: x, 1: y, 2: z)."""
+    U = np.asarray(U, dtype=np.float64)
+    r = U[0]
+    with np.errstate(all="ignore"):
+        m2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3]
+        ke = (0.5 * m2) / r
+        p = (gamma - 1.0) * (U[4] - ke)
+    f = np.clip((r - rho_lo) / (rho_hi - rho_lo), 0.0, 1.0)
+    fields = (r, p, ke, f, f * (1.0 - f))
+    # array axes are (z, y, x): sweep axis a is array axis 2 - a
+    other = tuple(i for i in range(3) if i != 2 - axis)
+    return np.stack([v.mean(axis=other) for v in fields], axis=1)
+
+
+def mixing(prof, dx_axis):
+    """(W, Theta) from a profile as returned by profile()."""
+    fbar = prof[:, 3]
+    den = float(np.sum(fbar * (1.0 - fbar)))
+    width = float(np.sum(4.0 * fbar * (1.0 - fbar)) * dx_axis)
+    theta = float(np.sum(prof[:, 4]) / den) if den > 0.0 else 0.0
+    return width, theta

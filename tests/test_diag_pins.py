@@ -1,0 +1,134 @@
+"""Pins of the diagnostics oracle (CPU): closed forms, exact bin placements
+and invariants that a wrong formula, axis or bin index would break."""
+import numpy as np
+import pytest
+
+import hydro_ic as ic
+from oracle import diagnostics as D
+
+GAMMA = 5.0 / 3.0
+
+
+def cons(rho, vx, vy, vz, p, gamma=GAMMA):
+    """Conserved state from primitives (arrays of one shape)."""
+    rho, vx, vy, vz, p = np.broadcast_arrays(*(np.asarray(a, dtype=np.float64)
+                                               for a in (rho, vx, vy, vz, p)))
+    E = p / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy + vz * vz)
+    return np.stack([rho, rho * vx, rho * vy, rho * vz, E])
+
+
+def at_rest(rho):
+    return cons(rho, 0.0, 0.0, 0.0, 1.0)
+
+
+# ---------------------------------------------------------------- PDF
+
+@pytest.mark.parametrize("nbins,lo,hi", [(8, 0.0, 1.0), (100, -3.0, 5.0), (1, 2.0, 3.0)])
+def test_pdf_bin_centres_one_count_each(nbins, lo, hi):
+    w = (hi - lo) / nbins
+    rho = lo + (np.arange(nbins) + 0.5) * w
+    c = D.pdf(at_rest(rho.reshape(1, 1, nbins)), GAMMA, D.RHO, lo, hi, nbins)
+    assert c[0] == 0 and c[-1] == 0
+    np.testing.assert_array_equal(c[1:-1], np.ones(nbins, np.int64))
+
+
+def test_pdf_edges_and_out_of_range():
+    # power-of-two bin width: every edge lo + i w is exact, so a value on an
+    # edge opens bin i; hi itself and beyond overflow; below lo and NaN
+    # underflow
+    lo, hi, nb = 0.0, 2.0, 8
+    edges = lo + np.arange(nb) * (hi - lo) / nb
+    extra = np.array([hi, 7.0, np.nextafter(lo, -1.0), -5.0, np.nan])
+    rho = np.concatenate([edges, extra]).reshape(1, 1, -1)
+    c = D.pdf(at_rest(rho), GAMMA, D.RHO, lo, hi, nb)
+    np.testing.assert_array_equal(c[1:-1], np.ones(nb, np.int64))
+    assert c[nb + 1] == 2 and c[0] == 3
+
+
+def test_pdf_total_is_the_cell_count():
+    rng = np.random.default_rng(5)
+    U = cons(rng.uniform(0.5, 2.0, (6, 7, 9)), rng.normal(size=(6, 7, 9)),
+             rng.normal(size=(6, 7, 9)), rng.normal(size=(6, 7, 9)),
+             rng.uniform(0.5, 3.0, (6, 7, 9)))
+    for q in D.QUANTITIES:
+        c = D.pdf(U, GAMMA, q, 0.0, 2.0, 13)
+        assert c.sum() == U[0].size
+
+
+def test_pdf_pressure_speed_mach_of_known_states():
+    # rho = 2, p = 2 / gamma, so c = sqrt(gamma p / rho) = 1; |v| = 0.5 (a
+    # 3-4-5 direction); every quantity lands in the bin centred on its value
+    rho, p = 2.0, 2.0 / GAMMA
+    U = cons(np.full((3, 4, 5), rho), 0.3, 0.0, 0.4, p)
+    nb = 10
+    for q, val in ((D.PRESSURE, p), (D.SPEED, 0.5), (D.MACH, 0.5), (D.RHO, rho)):
+        lo = val - 0.05 * nb / 2 - 0.025   # bin 5 is centred on val
+        c = D.pdf(U, GAMMA, q, lo, lo + 0.05 * nb, nb)
+        assert c[1 + 5] == U[0].size, (q, c)
+
+
+def test_pressure_of_the_kh_initial_state():
+    # the KH layer is built with p = 2.5 everywhere
+    spec = ic.batch_specs(1, seed=2, sizes=(16,))[0]
+    U = ic.kh_patch(spec, GAMMA)
+    p = D.quantity(U, GAMMA, D.PRESSURE)
+    np.testing.assert_allclose(p, 2.5, rtol=1e-14)
+
+
+# ------------------------------------------------------------ profiles
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_profile_follows_the_axis(axis):
+    nx, ny, nz = 5, 7, 3
+    idx = np.indices((nz, ny, nx))[2 - axis]          # index along the axis
+    U = at_rest(1.0 + idx)
+    prof = D.profile(U, GAMMA, axis, 0.0, 1.0)
+    n = (nx, ny, nz)[axis]
+    assert prof.shape == (n, 5)
+    np.testing.assert_allclose(prof[:, 0], 1.0 + np.arange(n), rtol=1e-15)
+    for other in {0, 1, 2} - {axis}:
+        m = (nx, ny, nz)[other]
+        np.testing.assert_allclose(D.profile(U, GAMMA, other, 0.0, 1.0)[:, 0],
+                                   np.full(m, 1.0 + (n - 1) / 2.0), rtol=1e-15)
+
+
+def test_profile_pressure_and_kinetic_energy_of_uniform_flow():
+    rho, v, p = 1.5, (0.2, -0.4, 0.1), 0.7
+    U = cons(np.full((4, 3, 2), rho), *v, p)
+    prof = D.profile(U, GAMMA, 2, 1.0, 2.0)
+    ke = 0.5 * rho * sum(c * c for c in v)
+    np.testing.assert_allclose(prof[:, 1], p, rtol=1e-14)
+    np.testing.assert_allclose(prof[:, 2], ke, rtol=1e-14)
+    np.testing.assert_allclose(prof[:, 3], 0.5, rtol=1e-15)      # f of 1.5 in [1, 2]
+    np.testing.assert_allclose(prof[:, 4], 0.25, rtol=1e-15)
+
+
+def test_mixing_width_of_a_sharp_interface_is_zero():
+    n = 8
+    z = np.arange(n).reshape(n, 1, 1)
+    U = at_rest(np.broadcast_to(np.where(z < n // 2, 2.0, 1.0), (n, 3, 4)))
+    W, theta = D.mixing(D.profile(U, GAMMA, 2, 1.0, 2.0), 1.0 / n)
+    assert W == 0.0 and theta == 0.0
+
+
+@pytest.mark.parametrize("n", [4, 10, 33])
+def test_mixing_width_of_a_linear_ramp(n):
+    # f_i = (i + 1/2) / n on slab i, uniform inside the slab:
+    # W = 4 dz sum f (1 - f) = 4 dz (n/6 + 1/(12 n)), Theta = 1
+    dz = 1.0 / n
+    f = (np.arange(n) + 0.5) / n
+    U = at_rest(np.broadcast_to((1.0 + f).reshape(n, 1, 1), (n, 2, 3)))
+    W, theta = D.mixing(D.profile(U, GAMMA, 2, 1.0, 2.0), dz)
+    np.testing.assert_allclose(W, 4.0 * dz * (n / 6.0 + 1.0 / (12.0 * n)), rtol=1e-13)
+    np.testing.assert_allclose(theta, 1.0, rtol=1e-13)
+
+
+def test_unmixed_slabs_have_zero_mixedness():
+    # every slab half heavy, half light: <f> = 1/2 gives W = n dz = 1, but
+    # f (1 - f) = 0 in every cell, so Theta = 0
+    n = 6
+    x = np.arange(4).reshape(1, 1, 4)
+    U = at_rest(np.broadcast_to(np.where(x < 2, 2.0, 1.0), (n, 3, 4)))
+    W, theta = D.mixing(D.profile(U, GAMMA, 2, 1.0, 2.0), 1.0 / n)
+    np.testing.assert_allclose(W, 1.0, rtol=1e-15)
+    assert theta == 0.0
