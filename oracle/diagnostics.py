@@ -30,6 +30,11 @@ between densities rho_lo and rho_hi.  From them:
     mixing width  W     = sum_i 4 <f>_i (1 - <f>_i) dx_axis
     mixedness     Theta = sum_i <f (1-f)>_i / sum_i <f>_i (1 - <f>_i)
                           (0 when the denominator is 0)
+
+Kinetic-energy spectrum along x: the x-line DFTs of the velocity m / rho,
+their power summed over components, averaged over lines and folded onto
+k = 0 .. nx//2 so that the spectrum sums to the mean specific kinetic
+energy (spectrum_x).
 """
 import numpy as np
 
@@ -101,3 +106,23 @@ def mixing(prof, dx_axis):
     width = float(np.sum(4.0 * fbar * (1.0 - fbar)) * dx_axis)
     theta = float(np.sum(prof[:, 4]) / den) if den > 0.0 else 0.0
     return width, theta
+
+
+def spectrum_x(U):
+    """One-dimensional kinetic-energy spectrum along x of the velocity
+    u = m / rho: with P[k] the mean over the x-lines of sum over the three
+    components of |FFT_x(u)[k]|^2 (numpy's unnormalised DFT, N = nx),
+        E[0] = P[0] / (2 N^2),  E[k] = P[k] / N^2 (0 < k < N/2),
+        E[N/2] = P[N/2] / (2 N^2) for even N,
+    k = 0 .. N//2 (the +k and -k halves folded), so that by Parseval
+    sum_k E[k] = (1/2) <|u|^2>, the mean specific kinetic energy."""
+    U = np.asarray(U, dtype=np.float64)
+    n = U.shape[3]
+    with np.errstate(all="ignore"):
+        u = U[1:4] / U[0]
+    P = (np.abs(np.fft.fft(u, axis=-1)) ** 2).sum(axis=0).reshape(-1, n).mean(axis=0)
+    E = P[:n // 2 + 1] / float(n * n)
+    E[0] *= 0.5
+    if n % 2 == 0:
+        E[n // 2] *= 0.5
+    return E

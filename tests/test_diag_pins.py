@@ -132,3 +132,49 @@ def test_unmixed_slabs_have_zero_mixedness():
     W, theta = D.mixing(D.profile(U, GAMMA, 2, 1.0, 2.0), 1.0 / n)
     np.testing.assert_allclose(W, 1.0, rtol=1e-15)
     assert theta == 0.0
+
+
+# ------------------------------------------------------------ spectrum
+
+def _line_state(ux, uy=0.0, uz=0.0, rho=1.0, shape=(3, 4)):
+    """A state whose every x-line carries the velocity profile (ux, uy, uz)."""
+    nx = np.broadcast_shapes(np.shape(ux), np.shape(uy), np.shape(uz), np.shape(rho))[-1]
+    full = shape + (nx,)
+    return cons(*(np.broadcast_to(a, full) for a in (rho, ux, uy, uz, 1.0)))
+
+
+@pytest.mark.parametrize("n", [12, 16, 24, 48])
+def test_spectrum_single_mode(n):
+    # u_x = A cos(2 pi k0 x / n + phi): all the energy A^2 / 4 sits at k0
+    A, k0, phi = 0.7, 3, 0.4
+    x = np.arange(n)
+    E = D.spectrum_x(_line_state(A * np.cos(2 * np.pi * k0 * x / n + phi)))
+    assert E.shape == (n // 2 + 1,)
+    np.testing.assert_allclose(E[k0], A * A / 4.0, rtol=1e-13)
+    rest = np.delete(E, k0)
+    assert np.all(np.abs(rest) < 1e-28)
+
+
+def test_spectrum_uniform_flow_and_nyquist():
+    n = 16
+    E = D.spectrum_x(_line_state(np.full(n, 0.3), 0.4, -1.2))
+    np.testing.assert_allclose(E[0], 0.5 * (0.09 + 0.16 + 1.44), rtol=1e-14)
+    assert np.all(np.abs(E[1:]) < 1e-28)
+    alt = 0.5 * (-1.0) ** np.arange(n)          # the Nyquist mode
+    E = D.spectrum_x(_line_state(0.0, alt))
+    np.testing.assert_allclose(E[n // 2], 0.5 * 0.25, rtol=1e-14)
+    assert np.all(np.abs(E[:n // 2]) < 1e-28)
+
+
+def test_spectrum_parseval_and_velocity_not_momentum():
+    # sum_k E[k] = <|u|^2> / 2 with u = m / rho; a density that varies along
+    # the line must not change the spectrum of a given velocity
+    rng = np.random.default_rng(9)
+    n = 24
+    u = rng.normal(size=(3, 5, 6, n))
+    rho = rng.uniform(0.5, 2.0, size=(5, 6, n))
+    U = cons(rho, u[0], u[1], u[2], 1.0)
+    E = D.spectrum_x(U)
+    np.testing.assert_allclose(E.sum(), 0.5 * (u * u).sum(axis=0).mean(), rtol=1e-13)
+    np.testing.assert_allclose(E, D.spectrum_x(cons(1.0, u[0], u[1], u[2], 1.0)), rtol=1e-12,
+                               atol=1e-15)
