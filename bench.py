@@ -107,6 +107,8 @@ def parse():
                     help="steps of the FP32-vs-FP64 comparison (0: the workload's own)")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--config", default="", help="force a kernel configuration")
+    ap.add_argument("--skip-diag", action="store_true",
+                    help="skip timing the in-situ diagnostics")
     ap.add_argument("--copy-only", action="store_true",
                     help="only time a plain device copy of the state size")
     return ap.parse_args()
@@ -204,10 +206,77 @@ def run_gpu(W, prec, args, torch, hydro):
     sms = obj.stream_ceiling(10)
     stream = {"bytes_per_pass": 2 * state_bytes, "mean_ms": sms,
               "gbs": 2 * state_bytes / (sms * 1e-3) / 1e9}
+    diag = None
+    if prec == hydro.FP32 and not args.skip_diag:
+        log("in-situ diagnostics on the evolved state")
+        diag = diag_timing(obj, W, args.workload, torch, hydro)
     obj.close()
     del U
     torch.cuda.empty_cache()
-    return sec, kms, cfg, state_bytes, stream
+    return sec, kms, cfg, state_bytes, stream, diag
+
+
+# slab-profile axis and density pair of each single-grid workload: the
+# layer's normal (KH: y, RT: z) and its two densities; turbulence has no
+# layer (x, and densities around its uniform rho = 1)
+DIAG_PROFILE = {"kh": (1, 1.0, 2.0), "rt": (2, 1.0, 2.0), "turb": (0, 0.9, 1.1)}
+
+
+def diag_timing(obj, W, name, torch, hydro, reps=10):
+    """Mean device time (hipEvents on the context's stream, `reps` calls) of
+    the in-situ diagnostics on the workload's evolved FP32 state: a Mach
+    number PDF (1000 bins; it reads all five planes) and, for a single grid,
+    the slab profiles along the layer normal with its mixing width and
+    mixedness (20 B read per interior zone each), and the x kinetic-energy
+    spectrum (16 B per zone: density and momentum)."""
+    zones = interior_zones(W)
+    nbytes = zones * 20
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+
+    def entry(ms):
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return {"mean_ms": ms, "bytes": nbytes, "gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+
+    counts = torch.empty(1002, dtype=torch.int64, device="cuda:0")
+    res = {"pdf_mach": entry(timed(lambda: obj.pdf(hydro.Q_MACH, 0.0, 2.0, 1000, out=counts)))}
+    c = counts.cpu()
+    res["pdf_mach"]["mean_mach"] = float(((torch.arange(1000, dtype=torch.float64) + 0.5)
+                                          * 0.002 * c[1:1001].double()).sum() / max(1, int(c.sum())))
+    if W["kind"] != "batch":
+        axis, lo, hi = DIAG_PROFILE[name]
+        buf = obj.profile(axis, lo, hi)
+        e = entry(timed(lambda: obj.profile(axis, lo, hi, out=buf)))
+        h = buf.cpu().numpy()
+        e.update({"axis": axis, "rho_lo": lo, "rho_hi": hi, "slabs": (len(h) - 2) // 5,
+                  "mixing_width": float(h[-2]), "mixedness": float(h[-1])})
+        res["profile"] = e
+        nx = W["grid"][0]
+        m = nx
+        for f in (2, 3):
+            while m % f == 0:
+                m //= f
+        if m == 1 and 2 <= nx <= 1024:
+            spec = obj.spectrum()
+            es = entry(timed(lambda: obj.spectrum(out=spec)))
+            es["bytes"] = zones * 16          # rho and the momentum: 4 planes
+            es["gbs"] = es["bytes"] / (es["mean_ms"] * 1e-3) / 1e9
+            es["frac"] = es["gbs"] / HBM_PEAK_GBS
+            E = spec.cpu().numpy()
+            es.update({"kmax": len(E) - 1, "total": float(E.sum()),
+                       "E_k1_to_16": [float(v) for v in E[1:17]]})
+            res["spectrum_x"] = es
+    return res
 
 
 def per_patch_loop(W, prec, npatch, steps, torch, hydro):
@@ -484,10 +553,10 @@ def main():
 
     W = make_workload(args)
     zones = interior_zones(W)
-    sec32, k32, cfg32, bytes32, stream32 = run_gpu(W, hydro.FP32, args, torch, hydro)
+    sec32, k32, cfg32, bytes32, stream32, diag32 = run_gpu(W, hydro.FP32, args, torch, hydro)
     fp64 = None
     if not args.skip_fp64:
-        sec64, k64, cfg64, _, stream64 = run_gpu(W, hydro.FP64, args, torch, hydro)
+        sec64, k64, cfg64, _, stream64, _ = run_gpu(W, hydro.FP64, args, torch, hydro)
         fp64 = {"value": zones / sec64, "unit": "zone-updates/s",
                 "ms_per_step": sec64 * 1e3,
                 "step_roofline_frac": zones / sec64 * 240 / (HBM_PEAK_GBS * 1e9),
@@ -552,6 +621,7 @@ def main():
         "copy_ceiling": copy_ceiling(torch, bytes32),
         "stream_ceiling": stream32,
         "kernel_source": kernel_source_hash(),
+        "diagnostics": diag32,
     }
     if W["kind"] == "batch" and not args.skip_loop:
         npl = min(len(W["specs"]), 1024)

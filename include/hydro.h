@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define HYDRO_ABI_VERSION 1
+#define HYDRO_ABI_VERSION 2
 
 typedef enum hydro_status {
   HYDRO_OK = 0,
@@ -196,6 +196,60 @@ int hydro_batch_step(hydro_ctx* c, double dt);
  * the origin at the low corner of the grid (of each patch).  Fixed
  * summation order: bitwise reproducible for a given shape.  Synchronous. */
 int hydro_totals(hydro_ctx* c, double out[6]);
+
+/* In-situ diagnostics.  Large runs need their analysis done in situ (the
+ * paper's discussion of the capabilities needed at the exascale); these are
+ * standard diagnostics of stratified and shear-layer flows, each one pass
+ * over the interior cells of the current state.  Cell quantities are
+ * computed in FP64 with IEEE operations in this order (an FP32 state is
+ * widened first, exactly):
+ *   m2 = mx*mx + my*my + mz*mz,  ke = (0.5*m2)/rho,  p = (gamma-1)*(E - ke),
+ *   speed = sqrt(m2)/rho,        mach = speed/sqrt((gamma*p)/rho). */
+typedef enum hydro_quantity {
+  HYDRO_Q_RHO = 0,       /* density */
+  HYDRO_Q_PRESSURE = 1,  /* p */
+  HYDRO_Q_SPEED = 2,     /* |v| */
+  HYDRO_Q_MACH = 3       /* |v| / c */
+} hydro_quantity;
+
+/* PDF (histogram) of a hydro_quantity over every interior cell (of every
+ * patch of a batch).  `counts` is a caller-owned DEVICE array of nbins + 2
+ * int64 (8-byte aligned): with w = nbins / (hi - lo) (computed in FP64),
+ *   counts[0]          cells with !(q >= lo)  (below the range, or NaN)
+ *   counts[1 + b]      cells with b = floor((q - lo) * w), 0 <= b < nbins
+ *   counts[nbins + 1]  cells at or above hi.
+ * Counts are exact.  1 <= nbins <= 2^24; lo, hi finite with hi > lo.
+ * Asynchronous on the context's stream (the array is overwritten).
+ * Errors: HYDRO_EINVAL, HYDRO_EDEVICE. */
+int hydro_diag_pdf(hydro_ctx* c, int quantity, double lo, double hi, int32_t nbins,
+                   int64_t* counts);
+
+/* Slab profiles of a single grid along `axis` (0 x, 1 y, 2 z): for each
+ * slab s (cells of equal index along the axis) the means of rho, p, ke, f
+ * and f(1-f), with the heavy-fluid fraction of a layer between densities
+ * rho_lo < rho_hi f = min(max((rho - rho_lo)/(rho_hi - rho_lo), 0), 1).
+ * `out` is a caller-owned DEVICE array of 5 n_axis + 2 doubles (8-byte
+ * aligned): out[5 s + k] for the five fields, then
+ *   out[5 n_axis]      mixing width W = dx_axis sum_s 4 <f>_s (1 - <f>_s)
+ *   out[5 n_axis + 1]  mixedness Theta = sum_s <f(1-f)>_s / sum_s <f>_s (1 - <f>_s)
+ *                      (0 when the denominator is 0).
+ * Sums run in FP64 in a fixed order: bitwise reproducible for a shape.
+ * Asynchronous on the context's stream.  Errors: HYDRO_EINVAL, HYDRO_ESTATE
+ * (batch context), HYDRO_EDEVICE. */
+int hydro_diag_profile(hydro_ctx* c, int axis, double rho_lo, double rho_hi, double* out);
+
+/* One-dimensional kinetic-energy spectrum along x of a single grid's
+ * velocity u = m/rho: with P[k] the mean over the x-lines of the power
+ * |DFT_x(u_c)[k]|^2 summed over the three components (unnormalised DFT of
+ * length N = nx, in FP64), `out` (a caller-owned DEVICE array of N/2 + 1
+ * doubles, 8-byte aligned) receives
+ *   out[0] = P[0]/(2N^2),  out[k] = P[k]/N^2 (0 < k < N/2),
+ *   out[N/2] = P[N/2]/(2N^2) for even N,
+ * so that sum_k out[k] = <|u|^2>/2 (Parseval).  nx must be 2^a 3^b with
+ * 2 <= nx <= 1024 (HYDRO_EINVAL otherwise).  Partial sums run in a fixed
+ * order: bitwise reproducible for a shape.  Asynchronous on the context's
+ * stream.  Errors: HYDRO_EINVAL, HYDRO_ESTATE (batch context), HYDRO_EDEVICE. */
+int hydro_diag_spectrum(hydro_ctx* c, double* out);
 
 /* Simulated time and step counter (Synchronous).  hydro_set_time restores a
  * checkpoint: the counter's parity selects the next sweep order, and the

@@ -357,6 +357,7 @@ struct hydro_ctx {
   hipStream_t cap = nullptr;
   DevScalars* scal = nullptr;
   double* partials = nullptr;
+  double* profile_partials = nullptr;  // single grid: slab profile partial sums
   PatchDev single{};
   // batch
   int32_t npatch = 0;
@@ -912,8 +913,17 @@ int read_scalars(hydro_ctx* c, DevScalars* out) {
   return HYDRO_OK;
 }
 
-size_t grid_workspace_bytes(int64_t cells) {
-  return kScalarBytes + align_up(size_t(chunks_for(cells)) * 6 * sizeof(double), 256);
+// Single-grid workspace: scalars, reduction partials, then the partial
+// sums of the slab profiles (kProfileChunksX per slab of the longest axis,
+// 5 values each).
+size_t grid_totals_bytes(int64_t cells) {
+  return align_up(size_t(chunks_for(cells)) * 6 * sizeof(double), 256);
+}
+size_t grid_workspace_bytes(const int32_t n[3]) {
+  const int64_t cells = int64_t(n[0]) * n[1] * n[2];
+  const int64_t nmax = std::max(n[0], std::max(n[1], n[2]));
+  return kScalarBytes + grid_totals_bytes(cells) +
+         align_up(size_t(nmax) * kProfileChunksX * 5 * sizeof(double), 256);
 }
 
 // layout of a batch workspace
@@ -1021,7 +1031,7 @@ int hydro_workspace_bytes(const hydro_desc* d, size_t* bytes) {
   double dx[3] = {d->dx, d->dy, d->dz};
   rc = check_extent(n, d->ng, dx);
   if (rc) return rc;
-  *bytes = grid_workspace_bytes(int64_t(n[0]) * n[1] * n[2]);
+  *bytes = grid_workspace_bytes(n);
   return HYDRO_OK;
 }
 
@@ -1055,6 +1065,8 @@ int hydro_init(const hydro_desc* d, void* state, size_t state_bytes, void* works
   c->stream = static_cast<hipStream_t>(stream);
   c->scal = reinterpret_cast<DevScalars*>(c->ws);
   c->partials = reinterpret_cast<double*>(c->ws + kScalarBytes);
+  c->profile_partials = reinterpret_cast<double*>(
+      c->ws + kScalarBytes + grid_totals_bytes(int64_t(n[0]) * n[1] * n[2]));
   c->single = P;
   for (int a = 0; a < 3; ++a) c->active[a] = n[a] > 1;
   c->cfg.ax[0] = default_x({P}, c->fp64);
@@ -1273,6 +1285,90 @@ int hydro_totals(hydro_ctx* c, double out[6]) {
   int rc = read_scalars(c, &s);
   if (rc) return rc;
   for (int v = 0; v < 6; ++v) out[v] = s.totals[v];
+  return HYDRO_OK;
+}
+
+int hydro_diag_pdf(hydro_ctx* c, int quantity, double lo, double hi, int32_t nbins,
+                   int64_t* counts) {
+  if (!c || !counts) return fail(HYDRO_EINVAL, "null argument");
+  if (reinterpret_cast<uintptr_t>(counts) & 7)
+    return fail(HYDRO_EINVAL, "counts must be 8-byte aligned");
+  if (quantity < HYDRO_Q_RHO || quantity > HYDRO_Q_MACH) return fail(HYDRO_EINVAL, "unknown quantity");
+  if (nbins < 1 || nbins > kPdfMaxBins) return fail(HYDRO_EINVAL, "nbins out of range");
+  if (!std::isfinite(lo) || !std::isfinite(hi) || !(hi > lo))
+    return fail(HYDRO_EINVAL, "the range must be finite with hi > lo");
+  const double w = double(nbins) / (hi - lo);
+  if (!std::isfinite(w)) return fail(HYDRO_EINVAL, "range too narrow");
+  LaunchDiag L{};
+  L.pool = c->pool;
+  L.patches = c->batch ? c->d_patches : nullptr;
+  L.single = c->single;
+  L.npatch = c->batch ? c->npatch : 1;
+  L.fp64 = c->fp64;
+  L.gamma = c->desc.gamma;
+  L.quantity = quantity;
+  L.nbins = nbins;
+  L.lo = lo;
+  L.w = w;
+  L.counts = reinterpret_cast<unsigned long long*>(counts);
+  HIP_TRY(launch_diag_pdf(L, c->stream));
+  return HYDRO_OK;
+}
+
+int hydro_diag_profile(hydro_ctx* c, int axis, double rho_lo, double rho_hi, double* out) {
+  if (!c || !out) return fail(HYDRO_EINVAL, "null argument");
+  if (c->batch) return fail(HYDRO_ESTATE, "slab profiles are defined for single grids");
+  if (reinterpret_cast<uintptr_t>(out) & 7) return fail(HYDRO_EINVAL, "out must be 8-byte aligned");
+  if (axis < 0 || axis > 2) return fail(HYDRO_EINVAL, "axis must be 0, 1 or 2");
+  if (!std::isfinite(rho_lo) || !std::isfinite(rho_hi) || !(rho_hi > rho_lo))
+    return fail(HYDRO_EINVAL, "the density range must be finite with rho_hi > rho_lo");
+  const PatchDev& P = c->single;
+  LaunchDiag L{};
+  L.pool = c->pool;
+  L.single = P;
+  L.fp64 = c->fp64;
+  L.gamma = c->desc.gamma;
+  L.axis = axis;
+  if (axis == 0) {
+    L.chunks = int32_t(std::min<int64_t>(kProfileChunksX, int64_t(P.n[1]) * P.n[2]));
+  } else {
+    const int64_t slab = int64_t(P.n[0]) * P.n[axis == 2 ? 1 : 2];
+    L.chunks = int32_t(std::max<int64_t>(
+        1, std::min<int64_t>(kProfileChunksYZ, (slab + 255) / 256)));
+  }
+  L.rho_lo = rho_lo;
+  L.drho = rho_hi - rho_lo;
+  L.dx_axis = P.dx[axis];
+  L.partials = c->profile_partials;
+  L.out = out;
+  HIP_TRY(launch_diag_profile(L, c->stream));
+  return HYDRO_OK;
+}
+
+int hydro_diag_spectrum(hydro_ctx* c, double* out) {
+  if (!c || !out) return fail(HYDRO_EINVAL, "null argument");
+  if (c->batch) return fail(HYDRO_ESTATE, "the spectrum is defined for single grids");
+  if (reinterpret_cast<uintptr_t>(out) & 7) return fail(HYDRO_EINVAL, "out must be 8-byte aligned");
+  const PatchDev& P = c->single;
+  int m = P.n[0];
+  while (m > 1 && m % 2 == 0) m /= 2;
+  while (m > 1 && m % 3 == 0) m /= 3;
+  if (P.n[0] < 2 || P.n[0] > kSpecMaxLen || m != 1)
+    return fail(HYDRO_EINVAL, "the x extent must be 2^a 3^b, from 2 to 1024");
+  LaunchDiag L{};
+  L.pool = c->pool;
+  L.single = P;
+  L.fp64 = c->fp64;
+  L.gamma = c->desc.gamma;
+  const int64_t lines = int64_t(P.n[1]) * P.n[2];
+  L.chunks = int32_t(std::min<int64_t>(kSpecBlocks, lines));
+  // the partial spectra share the profile partials' region
+  const int64_t nmax = std::max(P.n[0], std::max(P.n[1], P.n[2]));
+  if (int64_t(L.chunks) * (P.n[0] / 2 + 1) > nmax * kProfileChunksX * 5)
+    return fail(HYDRO_EINVAL, "spectrum partials exceed the workspace");
+  L.partials = c->profile_partials;
+  L.out = out;
+  HIP_TRY(launch_diag_spectrum(L, c->stream));
   return HYDRO_OK;
 }
 

@@ -1,0 +1,601 @@
+// diag.hip -- in-situ diagnostics on the GPU: PDFs (histograms) of cell
+// quantities and slab profiles with mixing measures.
+//
+// Large runs need their analysis done where the data is (the paper's
+// discussion of the capabilities needed at the exascale); it fixes no
+// diagnostic, so these are standard ones of stratified and shear-layer
+// flows.  Each is one HBM-bound pass over the interior cells.
+//
+// Cell quantities are evaluated in FP64 with IEEE operations (no contraction:
+// the library is built with -ffp-contract=off; FP64 division and square
+// root are correctly rounded), in a fixed order:
+//   m2 = mx mx + my my + mz mz,  ke = (0.5 m2) / rho,  p = (gamma-1)(E - ke),
+//   speed = sqrt(m2) / rho,      mach = speed / sqrt((gamma p) / rho).
+// An FP32 state is widened first (exact), so a quantity's bin is a pure
+// function of the stored bits.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "launch.hpp"
+
+namespace hydro {
+
+constexpr int kDiagBlock = 256;
+constexpr int kDiagCells = 4;   // cells per thread in flight (loads before arithmetic)
+
+// Unsigned 32-bit division by an invariant d >= 1 with one multiply-high
+// (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994, the unsigned algorithm of their figure 4.1):
+// l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1, and for every n
+// q = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0) with t = mulhi(m, n).
+struct FastDiv {
+  uint32_t d, m, s1, s2;
+  __host__ __device__ FastDiv() : d(1), m(1), s1(0), s2(0) {}
+  __host__ __device__ explicit FastDiv(uint32_t div) : d(div) {
+    uint32_t l = 0;
+    while ((uint64_t(1) << l) < div) ++l;
+    m = uint32_t(((uint64_t(1) << 32) * ((uint64_t(1) << l) - div)) / div + 1);
+    s1 = l < 1 ? l : 1;
+    s2 = l > 1 ? l - 1 : 0;
+  }
+  __device__ __forceinline__ uint32_t div(uint32_t n) const {
+    const uint32_t t = __umulhi(m, n);
+    return (t + ((n - t) >> s1)) >> s2;
+  }
+};
+
+template <class T, int Q>
+__device__ __forceinline__ double diag_quantity(const T* p0, int64_t plane, int64_t o,
+                                                double gamma) {
+  const double r = double(p0[o]);
+  if constexpr (Q == kQRho) {
+    return r;
+  } else {
+    const double mx = double(p0[o + plane]), my = double(p0[o + 2 * plane]);
+    const double mz = double(p0[o + 3 * plane]);
+    const double m2 = mx * mx + my * my + mz * mz;
+    if constexpr (Q == kQSpeed) {
+      return __builtin_sqrt(m2) / r;
+    } else {
+      const double e = double(p0[o + 4 * plane]);
+      const double p = (gamma - 1.0) * (e - (0.5 * m2) / r);
+      if constexpr (Q == kQPressure) return p;
+      const double speed = __builtin_sqrt(m2) / r;
+      return speed / __builtin_sqrt((gamma * p) / r);
+    }
+  }
+}
+
+// Bin of value v: 0 below lo (or NaN), 1 + floor((v - lo) w) inside,
+// nbins + 1 at or above hi.
+__device__ __forceinline__ int diag_bin(double v, double lo, double w, int nbins) {
+  if (!(v >= lo)) return 0;
+  const double t = (v - lo) * w;
+  return t < double(nbins) ? 1 + int(t) : nbins + 1;
+}
+
+// Adds one to counter b (b < 0: nothing) for every lane of the wave.  Lanes
+// that share the bin of the first lane still pending add together with one
+// atomic, twice over (a flow with few distinct values, like a two-density
+// layer, puts most of a wave in one or two bins); the lanes left add one
+// by one.  Integer adds commute, so the counts do not depend on the grouping.
+template <class C>
+__device__ __forceinline__ void count_bin(C* ctr, int b) {
+  bool todo = b >= 0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const unsigned long long m = __ballot(todo);
+    if (m == 0ull) return;  // wave-uniform
+    const int lead = __shfl(b, int(__builtin_ctzll(m)));
+    const bool mine = todo && b == lead;
+    const unsigned long long same = __ballot(mine);
+    if (mine) {
+      if ((threadIdx.x & 63) == unsigned(__builtin_ctzll(same)))
+        atomicAdd(&ctr[lead], C(__builtin_popcountll(same)));
+      todo = false;
+    }
+  }
+  if (todo) atomicAdd(&ctr[b], C(1));
+}
+
+__global__ void __launch_bounds__(kDiagBlock) zero_u64_kernel(unsigned long long* p, int n) {
+  for (int i = blockIdx.x * kDiagBlock + threadIdx.x; i < n; i += gridDim.x * kDiagBlock)
+    p[i] = 0ull;
+}
+
+template <class T>
+struct DiagArgs {
+  const T* pool;
+  const PatchDev* patches;  // null: single grid
+  PatchDev single;
+  double gamma;
+  int nbins;
+  double lo, w;
+  unsigned long long* counts;
+  bool lds;                 // per-workgroup LDS counters (nbins + 2 <= kPdfLdsBins)
+  int axis, chunks;
+  FastDiv dnx, dny;         // single grid: division by nx and ny
+  double rho_lo, drho, dx_axis;
+  double* partials;
+  double* out;
+};
+
+// Histogram of quantity Q over the interior cells of one grid (y = 0) or of
+// patch blockIdx.y: workgroups stride over the flattened cells (x fastest,
+// coalesced), count into LDS, then add their nonzero counters to the global
+// 64-bit counters (exact: integer adds commute).
+template <class T, int Q>
+__global__ void __launch_bounds__(kDiagBlock) pdf_kernel(DiagArgs<T> a) {
+  extern __shared__ unsigned int hist[];
+  const bool batch = a.patches != nullptr;
+  const PatchDev P = batch ? a.patches[blockIdx.y] : a.single;
+  const int nb2 = a.nbins + 2;
+  if (a.lds) {
+    for (int i = threadIdx.x; i < nb2; i += kDiagBlock) hist[i] = 0u;
+    __syncthreads();
+  }
+  const unsigned nx = unsigned(P.n[0]), ny = unsigned(P.n[1]);
+  const unsigned cells = nx * ny * unsigned(P.n[2]);
+  const FastDiv dnx = batch ? FastDiv(nx) : a.dnx, dny = batch ? FastDiv(ny) : a.dny;
+  const T* p0 = a.pool + P.base0;
+  constexpr int U = kDiagCells;
+  const unsigned stride = gridDim.x * kDiagBlock * U;
+  for (unsigned i0 = blockIdx.x * kDiagBlock * U + threadIdx.x; i0 < cells; i0 += stride) {
+    // the U cells' offsets, then their quantities (all loads issued first)
+    int64_t o[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const unsigned i = min(i0 + unsigned(u) * kDiagBlock, cells - 1);
+      const unsigned row = dnx.div(i), x = i - row * nx;
+      const unsigned z = dny.div(row), y = row - z * ny;
+      o[u] = int64_t(x) + int64_t(y) * P.sy + int64_t(z) * P.sz;
+    }
+    double q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) q[u] = diag_quantity<T, Q>(p0, P.plane, o[u], a.gamma);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool valid = i0 + unsigned(u) * kDiagBlock < cells;
+      const int b = valid ? diag_bin(q[u], a.lo, a.w, a.nbins) : -1;
+      if (a.lds)
+        count_bin(hist, b);
+      else
+        count_bin(a.counts, b);
+    }
+  }
+  if (a.lds) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb2; i += kDiagBlock)
+      if (hist[i]) atomicAdd(&a.counts[i], (unsigned long long)hist[i]);
+  }
+}
+
+// The five conserved values of one cell, widened to FP64.
+template <class T>
+__device__ __forceinline__ void load_cell(const T* p0, int64_t plane, int64_t o, double (&c)[5]) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) c[v] = double(p0[o + v * plane]);
+}
+
+// Adds the five profile fields of one cell: rho, p, ke, f, f (1 - f).
+template <class T>
+__device__ __forceinline__ void profile_add(const double (&c)[5], const DiagArgs<T>& a,
+                                            double (&acc)[5]) {
+  const double r = c[0];
+  const double m2 = c[1] * c[1] + c[2] * c[2] + c[3] * c[3];
+  const double ke = (0.5 * m2) / r;
+  const double p = (a.gamma - 1.0) * (c[4] - ke);
+  const double f = __builtin_fmin(__builtin_fmax((r - a.rho_lo) / a.drho, 0.0), 1.0);
+  acc[0] += r;
+  acc[1] += p;
+  acc[2] += ke;
+  acc[3] += f;
+  acc[4] += f * (1.0 - f);
+}
+
+// Slabs normal to y (axis 1) or z (axis 2): workgroup (c, s) sums the cells
+// j = c 256 U + t + u 256 (u < U), then the same plus C 256 U, ... of slab s
+// (x fastest), then reduces its threads in a fixed order into
+// partials[s][c][5].
+template <class T>
+__global__ void __launch_bounds__(kDiagBlock) profile_slab_kernel(DiagArgs<T> a) {
+  __shared__ double red[kDiagBlock / 64][5];
+  const PatchDev& P = a.single;
+  const int s = blockIdx.y, c = blockIdx.x;
+  const unsigned nx = unsigned(P.n[0]);
+  const unsigned rows = unsigned(a.axis == 2 ? P.n[1] : P.n[2]);
+  const unsigned cells = nx * rows;
+  const T* p0 = a.pool + P.base0;
+  const int64_t srow = a.axis == 2 ? P.sy : P.sz;          // stride between the slab's rows
+  const int64_t sbase = int64_t(s) * (a.axis == 2 ? P.sz : P.sy);
+  constexpr int U = kDiagCells;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (unsigned j0 = unsigned(c) * kDiagBlock * U + threadIdx.x; j0 < cells;
+       j0 += unsigned(a.chunks) * kDiagBlock * U) {
+    double cv[U][5];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const unsigned j = min(j0 + unsigned(u) * kDiagBlock, cells - 1);
+      const unsigned r = a.dnx.div(j), x = j - r * nx;
+      load_cell<T>(p0, P.plane, sbase + int64_t(x) + int64_t(r) * srow, cv[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (j0 + unsigned(u) * kDiagBlock < cells) profile_add<T>(cv[u], a, acc);
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v)
+    for (int off = 32; off > 0; off >>= 1) acc[v] += __shfl_xor(acc[v], off);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int v = 0; v < 5; ++v) red[wave][v] = acc[v];
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    double t = red[0][threadIdx.x];
+    for (int w = 1; w < kDiagBlock / 64; ++w) t += red[w][threadIdx.x];
+    a.partials[(int64_t(s) * a.chunks + c) * 5 + threadIdx.x] = t;
+  }
+}
+
+// Slabs normal to x (axis 0): thread x of workgroup (c, xb) sums rows
+// c, c + C, ... (U of them in flight) of the grid at its own x into
+// partials[x][c][5].
+template <class T>
+__global__ void __launch_bounds__(kDiagBlock) profile_xslab_kernel(DiagArgs<T> a) {
+  const PatchDev& P = a.single;
+  const int c = blockIdx.x;
+  const int x = blockIdx.y * kDiagBlock + threadIdx.x;
+  if (x >= P.n[0]) return;
+  const unsigned ny = unsigned(P.n[1]), rows = ny * unsigned(P.n[2]);
+  const T* p0 = a.pool + P.base0;
+  constexpr int U = kDiagCells;
+  const unsigned C = unsigned(a.chunks);
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (unsigned r0 = unsigned(c); r0 < rows; r0 += C * U) {
+    double cv[U][5];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const unsigned r = min(r0 + unsigned(u) * C, rows - 1);
+      const unsigned z = a.dny.div(r), y = r - z * ny;
+      load_cell<T>(p0, P.plane, int64_t(x) + int64_t(y) * P.sy + int64_t(z) * P.sz, cv[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (r0 + unsigned(u) * C < rows) profile_add<T>(cv[u], a, acc);
+  }
+  for (int v = 0; v < 5; ++v) a.partials[(int64_t(x) * a.chunks + c) * 5 + v] = acc[v];
+}
+
+// Sum of v over the workgroup in a fixed order (wave shuffles, then the
+// waves in order); the result is returned to every thread.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();  // red is free
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = red[0];
+  for (int w = 1; w < kDiagBlock / 64; ++w) t += red[w];
+  return t;
+}
+
+// Slab means out[s][v] = sum_c partials[s][c][v] / cells per slab (thread t
+// takes slabs t, t + 256, ...), then the mixing width and mixedness from
+// per-thread sums reduced in a fixed order (one workgroup).
+__global__ void __launch_bounds__(kDiagBlock) profile_final_kernel(const double* partials,
+                                                                     int nslab, int chunks,
+                                                                     double cells_per_slab,
+                                                                     double dx_axis, double* out) {
+  __shared__ double red[kDiagBlock / 64];
+  double w = 0.0, num = 0.0, den = 0.0;
+  for (int s = threadIdx.x; s < nslab; s += kDiagBlock) {
+    double m[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      double t = 0.0;
+      for (int c = 0; c < chunks; ++c) t += partials[(int64_t(s) * chunks + c) * 5 + v];
+      m[v] = t / cells_per_slab;
+      out[s * 5 + v] = m[v];
+    }
+    w += 4.0 * m[3] * (1.0 - m[3]);
+    den += m[3] * (1.0 - m[3]);
+    num += m[4];
+  }
+  w = block_sum(w, red);
+  den = block_sum(den, red);
+  num = block_sum(num, red);
+  if (threadIdx.x == 0) {
+    out[nslab * 5] = w * dx_axis;
+    out[nslab * 5 + 1] = den > 0.0 ? num / den : 0.0;
+  }
+}
+
+// --------------------------------------------------------------------------
+// One-dimensional kinetic-energy spectrum along x
+// --------------------------------------------------------------------------
+//
+// A workgroup owns whole x-lines (y, z): lines blockIdx.x, blockIdx.x +
+// gridDim.x, ...  For each it widens rho and m to FP64, forms u = m / rho
+// (IEEE division), packs two complex lines z1 = ux + i uy and z2 = uz, and
+// transforms both in LDS with a mixed-radix Stockham FFT (radices 4, 2, 3;
+// the autosort formulation of Govindaraju et al., SC 2008: stage s with
+// radix R and span Ns maps element j + r N/R, twiddled by W^(r (j mod Ns)
+// N/(Ns R)), through an R-point DFT to (j div Ns) Ns R + (j mod Ns) + r Ns;
+// the output lands in natural order).  For a real pair packed as a + i b,
+// |A(k)|^2 + |B(k)|^2 = (|Z(k)|^2 + |Z(N-k)|^2) / 2, so the power summed over
+// the three components needs no unpacking.  Thread t accumulates k = t,
+// t + 256, ... over its workgroup's lines (fixed order), writes its
+// partial spectrum, and one workgroup sums the partials in a fixed order.
+
+constexpr int kSpecMaxStages = 12;
+
+struct SpecArgs {
+  int n;                       // line length nx
+  int nst;                     // stages
+  int rad[kSpecMaxStages];     // radix of each stage
+};
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// -i a
+__device__ __forceinline__ double2 cmi(double2 a) { return make_double2(a.y, -a.x); }
+
+// One butterfly of a stage: R inputs j + r step (twiddled), R-point DFT,
+// outputs at base + r Ns.
+template <int R>
+__device__ __forceinline__ void fft_butterfly(const double2* src, double2* dst,
+                                              const double2* W, int n, int jj, int ns) {
+  const int step = n / R, k = jj % ns, tw = n / (ns * R);
+  double2 v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double2 x = src[jj + r * step];
+    v[r] = r == 0 ? x : cmul(x, W[r * k * tw]);
+  }
+  double2 b[R];
+  if constexpr (R == 2) {
+    b[0] = cadd(v[0], v[1]);
+    b[1] = csub(v[0], v[1]);
+  } else if constexpr (R == 4) {
+    const double2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    const double2 s13 = cadd(v[1], v[3]), d13 = cmi(csub(v[1], v[3]));  // -i (v1 - v3)
+    b[0] = cadd(s02, s13);
+    b[1] = cadd(d02, d13);
+    b[2] = csub(s02, s13);
+    b[3] = csub(d02, d13);
+  } else {  // R == 3: w = exp(-2 pi i / 3) = -1/2 - i sqrt(3)/2
+    const double h = 0.86602540378443864676;  // sqrt(3) / 2
+    const double2 t1 = cadd(v[1], v[2]);
+    const double2 t2 = make_double2(v[0].x - 0.5 * t1.x, v[0].y - 0.5 * t1.y);
+    const double2 dd = csub(v[1], v[2]);
+    const double2 t3 = make_double2(h * dd.y, -h * dd.x);  // -i h (v1 - v2)
+    b[0] = cadd(v[0], t1);
+    b[1] = cadd(t2, t3);
+    b[2] = csub(t2, t3);
+  }
+  const int base = (jj / ns) * ns * R + k;
+#pragma unroll
+  for (int r = 0; r < R; ++r) dst[base + r * ns] = b[r];
+}
+
+template <class T>
+__global__ void __launch_bounds__(kDiagBlock) spectrum_kernel(DiagArgs<T> a, SpecArgs sp) {
+  extern __shared__ double2 sbuf[];
+  const PatchDev& P = a.single;
+  const int n = sp.n;
+  double2* W = sbuf;              // W[t] = exp(-2 pi i t / n)
+  double2* bufA = sbuf + n;       // two lines
+  double2* bufB = sbuf + 3 * n;   // two lines
+  for (int t = threadIdx.x; t < n; t += kDiagBlock) {
+    double sn, cs;
+    sincospi(-2.0 * double(t) / double(n), &sn, &cs);
+    W[t] = make_double2(cs, sn);
+  }
+  constexpr int KPT = (kSpecMaxLen / 2 + 1 + kDiagBlock - 1) / kDiagBlock;  // k per thread
+  double acc[KPT];
+#pragma unroll
+  for (int i = 0; i < KPT; ++i) acc[i] = 0.0;
+  const int ny = P.n[1], lines = P.n[1] * P.n[2];
+  const T* p0 = a.pool + P.base0;
+  // this thread's cells x = t + 256 i of a line, fetched one line ahead so
+  // that the next line's loads are in flight during the current transform
+  constexpr int XPT = kSpecMaxLen / kDiagBlock;
+  T fr[XPT], fm[XPT][3];
+  auto fetch = [&](int line) {
+    const int z = line / ny, y = line - z * ny;
+    const int64_t o0 = int64_t(y) * P.sy + int64_t(z) * P.sz;
+#pragma unroll
+    for (int i = 0; i < XPT; ++i) {
+      const int x = threadIdx.x + i * kDiagBlock;
+      if (x < n) {
+        const int64_t o = o0 + x;
+        fr[i] = p0[o];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) fm[i][c] = p0[o + (c + 1) * P.plane];
+      }
+    }
+  };
+  if (int(blockIdx.x) < lines) fetch(blockIdx.x);
+  for (int line = blockIdx.x; line < lines; line += gridDim.x) {
+    __syncthreads();  // the previous line's buffers and the twiddles
+#pragma unroll
+    for (int i = 0; i < XPT; ++i) {
+      const int x = threadIdx.x + i * kDiagBlock;
+      if (x < n) {
+        const double r = double(fr[i]);
+        bufA[x] = make_double2(double(fm[i][0]) / r, double(fm[i][1]) / r);
+        bufA[n + x] = make_double2(double(fm[i][2]) / r, 0.0);
+      }
+    }
+    if (line + int(gridDim.x) < lines) fetch(line + gridDim.x);
+    double2* src = bufA;
+    double2* dst = bufB;
+    int ns = 1;
+    for (int s = 0; s < sp.nst; ++s) {
+      __syncthreads();
+      const int R = sp.rad[s];
+      const int m = n / R;
+      for (int j = threadIdx.x; j < 2 * m; j += kDiagBlock) {
+        const int l = j >= m ? 1 : 0;
+        const int jj = j - l * m;
+        if (R == 4)
+          fft_butterfly<4>(src + l * n, dst + l * n, W, n, jj, ns);
+        else if (R == 2)
+          fft_butterfly<2>(src + l * n, dst + l * n, W, n, jj, ns);
+        else
+          fft_butterfly<3>(src + l * n, dst + l * n, W, n, jj, ns);
+      }
+      double2* t = src;
+      src = dst;
+      dst = t;
+      ns *= R;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < KPT; ++i) {
+      const int k = threadIdx.x + i * kDiagBlock;
+      if (k <= n / 2) {
+        const int km = k == 0 ? 0 : n - k;
+        const double2 a1 = src[k], b1 = src[km], a2 = src[n + k], b2 = src[n + km];
+        acc[i] += 0.5 * ((a1.x * a1.x + a1.y * a1.y) + (b1.x * b1.x + b1.y * b1.y)) +
+                  0.5 * ((a2.x * a2.x + a2.y * a2.y) + (b2.x * b2.x + b2.y * b2.y));
+      }
+    }
+  }
+  const int nk = n / 2 + 1;
+#pragma unroll
+  for (int i = 0; i < KPT; ++i) {
+    const int k = threadIdx.x + i * kDiagBlock;
+    if (k < nk) a.partials[int64_t(blockIdx.x) * nk + k] = acc[i];
+  }
+}
+
+// E[k] = sum over workgroups of the partials / (lines n^2), halved at k = 0
+// and at the Nyquist wavenumber of an even n.  Workgroup k: thread t sums
+// partials t, t + 256, ..., then a fixed-order workgroup sum.
+__global__ void __launch_bounds__(kDiagBlock) spectrum_final_kernel(const double* partials,
+                                                                      int blocks, int n,
+                                                                      double lines, double* out) {
+  __shared__ double red[kDiagBlock / 64];
+  const int nk = n / 2 + 1, k = blockIdx.x;
+  double t = 0.0;
+  for (int b = threadIdx.x; b < blocks; b += kDiagBlock) t += partials[int64_t(b) * nk + k];
+  t = block_sum(t, red);
+  if (threadIdx.x == 0) {
+    double e = t / lines / (double(n) * double(n));
+    if (k == 0 || (2 * k == n)) e *= 0.5;
+    out[k] = e;
+  }
+}
+
+template <class T>
+static DiagArgs<T> to_dargs(const LaunchDiag& L) {
+  DiagArgs<T> a;
+  a.pool = static_cast<const T*>(L.pool);
+  a.patches = L.patches;
+  a.single = L.single;
+  a.gamma = L.gamma;
+  a.nbins = L.nbins;
+  a.lo = L.lo;
+  a.w = L.w;
+  a.counts = L.counts;
+  a.lds = L.nbins + 2 <= kPdfLdsBins;
+  a.axis = L.axis;
+  a.chunks = L.chunks;
+  a.dnx = FastDiv(uint32_t(L.single.n[0]));
+  a.dny = FastDiv(uint32_t(L.single.n[1]));
+  a.rho_lo = L.rho_lo;
+  a.drho = L.drho;
+  a.dx_axis = L.dx_axis;
+  a.partials = L.partials;
+  a.out = L.out;
+  return a;
+}
+
+template <class T>
+static hipError_t launch_pdf_t(const LaunchDiag& L, hipStream_t st) {
+  const DiagArgs<T> a = to_dargs<T>(L);
+  const int nb2 = L.nbins + 2;
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(unsigned(std::min(1024, (nb2 + kDiagBlock - 1) / kDiagBlock))),
+                     dim3(kDiagBlock), 0, st, L.counts, nb2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = a.lds ? size_t(nb2) * sizeof(unsigned int) : 0;
+  dim3 grid;
+  if (L.patches) {
+    grid = dim3(kPdfPatchBlocks, unsigned(L.npatch));
+  } else {
+    const int64_t cells = int64_t(L.single.n[0]) * L.single.n[1] * L.single.n[2];
+    const int64_t b = (cells + 4 * kDiagBlock - 1) / (4 * kDiagBlock);
+    grid = dim3(unsigned(std::max<int64_t>(1, std::min<int64_t>(b, kPdfMaxBlocks))));
+  }
+  switch (L.quantity) {
+    case kQRho: hipLaunchKernelGGL((pdf_kernel<T, kQRho>), grid, dim3(kDiagBlock), lds, st, a); break;
+    case kQPressure: hipLaunchKernelGGL((pdf_kernel<T, kQPressure>), grid, dim3(kDiagBlock), lds, st, a); break;
+    case kQSpeed: hipLaunchKernelGGL((pdf_kernel<T, kQSpeed>), grid, dim3(kDiagBlock), lds, st, a); break;
+    case kQMach: hipLaunchKernelGGL((pdf_kernel<T, kQMach>), grid, dim3(kDiagBlock), lds, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_pdf(const LaunchDiag& L, hipStream_t st) {
+  if (L.nbins < 1 || L.nbins > kPdfMaxBins) return hipErrorInvalidValue;
+  return L.fp64 ? launch_pdf_t<double>(L, st) : launch_pdf_t<float>(L, st);
+}
+
+template <class T>
+static hipError_t launch_profile_t(const LaunchDiag& L, hipStream_t st) {
+  const DiagArgs<T> a = to_dargs<T>(L);
+  const int ns = L.single.n[L.axis];
+  if (L.axis == 0)
+    hipLaunchKernelGGL(profile_xslab_kernel<T>,
+                       dim3(unsigned(L.chunks), unsigned((ns + kDiagBlock - 1) / kDiagBlock)),
+                       dim3(kDiagBlock), 0, st, a);
+  else
+    hipLaunchKernelGGL(profile_slab_kernel<T>, dim3(unsigned(L.chunks), unsigned(ns)),
+                       dim3(kDiagBlock), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const double cells = double(L.single.n[0]) * L.single.n[1] * L.single.n[2];
+  hipLaunchKernelGGL(profile_final_kernel, dim3(1), dim3(kDiagBlock), 0, st, L.partials, ns,
+                     L.chunks, cells / ns, L.dx_axis, L.out);
+  return hipGetLastError();
+}
+
+template <class T>
+static hipError_t launch_spectrum_t(const LaunchDiag& L, hipStream_t st) {
+  const DiagArgs<T> a = to_dargs<T>(L);
+  SpecArgs sp{};
+  sp.n = L.single.n[0];
+  int m = sp.n;
+  while (m % 4 == 0 && sp.nst < kSpecMaxStages) { sp.rad[sp.nst++] = 4; m /= 4; }
+  while (m % 2 == 0 && sp.nst < kSpecMaxStages) { sp.rad[sp.nst++] = 2; m /= 2; }
+  while (m % 3 == 0 && sp.nst < kSpecMaxStages) { sp.rad[sp.nst++] = 3; m /= 3; }
+  if (m != 1) return hipErrorInvalidValue;
+  const size_t lds = size_t(5) * sp.n * sizeof(double2);
+  hipLaunchKernelGGL(spectrum_kernel<T>, dim3(unsigned(L.chunks)), dim3(kDiagBlock), lds, st, a,
+                     sp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const double lines = double(L.single.n[1]) * L.single.n[2];
+  hipLaunchKernelGGL(spectrum_final_kernel, dim3(unsigned(sp.n / 2 + 1)), dim3(kDiagBlock), 0,
+                     st, L.partials, L.chunks, sp.n, lines, L.out);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_spectrum(const LaunchDiag& L, hipStream_t st) {
+  const int n = L.single.n[0];
+  if (L.patches || n < 2 || n > kSpecMaxLen || L.chunks < 1) return hipErrorInvalidValue;
+  return L.fp64 ? launch_spectrum_t<double>(L, st) : launch_spectrum_t<float>(L, st);
+}
+
+hipError_t launch_diag_profile(const LaunchDiag& L, hipStream_t st) {
+  if (L.axis < 0 || L.axis > 2 || L.chunks < 1 || L.patches) return hipErrorInvalidValue;
+  return L.fp64 ? launch_profile_t<double>(L, st) : launch_profile_t<float>(L, st);
+}
+
+}  // namespace hydro

@@ -52,7 +52,42 @@ struct LaunchReduce {
   int32_t fp64;
 };
 
+// In-situ diagnostics (diag.hip).
+constexpr int kQRho = 0, kQPressure = 1, kQSpeed = 2, kQMach = 3;  // hydro_quantity
+constexpr int kPdfLdsBins = 8192;       // counters (bins + 2) kept in LDS up to this
+constexpr int kPdfMaxBins = 1 << 24;
+constexpr int kPdfMaxBlocks = 4096;     // single grid
+constexpr int kPdfPatchBlocks = 4;      // batch: workgroups per patch
+constexpr int kProfileChunksX = 256;    // partial sums per slab, slabs normal to x
+constexpr int kProfileChunksYZ = 16;    // partial sums per slab, slabs normal to y or z
+constexpr int kSpecBlocks = 2048;       // spectrum: workgroups (partial spectra)
+constexpr int kSpecMaxLen = 1024;       // spectrum: longest x-line
+
+struct LaunchDiag {
+  const void* pool;
+  const PatchDev* patches;  // batch: device patch table (PDF only); null: single grid
+  PatchDev single;
+  int32_t npatch;
+  int32_t fp64;
+  double gamma;
+  // PDF
+  int32_t quantity;
+  int32_t nbins;
+  double lo, w;                   // w = nbins / (hi - lo)
+  unsigned long long* counts;     // device, nbins + 2
+  // slab profiles (single grid)
+  int32_t axis;
+  int32_t chunks;                 // partial sums per slab
+  double rho_lo, drho;            // f = clip((rho - rho_lo) / drho, 0, 1)
+  double dx_axis;
+  double* partials;               // device, n_axis * chunks * 5
+  double* out;                    // device, n_axis * 5 + 2
+};
+
 hipError_t launch_sweep(const LaunchSweep& L, hipStream_t st);
+hipError_t launch_diag_pdf(const LaunchDiag& L, hipStream_t st);
+hipError_t launch_diag_profile(const LaunchDiag& L, hipStream_t st);
+hipError_t launch_diag_spectrum(const LaunchDiag& L, hipStream_t st);
 hipError_t launch_cfl(const LaunchReduce& L, hipStream_t st);
 hipError_t launch_totals(const LaunchReduce& L, hipStream_t st);
 hipError_t launch_finish_step(DevScalars* s, hipStream_t st);

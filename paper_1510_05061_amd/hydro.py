@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libhydro.so")
 HYDRO_OK, HYDRO_EINVAL, HYDRO_EDEVICE, HYDRO_ENUMERIC, HYDRO_ESTATE = range(5)
 PERIODIC, OUTFLOW, REFLECT = 0, 1, 2
 FP32, FP64 = 0, 1
+Q_RHO, Q_PRESSURE, Q_SPEED, Q_MACH = 0, 1, 2, 3
 FLAG_NO_GRAPH, FLAG_NO_TUNE = 0x1, 0x2
 DT_CFL = 0.0
 
@@ -77,6 +78,11 @@ _SIGS = {
                           ctypes.POINTER(_vp)], ctypes.c_int),
     "hydro_batch_step": ([_vp, ctypes.c_double], ctypes.c_int),
     "hydro_totals": ([_vp, _dp], ctypes.c_int),
+    "hydro_diag_pdf": ([_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                        _vp], ctypes.c_int),
+    "hydro_diag_profile": ([_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, _vp],
+                           ctypes.c_int),
+    "hydro_diag_spectrum": ([_vp, _vp], ctypes.c_int),
     "hydro_get_time": ([_vp, _dp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "hydro_set_time": ([_vp, ctypes.c_double, ctypes.c_int64], ctypes.c_int),
     "hydro_set_t_end": ([_vp, ctypes.c_double], ctypes.c_int),
@@ -178,6 +184,32 @@ def hydro_totals(ctx):
     out = (ctypes.c_double * 6)()
     _check(lib().hydro_totals(ctx, out), "hydro_totals")
     return list(out)
+
+
+def hydro_diag_pdf(ctx, quantity, lo, hi, nbins, counts_ptr):
+    """Asynchronous; counts_ptr: device int64[nbins + 2]."""
+    _check(lib().hydro_diag_pdf(ctx, int(quantity), float(lo), float(hi), int(nbins),
+                                counts_ptr), "hydro_diag_pdf")
+
+
+def hydro_diag_profile(ctx, axis, rho_lo, rho_hi, out_ptr):
+    """Asynchronous; out_ptr: device float64[5 n_axis + 2]."""
+    _check(lib().hydro_diag_profile(ctx, int(axis), float(rho_lo), float(rho_hi), out_ptr),
+           "hydro_diag_profile")
+
+
+def hydro_diag_spectrum(ctx, out_ptr):
+    """Asynchronous; out_ptr: device float64[nx // 2 + 1]."""
+    _check(lib().hydro_diag_spectrum(ctx, out_ptr), "hydro_diag_spectrum")
+
+
+def _pdf(obj, quantity, lo, hi, nbins, out):
+    torch = _torch()
+    dev = obj.state.device if hasattr(obj, "state") else obj.pool.device
+    if out is None:
+        out = torch.empty(max(int(nbins), 0) + 2, dtype=torch.int64, device=dev)
+    hydro_diag_pdf(obj.ctx, quantity, lo, hi, nbins, ctypes.c_void_p(out.data_ptr()))
+    return out
 
 
 def hydro_get_time(ctx):
@@ -317,6 +349,28 @@ class Grid:
     def totals(self):
         return hydro_totals(self.ctx)
 
+    def pdf(self, quantity, lo, hi, nbins, out=None):
+        """Device int64 tensor of nbins + 2 counts (see hydro_diag_pdf)."""
+        return _pdf(self, quantity, lo, hi, nbins, out)
+
+    def profile(self, axis, rho_lo, rho_hi, out=None):
+        """Device float64 tensor of 5 n_axis + 2 values (see hydro_diag_profile)."""
+        torch = _torch()
+        n = (self.desc.nx, self.desc.ny, self.desc.nz)[axis] if axis in (0, 1, 2) else 0
+        if out is None:
+            out = torch.empty(5 * n + 2, dtype=torch.float64, device=self.state.device)
+        hydro_diag_profile(self.ctx, axis, rho_lo, rho_hi, ctypes.c_void_p(out.data_ptr()))
+        return out
+
+    def spectrum(self, out=None):
+        """Device float64 tensor of nx // 2 + 1 values (see hydro_diag_spectrum)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.desc.nx // 2 + 1, dtype=torch.float64,
+                              device=self.state.device)
+        hydro_diag_spectrum(self.ctx, ctypes.c_void_p(out.data_ptr()))
+        return out
+
     def time(self):
         return hydro_get_time(self.ctx)
 
@@ -405,6 +459,10 @@ class Batch:
 
     def totals(self):
         return hydro_totals(self.ctx)
+
+    def pdf(self, quantity, lo, hi, nbins, out=None):
+        """Device int64 tensor of nbins + 2 counts over every patch."""
+        return _pdf(self, quantity, lo, hi, nbins, out)
 
     def time(self):
         return hydro_get_time(self.ctx)
