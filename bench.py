@@ -210,10 +210,64 @@ def run_gpu(W, prec, args, torch, hydro):
     if prec == hydro.FP32 and not args.skip_diag:
         log("in-situ diagnostics on the evolved state")
         diag = diag_timing(obj, W, args.workload, torch, hydro)
+        if W["kind"] != "batch":
+            log("reactive source on the evolved state")
+            diag["burn"] = burn_timing(obj, W, torch, hydro)
     obj.close()
     del U
     torch.cuda.empty_cache()
     return sec, kms, cfg, state_bytes, stream, diag
+
+
+# FP64 vector peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA
+# x 2.4 GHz (one FP64 FMA per lane per cycle)
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+BURN_SPECIES, BURN_SUBSTEPS = 13, 64
+
+
+def burn_flops_per_zone(M, nsub):
+    """Algorithmic flops of one zone's reactive-source step (a division, exp
+    or reciprocal counted as one): temperature 10; per link (-Ta/T, exp, A*,
+    h*, 1+, reciprocal) 6; per substep 1 + 3 per later species (fma + mul);
+    energy 4 M + 3."""
+    return 10 + 6 * (M - 1) + nsub * (1 + 3 * (M - 1)) + 4 * M + 3
+
+
+def burn_timing(obj, W, torch, hydro, reps=5):
+    """Mean device time of the reactive-source step (a 13-species chain,
+    64 backward-Euler substeps, every zone starting as species 0) on the
+    evolved FP32 state: arithmetic-bound, so reported against the FP64
+    vector peak, with the HBM bytes (state and composition read, composition
+    and energy written) for context."""
+    import numpy as np
+    M, n = BURN_SPECIES, BURN_SUBSTEPS
+    rng = np.random.default_rng(13)
+    A = 10.0 ** rng.uniform(-1, 6, M - 1)
+    Ta = rng.uniform(0.0, 3.0, M - 1)
+    q = rng.uniform(0.01, 0.1, M - 1)
+    X = torch.zeros((M,) + tuple(obj.state.shape[1:]), dtype=obj.state.dtype, device="cuda:0")
+    X[0] = 1.0
+    dt = 1e-3
+    obj.burn(X, A, Ta, q, dt, n)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        obj.burn(X, A, Ta, q, dt, n)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    zones = interior_zones(W)
+    flops = burn_flops_per_zone(M, n) * zones
+    tf = flops / (ms * 1e-3) / 1e12
+    nbytes = zones * 4 * ((5 + M) + (M + 1))
+    return {"nspec": M, "nsub": n, "mean_ms": ms, "bound": "alu",
+            "flops_per_zone": burn_flops_per_zone(M, n), "achieved": tf,
+            "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": tf / FP64_VECTOR_PEAK_TFLOPS, "bytes": nbytes,
+            "gbs": nbytes / (ms * 1e-3) / 1e9,
+            "mass_sum_max_err": float((X.double().sum(dim=0) - 1.0).abs().max().item())}
 
 
 # slab-profile axis and density pair of each single-grid workload: the

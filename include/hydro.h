@@ -251,6 +251,35 @@ int hydro_diag_profile(hydro_ctx* c, int axis, double rho_lo, double rho_hi, dou
  * stream.  Errors: HYDRO_EINVAL, HYDRO_ESTATE (batch context), HYDRO_EDEVICE. */
 int hydro_diag_spectrum(hydro_ctx* c, double* out);
 
+/* Operator-split reactive source: a self-contained toy network.  The
+ * paper's explosion models carry nuclear networks of 10-20 nuclei without
+ * rates; this chain has the same shape of work, a stiff ODE per zone.
+ * Species 0 -> 1 -> ... -> nspec-1 (the last stable); link i converts
+ * species i to i+1 at k_i = A[i] exp(-Ta[i] / T), T = p/rho of the zone
+ * (code units, held fixed over the step), releasing q[i] per unit mass.
+ * The step integrates the mass fractions over dt with nsub backward-Euler
+ * substeps (exact forward substitution; L-stable; sum of X conserved) in
+ * FP64 and raises the total energy by rho sum_s B_s (X_s - X_s^0),
+ * B_s = q[0] + ... + q[s-1]. */
+#define HYDRO_MAX_SPECIES 20
+typedef struct hydro_network {
+  int32_t nspec;                     /* 2 .. HYDRO_MAX_SPECIES */
+  int32_t pad;
+  double A[HYDRO_MAX_SPECIES - 1];   /* link rate prefactors, >= 0, finite */
+  double Ta[HYDRO_MAX_SPECIES - 1];  /* link activation temperatures, finite */
+  double q[HYDRO_MAX_SPECIES - 1];   /* link specific energy releases, finite */
+} hydro_network;
+
+/* One reactive-source step of a single grid.  `X` is a caller-owned DEVICE
+ * array of nspec composition planes, each laid out exactly like one plane
+ * of the state (same element type, plane size, pitches and ghost layers;
+ * plane s starts s * plane-size elements after X), `x_bytes` its size.  X
+ * and the energy plane are updated in place; rho and momentum unchanged.
+ * dt >= 0 finite, 1 <= nsub <= 1000000.  Asynchronous on the context's
+ * stream.  Errors: HYDRO_EINVAL, HYDRO_ESTATE (batch context), HYDRO_EDEVICE. */
+int hydro_burn(hydro_ctx* c, void* X, size_t x_bytes, const hydro_network* net, double dt,
+               int32_t nsub);
+
 /* Simulated time and step counter (Synchronous).  hydro_set_time restores a
  * checkpoint: the counter's parity selects the next sweep order, and the
  * device dt is recomputed before the next HYDRO_DT_CFL step. */

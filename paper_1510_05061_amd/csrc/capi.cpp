@@ -1372,6 +1372,45 @@ int hydro_diag_spectrum(hydro_ctx* c, double* out) {
   return HYDRO_OK;
 }
 
+int hydro_burn(hydro_ctx* c, void* X, size_t x_bytes, const hydro_network* net, double dt,
+               int32_t nsub) {
+  if (!c || !X || !net) return fail(HYDRO_EINVAL, "null argument");
+  if (c->batch) return fail(HYDRO_ESTATE, "the reactive source is defined for single grids");
+  const int m = net->nspec;
+  if (m < 2 || m > HYDRO_MAX_SPECIES) return fail(HYDRO_EINVAL, "nspec must be in [2, 20]");
+  if (!std::isfinite(dt) || dt < 0.0) return fail(HYDRO_EINVAL, "dt must be finite and >= 0");
+  if (nsub < 1 || nsub > 1000000) return fail(HYDRO_EINVAL, "nsub must be in [1, 1e6]");
+  for (int i = 0; i < m - 1; ++i)
+    if (!std::isfinite(net->A[i]) || net->A[i] < 0.0 || !std::isfinite(net->Ta[i]) ||
+        !std::isfinite(net->q[i]))
+      return fail(HYDRO_EINVAL, "network rates and energies must be finite (A >= 0)");
+  const size_t esz = c->fp64 ? 8 : 4;
+  if (reinterpret_cast<uintptr_t>(X) % esz) return fail(HYDRO_EINVAL, "X is misaligned");
+  if (x_bytes < size_t(m) * size_t(c->single.plane) * esz)
+    return fail(HYDRO_EINVAL, "X holds fewer than nspec planes");
+  static_assert(HYDRO_MAX_SPECIES == kBurnMaxSpecies, "species limit");
+  LaunchBurn L{};
+  L.pool = c->pool;
+  L.X = X;
+  L.single = c->single;
+  L.fp64 = c->fp64;
+  L.nspec = m;
+  L.nsub = nsub;
+  L.gamma = c->desc.gamma;
+  L.h = dt / double(nsub);
+  double b = 0.0;
+  for (int s = 0; s < m; ++s) {
+    L.B[s] = b;
+    if (s < m - 1) {
+      L.A[s] = net->A[s];
+      L.Ta[s] = net->Ta[s];
+      b += net->q[s];
+    }
+  }
+  HIP_TRY(launch_burn(L, c->stream));
+  return HYDRO_OK;
+}
+
 int hydro_get_time(hydro_ctx* c, double* t, int64_t* step) {
   if (!c) return fail(HYDRO_EINVAL, "null context");
   DevScalars s;

@@ -84,7 +84,25 @@ struct LaunchDiag {
   double* out;                    // device, n_axis * 5 + 2
 };
 
+// Operator-split reactive source (burn.hip).
+constexpr int kBurnMaxSpecies = 20;
+
+struct LaunchBurn {
+  void* pool;                      // state (5 planes)
+  void* X;                         // composition (nspec planes, laid out like the state's)
+  PatchDev single;
+  int32_t fp64;
+  int32_t nspec;
+  int32_t nsub;
+  double gamma;
+  double h;                        // dt / nsub
+  double A[kBurnMaxSpecies - 1];   // link rate prefactors
+  double Ta[kBurnMaxSpecies - 1];  // link activation temperatures
+  double B[kBurnMaxSpecies];       // energy released in making species s from species 0
+};
+
 hipError_t launch_sweep(const LaunchSweep& L, hipStream_t st);
+hipError_t launch_burn(const LaunchBurn& L, hipStream_t st);
 hipError_t launch_diag_pdf(const LaunchDiag& L, hipStream_t st);
 hipError_t launch_diag_profile(const LaunchDiag& L, hipStream_t st);
 hipError_t launch_diag_spectrum(const LaunchDiag& L, hipStream_t st);

@@ -38,6 +38,28 @@ class HydroDesc(ctypes.Structure):
     ]
 
 
+MAX_SPECIES = 20
+
+
+class HydroNetwork(ctypes.Structure):
+    _fields_ = [
+        ("nspec", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("A", ctypes.c_double * (MAX_SPECIES - 1)),
+        ("Ta", ctypes.c_double * (MAX_SPECIES - 1)),
+        ("q", ctypes.c_double * (MAX_SPECIES - 1)),
+    ]
+
+
+def make_network(A, Ta, q):
+    """hydro_network for a chain of len(A) + 1 species."""
+    n = len(A) + 1
+    net = HydroNetwork()
+    net.nspec = n
+    for i in range(min(n - 1, MAX_SPECIES - 1)):
+        net.A[i], net.Ta[i], net.q[i] = float(A[i]), float(Ta[i]), float(q[i])
+    return net
+
+
 class HydroPatch(ctypes.Structure):
     _fields_ = [
         ("offset_elems", ctypes.c_int64),
@@ -83,6 +105,8 @@ _SIGS = {
     "hydro_diag_profile": ([_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, _vp],
                            ctypes.c_int),
     "hydro_diag_spectrum": ([_vp, _vp], ctypes.c_int),
+    "hydro_burn": ([_vp, _vp, _sz, ctypes.POINTER(HydroNetwork), ctypes.c_double, ctypes.c_int32],
+                   ctypes.c_int),
     "hydro_get_time": ([_vp, _dp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "hydro_set_time": ([_vp, ctypes.c_double, ctypes.c_int64], ctypes.c_int),
     "hydro_set_t_end": ([_vp, ctypes.c_double], ctypes.c_int),
@@ -201,6 +225,12 @@ def hydro_diag_profile(ctx, axis, rho_lo, rho_hi, out_ptr):
 def hydro_diag_spectrum(ctx, out_ptr):
     """Asynchronous; out_ptr: device float64[nx // 2 + 1]."""
     _check(lib().hydro_diag_spectrum(ctx, out_ptr), "hydro_diag_spectrum")
+
+
+def hydro_burn(ctx, x_ptr, x_bytes, net, dt, nsub):
+    """Asynchronous; x_ptr: device composition planes (see hydro_burn)."""
+    _check(lib().hydro_burn(ctx, x_ptr, int(x_bytes), ctypes.byref(net), float(dt), int(nsub)),
+           "hydro_burn")
 
 
 def _pdf(obj, quantity, lo, hi, nbins, out):
@@ -361,6 +391,19 @@ class Grid:
             out = torch.empty(5 * n + 2, dtype=torch.float64, device=self.state.device)
         hydro_diag_profile(self.ctx, axis, rho_lo, rho_hi, ctypes.c_void_p(out.data_ptr()))
         return out
+
+    def burn(self, X, A, Ta, q, dt, nsub):
+        """Reactive-source step on the composition tensor X (nspec planes
+        shaped like the state's: (nspec, nz+2ng, ny+2ng, nx+2ng), the state's
+        dtype, contiguous, on the same device); updates X and the energy."""
+        if (not X.is_cuda or not X.is_contiguous() or X.dtype != self.state.dtype
+                or tuple(X.shape[1:]) != tuple(self.state.shape[1:])):
+            raise ValueError("X must be a contiguous CUDA tensor shaped like the state's planes")
+        net = make_network(A, Ta, q)
+        if X.shape[0] != net.nspec:
+            raise ValueError("X must hold len(A) + 1 planes")
+        hydro_burn(self.ctx, ctypes.c_void_p(X.data_ptr()), X.numel() * X.element_size(), net,
+                   dt, nsub)
 
     def spectrum(self, out=None):
         """Device float64 tensor of nx // 2 + 1 values (see hydro_diag_spectrum)."""
