@@ -213,6 +213,9 @@ def run_gpu(W, prec, args, torch, hydro):
         if W["kind"] != "batch":
             log("reactive source on the evolved state")
             diag["burn"] = burn_timing(obj, W, torch, hydro)
+        else:
+            log("AMR operators on the pool")
+            diag["amr"] = amr_timing(obj, W, torch, hydro)
     obj.close()
     del U
     torch.cuda.empty_cache()
@@ -268,6 +271,46 @@ def burn_timing(obj, W, torch, hydro, reps=5):
             "frac": tf / FP64_VECTOR_PEAK_TFLOPS, "bytes": nbytes,
             "gbs": nbytes / (ms * 1e-3) / 1e9,
             "mass_sum_max_err": float((X.double().sum(dim=0) - 1.0).abs().max().item())}
+
+
+def amr_timing(obj, W, torch, hydro, reps=5):
+    """Mean device time of the AMR operators on the batch pool (FP32), run
+    after the timed steps: a stored-ghost fill of every patch (ghost shells
+    read from and written to the interior edges: 2 x 20 B per ghost cell),
+    and restriction and interior prolongation over links pairing each 32^3
+    patch with a distinct 64^3 patch at coarse offset (8, 8, 8) (restriction:
+    the fine interior read, the 16^3 covered coarse cells written;
+    prolongation: the fine interior written, the parents read)."""
+    specs = W["specs"]
+    ng = 4
+    ghost = sum((s.n + 2 * ng) ** 3 - s.n ** 3 for s in specs)
+    fine = [i for i, s in enumerate(specs) if s.n == 32]
+    coarse = [i for i, s in enumerate(specs) if s.n == 64]
+    links = [(f, c, 8, 8, 8) for f, c in zip(fine, coarse)]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+
+    def entry(ms, nbytes):
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return {"mean_ms": ms, "bytes": nbytes, "gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+
+    out = {"fill_ghosts": entry(timed(obj.fill_ghosts), ghost * 20 * 2),
+           "links": len(links)}
+    if links:
+        nf = len(links) * 32 ** 3
+        out["restrict"] = entry(timed(lambda: obj.restrict(links)), nf * 20 + nf // 8 * 20)
+        out["prolong"] = entry(timed(lambda: obj.prolong(links)), nf * 20 + nf // 8 * 20)
+    return out
 
 
 # slab-profile axis and density pair of each single-grid workload: the

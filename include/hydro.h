@@ -280,6 +280,51 @@ typedef struct hydro_network {
 int hydro_burn(hydro_ctx* c, void* X, size_t x_bytes, const hydro_network* net, double dt,
                int32_t nsub);
 
+/* AMR operators around the batched patches (refinement ratio 2).  The
+ * paper's codes run the hydrodynamics on adaptively refined grids; these are
+ * the standard conservative operators between levels.  The sweeps apply
+ * the physical boundary conditions on the fly and never read stored
+ * ghosts: these serve the layers around the step (regridding, coarse-fine
+ * exchange, output, checkpoints).  All are asynchronous on the context's
+ * stream and reproduce their definitions' operations in order (results
+ * bitwise equal to a plain FP64 evaluation, rounded once to the state's
+ * precision). */
+
+/* The stored ghost layers of a single grid (ng > 0) or of every patch, from
+ * the interior under the context's boundary conditions, axis by axis:
+ * periodic wraps, outflow copies the edge cell, reflect mirrors (ghost -k
+ * copies cell k-1, with period 2n beyond the interior) and negates the
+ * momentum normal to the reflecting side.  Errors: HYDRO_EINVAL,
+ * HYDRO_EDEVICE. */
+int hydro_fill_ghosts(hydro_ctx* c);
+
+/* A fine patch inside a coarse one of the same batch: fine interior cell
+ * (0,0,0) is the first child of coarse interior cell (ox, oy, oz); the fine
+ * cells are half as wide.  Fine interior extents must be even. */
+typedef struct hydro_amr_link {
+  int32_t fine, coarse;  /* patch indices */
+  int32_t ox, oy, oz;
+  int32_t pad;
+} hydro_amr_link;
+
+/* Restriction: every coarse cell covered by a fine patch becomes the mean
+ * of its 2x2x2 children (summed in (dz, dy, dx) order, times 1/8).  The
+ * covered cells must lie in the coarse interior.  Links of one call must not
+ * write overlapping cells, nor read cells another link writes.  Errors:
+ * HYDRO_EINVAL, HYDRO_ESTATE (single-grid context), HYDRO_EDEVICE. */
+int hydro_amr_restrict(hydro_ctx* c, const hydro_amr_link* links, int32_t n);
+
+/* Prolongation: fine cells from the coarse patch by MC-limited linear
+ * reconstruction, conservative (the eight children average to the parent):
+ *   child = ((U + s_x D_x) + s_y D_y) + s_z D_z,  s = -1/4 or +1/4,
+ * D = sign(a) min(2|a|, 2|b|, |a+b|/2) when the coarse one-sided
+ * differences a, b have a positive product, else 0.  ghosts_only = 0 fills
+ * the fine interior; 1 fills only the fine ghost shell (coarse-fine ghost
+ * exchange).  The coarse cells used (parents and their neighbours, coarse
+ * ghosts included: fill them first) must lie in the coarse patch's stored
+ * region.  Same independence rule and errors as hydro_amr_restrict. */
+int hydro_amr_prolong(hydro_ctx* c, const hydro_amr_link* links, int32_t n, int ghosts_only);
+
 /* Simulated time and step counter (Synchronous).  hydro_set_time restores a
  * checkpoint: the counter's parity selects the next sweep order, and the
  * device dt is recomputed before the next HYDRO_DT_CFL step. */

@@ -98,6 +98,7 @@ PatchDev make_patch(const int32_t n[3], int32_t ng, const double dx[3], int64_t 
   P.sy = int32_t(sx);
   P.sz = int32_t(sx * sy);
   P.base0 = offset + ng + ng * sx + ng * sx * sy;
+  P.ng = ng;
   for (int a = 0; a < 3; ++a) {
     P.n[a] = n[a];
     P.dx[a] = dx[a];
@@ -136,6 +137,7 @@ bool patch_from(const hydro_patch& p, PatchDev* out, int64_t* len) {
   P.sy = int32_t(rp);
   P.sz = int32_t(sp);
   P.base0 = p.offset_elems + io;
+  P.ng = p.ng;
   for (int a = 0; a < 3; ++a) {
     P.n[a] = n[a];
     P.dx[a] = dx[a];
@@ -1409,6 +1411,100 @@ int hydro_burn(hydro_ctx* c, void* X, size_t x_bytes, const hydro_network* net, 
   }
   HIP_TRY(launch_burn(L, c->stream));
   return HYDRO_OK;
+}
+
+int hydro_fill_ghosts(hydro_ctx* c) {
+  if (!c) return fail(HYDRO_EINVAL, "null context");
+  LaunchAmr L{};
+  L.op = kAmrFill;
+  L.fp64 = c->fp64;
+  L.pool = c->pool;
+  L.patches = c->batch ? c->d_patches : nullptr;
+  L.single = c->single;
+  L.npatch = c->batch ? c->npatch : 1;
+  L.ng = c->batch ? 0 : c->desc.ng;
+  for (int i = 0; i < 6; ++i) L.bc[i] = c->desc.bc[i];
+  int64_t most = 0;
+  int maxg = 0;
+  for (const PatchDev& P : c->batch ? c->patches : std::vector<PatchDev>{c->single}) {
+    const int64_t g = P.ng;
+    most = std::max(most, (P.n[0] + 2 * g) * (P.n[1] + 2 * g) * (P.n[2] + 2 * g));
+    maxg = std::max(maxg, P.ng);
+  }
+  if (maxg == 0) return HYDRO_OK;  // no stored ghosts
+  L.cells = most;
+  HIP_TRY(launch_amr(L, c->stream));
+  return HYDRO_OK;
+}
+
+namespace {
+
+// Checks one link of a restriction (prolong = false) or prolongation.
+int check_link(const hydro_ctx* c, const hydro_amr_link& k, bool prolong, bool ghosts_only) {
+  if (k.fine < 0 || k.fine >= c->npatch || k.coarse < 0 || k.coarse >= c->npatch ||
+      k.fine == k.coarse)
+    return fail(HYDRO_EINVAL, "link patch indices out of range");
+  const PatchDev& F = c->patches[size_t(k.fine)];
+  const PatchDev& C = c->patches[size_t(k.coarse)];
+  const int o[3] = {k.ox, k.oy, k.oz};
+  for (int a = 0; a < 3; ++a) {
+    if (F.n[a] % 2) return fail(HYDRO_EINVAL, "fine patch extents must be even");
+    if (!prolong) {
+      if (o[a] < 0 || o[a] + F.n[a] / 2 > C.n[a])
+        return fail(HYDRO_EINVAL, "the fine patch must lie inside the coarse interior");
+    } else {
+      const int g = ghosts_only ? F.ng : 0;
+      const int64_t lo = int64_t(o[a]) + ((-g) >> 1) - 1;
+      const int64_t hi = int64_t(o[a]) + ((F.n[a] + g - 1) >> 1) + 1;
+      if (lo < -C.ng || hi > int64_t(C.n[a]) + C.ng - 1)
+        return fail(HYDRO_EINVAL, "the coarse patch (with its ghosts) must cover the parents "
+                                  "and their neighbours");
+    }
+  }
+  return HYDRO_OK;
+}
+
+int amr_links(hydro_ctx* c, const hydro_amr_link* links, int32_t n, int op, int ghosts_only) {
+  if (!c || (!links && n > 0) || n < 0) return fail(HYDRO_EINVAL, "bad arguments");
+  if (!c->batch) return fail(HYDRO_ESTATE, "AMR links join patches of a batch");
+  for (int32_t i = 0; i < n; ++i) {
+    int rc = check_link(c, links[i], op == kAmrProlong, ghosts_only != 0);
+    if (rc) return rc;
+  }
+  for (int32_t b = 0; b < n; b += kAmrLinksPerLaunch) {
+    LaunchAmr L{};
+    L.op = op;
+    L.fp64 = c->fp64;
+    L.pool = c->pool;
+    L.patches = c->d_patches;
+    L.npatch = c->npatch;
+    L.ghosts_only = ghosts_only;
+    L.nlinks = std::min<int32_t>(kAmrLinksPerLaunch, n - b);
+    int64_t most = 0;
+    for (int32_t i = 0; i < L.nlinks; ++i) {
+      const hydro_amr_link& k = links[b + i];
+      L.links[i] = AmrLink{k.fine, k.coarse, k.ox, k.oy, k.oz, 0};
+      const PatchDev& F = c->patches[size_t(k.fine)];
+      const int64_t g = (op == kAmrProlong && ghosts_only) ? F.ng : 0;
+      const int64_t cells = op == kAmrRestrict
+                                ? int64_t(F.n[0] / 2) * (F.n[1] / 2) * (F.n[2] / 2)
+                                : (F.n[0] + 2 * g) * (F.n[1] + 2 * g) * (F.n[2] + 2 * g);
+      most = std::max(most, cells);
+    }
+    L.cells = most;
+    HIP_TRY(launch_amr(L, c->stream));
+  }
+  return HYDRO_OK;
+}
+
+}  // namespace
+
+int hydro_amr_restrict(hydro_ctx* c, const hydro_amr_link* links, int32_t n) {
+  return amr_links(c, links, n, kAmrRestrict, 0);
+}
+
+int hydro_amr_prolong(hydro_ctx* c, const hydro_amr_link* links, int32_t n, int ghosts_only) {
+  return amr_links(c, links, n, kAmrProlong, ghosts_only ? 1 : 0);
 }
 
 int hydro_get_time(hydro_ctx* c, double* t, int64_t* step) {

@@ -101,7 +101,36 @@ struct LaunchBurn {
   double B[kBurnMaxSpecies];       // energy released in making species s from species 0
 };
 
+// AMR operators (amr.hip).
+constexpr int kAmrFill = 0, kAmrRestrict = 1, kAmrProlong = 2;
+constexpr int kAmrLinksPerLaunch = 32;
+constexpr int kAmrMaxBlocks = 4096;
+
+// A fine patch inside a coarse one (refinement ratio 2): fine cell (0,0,0)
+// is the first child of coarse cell (ox, oy, oz).
+struct AmrLink {
+  int32_t fine, coarse;
+  int32_t ox, oy, oz;
+  int32_t pad;
+};
+
+struct LaunchAmr {
+  int32_t op;                        // kAmrFill, kAmrRestrict or kAmrProlong
+  int32_t fp64;
+  void* pool;
+  const PatchDev* patches;           // batch: device patch table; null: single grid
+  PatchDev single;
+  int32_t npatch;
+  int32_t ng;                        // single grid: stored ghost layers
+  int32_t bc[6];
+  AmrLink links[kAmrLinksPerLaunch];
+  int32_t nlinks;
+  int32_t ghosts_only;               // prolongation: the fine ghost shell only
+  int64_t cells;                     // most cells one workgroup row walks (grid sizing)
+};
+
 hipError_t launch_sweep(const LaunchSweep& L, hipStream_t st);
+hipError_t launch_amr(const LaunchAmr& L, hipStream_t st);
 hipError_t launch_burn(const LaunchBurn& L, hipStream_t st);
 hipError_t launch_diag_pdf(const LaunchDiag& L, hipStream_t st);
 hipError_t launch_diag_profile(const LaunchDiag& L, hipStream_t st);

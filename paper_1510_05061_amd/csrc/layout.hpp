@@ -18,6 +18,7 @@ struct PatchDev {
   int64_t plane;   // elements per plane of this patch
   int32_t n[3];    // interior cells along x, y, z
   int32_t sy, sz;  // element strides along y and z
+  int32_t ng;      // stored ghost layers on every side
   double dx[3];    // cell widths
   double idx[3];   // 1 / dx per axis, 0 along an axis with one cell
 };

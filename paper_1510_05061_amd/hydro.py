@@ -60,6 +60,19 @@ def make_network(A, Ta, q):
     return net
 
 
+class HydroAmrLink(ctypes.Structure):
+    _fields_ = [("fine", ctypes.c_int32), ("coarse", ctypes.c_int32), ("ox", ctypes.c_int32),
+                ("oy", ctypes.c_int32), ("oz", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+def make_links(links):
+    """hydro_amr_link array from (fine, coarse, ox, oy, oz) tuples."""
+    arr = (HydroAmrLink * max(1, len(links)))()
+    for i, (f, c, ox, oy, oz) in enumerate(links):
+        arr[i].fine, arr[i].coarse, arr[i].ox, arr[i].oy, arr[i].oz = f, c, ox, oy, oz
+    return arr
+
+
 class HydroPatch(ctypes.Structure):
     _fields_ = [
         ("offset_elems", ctypes.c_int64),
@@ -105,6 +118,10 @@ _SIGS = {
     "hydro_diag_profile": ([_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, _vp],
                            ctypes.c_int),
     "hydro_diag_spectrum": ([_vp, _vp], ctypes.c_int),
+    "hydro_fill_ghosts": ([_vp], ctypes.c_int),
+    "hydro_amr_restrict": ([_vp, ctypes.POINTER(HydroAmrLink), ctypes.c_int32], ctypes.c_int),
+    "hydro_amr_prolong": ([_vp, ctypes.POINTER(HydroAmrLink), ctypes.c_int32, ctypes.c_int],
+                          ctypes.c_int),
     "hydro_burn": ([_vp, _vp, _sz, ctypes.POINTER(HydroNetwork), ctypes.c_double, ctypes.c_int32],
                    ctypes.c_int),
     "hydro_get_time": ([_vp, _dp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
@@ -231,6 +248,21 @@ def hydro_burn(ctx, x_ptr, x_bytes, net, dt, nsub):
     """Asynchronous; x_ptr: device composition planes (see hydro_burn)."""
     _check(lib().hydro_burn(ctx, x_ptr, int(x_bytes), ctypes.byref(net), float(dt), int(nsub)),
            "hydro_burn")
+
+
+def hydro_fill_ghosts(ctx):
+    _check(lib().hydro_fill_ghosts(ctx), "hydro_fill_ghosts")
+
+
+def hydro_amr_restrict(ctx, links):
+    arr = make_links(links)
+    _check(lib().hydro_amr_restrict(ctx, arr, len(links)), "hydro_amr_restrict")
+
+
+def hydro_amr_prolong(ctx, links, ghosts_only=False):
+    arr = make_links(links)
+    _check(lib().hydro_amr_prolong(ctx, arr, len(links), int(bool(ghosts_only))),
+           "hydro_amr_prolong")
 
 
 def _pdf(obj, quantity, lo, hi, nbins, out):
@@ -379,6 +411,9 @@ class Grid:
     def totals(self):
         return hydro_totals(self.ctx)
 
+    def fill_ghosts(self):
+        hydro_fill_ghosts(self.ctx)
+
     def pdf(self, quantity, lo, hi, nbins, out=None):
         """Device int64 tensor of nbins + 2 counts (see hydro_diag_pdf)."""
         return _pdf(self, quantity, lo, hi, nbins, out)
@@ -502,6 +537,17 @@ class Batch:
 
     def totals(self):
         return hydro_totals(self.ctx)
+
+    def fill_ghosts(self):
+        hydro_fill_ghosts(self.ctx)
+
+    def restrict(self, links):
+        """links: (fine, coarse, ox, oy, oz) tuples (see hydro_amr_restrict)."""
+        hydro_amr_restrict(self.ctx, links)
+
+    def prolong(self, links, ghosts_only=False):
+        """links: (fine, coarse, ox, oy, oz) tuples (see hydro_amr_prolong)."""
+        hydro_amr_prolong(self.ctx, links, ghosts_only)
 
     def pdf(self, quantity, lo, hi, nbins, out=None):
         """Device int64 tensor of nbins + 2 counts over every patch."""
