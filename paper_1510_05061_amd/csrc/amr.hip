@@ -62,14 +62,14 @@ __global__ void __launch_bounds__(kAmrBlock) fill_ghosts_kernel(AmrArgs<T> a) {
   const PatchDev P = a.patches ? a.patches[blockIdx.y] : a.single;
   const int g = a.patches ? P.ng : a.ng;
   const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
-  const int sx = nx + 2 * g, sy = ny + 2 * g;
-  const int64_t total = int64_t(sx) * sy * (nz + 2 * g);
+  const unsigned sx = unsigned(nx + 2 * g), sxy = sx * unsigned(ny + 2 * g);
+  const unsigned total = sxy * unsigned(nz + 2 * g);  // a stored patch holds < 2^32 cells
   T* p0 = a.pool + P.base0;
-  for (int64_t c = int64_t(blockIdx.x) * kAmrBlock + threadIdx.x; c < total;
-       c += int64_t(gridDim.x) * kAmrBlock) {
-    const int k = int(c / (int64_t(sx) * sy)) - g;
-    const int rem = int(c - int64_t(k + g) * sx * sy);
-    const int j = rem / sx - g, i = rem % sx - g;
+  for (unsigned c = blockIdx.x * kAmrBlock + threadIdx.x; c < total;
+       c += gridDim.x * kAmrBlock) {
+    const unsigned kk = c / sxy, rem = c - kk * sxy;
+    const unsigned jj = rem / sx;
+    const int k = int(kk) - g, j = int(jj) - g, i = int(rem - jj * sx) - g;
     if (i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz) continue;
     bool fx = false, fy = false, fz = false;
     const int si = ghost_src(i, nx, a.bc[0], a.bc[1], fx);
@@ -90,17 +90,18 @@ template <class T>
 __global__ void __launch_bounds__(kAmrBlock) restrict_kernel(AmrArgs<T> a) {
   const AmrLink L = a.links[blockIdx.y];
   const PatchDev F = a.patches[L.fine], C = a.patches[L.coarse];
-  const int cx = F.n[0] / 2, cy = F.n[1] / 2, cz = F.n[2] / 2;
-  const int64_t total = int64_t(cx) * cy * cz;
+  const unsigned cx = unsigned(F.n[0] / 2), cxy = cx * unsigned(F.n[1] / 2);
+  const unsigned total = cxy * unsigned(F.n[2] / 2);
   const T* f0 = a.pool + F.base0;
   T* c0 = a.pool + C.base0;
-  for (int64_t c = int64_t(blockIdx.x) * kAmrBlock + threadIdx.x; c < total;
-       c += int64_t(gridDim.x) * kAmrBlock) {
-    const int k = int(c / (int64_t(cx) * cy));
-    const int rem = int(c - int64_t(k) * cx * cy);
-    const int j = rem / cx, i = rem % cx;
+  if (blockIdx.x * kAmrBlock >= total) return;
+  for (unsigned c = blockIdx.x * kAmrBlock + threadIdx.x; c < total;
+       c += gridDim.x * kAmrBlock) {
+    const unsigned k = c / cxy, rem = c - k * cxy;
+    const unsigned j = rem / cx, i = rem - j * cx;
     const int64_t fb = int64_t(2 * i) + int64_t(2 * j) * F.sy + int64_t(2 * k) * F.sz;
-    const int64_t cb = int64_t(L.ox + i) + int64_t(L.oy + j) * C.sy + int64_t(L.oz + k) * C.sz;
+    const int64_t cb = int64_t(L.ox + int(i)) + int64_t(L.oy + int(j)) * C.sy +
+                       int64_t(L.oz + int(k)) * C.sz;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       const T* f = f0 + fb + v * F.plane;
@@ -134,15 +135,16 @@ __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
   const PatchDev F = a.patches[L.fine], C = a.patches[L.coarse];
   const int nx = F.n[0], ny = F.n[1], nz = F.n[2];
   const int g = a.ghosts_only ? F.ng : 0;
-  const int sx = nx + 2 * g, sy = ny + 2 * g;
-  const int64_t total = int64_t(sx) * sy * (nz + 2 * g);
+  const unsigned sx = unsigned(nx + 2 * g), sxy = sx * unsigned(ny + 2 * g);
+  const unsigned total = sxy * unsigned(nz + 2 * g);
   T* f0 = a.pool + F.base0;
   const T* c0 = a.pool + C.base0;
-  for (int64_t c = int64_t(blockIdx.x) * kAmrBlock + threadIdx.x; c < total;
-       c += int64_t(gridDim.x) * kAmrBlock) {
-    const int k = int(c / (int64_t(sx) * sy)) - g;
-    const int rem = int(c - int64_t(k + g) * sx * sy);
-    const int j = rem / sx - g, i = rem % sx - g;
+  if (blockIdx.x * kAmrBlock >= total) return;
+  for (unsigned c = blockIdx.x * kAmrBlock + threadIdx.x; c < total;
+       c += gridDim.x * kAmrBlock) {
+    const unsigned kk = c / sxy, rem = c - kk * sxy;
+    const unsigned jj = rem / sx;
+    const int k = int(kk) - g, j = int(jj) - g, i = int(rem - jj * sx) - g;
     const bool inside = i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
     if (a.ghosts_only && inside) continue;
     const int64_t pc = int64_t(L.ox + (i >> 1)) + int64_t(L.oy + (j >> 1)) * C.sy +
@@ -184,9 +186,10 @@ template <class T>
 static hipError_t launch_amr_t(const LaunchAmr& L, hipStream_t st) {
   const AmrArgs<T> a = to_aargs<T>(L);
   if (L.op == kAmrFill) {
+    // a batch: a few workgroups per patch striding over its stored cells
     const unsigned ny = L.patches ? unsigned(L.npatch) : 1u;
-    hipLaunchKernelGGL(fill_ghosts_kernel<T>, dim3(amr_blocks(L.cells), ny), dim3(kAmrBlock), 0,
-                       st, a);
+    const unsigned nx = L.patches ? std::min(amr_blocks(L.cells), 32u) : amr_blocks(L.cells);
+    hipLaunchKernelGGL(fill_ghosts_kernel<T>, dim3(nx, ny), dim3(kAmrBlock), 0, st, a);
   } else if (L.op == kAmrRestrict) {
     hipLaunchKernelGGL(restrict_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
                        dim3(kAmrBlock), 0, st, a);

@@ -103,7 +103,7 @@ struct LaunchBurn {
 
 // AMR operators (amr.hip).
 constexpr int kAmrFill = 0, kAmrRestrict = 1, kAmrProlong = 2;
-constexpr int kAmrLinksPerLaunch = 32;
+constexpr int kAmrLinksPerLaunch = 128;  // links passed by value in the kernel arguments
 constexpr int kAmrMaxBlocks = 4096;
 
 // A fine patch inside a coarse one (refinement ratio 2): fine cell (0,0,0)
