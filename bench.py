@@ -637,7 +637,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md)"}))
+                                   "(the path would shard as z-slabs, one per GPU, with a 2-cell halo "
+                                   "exchange before each z sweep and a max all-reduce of the CFL rate)"}))
         sys.exit(2)
     import torch
 

@@ -4,7 +4,10 @@ FP64: every sweep and every step matches the oracle to 1e-12 relative
 (max |gpu - oracle| / max |oracle| per conserved variable) from the same
 input state; dt to 1e-14.  Shapes span several workgroup tiles and ragged
 tails (x widths not a multiple of 64, column lengths not a multiple of the
-segment length).  FP32: the L1 bound derived in the design doc.
+segment length).  FP32: relative L1 error of each conserved quantity within
+2e-6 of the FP64 oracle after one step from an FP32-representable state,
+about 34 units of FP32 round-off (one rounding of the stored state plus three
+sweeps of flux differences).
 """
 import math
 
