@@ -54,6 +54,8 @@ def _load():
                                 ctypes.c_int64, ctypes.POINTER(ctypes.c_long)]
     lib.oracle_sweep.argtypes = [ctypes.POINTER(Params), _dp, ctypes.c_double,
                                  ctypes.c_int, ctypes.POINTER(ctypes.c_long)]
+    lib.oracle_sweep_flux.argtypes = [ctypes.POINTER(Params), _dp, ctypes.c_double,
+                                      ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_long)]
     lib.oracle_run.argtypes = [ctypes.POINTER(Params), _dp, ctypes.c_int64,
                                ctypes.c_double, _dp,
                                ctypes.POINTER(ctypes.c_int64),
@@ -126,6 +128,22 @@ def sweep(p, U, dt, axis):
     if rc != OK:
         raise OracleError(f"oracle_sweep failed ({rc})")
     return fb.value
+
+
+def sweep_flux(p, U, dt, axis):
+    """sweep() that also returns the face fluxes it applied: float64
+    (5, ...) in lab components with n + 1 entries along `axis`, entry i
+    being the face between cells i - 1 and i."""
+    _check_shape(p, U)
+    shape = list(U.shape)
+    shape[3 - axis] += 1
+    F = np.zeros(shape)
+    fb = ctypes.c_long(0)
+    rc = _load().oracle_sweep_flux(ctypes.byref(p), _arr(U), dt, axis,
+                                   F.ctypes.data_as(_dp), ctypes.byref(fb))
+    if rc != OK:
+        raise OracleError(f"oracle_sweep_flux failed ({rc})")
+    return F
 
 
 def run(p, U, nsteps, t_end=0.0, t=0.0, step_index=0):

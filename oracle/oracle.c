@@ -360,7 +360,12 @@ static void fill_ghosts(grid *g, int d, const int bc[6]) {
 /* Sweeps and steps                                                    */
 /* ------------------------------------------------------------------ */
 
-static long sweep_axis(grid *g, int d, const orc_params *p, double dt) {
+/* One sweep along axis d.  fout (may be NULL) receives the face fluxes the
+ * update used: 5 planes (lab components rho, mx, my, mz, E) of the grid's
+ * shape with N + 1 entries along d, entry i being the face between cells
+ * i - 1 and i. */
+static long sweep_axis(grid *g, int d, const orc_params *p, double dt,
+                       double *fout) {
   int perm[3];
   axis_perm(d, perm);
   const int N = g->n[d];
@@ -368,6 +373,9 @@ static long sweep_axis(grid *g, int d, const orc_params *p, double dt) {
   const int M = N + 2 * NG;
   const long npencil = (long)n1 * n2;
   long fallbacks = 0;
+  int fn[3] = {g->n[0], g->n[1], g->n[2]};
+  fn[d] = N + 1;
+  const size_t fplane = (size_t)fn[0] * fn[1] * fn[2];
 
   fill_ghosts(g, d, p->bc);
 
@@ -393,6 +401,22 @@ static long sweep_axis(grid *g, int d, const orc_params *p, double dt) {
       fallbacks += sweep_pencil(pen, N, dt, p->dx[d], p->gamma, p->grav[d],
                                 p->bc[2 * d] == ORC_REFLECT,
                                 p->bc[2 * d + 1] == ORC_REFLECT, W, Wm, Wp, F);
+      if (fout) {
+        for (int i = 0; i <= N; ++i) {
+          /* face i - 1/2 is the face right of stored cell NG - 1 + i */
+          const double *f = F[NG - 1 + i];
+          int idx[3];
+          idx[perm[0]] = i;
+          idx[perm[1]] = a;
+          idx[perm[2]] = b;
+          const size_t o = ((size_t)idx[2] * fn[1] + idx[1]) * fn[0] + idx[0];
+          fout[o] = f[0];
+          fout[(1 + perm[0]) * fplane + o] = f[1];
+          fout[(1 + perm[1]) * fplane + o] = f[2];
+          fout[(1 + perm[2]) * fplane + o] = f[3];
+          fout[4 * fplane + o] = f[4];
+        }
+      }
       for (int c = NG; c < NG + N; ++c) {
         double *dst = cell_at(g, d, c - NG, a, b);
         dst[0] = pen[c][0];
@@ -475,7 +499,7 @@ static long grid_step(grid *g, const orc_params *p, double dt, int64_t step) {
   for (int s = 0; s < 3; ++s) {
     int d = order[s];
     if (g->n[d] == 1) continue;
-    fallbacks += sweep_axis(g, d, p, dt);
+    fallbacks += sweep_axis(g, d, p, dt, NULL);
   }
   return fallbacks;
 }
@@ -519,7 +543,26 @@ int oracle_sweep(const orc_params *p, double *planes, double dt, int d,
   grid g;
   if (grid_alloc(&g, p->n)) return ORC_ENOMEM;
   grid_load(&g, planes);
-  long fb = g.n[d] > 1 ? sweep_axis(&g, d, p, dt) : 0;
+  long fb = g.n[d] > 1 ? sweep_axis(&g, d, p, dt, NULL) : 0;
+  if (fallbacks) *fallbacks = fb;
+  grid_store(&g, planes);
+  grid_free(&g);
+  return ORC_OK;
+}
+
+/* A single sweep like oracle_sweep that also returns the face fluxes it
+ * applied (layout of sweep_axis' fout; the axis needs more than one cell).
+ * Refinement operators use them to make coarse and fine levels agree on the
+ * flux through a coarse-fine face. */
+int oracle_sweep_flux(const orc_params *p, double *planes, double dt, int d,
+                      double *flux, long *fallbacks) {
+  if (!params_ok(p) || d < 0 || d > 2 || !(dt >= 0.0) || !flux || p->n[d] < 2)
+    return ORC_EINVAL;
+  set_threads(p);
+  grid g;
+  if (grid_alloc(&g, p->n)) return ORC_ENOMEM;
+  grid_load(&g, planes);
+  long fb = sweep_axis(&g, d, p, dt, flux);
   if (fallbacks) *fallbacks = fb;
   grid_store(&g, planes);
   grid_free(&g);
