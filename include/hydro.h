@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define HYDRO_ABI_VERSION 2
+#define HYDRO_ABI_VERSION 3
 
 typedef enum hydro_status {
   HYDRO_OK = 0,
@@ -324,6 +324,48 @@ int hydro_amr_restrict(hydro_ctx* c, const hydro_amr_link* links, int32_t n);
  * ghosts included: fill them first) must lie in the coarse patch's stored
  * region.  Same independence rule and errors as hydro_amr_restrict. */
 int hydro_amr_prolong(hydro_ctx* c, const hydro_amr_link* links, int32_t n, int ghosts_only);
+
+/* One subcycled step of a two-level hierarchy with refluxing (Berger &
+ * Colella 1989; the paper's codes refine adaptively without fixing these
+ * operators).  `coarse` is a batch of coarse patches stepped with its own
+ * boundary conditions.  `fine` is a batch whose patch i is the whole stored
+ * box of fine patch i described without ghosts: extents n + 2 fine_ng and
+ * ng = 0, so its outer fine_ng layers (fine_ng >= 2) are the patch's ghost
+ * shell and are swept with it (the boundary conditions of `fine` act only
+ * on that shell's outer edge).  links[i].fine indexes `fine`,
+ * links[i].coarse indexes `coarse`; fine interior cell (0,0,0) is the first
+ * child of coarse interior cell (ox, oy, oz).  n must equal the number of
+ * fine patches, each linked once.  The step, on the stream both contexts
+ * share:
+ *   1. the coarse batch takes one Strang step of dt (sweep order by its
+ *      step counter), each sweep preceded by a flux register of the coarse
+ *      faces on every fine patch's boundary (R_c = dt F);
+ *   2. the fine batch takes two steps of dt/2 (orders by its counter); before
+ *      substep s its ghost shells are prolonged (as hydro_amr_prolong) from
+ *      the coarse data interpolated in time, U_old + (s/2)(U - U_old), and
+ *      each sweep registers the mean over the 2x2 fine faces of every coarse
+ *      face, summed in (t2, t1) order, times dt/2 (R_f);
+ *   3. restriction of every fine interior onto the coarse cells it covers;
+ *   4. refluxing (unless HYDRO_AMR_NO_REFLUX): the uncovered coarse cell
+ *      across each coarse-fine face gains (R_c - R_f)/dx on a patch's low
+ *      side and (R_f - R_c)/dx on its high side, per axis x, y, z, low sides
+ *      before high sides.
+ * Both levels need every axis > 1 cell, equal precision, gamma and gravity,
+ * fine cells exactly half as wide, even fine interior extents, each patch
+ * at least ceil(fine_ng/2) + 1 coarse cells inside the coarse interior, and
+ * patches on one coarse patch at least one coarse cell apart along some
+ * axis.  dt > 0 (for example min(coarse CFL dt, 2 x fine CFL dt)).  Both
+ * step counters advance (by 1 and 2) and the device dt of each context is
+ * recomputed before its next HYDRO_DT_CFL step.  The workspace (256-byte
+ * aligned, hydro_amr_step_workspace_bytes) holds a copy of the coarse pool
+ * and the registers.  Asynchronous.  Errors: HYDRO_EINVAL, HYDRO_ESTATE
+ * (not batches, work lists out of date), HYDRO_EDEVICE. */
+#define HYDRO_AMR_NO_REFLUX 0x1u
+int hydro_amr_step_workspace_bytes(const hydro_ctx* coarse, const hydro_ctx* fine,
+                                   int32_t fine_ng, size_t* bytes);
+int hydro_amr_step(hydro_ctx* coarse, hydro_ctx* fine, const hydro_amr_link* links, int32_t n,
+                   int32_t fine_ng, double dt, uint32_t flags, void* workspace,
+                   size_t ws_bytes);
 
 /* Simulated time and step counter (Synchronous).  hydro_set_time restores a
  * checkpoint: the counter's parity selects the next sweep order, and the

@@ -17,11 +17,21 @@
 //   * restriction: coarse = (sum of the 8 children in (dz, dy, dx) order)/8;
 //   * prolongation: child = ((U_c + s_x D_x) + s_y D_y) + s_z D_z with
 //     s = -1/4 or +1/4 and D the monotonised-central slope from the two
-//     coarse neighbours along each axis.
+//     coarse neighbours along each axis; for the ghosts of a subcycled fine
+//     step, U_c is first interpolated in time, U_old + theta (U - U_old);
+//   * flux registers: the flux of a sweep through the coarse-fine faces,
+//     evaluated from the cells the sweep reads with the sweep's own
+//     arithmetic (euler.hpp), so a coarse register holds the very flux the
+//     coarse update applied; fine fluxes are averaged over the 2 x 2 fine
+//     faces of a coarse face in (t2, t1) order;
+//   * refluxing: the uncovered coarse cell across a coarse-fine face trades
+//     the coarse flux for the fine one, U += (R_c - R_f)/dx on a patch's low
+//     side and (R_f - R_c)/dx on its high side (Berger & Colella 1989).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 
+#include "euler.hpp"
 #include "launch.hpp"
 
 namespace hydro {
@@ -53,7 +63,37 @@ struct AmrArgs {
   int bc[6];
   AmrLink links[kAmrLinksPerLaunch];
   int ghosts_only;
+  T* fpool;                 // fine side of the links
+  const PatchDev* fpatches;
+  int finset;
+  const T* cold;            // prolongation: coarse data at the start of the step
+  double theta;
+  double* reg;
+  int64_t nreg;
+  int link0, maxface;
+  int axis, side, fine;
+  double dt, weight, gamma, grav;
 };
+
+// Fine patch of a link: the table entry, or the patch inside a ghost-free
+// stored box whose outer `inset` layers are its ghost shell.
+__device__ __forceinline__ PatchDev fine_patch(const PatchDev* t, int i, int inset) {
+  PatchDev F = t[i];
+  if (inset) {
+    F.base0 += int64_t(inset) * (1 + int64_t(F.sy) + int64_t(F.sz));
+    for (int a = 0; a < 3; ++a) F.n[a] -= 2 * inset;
+    F.ng = inset;
+  }
+  return F;
+}
+
+// Element stride of an axis, and the two transverse axes of a sweep along
+// `axis` in ascending order.
+__device__ __forceinline__ int64_t axis_stride(const PatchDev& P, int a) {
+  return a == 0 ? 1 : a == 1 ? int64_t(P.sy) : int64_t(P.sz);
+}
+__device__ __forceinline__ int t1_of(int axis) { return axis == 0 ? 1 : 0; }
+__device__ __forceinline__ int t2_of(int axis) { return axis == 2 ? 1 : 2; }
 
 // Every stored ghost cell of the grid (y = 0) or of patch blockIdx.y, from
 // the interior.
@@ -89,10 +129,10 @@ __global__ void __launch_bounds__(kAmrBlock) fill_ghosts_kernel(AmrArgs<T> a) {
 template <class T>
 __global__ void __launch_bounds__(kAmrBlock) restrict_kernel(AmrArgs<T> a) {
   const AmrLink L = a.links[blockIdx.y];
-  const PatchDev F = a.patches[L.fine], C = a.patches[L.coarse];
+  const PatchDev F = fine_patch(a.fpatches, L.fine, a.finset), C = a.patches[L.coarse];
   const unsigned cx = unsigned(F.n[0] / 2), cxy = cx * unsigned(F.n[1] / 2);
   const unsigned total = cxy * unsigned(F.n[2] / 2);
-  const T* f0 = a.pool + F.base0;
+  const T* f0 = a.fpool + F.base0;
   T* c0 = a.pool + C.base0;
   if (blockIdx.x * kAmrBlock >= total) return;
   for (unsigned c = blockIdx.x * kAmrBlock + threadIdx.x; c < total;
@@ -132,13 +172,15 @@ __device__ __forceinline__ double mc_slope(double a, double b) {
 template <class T>
 __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
   const AmrLink L = a.links[blockIdx.y];
-  const PatchDev F = a.patches[L.fine], C = a.patches[L.coarse];
+  const PatchDev F = fine_patch(a.fpatches, L.fine, a.finset), C = a.patches[L.coarse];
   const int nx = F.n[0], ny = F.n[1], nz = F.n[2];
   const int g = a.ghosts_only ? F.ng : 0;
   const unsigned sx = unsigned(nx + 2 * g), sxy = sx * unsigned(ny + 2 * g);
   const unsigned total = sxy * unsigned(nz + 2 * g);
-  T* f0 = a.pool + F.base0;
+  T* f0 = a.fpool + F.base0;
   const T* c0 = a.pool + C.base0;
+  const T* o0 = a.cold ? a.cold + C.base0 : nullptr;
+  const double th = a.theta;
   if (blockIdx.x * kAmrBlock >= total) return;
   for (unsigned c = blockIdx.x * kAmrBlock + threadIdx.x; c < total;
        c += gridDim.x * kAmrBlock) {
@@ -155,11 +197,120 @@ __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       const T* q = c0 + pc + v * C.plane;
-      const double u = double(q[0]);
-      const double dx = mc_slope(u - double(q[-1]), double(q[1]) - u);
-      const double dy = mc_slope(u - double(q[-C.sy]), double(q[C.sy]) - u);
-      const double dz = mc_slope(u - double(q[-C.sz]), double(q[C.sz]) - u);
+      const T* qo = o0 ? o0 + pc + v * C.plane : nullptr;
+      // coarse value at offset d, interpolated in time when a start copy is given
+      auto cv = [&](int64_t d) {
+        if (!qo) return double(q[d]);
+        const double o = double(qo[d]);
+        return o + th * (double(q[d]) - o);
+      };
+      const double u = cv(0);
+      const double dx = mc_slope(u - cv(-1), cv(1) - u);
+      const double dy = mc_slope(u - cv(-C.sy), cv(C.sy) - u);
+      const double dz = mc_slope(u - cv(-C.sz), cv(C.sz) - u);
       f0[dst + v * F.plane] = T(((u + ox * dx) + oy * dy) + oz * dz);
+    }
+  }
+}
+
+// Flux through the face between cells f - 1 and f along `axis` at
+// transverse indices (i1, i2), from the four cells f - 2 .. f + 1 exactly as
+// a sweep computes it (interior cells: the full gravity half kick).
+// Returned in lab components (rho, mx, my, mz, E).
+template <class T>
+__device__ __forceinline__ void face_flux(const T* p0, const PatchDev& P, int axis, int f,
+                                          int i1, int i2, const SweepConst<T>& k,
+                                          double out[5]) {
+  const int a1 = t1_of(axis), a2 = t2_of(axis);
+  const int64_t sd = axis_stride(P, axis);
+  const int64_t c0 = int64_t(f) * sd + int64_t(i1) * axis_stride(P, a1) +
+                     int64_t(i2) * axis_stride(P, a2);
+  Prim<T> W[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const T* q = p0 + c0 + (m - 2) * sd;
+    Cons<T> U;
+    U.r = q[0];
+    U.mn = q[(1 + axis) * P.plane];
+    U.mt1 = q[(1 + a1) * P.plane];
+    U.mt2 = q[(1 + a2) * P.plane];
+    U.e = q[4 * P.plane];
+    W[m] = to_prim(U, k);
+  }
+  Prim<T> Wm0, Wp0, Wm1, Wp1;
+  face_states(W[0], W[1], W[2], k, k.kick, Wm0, Wp0);  // cell f - 1
+  face_states(W[1], W[2], W[3], k, k.kick, Wm1, Wp1);  // cell f
+  const Cons<T> F = hllc(Wp0, Wm1, k);
+  out[0] = double(F.r);
+  out[1 + axis] = double(F.mn);
+  out[1 + a1] = double(F.mt1);
+  out[1 + a2] = double(F.mt2);
+  out[4] = double(F.e);
+}
+
+// Flux registers of link blockIdx.y, side blockIdx.z, along a.axis: coarse
+// faces (a.fine = 0) or the means of the fine faces (a.fine = 1), times
+// a.weight, added to the register.
+template <class T>
+__global__ void __launch_bounds__(kAmrBlock) flux_reg_kernel(AmrArgs<T> a) {
+  const AmrLink L = a.links[blockIdx.y];
+  const int side = int(blockIdx.z);
+  const PatchDev F = fine_patch(a.fpatches, L.fine, a.finset);
+  const int axis = a.axis, a1 = t1_of(axis), a2 = t2_of(axis);
+  const int m1 = F.n[a1] / 2, m2 = F.n[a2] / 2;
+  const int nface = m1 * m2;
+  const int o[3] = {L.ox, L.oy, L.oz};
+  double* reg = a.reg + (a.fine ? a.nreg : 0) +
+                (((int64_t(a.link0) + blockIdx.y) * 3 + axis) * 2 + side) * a.maxface * 5;
+  const SweepConst<T> k = make_const<T>(a.dt, a.fine ? F.dx[axis] : a.patches[L.coarse].dx[axis],
+                                        a.gamma, a.grav);
+  for (int fc = blockIdx.x * kAmrBlock + threadIdx.x; fc < nface; fc += gridDim.x * kAmrBlock) {
+    const int j1 = fc % m1, j2 = fc / m1;
+    double acc[5];
+    if (!a.fine) {
+      const PatchDev C = a.patches[L.coarse];
+      const int f = o[axis] + (side ? F.n[axis] / 2 : 0);
+      face_flux(a.pool + C.base0, C, axis, f, o[a1] + j1, o[a2] + j2, k, acc);
+      for (int v = 0; v < 5; ++v) reg[int64_t(fc) * 5 + v] += a.weight * acc[v];
+    } else {
+      const int f = side ? F.n[axis] : 0;
+      double s[5];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {  // (t2, t1) offsets (0,0), (0,1), (1,0), (1,1)
+        face_flux(a.fpool + F.base0, F, axis, f, 2 * j1 + (q & 1), 2 * j2 + (q >> 1), k, acc);
+        for (int v = 0; v < 5; ++v) s[v] = q == 0 ? acc[v] : s[v] + acc[v];
+      }
+      for (int v = 0; v < 5; ++v) reg[int64_t(fc) * 5 + v] += a.weight * (0.25 * s[v]);
+    }
+  }
+}
+
+// Refluxing of link blockIdx.y across its a.side faces along a.axis.
+template <class T>
+__global__ void __launch_bounds__(kAmrBlock) reflux_kernel(AmrArgs<T> a) {
+  const AmrLink L = a.links[blockIdx.y];
+  const PatchDev F = fine_patch(a.fpatches, L.fine, a.finset);
+  const PatchDev C = a.patches[L.coarse];
+  const int axis = a.axis, a1 = t1_of(axis), a2 = t2_of(axis), side = a.side;
+  const int m1 = F.n[a1] / 2, m2 = F.n[a2] / 2;
+  const int nface = m1 * m2;
+  const int o[3] = {L.ox, L.oy, L.oz};
+  const int64_t ro = (((int64_t(a.link0) + blockIdx.y) * 3 + axis) * 2 + side) * a.maxface * 5;
+  const double* rc = a.reg + ro;
+  const double* rf = a.reg + a.nreg + ro;
+  const int c = side ? o[axis] + F.n[axis] / 2 : o[axis] - 1;  // the uncovered coarse cell
+  const double dx = C.dx[axis];
+  T* c0 = a.pool + C.base0;
+  for (int fc = blockIdx.x * kAmrBlock + threadIdx.x; fc < nface; fc += gridDim.x * kAmrBlock) {
+    const int j1 = fc % m1, j2 = fc / m1;
+    const int64_t cell = int64_t(c) * axis_stride(C, axis) +
+                         int64_t(o[a1] + j1) * axis_stride(C, a1) +
+                         int64_t(o[a2] + j2) * axis_stride(C, a2);
+    for (int v = 0; v < 5; ++v) {
+      const double rcv = rc[int64_t(fc) * 5 + v], rfv = rf[int64_t(fc) * 5 + v];
+      const double delta = side ? rfv - rcv : rcv - rfv;
+      T* u = c0 + cell + v * C.plane;
+      *u = T(double(*u) + delta / dx);
     }
   }
 }
@@ -174,8 +325,26 @@ static AmrArgs<T> to_aargs(const LaunchAmr& L) {
   for (int i = 0; i < 6; ++i) a.bc[i] = L.bc[i];
   for (int i = 0; i < L.nlinks; ++i) a.links[i] = L.links[i];
   a.ghosts_only = L.ghosts_only;
+  a.fpool = L.fpool ? static_cast<T*>(L.fpool) : a.pool;
+  a.fpatches = L.fpatches ? L.fpatches : L.patches;
+  a.finset = L.finset;
+  a.cold = static_cast<const T*>(L.cold);
+  a.theta = L.theta;
+  a.reg = L.reg;
+  a.nreg = L.nreg;
+  a.link0 = L.link0;
+  a.maxface = L.maxface;
+  a.axis = L.axis;
+  a.side = L.side;
+  a.fine = L.fine;
+  a.dt = L.dt;
+  a.weight = L.weight;
+  a.gamma = L.gamma;
+  a.grav = L.grav;
   return a;
 }
+
+static_assert(sizeof(AmrArgs<double>) <= 4096, "AMR kernel arguments exceed 4 KiB");
 
 static unsigned amr_blocks(int64_t cells) {
   return unsigned(std::max<int64_t>(1, std::min<int64_t>((cells + kAmrBlock - 1) / kAmrBlock,
@@ -193,15 +362,25 @@ static hipError_t launch_amr_t(const LaunchAmr& L, hipStream_t st) {
   } else if (L.op == kAmrRestrict) {
     hipLaunchKernelGGL(restrict_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
                        dim3(kAmrBlock), 0, st, a);
-  } else {
+  } else if (L.op == kAmrProlong) {
     hipLaunchKernelGGL(prolong_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
+                       dim3(kAmrBlock), 0, st, a);
+  } else if (L.op == kAmrFlux) {
+    hipLaunchKernelGGL(flux_reg_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks), 2u),
+                       dim3(kAmrBlock), 0, st, a);
+  } else {
+    hipLaunchKernelGGL(reflux_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
                        dim3(kAmrBlock), 0, st, a);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_amr(const LaunchAmr& L, hipStream_t st) {
+  if (L.op < kAmrFill || L.op > kAmrReflux) return hipErrorInvalidValue;
   if (L.op != kAmrFill && (!L.patches || L.nlinks < 1 || L.nlinks > kAmrLinksPerLaunch))
+    return hipErrorInvalidValue;
+  if ((L.op == kAmrFlux || L.op == kAmrReflux) &&
+      (!L.reg || L.maxface < 1 || L.axis < 0 || L.axis > 2 || L.side < 0 || L.side > 1))
     return hipErrorInvalidValue;
   return L.fp64 ? launch_amr_t<double>(L, st) : launch_amr_t<float>(L, st);
 }

@@ -9,6 +9,7 @@
 #include <sys/stat.h>
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -1505,6 +1506,200 @@ int hydro_amr_restrict(hydro_ctx* c, const hydro_amr_link* links, int32_t n) {
 
 int hydro_amr_prolong(hydro_ctx* c, const hydro_amr_link* links, int32_t n, int ghosts_only) {
   return amr_links(c, links, n, kAmrProlong, ghosts_only ? 1 : 0);
+}
+
+namespace {
+
+// Largest number of coarse faces on one side of a fine patch of `fine`
+// (stored boxes with `g` ghost layers).
+int64_t level_maxface(const hydro_ctx* fine, int g) {
+  int64_t m = 1;
+  for (const PatchDev& P : fine->patches) {
+    const int64_t n[3] = {(P.n[0] - 2 * g) / 2, (P.n[1] - 2 * g) / 2, (P.n[2] - 2 * g) / 2};
+    m = std::max({m, n[1] * n[2], n[0] * n[2], n[0] * n[1]});
+  }
+  return m;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Checks the two levels of hydro_amr_step and their links.
+int check_level(const hydro_ctx* coarse, const hydro_ctx* fine, const hydro_amr_link* links,
+                int32_t n, int g) {
+  if (!coarse || !fine || coarse == fine) return fail(HYDRO_EINVAL, "two distinct contexts needed");
+  if (!coarse->batch || !fine->batch) return fail(HYDRO_ESTATE, "both levels must be batches");
+  if (coarse->fp64 != fine->fp64) return fail(HYDRO_EINVAL, "the levels differ in precision");
+  if (coarse->stream != fine->stream) return fail(HYDRO_EINVAL, "the levels must share a stream");
+  if (coarse->desc.gamma != fine->desc.gamma) return fail(HYDRO_EINVAL, "the levels differ in gamma");
+  for (int a = 0; a < 3; ++a)
+    if (coarse->desc.grav[a] != fine->desc.grav[a])
+      return fail(HYDRO_EINVAL, "the levels differ in gravity");
+  if (!items_current(coarse) || !items_current(fine))
+    return fail(HYDRO_ESTATE, "batch work lists out of date");
+  if (g < 2) return fail(HYDRO_EINVAL, "fine patches need at least 2 ghost layers");
+  if (!links || n != fine->npatch) return fail(HYDRO_EINVAL, "one link per fine patch needed");
+  const int m = (g + 1) / 2 + 1;  // coarse cells between a patch and the coarse edge
+  std::vector<int> seen(size_t(fine->npatch), 0);
+  for (int32_t i = 0; i < n; ++i) {
+    const hydro_amr_link& k = links[i];
+    if (k.fine < 0 || k.fine >= fine->npatch || k.coarse < 0 || k.coarse >= coarse->npatch)
+      return fail(HYDRO_EINVAL, "link patch indices out of range");
+    if (seen[size_t(k.fine)]++) return fail(HYDRO_EINVAL, "a fine patch is linked twice");
+    const PatchDev& F = fine->patches[size_t(k.fine)];
+    const PatchDev& C = coarse->patches[size_t(k.coarse)];
+    const int o[3] = {k.ox, k.oy, k.oz};
+    for (int a = 0; a < 3; ++a) {
+      const int nf = F.n[a] - 2 * g;
+      if (C.n[a] < 2 || nf < 2 || nf % 2)
+        return fail(HYDRO_EINVAL, "every axis needs > 1 coarse cell and even fine extents");
+      if (F.dx[a] * 2.0 != C.dx[a]) return fail(HYDRO_EINVAL, "fine cells must be half as wide");
+      if (o[a] < m || int64_t(o[a]) + nf / 2 + m > C.n[a])
+        return fail(HYDRO_EINVAL, "fine patch too close to the coarse edge");
+    }
+    for (int32_t j = 0; j < i; ++j) {
+      const hydro_amr_link& q = links[j];
+      if (q.coarse != k.coarse) continue;
+      const PatchDev& Q = fine->patches[size_t(q.fine)];
+      const int p[3] = {q.ox, q.oy, q.oz};
+      bool apart = false;
+      for (int a = 0; a < 3; ++a) {
+        const int hk = o[a] + (F.n[a] - 2 * g) / 2, hq = p[a] + (Q.n[a] - 2 * g) / 2;
+        apart = apart || p[a] >= hk + 1 || o[a] >= hq + 1;
+      }
+      if (!apart) return fail(HYDRO_EINVAL, "fine patches must be a coarse cell apart");
+    }
+  }
+  return HYDRO_OK;
+}
+
+// Launches one AMR operator over every link in chunks of the kernel limit.
+int level_launch(const hydro_ctx* coarse, const hydro_ctx* fine, const hydro_amr_link* links,
+                 int32_t n, int g, int op, const std::function<void(LaunchAmr&)>& fill) {
+  for (int32_t b = 0; b < n; b += kAmrLinksPerLaunch) {
+    LaunchAmr L{};
+    L.op = op;
+    L.fp64 = coarse->fp64;
+    L.pool = coarse->pool;
+    L.patches = coarse->d_patches;
+    L.npatch = coarse->npatch;
+    L.fpool = fine->pool;
+    L.fpatches = fine->d_patches;
+    L.finset = g;
+    L.link0 = b;
+    L.nlinks = std::min<int32_t>(kAmrLinksPerLaunch, n - b);
+    int64_t most = 0;
+    for (int32_t i = 0; i < L.nlinks; ++i) {
+      const hydro_amr_link& k = links[b + i];
+      L.links[i] = AmrLink{k.fine, k.coarse, k.ox, k.oy, k.oz, 0};
+      const PatchDev& F = fine->patches[size_t(k.fine)];
+      const int64_t nf[3] = {F.n[0] - 2 * g, F.n[1] - 2 * g, F.n[2] - 2 * g};
+      int64_t cells = 0;
+      if (op == kAmrRestrict) cells = (nf[0] / 2) * (nf[1] / 2) * (nf[2] / 2);
+      else if (op == kAmrProlong) cells = int64_t(F.n[0]) * F.n[1] * F.n[2];
+      else cells = std::max({nf[1] * nf[2], nf[0] * nf[2], nf[0] * nf[1]}) / 4;
+      most = std::max(most, cells);
+    }
+    L.cells = most;
+    fill(L);
+    HIP_TRY(launch_amr(L, coarse->stream));
+  }
+  return HYDRO_OK;
+}
+
+// The sweeps of one step of a level (no fused plane launch), each preceded
+// by the flux registers of its axis; then the step bookkeeping.
+int level_sweeps(hydro_ctx* c, const hydro_ctx* coarse, const hydro_ctx* fine,
+                 const hydro_amr_link* links, int32_t n, int g, bool fine_side, double dt,
+                 double* reg, int64_t nreg, int64_t maxface) {
+  static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
+  const int* order = (c->step & 1) ? odd : even;
+  HIP_TRY(launch_set_dt(c->scal, dt, c->stream));
+  for (int i = 0; i < 3; ++i) {
+    const int ax = order[i];
+    int rc = level_launch(coarse, fine, links, n, g, kAmrFlux, [&](LaunchAmr& L) {
+      L.reg = reg;
+      L.nreg = nreg;
+      L.maxface = int32_t(maxface);
+      L.axis = ax;
+      L.fine = fine_side ? 1 : 0;
+      L.dt = dt;
+      L.weight = dt;
+      L.gamma = c->desc.gamma;
+      L.grav = c->desc.grav[ax];
+    });
+    if (rc) return rc;
+    if (c->nitems[ax] > 0) HIP_TRY(launch_sweep(sweep_launch(c, ax, i == 2 ? 1 : 0), c->stream));
+  }
+  HIP_TRY(launch_finish_step(c->scal, c->stream));
+  c->step += 1;
+  c->dt_valid = false;
+  return HYDRO_OK;
+}
+
+}  // namespace
+
+int hydro_amr_step_workspace_bytes(const hydro_ctx* coarse, const hydro_ctx* fine,
+                                   int32_t fine_ng, size_t* bytes) {
+  if (!coarse || !fine || !bytes) return fail(HYDRO_EINVAL, "null argument");
+  if (!coarse->batch || !fine->batch) return fail(HYDRO_ESTATE, "both levels must be batches");
+  if (fine_ng < 2) return fail(HYDRO_EINVAL, "fine patches need at least 2 ghost layers");
+  const int64_t nreg = int64_t(fine->npatch) * 30 * level_maxface(fine, fine_ng);
+  *bytes = align256(coarse->pool_bytes) + size_t(2 * nreg) * sizeof(double);
+  return HYDRO_OK;
+}
+
+int hydro_amr_step(hydro_ctx* coarse, hydro_ctx* fine, const hydro_amr_link* links, int32_t n,
+                   int32_t fine_ng, double dt, uint32_t flags, void* workspace,
+                   size_t ws_bytes) {
+  int rc = check_level(coarse, fine, links, n, fine_ng);
+  if (rc) return rc;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HYDRO_EINVAL, "dt must be > 0 and finite");
+  if (flags & ~uint32_t(HYDRO_AMR_NO_REFLUX)) return fail(HYDRO_EINVAL, "unknown flags");
+  size_t need = 0;
+  rc = hydro_amr_step_workspace_bytes(coarse, fine, fine_ng, &need);
+  if (rc) return rc;
+  if (!workspace || ws_bytes < need) return fail(HYDRO_EINVAL, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(HYDRO_EINVAL, "workspace misaligned");
+  const int g = fine_ng;
+  const int64_t maxface = level_maxface(fine, g);
+  const int64_t nreg = int64_t(n) * 30 * maxface;
+  char* ws = static_cast<char*>(workspace);
+  void* cold = ws;
+  double* reg = reinterpret_cast<double*>(ws + align256(coarse->pool_bytes));
+  hipStream_t st = coarse->stream;
+  HIP_TRY(hipMemcpyAsync(cold, coarse->pool, coarse->pool_bytes, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemsetAsync(reg, 0, size_t(2 * nreg) * sizeof(double), st));
+  // 1. the coarse step, registering its fluxes through the coarse-fine faces
+  rc = level_sweeps(coarse, coarse, fine, links, n, g, false, dt, reg, nreg, maxface);
+  if (rc) return rc;
+  // 2. two fine substeps, ghosts from the coarse data interpolated in time
+  for (int s = 0; s < 2; ++s) {
+    rc = level_launch(coarse, fine, links, n, g, kAmrProlong, [&](LaunchAmr& L) {
+      L.ghosts_only = 1;
+      L.cold = cold;
+      L.theta = 0.5 * s;
+    });
+    if (rc) return rc;
+    rc = level_sweeps(fine, coarse, fine, links, n, g, true, 0.5 * dt, reg, nreg, maxface);
+    if (rc) return rc;
+  }
+  // 3. restriction, 4. refluxing
+  rc = level_launch(coarse, fine, links, n, g, kAmrRestrict, [](LaunchAmr&) {});
+  if (rc) return rc;
+  if (!(flags & HYDRO_AMR_NO_REFLUX)) {
+    for (int ax = 0; ax < 3; ++ax)
+      for (int side = 0; side < 2; ++side) {
+        rc = level_launch(coarse, fine, links, n, g, kAmrReflux, [&](LaunchAmr& L) {
+          L.reg = reg;
+          L.nreg = nreg;
+          L.maxface = int32_t(maxface);
+          L.axis = ax;
+          L.side = side;
+        });
+        if (rc) return rc;
+      }
+  }
+  return HYDRO_OK;
 }
 
 int hydro_get_time(hydro_ctx* c, double* t, int64_t* step) {

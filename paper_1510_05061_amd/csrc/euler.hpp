@@ -95,6 +95,23 @@ struct SweepConst {
   bool has_g;     // g along the sweep axis is nonzero
 };
 
+// Constants of a sweep of length dt over cells of width dx along an axis
+// with gravity g, rounded once from FP64 into the arithmetic type.
+template <class T>
+__device__ __forceinline__ SweepConst<T> make_const(double dt, double dx, double gamma,
+                                                    double g) {
+  SweepConst<T> k;
+  k.gamma = T(gamma);
+  k.gm1 = T(gamma - 1.0);
+  k.inv_gm1 = T(1.0 / (gamma - 1.0));
+  double dtdx = dt / dx;
+  k.dtdx = T(dtdx);
+  k.kick = T(0.5 * dt * g);
+  k.dtg = T(dt * g);
+  k.has_g = (g != 0.0);
+  return k;
+}
+
 // Conserved -> primitive; p = (gamma-1)(E - |m|^2 / (2 rho)).
 template <class T>
 __device__ __forceinline__ Prim<T> to_prim(const Cons<T>& U, const SweepConst<T>& k) {

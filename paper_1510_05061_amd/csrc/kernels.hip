@@ -49,21 +49,6 @@ struct SweepArgs {
   DevScalars* scal;
 };
 
-template <class T>
-__device__ __forceinline__ SweepConst<T> make_const(double dt, double dx, double gamma,
-                                                    double g) {
-  SweepConst<T> k;
-  k.gamma = T(gamma);
-  k.gm1 = T(gamma - 1.0);
-  k.inv_gm1 = T(1.0 / (gamma - 1.0));
-  double dtdx = dt / dx;
-  k.dtdx = T(dtdx);
-  k.kick = T(0.5 * dt * g);
-  k.dtg = T(dt * g);
-  k.has_g = (g != 0.0);
-  return k;
-}
-
 // plane indices of (normal, transverse 1, transverse 2) momenta per axis
 template <int AXIS> struct Rot;
 template <> struct Rot<0> { static constexpr int n = 1, t1 = 2, t2 = 3; };

@@ -102,7 +102,7 @@ struct LaunchBurn {
 };
 
 // AMR operators (amr.hip).
-constexpr int kAmrFill = 0, kAmrRestrict = 1, kAmrProlong = 2;
+constexpr int kAmrFill = 0, kAmrRestrict = 1, kAmrProlong = 2, kAmrFlux = 3, kAmrReflux = 4;
 constexpr int kAmrLinksPerLaunch = 128;  // links passed by value in the kernel arguments
 constexpr int kAmrMaxBlocks = 4096;
 
@@ -115,9 +115,9 @@ struct AmrLink {
 };
 
 struct LaunchAmr {
-  int32_t op;                        // kAmrFill, kAmrRestrict or kAmrProlong
+  int32_t op;                        // kAmrFill ... kAmrReflux
   int32_t fp64;
-  void* pool;
+  void* pool;                        // coarse patches (fill: the patches)
   const PatchDev* patches;           // batch: device patch table; null: single grid
   PatchDev single;
   int32_t npatch;
@@ -127,6 +127,27 @@ struct LaunchAmr {
   int32_t nlinks;
   int32_t ghosts_only;               // prolongation: the fine ghost shell only
   int64_t cells;                     // most cells one workgroup row walks (grid sizing)
+  // Fine side of the links (null: the coarse pool and table).  finset > 0:
+  // each fine table entry is a whole stored box without ghosts whose outer
+  // finset layers are the ghost shell of the patch inside.
+  void* fpool;
+  const PatchDev* fpatches;
+  int32_t finset;
+  // prolongation: coarse data at theta in [0, 1] between cold (a copy of
+  // the coarse pool at the start of the step) and the pool; cold null: pool
+  const void* cold;
+  double theta;
+  // flux registers (kAmrFlux, kAmrReflux): register of (link, axis, side,
+  // coarse face, variable) at reg + ((((link0 + l) * 3 + axis) * 2 + side) *
+  // maxface + face) * 5 + v, the fine registers nreg doubles further on
+  double* reg;
+  int64_t nreg;
+  int32_t link0, maxface;
+  int32_t axis, side;                // side: reflux only (flux does both)
+  int32_t fine;                      // kAmrFlux: 1 fine faces, 0 coarse faces
+  double dt;                         // kAmrFlux: sweep length
+  double weight;                     // kAmrFlux: register += weight * flux
+  double gamma, grav;                // kAmrFlux: sweep constants (gravity along axis)
 };
 
 hipError_t launch_sweep(const LaunchSweep& L, hipStream_t st);

@@ -122,6 +122,10 @@ _SIGS = {
     "hydro_amr_restrict": ([_vp, ctypes.POINTER(HydroAmrLink), ctypes.c_int32], ctypes.c_int),
     "hydro_amr_prolong": ([_vp, ctypes.POINTER(HydroAmrLink), ctypes.c_int32, ctypes.c_int],
                           ctypes.c_int),
+    "hydro_amr_step_workspace_bytes": ([_vp, _vp, ctypes.c_int32, ctypes.POINTER(_sz)],
+                                       ctypes.c_int),
+    "hydro_amr_step": ([_vp, _vp, ctypes.POINTER(HydroAmrLink), ctypes.c_int32, ctypes.c_int32,
+                        ctypes.c_double, ctypes.c_uint32, _vp, _sz], ctypes.c_int),
     "hydro_burn": ([_vp, _vp, _sz, ctypes.POINTER(HydroNetwork), ctypes.c_double, ctypes.c_int32],
                    ctypes.c_int),
     "hydro_get_time": ([_vp, _dp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
@@ -263,6 +267,46 @@ def hydro_amr_prolong(ctx, links, ghosts_only=False):
     arr = make_links(links)
     _check(lib().hydro_amr_prolong(ctx, arr, len(links), int(bool(ghosts_only))),
            "hydro_amr_prolong")
+
+
+AMR_NO_REFLUX = 0x1
+
+
+def hydro_amr_step_workspace_bytes(coarse_ctx, fine_ctx, fine_ng):
+    n = _sz(0)
+    _check(lib().hydro_amr_step_workspace_bytes(coarse_ctx, fine_ctx, fine_ng, ctypes.byref(n)),
+           "hydro_amr_step_workspace_bytes")
+    return n.value
+
+
+def hydro_amr_step(coarse_ctx, fine_ctx, links, fine_ng, dt, flags, ws_ptr, ws_bytes):
+    arr = make_links(links)
+    _check(lib().hydro_amr_step(coarse_ctx, fine_ctx, arr, len(links), fine_ng, dt, flags,
+                                ws_ptr, ws_bytes), "hydro_amr_step")
+
+
+class AmrLevels:
+    """A coarse Batch and a fine Batch of whole stored boxes (see
+    hydro_amr_step) joined by (fine, coarse, ox, oy, oz) links, stepped by
+    hydro_amr_step with a workspace this object owns."""
+
+    def __init__(self, coarse, fine, links, fine_ng):
+        torch = _torch()
+        self.coarse, self.fine = coarse, fine
+        self.links = [tuple(k) for k in links]
+        self.fine_ng = int(fine_ng)
+        nbytes = hydro_amr_step_workspace_bytes(coarse.ctx, fine.ctx, self.fine_ng)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=coarse.pool.device)
+
+    def step(self, dt, reflux=True):
+        hydro_amr_step(self.coarse.ctx, self.fine.ctx, self.links, self.fine_ng, dt,
+                       0 if reflux else AMR_NO_REFLUX,
+                       ctypes.c_void_p(self.workspace.data_ptr()),
+                       self.workspace.numel())
+
+    def cfl_dt(self):
+        """Largest stable coarse dt: min(coarse CFL dt, 2 x fine CFL dt)."""
+        return min(self.coarse.cfl_dt(), 2.0 * self.fine.cfl_dt())
 
 
 def _pdf(obj, quantity, lo, hi, nbins, out):

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     for n in _declared():
         assert hasattr(L, n), n
     assert set(_declared()) == set(hydro.exported_symbols())
-    assert L.hydro_abi_version() == 2
+    assert L.hydro_abi_version() == 3
 
 
 def test_status_strings_and_struct_layout():

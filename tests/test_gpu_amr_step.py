@@ -1,0 +1,175 @@
+"""The subcycled two-level step (hydro_amr_step) on the GPU against the
+oracle's level_step: a periodic coarse grid with two fine patches of uneven
+shapes, two steps (both sweep orders), FP64 to 1e-12 and FP32 to an L1
+bound, with and without refluxing; the composite totals conserved on the
+GPU; and the argument errors, all raised on the host before any launch."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import hydro_ic as ic
+import oracle
+from gpu_util import l1_fp32_errors, say, torch
+from oracle import amr
+from paper_1510_05061_amd import hydro
+
+pytestmark = pytest.mark.gpu
+
+G = 4
+GAMMA = 1.4
+SHAPE = (14, 16, 18)                      # coarse (nz, ny, nx)
+DX = (1 / 18, 1 / 16, 1 / 14)
+# fine interior extents (nx, ny, nz) and the coarse cell of fine cell (0,0,0)
+FINE = [((10, 8, 6), (3, 4, 3)), ((6, 8, 8), (11, 7, 6))]
+
+
+def inputs(seed):
+    C = ic.smooth_random(SHAPE, seed, gamma=GAMMA, mach=0.3).U
+    fines = []
+    for i, (n, _) in enumerate(FINE):
+        shp = (n[2] + 2 * G, n[1] + 2 * G, n[0] + 2 * G)
+        fines.append(ic.smooth_random(shp, seed + 10 + i, gamma=GAMMA, mach=0.3).U)
+    return C, fines
+
+
+def device_levels(C, fines, prec, bc_fine=(hydro.OUTFLOW,) * 6):
+    dt = np.float64 if prec == hydro.FP64 else np.float32
+    tc = torch().from_numpy(C.reshape(-1).astype(dt)).to("cuda:0")
+    coarse = hydro.Batch(tc, [(0, SHAPE[2], SHAPE[1], SHAPE[0], 0) + DX], GAMMA,
+                         flags=hydro.FLAG_NO_TUNE)
+    offs, flat = [], []
+    off = 0
+    for F in fines:
+        offs.append(off)
+        flat.append(F.reshape(-1))
+        off += F.size
+        pad = (-off) % 64
+        flat.append(np.zeros(pad))
+        off += pad
+    tf = torch().from_numpy(np.concatenate(flat).astype(dt)).to("cuda:0")
+    patches = []
+    for o, F in zip(offs, fines):
+        nz, ny, nx = F.shape[1:]
+        patches.append((o, nx, ny, nz, 0, DX[0] / 2, DX[1] / 2, DX[2] / 2))
+    fine = hydro.Batch(tf, patches, GAMMA, bc=bc_fine, flags=hydro.FLAG_NO_TUNE)
+    links = [(i, 0) + tuple(o) for i, (_, o) in enumerate(FINE)]
+    return coarse, fine, tc, tf, offs, links
+
+
+def read(tc, tf, offs, fines):
+    C = tc.double().cpu().numpy().reshape((5,) + SHAPE)
+    f = tf.double().cpu().numpy()
+    return C, [f[o:o + F.size].reshape(F.shape) for o, F in zip(offs, fines)]
+
+
+def step_dt(C, fines):
+    pc = oracle.make_params(SHAPE, DX, GAMMA)
+    dtf = min(oracle.cfl_dt(oracle.make_params(F.shape[1:], tuple(h / 2 for h in DX), GAMMA), F)
+              for F in fines)
+    return 0.5 * min(oracle.cfl_dt(pc, C), 2 * dtf)
+
+
+def max_rel(got, want):
+    return max(float(np.abs(got[v] - want[v]).max() / max(np.abs(want[v]).max(), 1e-300))
+               for v in range(5))
+
+
+def composite(C, fines):
+    cov = np.zeros(SHAPE, bool)
+    tot = np.zeros(5)
+    for F, (n, o) in zip(fines, FINE):
+        cov[o[2]:o[2] + n[2] // 2, o[1]:o[1] + n[1] // 2, o[0]:o[0] + n[0] // 2] = True
+        tot += F[:, G:-G, G:-G, G:-G].sum(axis=(1, 2, 3)) / 8
+    return (tot + C[:, ~cov].sum(axis=1)) * np.prod(DX)
+
+
+@pytest.mark.parametrize("reflux", [True, False])
+@pytest.mark.parametrize("prec", [hydro.FP64, hydro.FP32])
+def test_two_steps_match_the_oracle(prec, reflux):
+    say(f"amr step prec={prec} reflux={reflux}")
+    C, fines = inputs(21)
+    if prec == hydro.FP32:
+        C = C.astype(np.float32).astype(np.float64)
+        fines = [F.astype(np.float32).astype(np.float64) for F in fines]
+    coarse, fine, tc, tf, offs, links = device_levels(C, fines, prec)
+    lv = hydro.AmrLevels(coarse, fine, links, G)
+    Cw, fw = C, fines
+    offsets = [o for _, o in FINE]
+    for s in range(2):
+        dt = step_dt(Cw, fw)
+        Cw, fw = amr.level_step(Cw, fw, offsets, G, dt, GAMMA, DX, step_c=s, step_f=2 * s,
+                                reflux=reflux)
+        lv.step(dt, reflux=reflux)
+        Cg, fg = read(tc, tf, offs, fines)
+        if prec == hydro.FP64:
+            e = [max_rel(Cg, Cw)] + [max_rel(a, b) for a, b in zip(fg, fw)]
+            say(f"  step {s} max rel {e}")
+            assert max(e) <= 1e-12, e
+        else:
+            e = [l1_fp32_errors(Cg, Cw)] + [l1_fp32_errors(a[:, G:-G, G:-G, G:-G],
+                                                           b[:, G:-G, G:-G, G:-G])
+                                            for a, b in zip(fg, fw)]
+            say(f"  step {s} L1 {e}")
+            # one step (each starts from the GPU state) on two levels: a few
+            # FP32 roundings per sweep, like the single-grid bound of 2e-6
+            assert max(max(x) for x in e) <= 4e-6, e
+        Cw, fw = Cg, fg          # the next step starts from the GPU state
+    assert coarse.time()[1] == 2 and fine.time()[1] == 4
+    coarse.close()
+    fine.close()
+
+
+def test_composite_totals_are_conserved_on_the_gpu():
+    say("amr step conservation")
+    C, fines = inputs(22)
+    coarse, fine, tc, tf, offs, links = device_levels(C, fines, hydro.FP64)
+    lv = hydro.AmrLevels(coarse, fine, links, G)
+    before = composite(C, fines)
+    scale = np.abs(C).sum(axis=(1, 2, 3)) * np.prod(DX)
+    for s in range(3):
+        lv.step(step_dt(*read(tc, tf, offs, fines)))
+    Cg, fg = read(tc, tf, offs, fines)
+    after = composite(Cg, fg)
+    tot = np.asarray(coarse.totals()[:5])
+    err = np.abs(after - before) / scale
+    say(f"  conservation {err}")
+    assert err.max() < 1e-13, err
+    np.testing.assert_allclose(tot, after, rtol=1e-13, atol=1e-13 * scale.max())
+    coarse.close()
+    fine.close()
+
+
+def test_argument_errors():
+    say("amr step errors")
+    C, fines = inputs(23)
+    coarse, fine, tc, tf, offs, links = device_levels(C, fines, hydro.FP64)
+    lib = hydro.lib()
+    nbytes = hydro.hydro_amr_step_workspace_bytes(coarse.ctx, fine.ctx, G)
+    ws = torch().empty(nbytes, dtype=torch().uint8, device="cuda:0")
+    wp = ctypes.c_void_p(ws.data_ptr())
+
+    def call(lk, g=G, dt=1e-3, flags=0, c=coarse.ctx, f=fine.ctx, nb=nbytes):
+        arr = hydro.make_links(lk)
+        return lib.hydro_amr_step(c, f, arr, len(lk), g, dt, flags, wp, nb)
+
+    E = hydro.HYDRO_EINVAL
+    assert call(links, g=1) == E                                   # too few ghosts
+    assert call([links[0]]) == E                                   # a fine patch unlinked
+    assert call([links[0], links[0]]) == E                         # linked twice
+    assert call([(0, 0, 2, 4, 3), links[1]]) == E                  # too close to the edge
+    assert call([links[0], (1, 0, 8, 4, 3)]) == E                  # touching patch 0
+    assert call([links[0], (1, 1, 11, 7, 6)]) == E                 # no such coarse patch
+    assert call(links, dt=0.0) == E
+    assert call(links, flags=4) == E
+    assert call(links, nb=nbytes - 8) == E
+    assert call(links, f=coarse.ctx) == E                          # one context twice
+    # fine cells not half as wide
+    tf2 = tf.clone()
+    wrong = [(o, F.shape[3], F.shape[2], F.shape[1], 0, DX[0], DX[1] / 2, DX[2] / 2)
+             for o, F in zip(offs, fines)]
+    fine2 = hydro.Batch(tf2, wrong, GAMMA, flags=hydro.FLAG_NO_TUNE)
+    assert call(links, f=fine2.ctx) == E
+    fine2.close()
+    coarse.close()
+    fine.close()
