@@ -213,6 +213,10 @@ def run_gpu(W, prec, args, torch, hydro):
         if W["kind"] != "batch":
             log("reactive source on the evolved state")
             diag["burn"] = burn_timing(obj, W, torch, hydro)
+            if args.workload == "kh":
+                log("two-level AMR step on the evolved state")
+                diag["amr_level"] = amr_level_timing(
+                    U, W, torch, hydro, hydro.FLAG_NO_TUNE if args.no_tune else 0)
         else:
             log("AMR operators on the pool")
             diag["amr"] = amr_timing(obj, W, torch, hydro)
@@ -310,6 +314,76 @@ def amr_timing(obj, W, torch, hydro, reps=5):
         nf = len(links) * 32 ** 3
         out["restrict"] = entry(timed(lambda: obj.restrict(links)), nf * 20 + nf // 8 * 20)
         out["prolong"] = entry(timed(lambda: obj.prolong(links)), nf * 20 + nf // 8 * 20)
+    return out
+
+
+AMR_FINE_N, AMR_FINE_G = 32, 4   # fine interior cells per axis, ghost layers
+
+
+def amr_level_timing(U, W, torch, hydro, flags, reps=5):
+    """Mean device time of one subcycled two-level step (hydro_amr_step,
+    FP32) on the evolved single grid: a coarse batch holding a copy of the
+    grid, and fine patches of 32^3 cells (4 ghost layers, stored 40^3) on a
+    lattice of 16^3-coarse-cell blocks two coarse cells apart covering both
+    shear layers (y = 1/4 and 3/4), filled by copying each coarse cell into
+    its 8 children.  Reported: the step's time, the composite zone-updates
+    per second (coarse cells plus two updates of every fine interior cell),
+    and the time of the same sweeps as plain batch steps (one coarse step of
+    dt, two fine steps of dt/2 over the stored boxes), so the difference is
+    the cost of the registers, ghosts, restriction and refluxing."""
+    nz, ny, nx = U.shape[1:]
+    P = W["P"]
+    n, g = AMR_FINE_N, AMR_FINE_G
+    m, h = n // 2, g // 2
+    lo = h + 2                                  # ceil(g/2) + 1 coarse cells of margin
+    xs = list(range(lo, nx - lo - m + 1, m + 2))
+    zs = list(range(lo, nz - lo - m + 1, m + 2))
+    ys = [ny // 4 - m // 2, 3 * ny // 4 - m // 2]
+    offs = [(x, y, z) for z in zs for y in ys for x in xs]
+    Cp = U.reshape(-1).clone()
+    coarse = hydro.Batch(Cp, [(0, nx, ny, nz, 0) + tuple(P.dx)], P.gamma, P.cfl, P.bc,
+                         flags=flags)
+    box = n + 2 * g
+    per = 5 * box ** 3
+    fpool = torch.empty(per * len(offs), dtype=U.dtype, device=U.device)
+    for i, (x, y, z) in enumerate(offs):
+        sub = U[:, z - h:z + m + h, y - h:y + m + h, x - h:x + m + h]
+        up = sub.repeat_interleave(2, 1).repeat_interleave(2, 2).repeat_interleave(2, 3)
+        fpool[i * per:(i + 1) * per] = up.reshape(-1)
+    fine = hydro.Batch(fpool, [(i * per, box, box, box, 0) + tuple(d / 2 for d in P.dx)
+                               for i in range(len(offs))], P.gamma, P.cfl,
+                       (hydro.OUTFLOW,) * 6, flags=flags)
+    links = [(i, 0) + o for i, o in enumerate(offs)]
+    lv = hydro.AmrLevels(coarse, fine, links, g)
+    dt = 0.5 * lv.cfl_dt()                     # a dozen steps at a fixed dt
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ms = timed(lambda: lv.step(dt))
+    if coarse.error() != hydro.HYDRO_OK or fine.error() != hydro.HYDRO_OK:
+        raise RuntimeError("numeric error flag set in the AMR level step")
+    plain = timed(lambda: (coarse.step(dt), fine.step(0.5 * dt), fine.step(0.5 * dt)))
+    zc = nx * ny * nz
+    zf = len(offs) * n ** 3
+    out = {"patches": len(offs), "fine_n": n, "ghosts": g, "mean_ms": ms,
+           "coarse_config": coarse.config, "fine_config": fine.config,
+           "coarse_zones": zc, "fine_zones": zf,
+           "composite_zone_updates_per_s": (zc + 2 * zf) / (ms * 1e-3),
+           "plain_steps_ms": plain, "overhead_frac": ms / plain - 1.0}
+    coarse.close()
+    fine.close()
+    del lv, Cp, fpool
+    torch.cuda.empty_cache()
     return out
 
 

@@ -168,15 +168,20 @@ __device__ __forceinline__ double mc_slope(double a, double b) {
   return a * b > 0.0 ? copysign(m, a) : 0.0;
 }
 
-// Fine cells (interior, or the stored ghost shell) of link blockIdx.y.
+// Fine cells (interior, or the stored ghost shell) of link blockIdx.y, one
+// coarse parent per thread: the parent's value and its three limited slopes
+// are formed once and give each of its children that is written.
 template <class T>
 __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
   const AmrLink L = a.links[blockIdx.y];
   const PatchDev F = fine_patch(a.fpatches, L.fine, a.finset), C = a.patches[L.coarse];
   const int nx = F.n[0], ny = F.n[1], nz = F.n[2];
   const int g = a.ghosts_only ? F.ng : 0;
-  const unsigned sx = unsigned(nx + 2 * g), sxy = sx * unsigned(ny + 2 * g);
-  const unsigned total = sxy * unsigned(nz + 2 * g);
+  // parents of the fine cells -g .. n + g - 1 along each axis
+  const int lo = (-g) >> 1;
+  const unsigned px = unsigned(((nx + g - 1) >> 1) - lo + 1);
+  const unsigned pxy = px * unsigned(((ny + g - 1) >> 1) - lo + 1);
+  const unsigned total = pxy * unsigned(((nz + g - 1) >> 1) - lo + 1);
   T* f0 = a.fpool + F.base0;
   const T* c0 = a.pool + C.base0;
   const T* o0 = a.cold ? a.cold + C.base0 : nullptr;
@@ -184,17 +189,16 @@ __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
   if (blockIdx.x * kAmrBlock >= total) return;
   for (unsigned c = blockIdx.x * kAmrBlock + threadIdx.x; c < total;
        c += gridDim.x * kAmrBlock) {
-    const unsigned kk = c / sxy, rem = c - kk * sxy;
-    const unsigned jj = rem / sx;
-    const int k = int(kk) - g, j = int(jj) - g, i = int(rem - jj * sx) - g;
-    const bool inside = i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
-    if (a.ghosts_only && inside) continue;
-    const int64_t pc = int64_t(L.ox + (i >> 1)) + int64_t(L.oy + (j >> 1)) * C.sy +
-                       int64_t(L.oz + (k >> 1)) * C.sz;
-    const double ox = (i & 1) ? 0.25 : -0.25, oy = (j & 1) ? 0.25 : -0.25,
-                 oz = (k & 1) ? 0.25 : -0.25;
-    const int64_t dst = int64_t(i) + int64_t(j) * F.sy + int64_t(k) * F.sz;
-#pragma unroll
+    const unsigned kk = c / pxy, rem = c - kk * pxy;
+    const unsigned jj = rem / px;
+    const int pk = int(kk) + lo, pj = int(jj) + lo, pi = int(rem - jj * px) + lo;
+    // a parent whose children are all interior has none in the ghost shell
+    if (a.ghosts_only && pi >= 0 && 2 * pi < nx && pj >= 0 && 2 * pj < ny && pk >= 0 &&
+        2 * pk < nz)
+      continue;
+    const int64_t pc = int64_t(L.ox + pi) + int64_t(L.oy + pj) * C.sy +
+                       int64_t(L.oz + pk) * C.sz;
+#pragma unroll 1
     for (int v = 0; v < 5; ++v) {
       const T* q = c0 + pc + v * C.plane;
       const T* qo = o0 ? o0 + pc + v * C.plane : nullptr;
@@ -208,7 +212,18 @@ __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
       const double dx = mc_slope(u - cv(-1), cv(1) - u);
       const double dy = mc_slope(u - cv(-C.sy), cv(C.sy) - u);
       const double dz = mc_slope(u - cv(-C.sz), cv(C.sz) - u);
-      f0[dst + v * F.plane] = T(((u + ox * dx) + oy * dy) + oz * dz);
+      T* fv = f0 + v * F.plane;
+#pragma unroll
+      for (int ch = 0; ch < 8; ++ch) {
+        const int i = 2 * pi + (ch & 1), j = 2 * pj + ((ch >> 1) & 1), k = 2 * pk + (ch >> 2);
+        if (i < -g || i >= nx + g || j < -g || j >= ny + g || k < -g || k >= nz + g) continue;
+        const bool inside = i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
+        if (inside == bool(a.ghosts_only)) continue;
+        const double ox = (ch & 1) ? 0.25 : -0.25, oy = ((ch >> 1) & 1) ? 0.25 : -0.25,
+                     oz = (ch >> 2) ? 0.25 : -0.25;
+        fv[int64_t(i) + int64_t(j) * F.sy + int64_t(k) * F.sz] =
+            T(((u + ox * dx) + oy * dy) + oz * dz);
+      }
     }
   }
 }

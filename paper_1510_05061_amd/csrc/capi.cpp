@@ -1486,10 +1486,11 @@ int amr_links(hydro_ctx* c, const hydro_amr_link* links, int32_t n, int op, int 
       const hydro_amr_link& k = links[b + i];
       L.links[i] = AmrLink{k.fine, k.coarse, k.ox, k.oy, k.oz, 0};
       const PatchDev& F = c->patches[size_t(k.fine)];
+      // restriction: coarse cells; prolongation: parents of the written cells
       const int64_t g = (op == kAmrProlong && ghosts_only) ? F.ng : 0;
       const int64_t cells = op == kAmrRestrict
                                 ? int64_t(F.n[0] / 2) * (F.n[1] / 2) * (F.n[2] / 2)
-                                : (F.n[0] + 2 * g) * (F.n[1] + 2 * g) * (F.n[2] + 2 * g);
+                                : (F.n[0] / 2 + g) * (F.n[1] / 2 + g) * (F.n[2] / 2 + g);
       most = std::max(most, cells);
     }
     L.cells = most;
@@ -1595,7 +1596,7 @@ int level_launch(const hydro_ctx* coarse, const hydro_ctx* fine, const hydro_amr
       const int64_t nf[3] = {F.n[0] - 2 * g, F.n[1] - 2 * g, F.n[2] - 2 * g};
       int64_t cells = 0;
       if (op == kAmrRestrict) cells = (nf[0] / 2) * (nf[1] / 2) * (nf[2] / 2);
-      else if (op == kAmrProlong) cells = int64_t(F.n[0]) * F.n[1] * F.n[2];
+      else if (op == kAmrProlong) cells = (nf[0] / 2 + g) * (nf[1] / 2 + g) * (nf[2] / 2 + g);
       else cells = std::max({nf[1] * nf[2], nf[0] * nf[2], nf[0] * nf[1]}) / 4;
       most = std::max(most, cells);
     }
