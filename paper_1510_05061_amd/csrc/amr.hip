@@ -73,7 +73,14 @@ struct AmrArgs {
   int link0, maxface;
   int axis, side, fine;
   double dt, weight, gamma, grav;
+  const AmrLink* dlinks;
 };
+
+// Link blockIdx.y of a launch.
+template <class T>
+__device__ __forceinline__ AmrLink link_of(const AmrArgs<T>& a) {
+  return a.dlinks ? a.dlinks[blockIdx.y] : a.links[blockIdx.y];
+}
 
 // Fine patch of a link: the table entry, or the patch inside a ghost-free
 // stored box whose outer `inset` layers are its ghost shell.
@@ -128,7 +135,7 @@ __global__ void __launch_bounds__(kAmrBlock) fill_ghosts_kernel(AmrArgs<T> a) {
 // Coarse cells covered by the fine patch of link blockIdx.y.
 template <class T>
 __global__ void __launch_bounds__(kAmrBlock) restrict_kernel(AmrArgs<T> a) {
-  const AmrLink L = a.links[blockIdx.y];
+  const AmrLink L = link_of(a);
   const PatchDev F = fine_patch(a.fpatches, L.fine, a.finset), C = a.patches[L.coarse];
   const unsigned cx = unsigned(F.n[0] / 2), cxy = cx * unsigned(F.n[1] / 2);
   const unsigned total = cxy * unsigned(F.n[2] / 2);
@@ -173,7 +180,7 @@ __device__ __forceinline__ double mc_slope(double a, double b) {
 // are formed once and give each of its children that is written.
 template <class T>
 __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
-  const AmrLink L = a.links[blockIdx.y];
+  const AmrLink L = link_of(a);
   const PatchDev F = fine_patch(a.fpatches, L.fine, a.finset), C = a.patches[L.coarse];
   const int nx = F.n[0], ny = F.n[1], nz = F.n[2];
   const int g = a.ghosts_only ? F.ng : 0;
@@ -268,7 +275,7 @@ __device__ __forceinline__ void face_flux(const T* p0, const PatchDev& P, int ax
 // a.weight, added to the register.
 template <class T>
 __global__ void __launch_bounds__(kAmrBlock) flux_reg_kernel(AmrArgs<T> a) {
-  const AmrLink L = a.links[blockIdx.y];
+  const AmrLink L = link_of(a);
   const int side = int(blockIdx.z);
   const PatchDev F = fine_patch(a.fpatches, L.fine, a.finset);
   const int axis = a.axis, a1 = t1_of(axis), a2 = t2_of(axis);
@@ -279,31 +286,46 @@ __global__ void __launch_bounds__(kAmrBlock) flux_reg_kernel(AmrArgs<T> a) {
                 (((int64_t(a.link0) + blockIdx.y) * 3 + axis) * 2 + side) * a.maxface * 5;
   const SweepConst<T> k = make_const<T>(a.dt, a.fine ? F.dx[axis] : a.patches[L.coarse].dx[axis],
                                         a.gamma, a.grav);
-  for (int fc = blockIdx.x * kAmrBlock + threadIdx.x; fc < nface; fc += gridDim.x * kAmrBlock) {
-    const int j1 = fc % m1, j2 = fc / m1;
-    double acc[5];
-    if (!a.fine) {
-      const PatchDev C = a.patches[L.coarse];
-      const int f = o[axis] + (side ? F.n[axis] / 2 : 0);
+  double acc[5];
+  if (!a.fine) {
+    const PatchDev C = a.patches[L.coarse];
+    const int f = o[axis] + (side ? F.n[axis] / 2 : 0);
+    for (int fc = blockIdx.x * kAmrBlock + threadIdx.x; fc < nface;
+         fc += gridDim.x * kAmrBlock) {
+      const int j1 = fc % m1, j2 = fc / m1;
       face_flux(a.pool + C.base0, C, axis, f, o[a1] + j1, o[a2] + j2, k, acc);
       for (int v = 0; v < 5; ++v) reg[int64_t(fc) * 5 + v] += a.weight * acc[v];
-    } else {
-      const int f = side ? F.n[axis] : 0;
+    }
+  } else {
+    // four consecutive lanes per coarse face, lane q on the fine face with
+    // (t2, t1) offsets (q >> 1, q & 1); the group's first lane sums the four
+    // in the order (0,0), (0,1), (1,0), (1,1).  Groups are whole: the block
+    // size and the trip bound are multiples of 4.
+    const int f = side ? F.n[axis] : 0;
+    const int q = threadIdx.x & 3;
+    for (int t = blockIdx.x * kAmrBlock + threadIdx.x; t < 4 * nface;
+         t += gridDim.x * kAmrBlock) {
+      const int fc = t >> 2;
+      const int j1 = fc % m1, j2 = fc / m1;
+      face_flux(a.fpool + F.base0, F, axis, f, 2 * j1 + (q & 1), 2 * j2 + (q >> 1), k, acc);
       double s[5];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {  // (t2, t1) offsets (0,0), (0,1), (1,0), (1,1)
-        face_flux(a.fpool + F.base0, F, axis, f, 2 * j1 + (q & 1), 2 * j2 + (q >> 1), k, acc);
-        for (int v = 0; v < 5; ++v) s[v] = q == 0 ? acc[v] : s[v] + acc[v];
+      for (int v = 0; v < 5; ++v) {
+        const double x0 = __shfl(acc[v], 0, 4), x1 = __shfl(acc[v], 1, 4);
+        const double x2 = __shfl(acc[v], 2, 4), x3 = __shfl(acc[v], 3, 4);
+        s[v] = ((x0 + x1) + x2) + x3;
       }
-      for (int v = 0; v < 5; ++v) reg[int64_t(fc) * 5 + v] += a.weight * (0.25 * s[v]);
+      if (q == 0)
+        for (int v = 0; v < 5; ++v) reg[int64_t(fc) * 5 + v] += a.weight * (0.25 * s[v]);
     }
   }
 }
+static_assert(kAmrBlock % 4 == 0, "whole lane groups per workgroup");
 
 // Refluxing of link blockIdx.y across its a.side faces along a.axis.
 template <class T>
 __global__ void __launch_bounds__(kAmrBlock) reflux_kernel(AmrArgs<T> a) {
-  const AmrLink L = a.links[blockIdx.y];
+  const AmrLink L = link_of(a);
   const PatchDev F = fine_patch(a.fpatches, L.fine, a.finset);
   const PatchDev C = a.patches[L.coarse];
   const int axis = a.axis, a1 = t1_of(axis), a2 = t2_of(axis), side = a.side;
@@ -338,7 +360,12 @@ static AmrArgs<T> to_aargs(const LaunchAmr& L) {
   a.single = L.single;
   a.ng = L.ng;
   for (int i = 0; i < 6; ++i) a.bc[i] = L.bc[i];
-  for (int i = 0; i < L.nlinks; ++i) a.links[i] = L.links[i];
+  // by-value links only without a device table (launch_amr caps them at
+  // kAmrLinksPerLaunch); with one, nlinks may exceed the array
+  if (!L.dlinks) {
+    const int m = std::min<int32_t>(L.nlinks, kAmrLinksPerLaunch);
+    for (int i = 0; i < m; ++i) a.links[i] = L.links[i];
+  }
   a.ghosts_only = L.ghosts_only;
   a.fpool = L.fpool ? static_cast<T*>(L.fpool) : a.pool;
   a.fpatches = L.fpatches ? L.fpatches : L.patches;
@@ -356,7 +383,30 @@ static AmrArgs<T> to_aargs(const LaunchAmr& L) {
   a.weight = L.weight;
   a.gamma = L.gamma;
   a.grav = L.grav;
+  a.dlinks = L.dlinks;
   return a;
+}
+
+struct LinkChunk {
+  AmrLink l[kAmrLinksPerLaunch];
+};
+
+__global__ void upload_links_kernel(AmrLink* dst, LinkChunk src, int n) {
+  const int i = int(threadIdx.x);
+  if (i < n) dst[i] = src.l[i];
+}
+
+hipError_t launch_amr_upload(AmrLink* dst, const AmrLink* src, int32_t n, hipStream_t st) {
+  for (int32_t b = 0; b < n; b += kAmrLinksPerLaunch) {
+    LinkChunk c{};
+    const int m = std::min<int32_t>(kAmrLinksPerLaunch, n - b);
+    for (int i = 0; i < m; ++i) c.l[i] = src[b + i];
+    hipLaunchKernelGGL(upload_links_kernel, dim3(1), dim3(kAmrLinksPerLaunch), 0, st, dst + b,
+                       c, m);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 static_assert(sizeof(AmrArgs<double>) <= 4096, "AMR kernel arguments exceed 4 KiB");
@@ -392,7 +442,9 @@ static hipError_t launch_amr_t(const LaunchAmr& L, hipStream_t st) {
 
 hipError_t launch_amr(const LaunchAmr& L, hipStream_t st) {
   if (L.op < kAmrFill || L.op > kAmrReflux) return hipErrorInvalidValue;
-  if (L.op != kAmrFill && (!L.patches || L.nlinks < 1 || L.nlinks > kAmrLinksPerLaunch))
+  if (L.op != kAmrFill &&
+      (!L.patches || L.nlinks < 1 || (!L.dlinks && L.nlinks > kAmrLinksPerLaunch) ||
+       L.nlinks > 65535))
     return hipErrorInvalidValue;
   if ((L.op == kAmrFlux || L.op == kAmrReflux) &&
       (!L.reg || L.maxface < 1 || L.axis < 0 || L.axis > 2 || L.side < 0 || L.side > 1))

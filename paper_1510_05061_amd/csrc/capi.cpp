@@ -1539,6 +1539,7 @@ int check_level(const hydro_ctx* coarse, const hydro_ctx* fine, const hydro_amr_
     return fail(HYDRO_ESTATE, "batch work lists out of date");
   if (g < 2) return fail(HYDRO_EINVAL, "fine patches need at least 2 ghost layers");
   if (!links || n != fine->npatch) return fail(HYDRO_EINVAL, "one link per fine patch needed");
+  if (n > 65535) return fail(HYDRO_EINVAL, "at most 65535 fine patches");
   const int m = (g + 1) / 2 + 1;  // coarse cells between a patch and the coarse edge
   std::vector<int> seen(size_t(fine->npatch), 0);
   for (int32_t i = 0; i < n; ++i) {
@@ -1573,37 +1574,35 @@ int check_level(const hydro_ctx* coarse, const hydro_ctx* fine, const hydro_amr_
   return HYDRO_OK;
 }
 
-// Launches one AMR operator over every link in chunks of the kernel limit.
+// Launches one AMR operator over every link: one launch reading the device
+// link table `dlinks` (the same links, uploaded).
 int level_launch(const hydro_ctx* coarse, const hydro_ctx* fine, const hydro_amr_link* links,
-                 int32_t n, int g, int op, const std::function<void(LaunchAmr&)>& fill) {
-  for (int32_t b = 0; b < n; b += kAmrLinksPerLaunch) {
-    LaunchAmr L{};
-    L.op = op;
-    L.fp64 = coarse->fp64;
-    L.pool = coarse->pool;
-    L.patches = coarse->d_patches;
-    L.npatch = coarse->npatch;
-    L.fpool = fine->pool;
-    L.fpatches = fine->d_patches;
-    L.finset = g;
-    L.link0 = b;
-    L.nlinks = std::min<int32_t>(kAmrLinksPerLaunch, n - b);
-    int64_t most = 0;
-    for (int32_t i = 0; i < L.nlinks; ++i) {
-      const hydro_amr_link& k = links[b + i];
-      L.links[i] = AmrLink{k.fine, k.coarse, k.ox, k.oy, k.oz, 0};
-      const PatchDev& F = fine->patches[size_t(k.fine)];
-      const int64_t nf[3] = {F.n[0] - 2 * g, F.n[1] - 2 * g, F.n[2] - 2 * g};
-      int64_t cells = 0;
-      if (op == kAmrRestrict) cells = (nf[0] / 2) * (nf[1] / 2) * (nf[2] / 2);
-      else if (op == kAmrProlong) cells = (nf[0] / 2 + g) * (nf[1] / 2 + g) * (nf[2] / 2 + g);
-      else cells = std::max({nf[1] * nf[2], nf[0] * nf[2], nf[0] * nf[1]}) / 4;
-      most = std::max(most, cells);
-    }
-    L.cells = most;
-    fill(L);
-    HIP_TRY(launch_amr(L, coarse->stream));
+                 int32_t n, int g, int op, const AmrLink* dlinks,
+                 const std::function<void(LaunchAmr&)>& fill) {
+  LaunchAmr L{};
+  L.op = op;
+  L.fp64 = coarse->fp64;
+  L.pool = coarse->pool;
+  L.patches = coarse->d_patches;
+  L.npatch = coarse->npatch;
+  L.fpool = fine->pool;
+  L.fpatches = fine->d_patches;
+  L.finset = g;
+  L.nlinks = n;
+  L.dlinks = dlinks;
+  int64_t most = 0;  // most work items of one link (grid sizing)
+  for (int32_t i = 0; i < n; ++i) {
+    const PatchDev& F = fine->patches[size_t(links[i].fine)];
+    const int64_t nf[3] = {F.n[0] - 2 * g, F.n[1] - 2 * g, F.n[2] - 2 * g};
+    int64_t cells = 0;
+    if (op == kAmrRestrict) cells = (nf[0] / 2) * (nf[1] / 2) * (nf[2] / 2);
+    else if (op == kAmrProlong) cells = (nf[0] / 2 + g) * (nf[1] / 2 + g) * (nf[2] / 2 + g);
+    else cells = std::max({nf[1] * nf[2], nf[0] * nf[2], nf[0] * nf[1]}) / 4;
+    most = std::max(most, cells);
   }
+  L.cells = most;
+  fill(L);
+  HIP_TRY(launch_amr(L, coarse->stream));
   return HYDRO_OK;
 }
 
@@ -1611,18 +1610,19 @@ int level_launch(const hydro_ctx* coarse, const hydro_ctx* fine, const hydro_amr
 // by the flux registers of its axis; then the step bookkeeping.
 int level_sweeps(hydro_ctx* c, const hydro_ctx* coarse, const hydro_ctx* fine,
                  const hydro_amr_link* links, int32_t n, int g, bool fine_side, double dt,
-                 double* reg, int64_t nreg, int64_t maxface) {
+                 double* reg, int64_t nreg, int64_t maxface, const AmrLink* dlinks) {
   static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
   const int* order = (c->step & 1) ? odd : even;
   HIP_TRY(launch_set_dt(c->scal, dt, c->stream));
   for (int i = 0; i < 3; ++i) {
     const int ax = order[i];
-    int rc = level_launch(coarse, fine, links, n, g, kAmrFlux, [&](LaunchAmr& L) {
+    int rc = level_launch(coarse, fine, links, n, g, kAmrFlux, dlinks, [&](LaunchAmr& L) {
       L.reg = reg;
       L.nreg = nreg;
       L.maxface = int32_t(maxface);
       L.axis = ax;
       L.fine = fine_side ? 1 : 0;
+      if (fine_side) L.cells *= 4;  // four lanes per coarse face
       L.dt = dt;
       L.weight = dt;
       L.gamma = c->desc.gamma;
@@ -1645,7 +1645,8 @@ int hydro_amr_step_workspace_bytes(const hydro_ctx* coarse, const hydro_ctx* fin
   if (!coarse->batch || !fine->batch) return fail(HYDRO_ESTATE, "both levels must be batches");
   if (fine_ng < 2) return fail(HYDRO_EINVAL, "fine patches need at least 2 ghost layers");
   const int64_t nreg = int64_t(fine->npatch) * 30 * level_maxface(fine, fine_ng);
-  *bytes = align256(coarse->pool_bytes) + size_t(2 * nreg) * sizeof(double);
+  *bytes = align256(coarse->pool_bytes) + align256(size_t(2 * nreg) * sizeof(double)) +
+           size_t(fine->npatch) * sizeof(AmrLink);
   return HYDRO_OK;
 }
 
@@ -1667,30 +1668,37 @@ int hydro_amr_step(hydro_ctx* coarse, hydro_ctx* fine, const hydro_amr_link* lin
   char* ws = static_cast<char*>(workspace);
   void* cold = ws;
   double* reg = reinterpret_cast<double*>(ws + align256(coarse->pool_bytes));
+  AmrLink* dlinks = reinterpret_cast<AmrLink*>(ws + align256(coarse->pool_bytes) +
+                                               align256(size_t(2 * nreg) * sizeof(double)));
   hipStream_t st = coarse->stream;
+  std::vector<AmrLink> hl(static_cast<size_t>(n));
+  for (int32_t i = 0; i < n; ++i)
+    hl[size_t(i)] = AmrLink{links[i].fine, links[i].coarse, links[i].ox, links[i].oy, links[i].oz, 0};
+  HIP_TRY(launch_amr_upload(dlinks, hl.data(), n, st));
   HIP_TRY(hipMemcpyAsync(cold, coarse->pool, coarse->pool_bytes, hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipMemsetAsync(reg, 0, size_t(2 * nreg) * sizeof(double), st));
   // 1. the coarse step, registering its fluxes through the coarse-fine faces
-  rc = level_sweeps(coarse, coarse, fine, links, n, g, false, dt, reg, nreg, maxface);
+  rc = level_sweeps(coarse, coarse, fine, links, n, g, false, dt, reg, nreg, maxface, dlinks);
   if (rc) return rc;
   // 2. two fine substeps, ghosts from the coarse data interpolated in time
   for (int s = 0; s < 2; ++s) {
-    rc = level_launch(coarse, fine, links, n, g, kAmrProlong, [&](LaunchAmr& L) {
+    rc = level_launch(coarse, fine, links, n, g, kAmrProlong, dlinks, [&](LaunchAmr& L) {
       L.ghosts_only = 1;
       L.cold = cold;
       L.theta = 0.5 * s;
     });
     if (rc) return rc;
-    rc = level_sweeps(fine, coarse, fine, links, n, g, true, 0.5 * dt, reg, nreg, maxface);
+    rc = level_sweeps(fine, coarse, fine, links, n, g, true, 0.5 * dt, reg, nreg, maxface,
+                      dlinks);
     if (rc) return rc;
   }
   // 3. restriction, 4. refluxing
-  rc = level_launch(coarse, fine, links, n, g, kAmrRestrict, [](LaunchAmr&) {});
+  rc = level_launch(coarse, fine, links, n, g, kAmrRestrict, dlinks, [](LaunchAmr&) {});
   if (rc) return rc;
   if (!(flags & HYDRO_AMR_NO_REFLUX)) {
     for (int ax = 0; ax < 3; ++ax)
       for (int side = 0; side < 2; ++side) {
-        rc = level_launch(coarse, fine, links, n, g, kAmrReflux, [&](LaunchAmr& L) {
+        rc = level_launch(coarse, fine, links, n, g, kAmrReflux, dlinks, [&](LaunchAmr& L) {
           L.reg = reg;
           L.nreg = nreg;
           L.maxface = int32_t(maxface);

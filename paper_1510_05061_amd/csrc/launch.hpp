@@ -148,7 +148,13 @@ struct LaunchAmr {
   double dt;                         // kAmrFlux: sweep length
   double weight;                     // kAmrFlux: register += weight * flux
   double gamma, grav;                // kAmrFlux: sweep constants (gravity along axis)
+  // device link table (null: `links`); with it one launch takes nlinks links
+  // and link l of the launch is table entry l
+  const AmrLink* dlinks;
 };
+
+// Writes n links into a device table, from kernel arguments (no host copy).
+hipError_t launch_amr_upload(AmrLink* dst, const AmrLink* src, int32_t n, hipStream_t st);
 
 hipError_t launch_sweep(const LaunchSweep& L, hipStream_t st);
 hipError_t launch_amr(const LaunchAmr& L, hipStream_t st);

@@ -173,3 +173,40 @@ def test_argument_errors():
     fine2.close()
     coarse.close()
     fine.close()
+
+
+def test_many_small_patches_match_the_oracle():
+    # 144 one-coarse-cell patches: more links than one kernel's arguments
+    # hold, so the device link table is written in several chunks
+    say("amr step 144 small patches")
+    shape = (16, 16, 16)
+    dx = (1 / 16,) * 3
+    g = 2
+    offs = [(x, y, z) for z in range(2, 14, 3) for y in range(2, 14, 2)
+            for x in range(2, 14, 2)]
+    assert len(offs) == 144
+    C = ic.smooth_random(shape, 31, gamma=GAMMA, mach=0.3).U
+    fines = [ic.smooth_random((6, 6, 6), 100 + i, gamma=GAMMA, mach=0.3).U
+             for i in range(len(offs))]
+    tc = torch().from_numpy(C.reshape(-1).copy()).to("cuda:0")
+    coarse = hydro.Batch(tc, [(0, 16, 16, 16, 0) + dx], GAMMA, flags=hydro.FLAG_NO_TUNE)
+    per = 5 * 6 ** 3
+    tf = torch().from_numpy(np.concatenate([F.reshape(-1) for F in fines])).to("cuda:0")
+    fine = hydro.Batch(tf, [(i * per, 6, 6, 6, 0) + tuple(h / 2 for h in dx)
+                            for i in range(len(offs))], GAMMA,
+                       bc=(hydro.OUTFLOW,) * 6, flags=hydro.FLAG_NO_TUNE)
+    links = [(i, 0) + o for i, o in enumerate(offs)]
+    lv = hydro.AmrLevels(coarse, fine, links, g)
+    dtf = min(oracle.cfl_dt(oracle.make_params((6, 6, 6), tuple(h / 2 for h in dx), GAMMA), F)
+              for F in fines)
+    dt = 0.5 * min(oracle.cfl_dt(oracle.make_params(shape, dx, GAMMA), C), 2 * dtf)
+    Cw, fw = amr.level_step(C, fines, offs, g, dt, GAMMA, dx)
+    lv.step(dt)
+    Cg = tc.cpu().numpy().reshape((5,) + shape)
+    fg = tf.cpu().numpy()
+    e = [max_rel(Cg, Cw)] + [max_rel(fg[i * per:(i + 1) * per].reshape(5, 6, 6, 6), fw[i])
+                             for i in range(len(offs))]
+    say(f"  max rel {max(e)}")
+    assert max(e) <= 1e-12
+    coarse.close()
+    fine.close()
