@@ -99,6 +99,16 @@ __device__ __forceinline__ PatchDev fine_patch(const PatchDev* t, int i, int ins
 __device__ __forceinline__ int64_t axis_stride(const PatchDev& P, int a) {
   return a == 0 ? 1 : a == 1 ? int64_t(P.sy) : int64_t(P.sz);
 }
+// Component a of a 3-vector by selects (a runtime index into a local array
+// would put the array in scratch memory).
+template <class U>
+__device__ __forceinline__ U sel3(int a, U x, U y, U z) {
+  return a == 0 ? x : a == 1 ? y : z;
+}
+__device__ __forceinline__ int ext(const PatchDev& P, int a) { return sel3(a, P.n[0], P.n[1], P.n[2]); }
+__device__ __forceinline__ double width(const PatchDev& P, int a) {
+  return sel3(a, P.dx[0], P.dx[1], P.dx[2]);
+}
 __device__ __forceinline__ int t1_of(int axis) { return axis == 0 ? 1 : 0; }
 __device__ __forceinline__ int t2_of(int axis) { return axis == 2 ? 1 : 2; }
 
@@ -205,7 +215,7 @@ __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
       continue;
     const int64_t pc = int64_t(L.ox + pi) + int64_t(L.oy + pj) * C.sy +
                        int64_t(L.oz + pk) * C.sz;
-#pragma unroll 1
+#pragma unroll
     for (int v = 0; v < 5; ++v) {
       const T* q = c0 + pc + v * C.plane;
       const T* qo = o0 ? o0 + pc + v * C.plane : nullptr;
@@ -238,7 +248,13 @@ __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
 // Flux through the face between cells f - 1 and f along `axis` at
 // transverse indices (i1, i2), from the four cells f - 2 .. f + 1 exactly as
 // a sweep computes it (interior cells: the full gravity half kick).
-// Returned in lab components (rho, mx, my, mz, E).
+// Returned in the sweep frame (rho, m_n, m_t1, m_t2, E); lab_var maps a
+// sweep-frame component to its lab index (kept out of the local array so
+// that it stays in registers).
+__device__ __forceinline__ int lab_var(int axis, int v) {
+  return v == 1 ? 1 + axis : v == 2 ? 1 + t1_of(axis) : v == 3 ? 1 + t2_of(axis) : v;
+}
+
 template <class T>
 __device__ __forceinline__ void face_flux(const T* p0, const PatchDev& P, int axis, int f,
                                           int i1, int i2, const SweepConst<T>& k,
@@ -264,9 +280,9 @@ __device__ __forceinline__ void face_flux(const T* p0, const PatchDev& P, int ax
   face_states(W[1], W[2], W[3], k, k.kick, Wm1, Wp1);  // cell f
   const Cons<T> F = hllc(Wp0, Wm1, k);
   out[0] = double(F.r);
-  out[1 + axis] = double(F.mn);
-  out[1 + a1] = double(F.mt1);
-  out[1 + a2] = double(F.mt2);
+  out[1] = double(F.mn);
+  out[2] = double(F.mt1);
+  out[3] = double(F.mt2);
   out[4] = double(F.e);
 }
 
@@ -279,29 +295,30 @@ __global__ void __launch_bounds__(kAmrBlock) flux_reg_kernel(AmrArgs<T> a) {
   const int side = int(blockIdx.z);
   const PatchDev F = fine_patch(a.fpatches, L.fine, a.finset);
   const int axis = a.axis, a1 = t1_of(axis), a2 = t2_of(axis);
-  const int m1 = F.n[a1] / 2, m2 = F.n[a2] / 2;
+  const int m1 = ext(F, a1) / 2, m2 = ext(F, a2) / 2;
   const int nface = m1 * m2;
-  const int o[3] = {L.ox, L.oy, L.oz};
   double* reg = a.reg + (a.fine ? a.nreg : 0) +
                 (((int64_t(a.link0) + blockIdx.y) * 3 + axis) * 2 + side) * a.maxface * 5;
-  const SweepConst<T> k = make_const<T>(a.dt, a.fine ? F.dx[axis] : a.patches[L.coarse].dx[axis],
+  const PatchDev C = a.patches[L.coarse];
+  const SweepConst<T> k = make_const<T>(a.dt, a.fine ? width(F, axis) : width(C, axis),
                                         a.gamma, a.grav);
   double acc[5];
   if (!a.fine) {
-    const PatchDev C = a.patches[L.coarse];
-    const int f = o[axis] + (side ? F.n[axis] / 2 : 0);
+    const int f = sel3(axis, L.ox, L.oy, L.oz) + (side ? ext(F, axis) / 2 : 0);
+    const int c1 = sel3(a1, L.ox, L.oy, L.oz), c2 = sel3(a2, L.ox, L.oy, L.oz);
     for (int fc = blockIdx.x * kAmrBlock + threadIdx.x; fc < nface;
          fc += gridDim.x * kAmrBlock) {
       const int j1 = fc % m1, j2 = fc / m1;
-      face_flux(a.pool + C.base0, C, axis, f, o[a1] + j1, o[a2] + j2, k, acc);
-      for (int v = 0; v < 5; ++v) reg[int64_t(fc) * 5 + v] += a.weight * acc[v];
+      face_flux(a.pool + C.base0, C, axis, f, c1 + j1, c2 + j2, k, acc);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) reg[int64_t(fc) * 5 + lab_var(axis, v)] += a.weight * acc[v];
     }
   } else {
     // four consecutive lanes per coarse face, lane q on the fine face with
     // (t2, t1) offsets (q >> 1, q & 1); the group's first lane sums the four
     // in the order (0,0), (0,1), (1,0), (1,1).  Groups are whole: the block
     // size and the trip bound are multiples of 4.
-    const int f = side ? F.n[axis] : 0;
+    const int f = side ? ext(F, axis) : 0;
     const int q = threadIdx.x & 3;
     for (int t = blockIdx.x * kAmrBlock + threadIdx.x; t < 4 * nface;
          t += gridDim.x * kAmrBlock) {
@@ -315,8 +332,11 @@ __global__ void __launch_bounds__(kAmrBlock) flux_reg_kernel(AmrArgs<T> a) {
         const double x2 = __shfl(acc[v], 2, 4), x3 = __shfl(acc[v], 3, 4);
         s[v] = ((x0 + x1) + x2) + x3;
       }
-      if (q == 0)
-        for (int v = 0; v < 5; ++v) reg[int64_t(fc) * 5 + v] += a.weight * (0.25 * s[v]);
+      if (q == 0) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+          reg[int64_t(fc) * 5 + lab_var(axis, v)] += a.weight * (0.25 * s[v]);
+      }
     }
   }
 }
@@ -329,20 +349,22 @@ __global__ void __launch_bounds__(kAmrBlock) reflux_kernel(AmrArgs<T> a) {
   const PatchDev F = fine_patch(a.fpatches, L.fine, a.finset);
   const PatchDev C = a.patches[L.coarse];
   const int axis = a.axis, a1 = t1_of(axis), a2 = t2_of(axis), side = a.side;
-  const int m1 = F.n[a1] / 2, m2 = F.n[a2] / 2;
+  const int m1 = ext(F, a1) / 2, m2 = ext(F, a2) / 2;
   const int nface = m1 * m2;
-  const int o[3] = {L.ox, L.oy, L.oz};
+  const int od = sel3(axis, L.ox, L.oy, L.oz);
+  const int c1 = sel3(a1, L.ox, L.oy, L.oz), c2 = sel3(a2, L.ox, L.oy, L.oz);
   const int64_t ro = (((int64_t(a.link0) + blockIdx.y) * 3 + axis) * 2 + side) * a.maxface * 5;
   const double* rc = a.reg + ro;
   const double* rf = a.reg + a.nreg + ro;
-  const int c = side ? o[axis] + F.n[axis] / 2 : o[axis] - 1;  // the uncovered coarse cell
-  const double dx = C.dx[axis];
+  const int c = side ? od + ext(F, axis) / 2 : od - 1;  // the uncovered coarse cell
+  const double dx = width(C, axis);
   T* c0 = a.pool + C.base0;
   for (int fc = blockIdx.x * kAmrBlock + threadIdx.x; fc < nface; fc += gridDim.x * kAmrBlock) {
     const int j1 = fc % m1, j2 = fc / m1;
     const int64_t cell = int64_t(c) * axis_stride(C, axis) +
-                         int64_t(o[a1] + j1) * axis_stride(C, a1) +
-                         int64_t(o[a2] + j2) * axis_stride(C, a2);
+                         int64_t(c1 + j1) * axis_stride(C, a1) +
+                         int64_t(c2 + j2) * axis_stride(C, a2);
+#pragma unroll
     for (int v = 0; v < 5; ++v) {
       const double rcv = rc[int64_t(fc) * 5 + v], rfv = rf[int64_t(fc) * 5 + v];
       const double delta = side ? rfv - rcv : rcv - rfv;
