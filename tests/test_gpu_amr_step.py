@@ -239,3 +239,29 @@ def test_many_small_patches_match_the_oracle():
     assert max(e) <= 1e-12
     coarse.close()
     fine.close()
+
+
+def test_fp32_ten_steps_stay_within_the_l1_bound():
+    # an FP32 trajectory of ten steps against the FP64 oracle's, both from
+    # the same FP32-representable state with the oracle's dt sequence: the
+    # error is FP32 round-off accumulated over the steps
+    say("amr step fp32 ten steps")
+    C, fines = inputs(25)
+    C = C.astype(np.float32).astype(np.float64)
+    fines = [F.astype(np.float32).astype(np.float64) for F in fines]
+    coarse, fine, tc, tf, offs, links = device_levels(C, fines, hydro.FP32)
+    lv = hydro.AmrLevels(coarse, fine, links, G)
+    offsets = [o for _, o in FINE]
+    Cw, fw = C, fines
+    for s in range(10):
+        dt = step_dt(Cw, fw)
+        Cw, fw = amr.level_step(Cw, fw, offsets, G, dt, GAMMA, DX, step_c=s, step_f=2 * s)
+        lv.step(dt)
+    Cg, fg = read(tc, tf, offs, fines)
+    e = [l1_fp32_errors(Cg, Cw)] + [l1_fp32_errors(a[:, G:-G, G:-G, G:-G],
+                                                   b[:, G:-G, G:-G, G:-G])
+                                    for a, b in zip(fg, fw)]
+    say(f"  ten-step L1 (rho, m, E) per level {e}")
+    assert max(max(x) for x in e) <= 2e-5, e
+    coarse.close()
+    fine.close()
