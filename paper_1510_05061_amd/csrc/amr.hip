@@ -188,7 +188,7 @@ __device__ __forceinline__ double mc_slope(double a, double b) {
 // Fine cells (interior, or the stored ghost shell) of link blockIdx.y, one
 // coarse parent per thread: the parent's value and its three limited slopes
 // are formed once and give each of its children that is written.
-template <class T>
+template <class T, bool COLD>
 __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
   const AmrLink L = link_of(a);
   const PatchDev F = fine_patch(a.fpatches, L.fine, a.finset), C = a.patches[L.coarse];
@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
   const unsigned total = pxy * unsigned(((nz + g - 1) >> 1) - lo + 1);
   T* f0 = a.fpool + F.base0;
   const T* c0 = a.pool + C.base0;
-  const T* o0 = a.cold ? a.cold + C.base0 : nullptr;
+  const T* o0 = COLD ? a.cold + C.base0 : nullptr;
   const double th = a.theta;
   if (blockIdx.x * kAmrBlock >= total) return;
   for (unsigned c = blockIdx.x * kAmrBlock + threadIdx.x; c < total;
@@ -218,12 +218,15 @@ __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       const T* q = c0 + pc + v * C.plane;
-      const T* qo = o0 ? o0 + pc + v * C.plane : nullptr;
+      const T* qo = COLD ? o0 + pc + v * C.plane : nullptr;
       // coarse value at offset d, interpolated in time when a start copy is given
       auto cv = [&](int64_t d) {
-        if (!qo) return double(q[d]);
-        const double o = double(qo[d]);
-        return o + th * (double(q[d]) - o);
+        if constexpr (!COLD) {
+          return double(q[d]);
+        } else {
+          const double o = double(qo[d]);
+          return o + th * (double(q[d]) - o);
+        }
       };
       const double u = cv(0);
       const double dx = mc_slope(u - cv(-1), cv(1) - u);
@@ -450,8 +453,12 @@ static hipError_t launch_amr_t(const LaunchAmr& L, hipStream_t st) {
     hipLaunchKernelGGL(restrict_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
                        dim3(kAmrBlock), 0, st, a);
   } else if (L.op == kAmrProlong) {
-    hipLaunchKernelGGL(prolong_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
-                       dim3(kAmrBlock), 0, st, a);
+    if (L.cold)
+      hipLaunchKernelGGL((prolong_kernel<T, true>), dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
+                         dim3(kAmrBlock), 0, st, a);
+    else
+      hipLaunchKernelGGL((prolong_kernel<T, false>), dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
+                         dim3(kAmrBlock), 0, st, a);
   } else if (L.op == kAmrFlux) {
     hipLaunchKernelGGL(flux_reg_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks), 2u),
                        dim3(kAmrBlock), 0, st, a);
