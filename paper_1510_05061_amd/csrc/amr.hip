@@ -105,7 +105,9 @@ template <class U>
 __device__ __forceinline__ U sel3(int a, U x, U y, U z) {
   return a == 0 ? x : a == 1 ? y : z;
 }
-__device__ __forceinline__ int ext(const PatchDev& P, int a) { return sel3(a, P.n[0], P.n[1], P.n[2]); }
+__device__ __forceinline__ int ext(const PatchDev& P, int a) {
+  return sel3(a, P.n[0], P.n[1], P.n[2]);
+}
 __device__ __forceinline__ double width(const PatchDev& P, int a) {
   return sel3(a, P.dx[0], P.dx[1], P.dx[2]);
 }
