@@ -604,6 +604,58 @@ def default_cpu_steps(W):
     return max(1, min(24, int(4e8 // W["P"].zones)))
 
 
+ORACLE_1T_ZONES = 4 * 1024 * 1024   # bounded single-thread sample (a few seconds)
+
+
+def oracle_single_thread(W):
+    """The same oracle on one host thread over about 4 M zones of the
+    workload: a z-slab of the grid's initial state (its own boundary
+    conditions) for one CFL pass and one step, or one step of the leading
+    patches of the batch."""
+    import numpy as np
+    import hydro_ic as ic
+    import oracle
+    zu, sec = 0, 0.0
+    if W["kind"] == "grid":
+        P = W["P"]
+        nz, ny, nx = P.shape
+        depth = max(2, min(nz, ORACLE_1T_ZONES // (ny * nx)))
+        U = np.ascontiguousarray(P.U[:, :depth], dtype=np.float64)
+        p = oracle.make_params((depth, ny, nx), P.dx, P.gamma, P.cfl, P.bc, P.grav, nthreads=1)
+        t0 = time.perf_counter()
+        oracle.step(p, U, oracle.cfl_dt(p, U), 0)
+        sec = time.perf_counter() - t0
+        zu = depth * ny * nx
+        sample = f"one CFL pass and step of a {depth}x{ny}x{nx} z-slab of the grid, 1 thread"
+    else:
+        n = 0
+        for s in W["specs"]:
+            if zu >= ORACLE_1T_ZONES:
+                break
+            p = oracle.make_params((s.n,) * 3, 1.0 / s.n, 5.0 / 3.0, 0.8, nthreads=1)
+            U = ic.kh_patch(s)
+            t0 = time.perf_counter()
+            oracle.step(p, U, oracle.cfl_dt(p, U), 0)
+            sec += time.perf_counter() - t0
+            zu += s.n ** 3
+            n += 1
+        sample = f"one CFL pass and step of each of the first {n} patches, 1 thread"
+    return {"value": zu / sec, "unit": "zone-updates/s", "cores": 1, "sample": sample}
+
+
+def host_cpu():
+    """nproc and the CPU model of the host the oracle ran on."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
+
+
 def cpu_baseline(W, steps, args, torch, hydro):
     """The FP64 oracle timed on the host over a bounded sample of the
     workload.  Its end state is also the reference of the `vs_oracle`
@@ -669,7 +721,7 @@ def cpu_baseline(W, steps, args, torch, hydro):
                   f"patch) at one dt, the smallest oracle CFL dt over the patches; CFL "
                   f"pass and step timed, {sec:.1f} s wall")
     base = {"value": zu / sec, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
-            "sample": sample}
+            "sample": sample, "single_thread": oracle_single_thread(W), "host": host_cpu()}
     vs = {"steps": len(dts), "t": float(sum(dts)),
           "dt": "the oracle's CFL dt sequence, replayed by both GPU paths",
           "fp32": acc32.result(), "fp64": acc64.result()}
