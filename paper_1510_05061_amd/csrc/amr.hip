@@ -318,6 +318,71 @@ __global__ void __launch_bounds__(kAmrBlock) flux_reg_kernel(AmrArgs<T> a) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) reg[int64_t(fc) * 5 + lab_var(axis, v)] += a.weight * acc[v];
     }
+  } else if (axis == 0) {
+    // x faces: sixteen lanes per coarse face, lane 4q + m on cell m of the
+    // 4-cell stencil of fine face q (t2, t1 offsets (q >> 1, q & 1)), so the
+    // four lanes of a stencil read one contiguous run.  Each lane forms its
+    // cell's primitives; the face states of cells f - 1 (m = 1) and f (m = 2)
+    // take their neighbours' primitives by shuffle, and lane m = 2 forms the
+    // flux from exactly the operands a sweep uses.  The segment's first lane
+    // sums the four fine fluxes in the order (0,0), (0,1), (1,0), (1,1).
+    const int f = side ? ext(F, 0) : 0;
+    const int l = threadIdx.x & 15, q = l >> 2, m = l & 3;
+    for (int t = blockIdx.x * kAmrBlock + threadIdx.x; t < 16 * nface;
+         t += gridDim.x * kAmrBlock) {
+      const int fc = t >> 4;
+      const int j1 = fc % m1, j2 = fc / m1;
+      const int64_t cell = int64_t(f - 2 + m) + int64_t(2 * j1 + (q & 1)) * F.sy +
+                           int64_t(2 * j2 + (q >> 1)) * F.sz;
+      const T* c = a.fpool + F.base0 + cell;
+      Cons<T> U;
+      U.r = c[0];
+      U.mn = c[F.plane];
+      U.mt1 = c[2 * F.plane];
+      U.mt2 = c[3 * F.plane];
+      U.e = c[4 * F.plane];
+      const Prim<T> W = to_prim(U, k);
+      // neighbours m - 1 and m + 1 within the stencil (the ends take
+      // unused values)
+      Prim<T> Wl, Wr;
+      Wl.r = __shfl(W.r, l - 1, 16);
+      Wl.u = __shfl(W.u, l - 1, 16);
+      Wl.t1 = __shfl(W.t1, l - 1, 16);
+      Wl.t2 = __shfl(W.t2, l - 1, 16);
+      Wl.p = __shfl(W.p, l - 1, 16);
+      Wl.ri = T(0);
+      Wr.r = __shfl(W.r, l + 1, 16);
+      Wr.u = __shfl(W.u, l + 1, 16);
+      Wr.t1 = __shfl(W.t1, l + 1, 16);
+      Wr.t2 = __shfl(W.t2, l + 1, 16);
+      Wr.p = __shfl(W.p, l + 1, 16);
+      Wr.ri = T(0);
+      Prim<T> Wm, Wp;
+      face_states(Wl, W, Wr, k, k.kick, Wm, Wp);
+      // lane m = 2 takes W+ of cell f - 1 from lane m = 1
+      Prim<T> L1;
+      L1.r = __shfl(Wp.r, l - 1, 16);
+      L1.u = __shfl(Wp.u, l - 1, 16);
+      L1.t1 = __shfl(Wp.t1, l - 1, 16);
+      L1.t2 = __shfl(Wp.t2, l - 1, 16);
+      L1.p = __shfl(Wp.p, l - 1, 16);
+      L1.ri = T(0);
+      const Cons<T> Fx = hllc(L1, Wm, k);
+      const double fl[5] = {double(Fx.r), double(Fx.mn), double(Fx.mt1), double(Fx.mt2),
+                            double(Fx.e)};
+      double s5[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const double x0 = __shfl(fl[v], 2, 16), x1 = __shfl(fl[v], 6, 16);
+        const double x2 = __shfl(fl[v], 10, 16), x3 = __shfl(fl[v], 14, 16);
+        s5[v] = ((x0 + x1) + x2) + x3;
+      }
+      if (l == 0) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+          reg[int64_t(fc) * 5 + lab_var(0, v)] += a.weight * (0.25 * s5[v]);
+      }
+    }
   } else {
     // four consecutive lanes per coarse face, lane q on the fine face with
     // (t2, t1) offsets (q >> 1, q & 1); the group's first lane sums the four
@@ -345,7 +410,7 @@ __global__ void __launch_bounds__(kAmrBlock) flux_reg_kernel(AmrArgs<T> a) {
     }
   }
 }
-static_assert(kAmrBlock % 4 == 0, "whole lane groups per workgroup");
+static_assert(kAmrBlock % 16 == 0, "whole lane groups per workgroup");
 
 // Refluxing of link blockIdx.y across its a.side faces along a.axis.
 template <class T>

@@ -1622,7 +1622,7 @@ int level_sweeps(hydro_ctx* c, const hydro_ctx* coarse, const hydro_ctx* fine,
       L.maxface = int32_t(maxface);
       L.axis = ax;
       L.fine = fine_side ? 1 : 0;
-      if (fine_side) L.cells *= 4;  // four lanes per coarse face
+      if (fine_side) L.cells *= ax == 0 ? 16 : 4;  // lanes per coarse face
       L.dt = dt;
       L.weight = dt;
       L.gamma = c->desc.gamma;
