@@ -357,8 +357,9 @@ int hydro_amr_prolong(hydro_ctx* c, const hydro_amr_link* links, int32_t n, int 
  * axis.  dt > 0 (for example min(coarse CFL dt, 2 x fine CFL dt)).  Both
  * step counters advance (by 1 and 2) and the device dt of each context is
  * recomputed before its next HYDRO_DT_CFL step.  The workspace (256-byte
- * aligned, hydro_amr_step_workspace_bytes) holds a copy of the coarse pool
- * and the registers.  Asynchronous.  Errors: HYDRO_EINVAL, HYDRO_ESTATE
+ * aligned, hydro_amr_step_workspace_bytes) holds the start-of-step copy of
+ * the coarse cells that prolongation reads (at the coarse pool's offsets, so
+ * it is as large as the pool), the registers and the link table.  Asynchronous.  Errors: HYDRO_EINVAL, HYDRO_ESTATE
  * (not batches, work lists out of date), HYDRO_EDEVICE. */
 #define HYDRO_AMR_NO_REFLUX 0x1u
 int hydro_amr_step_workspace_bytes(const hydro_ctx* coarse, const hydro_ctx* fine,

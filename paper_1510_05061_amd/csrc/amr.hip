@@ -67,6 +67,7 @@ struct AmrArgs {
   const PatchDev* fpatches;
   int finset;
   const T* cold;            // prolongation: coarse data at the start of the step
+  int margin;               // snapshot: coarse cells around each covered box
   double theta;
   double* reg;
   int64_t nreg;
@@ -247,6 +248,30 @@ __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
             T(((u + ox * dx) + oy * dy) + oz * dz);
       }
     }
+  }
+}
+
+// Copy of the coarse cells within a.margin of the box link blockIdx.y
+// covers (every cell its ghost prolongation reads), into a.cold at the
+// pool's offsets.  Boxes of neighbouring links may overlap; they copy the
+// same values.
+template <class T>
+__global__ void __launch_bounds__(kAmrBlock) snapshot_kernel(AmrArgs<T> a) {
+  const AmrLink L = link_of(a);
+  const PatchDev F = fine_patch(a.fpatches, L.fine, a.finset), C = a.patches[L.coarse];
+  const int m = a.margin;
+  const unsigned bx = unsigned(F.n[0] / 2 + 2 * m), bxy = bx * unsigned(F.n[1] / 2 + 2 * m);
+  const unsigned total = bxy * unsigned(F.n[2] / 2 + 2 * m);
+  const T* c0 = a.pool + C.base0;
+  T* o0 = const_cast<T*>(a.cold) + C.base0;
+  for (unsigned c = blockIdx.x * kAmrBlock + threadIdx.x; c < total;
+       c += gridDim.x * kAmrBlock) {
+    const unsigned kk = c / bxy, rem = c - kk * bxy;
+    const unsigned jj = rem / bx;
+    const int64_t cell = int64_t(L.ox - m + int(rem - jj * bx)) +
+                         int64_t(L.oy - m + int(jj)) * C.sy + int64_t(L.oz - m + int(kk)) * C.sz;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) o0[cell + v * C.plane] = c0[cell + v * C.plane];
   }
 }
 
@@ -463,6 +488,7 @@ static AmrArgs<T> to_aargs(const LaunchAmr& L) {
   a.fpatches = L.fpatches ? L.fpatches : L.patches;
   a.finset = L.finset;
   a.cold = static_cast<const T*>(L.cold);
+  a.margin = L.margin;
   a.theta = L.theta;
   a.reg = L.reg;
   a.nreg = L.nreg;
@@ -526,6 +552,9 @@ static hipError_t launch_amr_t(const LaunchAmr& L, hipStream_t st) {
     else
       hipLaunchKernelGGL((prolong_kernel<T, false>), dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
                          dim3(kAmrBlock), 0, st, a);
+  } else if (L.op == kAmrSnapshot) {
+    hipLaunchKernelGGL(snapshot_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
+                       dim3(kAmrBlock), 0, st, a);
   } else if (L.op == kAmrFlux) {
     hipLaunchKernelGGL(flux_reg_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks), 2u),
                        dim3(kAmrBlock), 0, st, a);
@@ -537,7 +566,8 @@ static hipError_t launch_amr_t(const LaunchAmr& L, hipStream_t st) {
 }
 
 hipError_t launch_amr(const LaunchAmr& L, hipStream_t st) {
-  if (L.op < kAmrFill || L.op > kAmrReflux) return hipErrorInvalidValue;
+  if (L.op < kAmrFill || L.op > kAmrSnapshot) return hipErrorInvalidValue;
+  if (L.op == kAmrSnapshot && (!L.cold || L.margin < 0)) return hipErrorInvalidValue;
   if (L.op != kAmrFill &&
       (!L.patches || L.nlinks < 1 || (!L.dlinks && L.nlinks > kAmrLinksPerLaunch) ||
        L.nlinks > 65535))

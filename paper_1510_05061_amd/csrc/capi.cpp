@@ -1595,7 +1595,10 @@ int level_launch(const hydro_ctx* coarse, const hydro_ctx* fine, const hydro_amr
     const PatchDev& F = fine->patches[size_t(links[i].fine)];
     const int64_t nf[3] = {F.n[0] - 2 * g, F.n[1] - 2 * g, F.n[2] - 2 * g};
     int64_t cells = 0;
+    const int64_t mg = (g + 1) / 2 + 1;  // snapshot margin
     if (op == kAmrRestrict) cells = (nf[0] / 2) * (nf[1] / 2) * (nf[2] / 2);
+    else if (op == kAmrSnapshot)
+      cells = (nf[0] / 2 + 2 * mg) * (nf[1] / 2 + 2 * mg) * (nf[2] / 2 + 2 * mg);
     else if (op == kAmrProlong) cells = (nf[0] / 2 + g) * (nf[1] / 2 + g) * (nf[2] / 2 + g);
     else cells = std::max({nf[1] * nf[2], nf[0] * nf[2], nf[0] * nf[1]}) / 4;
     most = std::max(most, cells);
@@ -1675,7 +1678,14 @@ int hydro_amr_step(hydro_ctx* coarse, hydro_ctx* fine, const hydro_amr_link* lin
   for (int32_t i = 0; i < n; ++i)
     hl[size_t(i)] = AmrLink{links[i].fine, links[i].coarse, links[i].ox, links[i].oy, links[i].oz, 0};
   HIP_TRY(launch_amr_upload(dlinks, hl.data(), n, st));
-  HIP_TRY(hipMemcpyAsync(cold, coarse->pool, coarse->pool_bytes, hipMemcpyDeviceToDevice, st));
+  // the start-of-step coarse cells that ghost prolongation reads: every
+  // cell within ceil(g/2) + 1 of a covered box (the parents of the ghost
+  // shell and their neighbours), at their pool offsets
+  rc = level_launch(coarse, fine, links, n, g, kAmrSnapshot, dlinks, [&](LaunchAmr& L) {
+    L.cold = cold;
+    L.margin = (g + 1) / 2 + 1;
+  });
+  if (rc) return rc;
   HIP_TRY(hipMemsetAsync(reg, 0, size_t(2 * nreg) * sizeof(double), st));
   // 1. the coarse step, registering its fluxes through the coarse-fine faces
   rc = level_sweeps(coarse, coarse, fine, links, n, g, false, dt, reg, nreg, maxface, dlinks);

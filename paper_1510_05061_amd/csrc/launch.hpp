@@ -102,7 +102,8 @@ struct LaunchBurn {
 };
 
 // AMR operators (amr.hip).
-constexpr int kAmrFill = 0, kAmrRestrict = 1, kAmrProlong = 2, kAmrFlux = 3, kAmrReflux = 4;
+constexpr int kAmrFill = 0, kAmrRestrict = 1, kAmrProlong = 2, kAmrFlux = 3, kAmrReflux = 4,
+              kAmrSnapshot = 5;
 constexpr int kAmrLinksPerLaunch = 128;  // links passed by value in the kernel arguments
 constexpr int kAmrMaxBlocks = 4096;
 
@@ -134,8 +135,11 @@ struct LaunchAmr {
   const PatchDev* fpatches;
   int32_t finset;
   // prolongation: coarse data at theta in [0, 1] between cold (a copy of
-  // the coarse pool at the start of the step) and the pool; cold null: pool
+  // the coarse cells it reads, taken at the start of the step at their pool
+  // offsets) and the pool; cold null: pool.  kAmrSnapshot writes that copy
+  // (cells within `margin` coarse cells of each link's covered box).
   const void* cold;
+  int32_t margin;
   double theta;
   // flux registers (kAmrFlux, kAmrReflux): register of (link, axis, side,
   // coarse face, variable) at reg + ((((link0 + l) * 3 + axis) * 2 + side) *
