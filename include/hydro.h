@@ -342,7 +342,8 @@ int hydro_amr_prolong(hydro_ctx* c, const hydro_amr_link* links, int32_t n, int 
  *      faces on every fine patch's boundary (R_c = dt F);
  *   2. the fine batch takes two steps of dt/2 (orders by its counter); before
  *      substep s its ghost shells are prolonged (as hydro_amr_prolong) from
- *      the coarse data interpolated in time, U_old + (s/2)(U - U_old), and
+ *      the coarse data interpolated in time, U_old + (s/2)(U - U_old) (U_old
+ *      itself for s = 0), and
  *      each sweep registers the mean over the 2x2 fine faces of every coarse
  *      face, summed in (t2, t1) order, times dt/2 (R_f);
  *   3. restriction of every fine interior onto the coarse cells it covers;

@@ -39,7 +39,8 @@ of (rho, mx, my, mz, E):
     2. each fine patch takes two steps of dt/2 (sweep orders by the fine
        step counter).  Before substep s its ghost shell (g >= 2 layers) is
        prolonged from the coarse grid interpolated linearly in time,
-       C_old + theta (C_new - C_old) with theta = s/2.  The whole stored box
+       C_old + theta (C_new - C_old) with theta = s/2 (at theta = 0 the
+       start-of-step state itself).  The whole stored box
        (interior and ghosts, outflow at its outer edge) is swept, so ghost
        cells move with each sweep and the next sweep sees advanced values;
        the interior depends only on cells within 2 of it per sweep, never on
@@ -248,7 +249,7 @@ def level_step(C, fines, offsets, g, dt, gamma, dx, grav=(0.0, 0.0, 0.0),
     h = 0.5 * dt
     for s in (0, 1):
         theta = 0.5 * s
-        Ct = Cold + theta * (C - Cold)
+        Ct = Cold if theta == 0.0 else Cold + theta * (C - Cold)
         for i, o in enumerate(offsets):
             fines[i] = prolong(Ct, 0, fines[i], g, o, ghosts_only=True)
         for d in order(step_f + s):

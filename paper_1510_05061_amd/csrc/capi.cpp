@@ -1694,8 +1694,12 @@ int hydro_amr_step(hydro_ctx* coarse, hydro_ctx* fine, const hydro_amr_link* lin
   for (int s = 0; s < 2; ++s) {
     rc = level_launch(coarse, fine, links, n, g, kAmrProlong, dlinks, [&](LaunchAmr& L) {
       L.ghosts_only = 1;
-      L.cold = cold;
-      L.theta = 0.5 * s;
+      if (s == 0) {
+        L.pool = cold;  // theta = 0: the start-of-step cells themselves
+      } else {
+        L.cold = cold;
+        L.theta = 0.5 * s;
+      }
     });
     if (rc) return rc;
     rc = level_sweeps(fine, coarse, fine, links, n, g, true, 0.5 * dt, reg, nreg, maxface,
