@@ -333,6 +333,10 @@ struct SpecArgs {
   int n;                       // line length nx
   int nst;                     // stages
   int rad[kSpecMaxStages];     // radix of each stage
+  int ns[kSpecMaxStages];      // span Ns of each stage (product of the earlier radices)
+  int tw[kSpecMaxStages];      // twiddle step n / (Ns R)
+  FastDiv nsd[kSpecMaxStages];  // division by Ns
+  FastDiv md[kSpecMaxStages];   // division by n / R (butterflies per complex line)
 };
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -347,8 +351,10 @@ __device__ __forceinline__ double2 cmi(double2 a) { return make_double2(a.y, -a.
 // outputs at base + r Ns.
 template <int R>
 __device__ __forceinline__ void fft_butterfly(const double2* src, double2* dst,
-                                              const double2* W, int n, int jj, int ns) {
-  const int step = n / R, k = jj % ns, tw = n / (ns * R);
+                                              const double2* W, int n, int jj, int ns,
+                                              const FastDiv& nsd, int tw) {
+  const int step = n / R;
+  const int q = int(nsd.div(uint32_t(jj))), k = jj - q * ns;
   double2 v[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -376,19 +382,22 @@ __device__ __forceinline__ void fft_butterfly(const double2* src, double2* dst,
     b[1] = cadd(t2, t3);
     b[2] = csub(t2, t3);
   }
-  const int base = (jj / ns) * ns * R + k;
+  const int base = q * ns * R + k;
 #pragma unroll
   for (int r = 0; r < R; ++r) dst[base + r * ns] = b[r];
 }
 
-template <class T>
+// P x-lines per pass (P = 2 for lines of up to 256 cells, so that every
+// thread has a butterfly in each stage and a pass pays for its barriers
+// once for two lines).
+template <class T, int P>
 __global__ void __launch_bounds__(kDiagBlock) spectrum_kernel(DiagArgs<T> a, SpecArgs sp) {
   extern __shared__ double2 sbuf[];
-  const PatchDev& P = a.single;
+  const PatchDev& Pd = a.single;
   const int n = sp.n;
-  double2* W = sbuf;              // W[t] = exp(-2 pi i t / n)
-  double2* bufA = sbuf + n;       // two lines
-  double2* bufB = sbuf + 3 * n;   // two lines
+  double2* W = sbuf;                  // W[t] = exp(-2 pi i t / n)
+  double2* bufA = sbuf + n;           // 2P complex lines
+  double2* bufB = sbuf + (1 + 2 * P) * n;
   for (int t = threadIdx.x; t < n; t += kDiagBlock) {
     double sn, cs;
     sincospi(-2.0 * double(t) / double(n), &sn, &cs);
@@ -398,70 +407,84 @@ __global__ void __launch_bounds__(kDiagBlock) spectrum_kernel(DiagArgs<T> a, Spe
   double acc[KPT];
 #pragma unroll
   for (int i = 0; i < KPT; ++i) acc[i] = 0.0;
-  const int ny = P.n[1], lines = P.n[1] * P.n[2];
-  const T* p0 = a.pool + P.base0;
-  // this thread's cells x = t + 256 i of a line, fetched one line ahead so
-  // that the next line's loads are in flight during the current transform
+  const int ny = Pd.n[1], lines = Pd.n[1] * Pd.n[2];
+  const int groups = (lines + P - 1) / P;
+  const T* p0 = a.pool + Pd.base0;
+  // this thread's cells c = t + 256 i of the pass (line c / n of the group,
+  // x = c mod n), fetched one pass ahead so that the next pass's loads are
+  // in flight during the current transform
   constexpr int XPT = kSpecMaxLen / kDiagBlock;
   T fr[XPT], fm[XPT][3];
-  auto fetch = [&](int line) {
-    const int z = line / ny, y = line - z * ny;
-    const int64_t o0 = int64_t(y) * P.sy + int64_t(z) * P.sz;
+  auto fetch = [&](int grp) {
 #pragma unroll
     for (int i = 0; i < XPT; ++i) {
-      const int x = threadIdx.x + i * kDiagBlock;
-      if (x < n) {
-        const int64_t o = o0 + x;
+      const int c = threadIdx.x + i * kDiagBlock;
+      const int lp = P == 1 ? 0 : (c >= n ? 1 : 0);
+      const int x = c - lp * n, line = grp * P + lp;
+      if (c < P * n && line < lines) {
+        const int z = line / ny, y = line - z * ny;
+        const int64_t o = int64_t(y) * Pd.sy + int64_t(z) * Pd.sz + x;
         fr[i] = p0[o];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) fm[i][c] = p0[o + (c + 1) * P.plane];
+        for (int v = 0; v < 3; ++v) fm[i][v] = p0[o + (v + 1) * Pd.plane];
       }
     }
   };
-  if (int(blockIdx.x) < lines) fetch(blockIdx.x);
-  for (int line = blockIdx.x; line < lines; line += gridDim.x) {
-    __syncthreads();  // the previous line's buffers and the twiddles
+  if (int(blockIdx.x) < groups) fetch(blockIdx.x);
+  for (int grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+    __syncthreads();  // the previous pass's buffers and the twiddles
 #pragma unroll
     for (int i = 0; i < XPT; ++i) {
-      const int x = threadIdx.x + i * kDiagBlock;
-      if (x < n) {
-        const double r = double(fr[i]);
-        bufA[x] = make_double2(double(fm[i][0]) / r, double(fm[i][1]) / r);
-        bufA[n + x] = make_double2(double(fm[i][2]) / r, 0.0);
+      const int c = threadIdx.x + i * kDiagBlock;
+      const int lp = P == 1 ? 0 : (c >= n ? 1 : 0);
+      const int x = c - lp * n;
+      if (c < P * n) {
+        double2 z1 = make_double2(0.0, 0.0), z2 = z1;  // a missing last line: zeros
+        if (grp * P + lp < lines) {
+          const double r = double(fr[i]);
+          z1 = make_double2(double(fm[i][0]) / r, double(fm[i][1]) / r);
+          z2 = make_double2(double(fm[i][2]) / r, 0.0);
+        }
+        bufA[2 * lp * n + x] = z1;
+        bufA[(2 * lp + 1) * n + x] = z2;
       }
     }
-    if (line + int(gridDim.x) < lines) fetch(line + gridDim.x);
+    if (grp + int(gridDim.x) < groups) fetch(grp + gridDim.x);
     double2* src = bufA;
     double2* dst = bufB;
-    int ns = 1;
     for (int s = 0; s < sp.nst; ++s) {
       __syncthreads();
-      const int R = sp.rad[s];
+      const int R = sp.rad[s], ns = sp.ns[s], tw = sp.tw[s];
+      const FastDiv nsd = sp.nsd[s], md = sp.md[s];
       const int m = n / R;
-      for (int j = threadIdx.x; j < 2 * m; j += kDiagBlock) {
-        const int l = j >= m ? 1 : 0;
+      for (int j = threadIdx.x; j < 2 * P * m; j += kDiagBlock) {
+        const int l = int(md.div(uint32_t(j)));  // complex line of the pass
         const int jj = j - l * m;
         if (R == 4)
-          fft_butterfly<4>(src + l * n, dst + l * n, W, n, jj, ns);
+          fft_butterfly<4>(src + l * n, dst + l * n, W, n, jj, ns, nsd, tw);
         else if (R == 2)
-          fft_butterfly<2>(src + l * n, dst + l * n, W, n, jj, ns);
+          fft_butterfly<2>(src + l * n, dst + l * n, W, n, jj, ns, nsd, tw);
         else
-          fft_butterfly<3>(src + l * n, dst + l * n, W, n, jj, ns);
+          fft_butterfly<3>(src + l * n, dst + l * n, W, n, jj, ns, nsd, tw);
       }
       double2* t = src;
       src = dst;
       dst = t;
-      ns *= R;
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < KPT; ++i) {
-      const int k = threadIdx.x + i * kDiagBlock;
-      if (k <= n / 2) {
-        const int km = k == 0 ? 0 : n - k;
-        const double2 a1 = src[k], b1 = src[km], a2 = src[n + k], b2 = src[n + km];
-        acc[i] += 0.5 * ((a1.x * a1.x + a1.y * a1.y) + (b1.x * b1.x + b1.y * b1.y)) +
-                  0.5 * ((a2.x * a2.x + a2.y * a2.y) + (b2.x * b2.x + b2.y * b2.y));
+    for (int lp = 0; lp < P; ++lp) {
+      if (grp * P + lp >= lines) break;
+      const double2* z = src + 2 * lp * n;
+#pragma unroll
+      for (int i = 0; i < KPT; ++i) {
+        const int k = threadIdx.x + i * kDiagBlock;
+        if (k <= n / 2) {
+          const int km = k == 0 ? 0 : n - k;
+          const double2 a1 = z[k], b1 = z[km], a2 = z[n + k], b2 = z[n + km];
+          acc[i] += 0.5 * ((a1.x * a1.x + a1.y * a1.y) + (b1.x * b1.x + b1.y * b1.y)) +
+                    0.5 * ((a2.x * a2.x + a2.y * a2.y) + (b2.x * b2.x + b2.y * b2.y));
+        }
       }
     }
   }
@@ -576,9 +599,21 @@ static hipError_t launch_spectrum_t(const LaunchDiag& L, hipStream_t st) {
   while (m % 2 == 0 && sp.nst < kSpecMaxStages) { sp.rad[sp.nst++] = 2; m /= 2; }
   while (m % 3 == 0 && sp.nst < kSpecMaxStages) { sp.rad[sp.nst++] = 3; m /= 3; }
   if (m != 1) return hipErrorInvalidValue;
-  const size_t lds = size_t(5) * sp.n * sizeof(double2);
-  hipLaunchKernelGGL(spectrum_kernel<T>, dim3(unsigned(L.chunks)), dim3(kDiagBlock), lds, st, a,
-                     sp);
+  for (int s = 0, ns = 1; s < sp.nst; ns *= sp.rad[s], ++s) {
+    sp.ns[s] = ns;
+    sp.tw[s] = sp.n / (ns * sp.rad[s]);
+    sp.nsd[s] = FastDiv(uint32_t(ns));
+    sp.md[s] = FastDiv(uint32_t(sp.n / sp.rad[s]));
+  }
+  if (sp.n <= kDiagBlock) {  // two lines per pass
+    const size_t lds = size_t(9) * sp.n * sizeof(double2);
+    hipLaunchKernelGGL((spectrum_kernel<T, 2>), dim3(unsigned(L.chunks)), dim3(kDiagBlock), lds,
+                       st, a, sp);
+  } else {
+    const size_t lds = size_t(5) * sp.n * sizeof(double2);
+    hipLaunchKernelGGL((spectrum_kernel<T, 1>), dim3(unsigned(L.chunks)), dim3(kDiagBlock), lds,
+                       st, a, sp);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const double lines = double(L.single.n[1]) * L.single.n[2];
