@@ -265,3 +265,89 @@ def test_fp32_ten_steps_stay_within_the_l1_bound():
     assert max(max(x) for x in e) <= 2e-5, e
     coarse.close()
     fine.close()
+
+
+def test_two_coarse_patches_one_with_stored_ghosts():
+    # links point at two coarse patches of one batch; the second keeps 2
+    # stored ghost layers (its interior sits at an offset in the pool).  The
+    # patches are independent, so the oracle steps each with its own fine
+    # patches.
+    say("amr step two coarse patches")
+    shapes = [(14, 16, 18), (12, 12, 16)]          # (nz, ny, nx)
+    ngs = [0, 2]
+    dxs = [(1 / 18, 1 / 16, 1 / 14), (1 / 16, 1 / 12, 1 / 12)]
+    fine_of = [[((10, 8, 6), (3, 4, 3)), ((6, 8, 8), (11, 7, 6))], [((8, 6, 6), (4, 3, 3))]]
+    Cs = [ic.smooth_random(s, 41 + i, gamma=GAMMA, mach=0.3).U for i, s in enumerate(shapes)]
+    fines = []
+    for c, fl in enumerate(fine_of):
+        for i, (n, _) in enumerate(fl):
+            shp = (n[2] + 2 * G, n[1] + 2 * G, n[0] + 2 * G)
+            fines.append(ic.smooth_random(shp, 60 + 10 * c + i, gamma=GAMMA, mach=0.3).U)
+    # coarse pool: patch 0 packed, patch 1 with its stored ghosts (NaN)
+    parts, cpatches, off = [], [], 0
+    for C, ng, dx in zip(Cs, ngs, dxs):
+        S = np.full((5,) + tuple(s + 2 * ng for s in C.shape[1:]), np.nan)
+        S[:, ng:S.shape[1] - ng, ng:S.shape[2] - ng, ng:S.shape[3] - ng] = C
+        parts.append(S.reshape(-1))
+        nz, ny, nx = C.shape[1:]
+        cpatches.append((off, nx, ny, nz, ng) + dx)
+        off += S.size
+        pad = (-off) % 64
+        parts.append(np.zeros(pad))
+        off += pad
+    tc = torch().from_numpy(np.concatenate(parts)).to("cuda:0")
+    coarse = hydro.Batch(tc, cpatches, GAMMA, flags=hydro.FLAG_NO_TUNE)
+    fparts, fpatches, foffs, off = [], [], [], 0
+    k = 0
+    for c, fl in enumerate(fine_of):
+        for (n, o) in fl:
+            F = fines[k]
+            foffs.append(off)
+            fparts.append(F.reshape(-1))
+            nz, ny, nx = F.shape[1:]
+            fpatches.append((off, nx, ny, nz, 0) + tuple(h / 2 for h in dxs[c]))
+            off += F.size
+            pad = (-off) % 64
+            fparts.append(np.zeros(pad))
+            off += pad
+            k += 1
+    tf = torch().from_numpy(np.concatenate(fparts)).to("cuda:0")
+    fine = hydro.Batch(tf, fpatches, GAMMA, bc=(hydro.OUTFLOW,) * 6, flags=hydro.FLAG_NO_TUNE)
+    links, k = [], 0
+    for c, fl in enumerate(fine_of):
+        for (_, o) in fl:
+            links.append((k, c) + tuple(o))
+            k += 1
+    lv = hydro.AmrLevels(coarse, fine, links, G)
+    dt = 1e30
+    k = 0
+    for c, fl in enumerate(fine_of):
+        pc = oracle.make_params(shapes[c], dxs[c], GAMMA)
+        dt = min(dt, oracle.cfl_dt(pc, Cs[c]))
+        for _ in fl:
+            pf = oracle.make_params(fines[k].shape[1:], tuple(h / 2 for h in dxs[c]), GAMMA)
+            dt = min(dt, 2 * oracle.cfl_dt(pf, fines[k]))
+            k += 1
+    dt *= 0.5
+    lv.step(dt)
+    got_pool = tc.cpu().numpy()
+    got_f = tf.cpu().numpy()
+    k = 0
+    for c, fl in enumerate(fine_of):
+        want_c, want_f = amr.level_step(Cs[c], fines[k:k + len(fl)], [o for _, o in fl], G, dt,
+                                        GAMMA, dxs[c])
+        o0, nx, ny, nz, ng = cpatches[c][:5]
+        S = got_pool[o0:o0 + 5 * (nz + 2 * ng) * (ny + 2 * ng) * (nx + 2 * ng)].reshape(
+            5, nz + 2 * ng, ny + 2 * ng, nx + 2 * ng)
+        got_c = S[:, ng:ng + nz, ng:ng + ny, ng:ng + nx]
+        e = [max_rel(got_c, want_c)]
+        if ng:
+            assert np.all(np.isnan(S[:, :ng])), "stored coarse ghosts were written"
+        for i, W in enumerate(want_f):
+            F = got_f[foffs[k + i]:foffs[k + i] + W.size].reshape(W.shape)
+            e.append(max_rel(F, W))
+        say(f"  coarse patch {c}: max rel {e}")
+        assert max(e) <= 1e-12, e
+        k += len(fl)
+    coarse.close()
+    fine.close()
