@@ -15,7 +15,7 @@ FP32 state is widened to FP64 first, which is exact):
     ke    = (0.5 * m2) / rho                 kinetic energy density
     p     = (gamma - 1) * (E - ke)           pressure
     speed = sqrt(m2) / rho                   |v|
-    mach  = speed / sqrt((gamma * p) / rho)  |v| / c
+    mach  = sqrt(m2 / ((gamma * p) * rho))   |v| / c = sqrt(|m|^2 / (gamma p rho))
 
 PDF of a quantity q over [lo, hi) in nbins bins, with w = nbins / (hi - lo):
     counts[0]          cells with not (q >= lo)  (below range, or NaN)
@@ -55,11 +55,10 @@ def quantity(U, gamma, q):
         p = (gamma - 1.0) * (e - ke)
         if q == PRESSURE:
             return p
-        speed = np.sqrt(m2) / r
         if q == SPEED:
-            return speed
+            return np.sqrt(m2) / r
         if q == MACH:
-            return speed / np.sqrt((gamma * p) / r)
+            return np.sqrt(m2 / ((gamma * p) * r))
     raise ValueError(f"unknown quantity {q}")
 
 

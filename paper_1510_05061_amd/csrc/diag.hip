@@ -61,8 +61,8 @@ __device__ __forceinline__ double diag_quantity(const T* p0, int64_t plane, int6
       const double e = double(p0[o + 4 * plane]);
       const double p = (gamma - 1.0) * (e - (0.5 * m2) / r);
       if constexpr (Q == kQPressure) return p;
-      const double speed = __builtin_sqrt(m2) / r;
-      return speed / __builtin_sqrt((gamma * p) / r);
+      // |v| / c = sqrt(|m|^2 / (gamma p rho)): one division and one root
+      return __builtin_sqrt(m2 / ((gamma * p) * r));
     }
   }
 }
