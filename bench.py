@@ -215,8 +215,10 @@ def run_gpu(W, prec, args, torch, hydro):
             diag["burn"] = burn_timing(obj, W, torch, hydro)
             if args.workload == "kh":
                 log("two-level AMR step on the evolved state")
-                diag["amr_level"] = amr_level_timing(
-                    U, W, torch, hydro, hydro.FLAG_NO_TUNE if args.no_tune else 0)
+                fl = hydro.FLAG_NO_TUNE if args.no_tune else 0
+                diag["amr_level"] = amr_level_timing(U, W, torch, hydro, fl)
+                # the fewest ghost layers the step needs (2): smaller fine boxes
+                diag["amr_level_g2"] = amr_level_timing(U, W, torch, hydro, fl, g=2)
         else:
             log("AMR operators on the pool")
             diag["amr"] = amr_timing(obj, W, torch, hydro)
@@ -320,10 +322,11 @@ def amr_timing(obj, W, torch, hydro, reps=5):
 AMR_FINE_N, AMR_FINE_G = 32, 4   # fine interior cells per axis, ghost layers
 
 
-def amr_level_timing(U, W, torch, hydro, flags, reps=5):
+def amr_level_timing(U, W, torch, hydro, flags, reps=5, g=AMR_FINE_G):
     """Mean device time of one subcycled two-level step (hydro_amr_step,
     FP32) on the evolved single grid: a coarse batch holding a copy of the
-    grid, and fine patches of 32^3 cells (4 ghost layers, stored 40^3) on a
+    grid, and fine patches of 32^3 cells (g ghost layers: 4 as the batched
+    patches store, stored 40^3; 2 is the least the step needs) on a
     lattice of 16^3-coarse-cell blocks two coarse cells apart covering both
     shear layers (y = 1/4 and 3/4), filled by copying each coarse cell into
     its 8 children.  Reported: the step's time, the composite zone-updates
@@ -333,7 +336,7 @@ def amr_level_timing(U, W, torch, hydro, flags, reps=5):
     the cost of the registers, ghosts, restriction and refluxing."""
     nz, ny, nx = U.shape[1:]
     P = W["P"]
-    n, g = AMR_FINE_N, AMR_FINE_G
+    n = AMR_FINE_N
     m, h = n // 2, g // 2
     lo = h + 2                                  # ceil(g/2) + 1 coarse cells of margin
     xs = list(range(lo, nx - lo - m + 1, m + 2))
