@@ -149,10 +149,14 @@ def test_gravity_matches_the_oracle():
     fine.close()
 
 
-def test_composite_totals_are_conserved_on_the_gpu():
-    say("amr step conservation")
+@pytest.mark.parametrize("prec", [hydro.FP64, hydro.FP32])
+def test_composite_totals_are_conserved_on_the_gpu(prec):
+    say(f"amr step conservation prec={prec}")
     C, fines = inputs(22)
-    coarse, fine, tc, tf, offs, links = device_levels(C, fines, hydro.FP64)
+    if prec == hydro.FP32:
+        C = C.astype(np.float32).astype(np.float64)
+        fines = [F.astype(np.float32).astype(np.float64) for F in fines]
+    coarse, fine, tc, tf, offs, links = device_levels(C, fines, prec)
     lv = hydro.AmrLevels(coarse, fine, links, G)
     before = composite(C, fines)
     scale = np.abs(C).sum(axis=(1, 2, 3)) * np.prod(DX)
@@ -163,8 +167,12 @@ def test_composite_totals_are_conserved_on_the_gpu():
     tot = np.asarray(coarse.totals()[:5])
     err = np.abs(after - before) / scale
     say(f"  conservation {err}")
-    assert err.max() < 1e-13, err
-    np.testing.assert_allclose(tot, after, rtol=1e-13, atol=1e-13 * scale.max())
+    # FP64: round-off; FP32: every update of a cell is rounded to FP32,
+    # random-signed errors of 2^-24 relative that largely cancel in the
+    # totals (measured about 2e-9)
+    bound = 1e-13 if prec == hydro.FP64 else 1e-7
+    assert err.max() < bound, err
+    np.testing.assert_allclose(tot, after, rtol=bound, atol=bound * scale.max())
     coarse.close()
     fine.close()
 
