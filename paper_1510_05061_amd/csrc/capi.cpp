@@ -1558,16 +1558,30 @@ int check_level(const hydro_ctx* coarse, const hydro_ctx* fine, const hydro_amr_
       if (o[a] < m || int64_t(o[a]) + nf / 2 + m > C.n[a])
         return fail(HYDRO_EINVAL, "fine patch too close to the coarse edge");
     }
-    for (int32_t j = 0; j < i; ++j) {
-      const hydro_amr_link& q = links[j];
-      if (q.coarse != k.coarse) continue;
-      const PatchDev& Q = fine->patches[size_t(q.fine)];
-      const int p[3] = {q.ox, q.oy, q.oz};
+  }
+  // separation: sort by (coarse patch, x offset) and compare each link only
+  // with the later ones whose x range can still touch its own
+  std::vector<int32_t> ord(static_cast<size_t>(n));
+  for (int32_t i = 0; i < n; ++i) ord[size_t(i)] = i;
+  std::sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+    return links[a].coarse != links[b].coarse ? links[a].coarse < links[b].coarse
+                                              : links[a].ox < links[b].ox;
+  });
+  auto hi = [&](const hydro_amr_link& k, int a) {  // one past the covered coarse cells
+    const PatchDev& F = fine->patches[size_t(k.fine)];
+    const int o[3] = {k.ox, k.oy, k.oz};
+    return o[a] + (F.n[a] - 2 * g) / 2;
+  };
+  for (int32_t u = 0; u < n; ++u) {
+    const hydro_amr_link& k = links[ord[size_t(u)]];
+    const int ok[3] = {k.ox, k.oy, k.oz};
+    for (int32_t v = u + 1; v < n; ++v) {
+      const hydro_amr_link& q = links[ord[size_t(v)]];
+      if (q.coarse != k.coarse || q.ox >= hi(k, 0) + 1) break;  // apart along x, as all later
+      const int oq[3] = {q.ox, q.oy, q.oz};
       bool apart = false;
-      for (int a = 0; a < 3; ++a) {
-        const int hk = o[a] + (F.n[a] - 2 * g) / 2, hq = p[a] + (Q.n[a] - 2 * g) / 2;
-        apart = apart || p[a] >= hk + 1 || o[a] >= hq + 1;
-      }
+      for (int a = 0; a < 3; ++a)
+        apart = apart || oq[a] >= hi(k, a) + 1 || ok[a] >= hi(q, a) + 1;
       if (!apart) return fail(HYDRO_EINVAL, "fine patches must be a coarse cell apart");
     }
   }
