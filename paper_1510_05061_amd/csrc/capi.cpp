@@ -630,7 +630,7 @@ int time_steps(hydro_ctx* c, int reps, double* ms) {
 std::string shape_key(const hydro_ctx* c, int axis) {
   std::ostringstream o;
   o << c->arch << ":cu" << c->cu_count << ":" << (c->fp64 ? "fp64" : "fp32") << ":ax" << axis
-    << ":k6";
+    << ":k7";
   if (c->batch) {
     o << ":batch" << c->npatch << "x" << c->max_patch_cells;
   } else {
@@ -693,7 +693,8 @@ int rebuild_items(hydro_ctx* c);
 // With HYDRO_TUNE_LOG set, every timing goes to stderr as
 // "tune <what> <candidate> <round> <ms>".
 template <class Apply, class Measure>
-int fastest_of(const char* what, int n, int rounds, Apply apply, Measure measure, int* best) {
+int fastest_of(const char* what, int n, int rounds, Apply apply, Measure measure, int* best,
+               std::vector<double>* times = nullptr) {
   const char* lg = std::getenv("HYDRO_TUNE_LOG");
   const bool log = lg && *lg && std::strcmp(lg, "0") != 0;
   std::vector<double> t(size_t(n), 1e30);
@@ -708,6 +709,7 @@ int fastest_of(const char* what, int n, int rounds, Apply apply, Measure measure
       if (log) std::fprintf(stderr, "tune %s %d %d %.4f\n", what, i, r, ms);
     }
   *best = int(std::min_element(t.begin(), t.end()) - t.begin());
+  if (times) *times = t;
   return HYDRO_OK;
 }
 
@@ -758,13 +760,35 @@ int choose_config(hydro_ctx* c) {
     int bi = 0;
     if (!cands.empty()) {
       static const char* const names[3] = {"x", "y", "z"};
+      std::vector<double> iso;
       rc = fastest_of(
           names[axis], int(cands.size()), 2,
           [&](int i) {
             c->cfg.ax[axis] = cands[size_t(i)];
             return c->batch ? rebuild_items(c) : HYDRO_OK;
           },
-          [&](double* ms) { return time_sweep(c, axis, 5, ms); }, &bi);
+          [&](double* ms) { return time_sweep(c, axis, 5, ms); }, &bi, &iso);
+      if (rc == HYDRO_OK && !c->batch && cands.size() > 1) {
+        // A sweep repeated alone runs in a different cache state from the
+        // same sweep inside a step (it follows another axis' writes), and
+        // the ranking can differ: the fastest few alone are timed again
+        // over whole even + odd steps.
+        static const char* const step_names[3] = {"x-in-step", "y-in-step", "z-in-step"};
+        std::vector<int> idx(cands.size());
+        for (size_t i = 0; i < idx.size(); ++i) idx[i] = int(i);
+        std::sort(idx.begin(), idx.end(),
+                  [&](int a, int b) { return iso[size_t(a)] < iso[size_t(b)]; });
+        const int top = std::min<int>(3, int(idx.size()));
+        int bs = 0;
+        rc = fastest_of(
+            step_names[axis], top, 3,
+            [&](int i) {
+              c->cfg.ax[axis] = cands[size_t(idx[size_t(i)])];
+              return HYDRO_OK;
+            },
+            [&](double* ms) { return time_steps(c, 2, ms); }, &bs);
+        if (rc == HYDRO_OK) bi = idx[size_t(bs)];
+      }
       if (rc == HYDRO_OK) best_cfg = cands[size_t(bi)];
     }
     c->cfg.ax[axis] = best_cfg;
