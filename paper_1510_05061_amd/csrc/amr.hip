@@ -218,8 +218,8 @@ __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
       continue;
     const int64_t pc = int64_t(L.ox + pi) + int64_t(L.oy + pj) * C.sy +
                        int64_t(L.oz + pk) * C.sz;
-    {
-      const int v = int(blockIdx.z);  // one variable per grid layer
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
       const T* q = c0 + pc + v * C.plane;
       const T* qo = COLD ? o0 + pc + v * C.plane : nullptr;
       // coarse value at offset d, interpolated in time when a start copy is given
@@ -546,11 +546,12 @@ static hipError_t launch_amr_t(const LaunchAmr& L, hipStream_t st) {
     hipLaunchKernelGGL(restrict_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
                        dim3(kAmrBlock), 0, st, a);
   } else if (L.op == kAmrProlong) {
-    const dim3 grid(amr_blocks(L.cells), unsigned(L.nlinks), 5u);
     if (L.cold)
-      hipLaunchKernelGGL((prolong_kernel<T, true>), grid, dim3(kAmrBlock), 0, st, a);
+      hipLaunchKernelGGL((prolong_kernel<T, true>), dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
+                         dim3(kAmrBlock), 0, st, a);
     else
-      hipLaunchKernelGGL((prolong_kernel<T, false>), grid, dim3(kAmrBlock), 0, st, a);
+      hipLaunchKernelGGL((prolong_kernel<T, false>), dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
+                         dim3(kAmrBlock), 0, st, a);
   } else if (L.op == kAmrSnapshot) {
     hipLaunchKernelGGL(snapshot_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
                        dim3(kAmrBlock), 0, st, a);
