@@ -120,6 +120,69 @@ def advected_profile(n=64, kind="sine", gamma=1.4, u0=1.0, p0=1.0):
     return Problem(U=U, dx=(1.0 / n,) * 3, gamma=gamma, name=f"advect_{kind}")
 
 
+def _embed_along(profile_fields, axis, n, transverse):
+    """Fields given as 1D arrays of n cells along `axis`, repeated over a
+    (transverse, transverse) cross-section: returns the grid shape (nz, ny,
+    nx) and the broadcast fields."""
+    dims = [transverse] * 3
+    dims[axis] = n
+    shape = (dims[2], dims[1], dims[0])
+    bshape = [1, 1, 1]
+    bshape[2 - axis] = n
+    return shape, [np.broadcast_to(np.asarray(f, dtype=np.float64).reshape(bshape), shape)
+                   for f in profile_fields]
+
+
+def steep_supersonic(kind, n=16, k=7, axis=0, transverse=1, gamma=1.4, speed=20.0,
+                     grav=0.0):
+    """A supersonic flow along `axis` (|u| = speed, above every sound speed)
+    carrying a three-level staircase in one field: 100 upstream of cell k,
+    10 in cell k, 1 downstream ('rho_*': density with p = 1; 'p_*': pressure
+    with rho = 1).  '*_left' flows towards low indices with the staircase
+    falling towards high indices; '*_right' is its mirror image.  Only cell
+    k has a nonzero limited slope, and its Hancock face state on the side
+    away from the upstream plateau has a negative density or pressure.
+    Outflow ends along the axis, periodic transverse axes, equal cell widths
+    1/n; `grav` is the gravity along the axis."""
+    i = np.arange(n)
+    left = kind.endswith("_left")
+    if kind not in ("rho_left", "rho_right", "p_left", "p_right"):
+        raise ValueError(kind)
+    up = (i < k) if left else (i > k)
+    stair = np.where(up, 100.0, np.where(i == k, 10.0, 1.0))
+    one = np.ones(n)
+    rho, p = (stair, one) if kind.startswith("rho") else (one, stair)
+    u = (-speed if left else speed) * one
+    shape, (rho, u, p) = _embed_along((rho, u, p), axis, n, transverse)
+    z = np.zeros(shape)
+    vel = [z, z, z]
+    vel[axis] = u
+    U = conserved(rho, vel[0], vel[1], vel[2], p, gamma)
+    bc = [PERIODIC] * 6
+    bc[2 * axis] = bc[2 * axis + 1] = OUTFLOW
+    g = [0.0, 0.0, 0.0]
+    g[axis] = grav
+    return Problem(U=np.ascontiguousarray(U), dx=(1.0 / n,) * 3, gamma=gamma, bc=tuple(bc),
+                   grav=tuple(g), name=f"steep_{kind}", meta={"axis": axis, "k": k, "n": n})
+
+
+def two_rarefactions(n=64, speed=10.0, gamma=1.4, axis=0, transverse=1):
+    """Two strong rarefactions moving apart from x = 0.5 (rho = 1, p = 0.4,
+    u = -speed | +speed; Toro's test 2 has speed 2): the near-vacuum centre
+    drives Hancock face states non-positive.  Outflow ends, t_end = 0.02."""
+    x = centres(n)
+    u1 = np.where(x < 0.5, -speed, speed)
+    shape, (rho, u, p) = _embed_along((np.ones(n), u1, 0.4 * np.ones(n)), axis, n, transverse)
+    z = np.zeros(shape)
+    vel = [z, z, z]
+    vel[axis] = u
+    U = conserved(rho, vel[0], vel[1], vel[2], p, gamma)
+    bc = [PERIODIC] * 6
+    bc[2 * axis] = bc[2 * axis + 1] = OUTFLOW
+    return Problem(U=np.ascontiguousarray(U), dx=(1.0 / n,) * 3, gamma=gamma, bc=tuple(bc),
+                   t_end=0.02, name="two_rarefactions", meta={"axis": axis, "n": n})
+
+
 def stationary_contact(n=64, gamma=1.4, bc=OUTFLOW):
     """u = 0, uniform p = 1, density 1 | 0.25 at x = 0.5."""
     x = centres(n)

@@ -41,7 +41,16 @@ MUTANTS = {
                   "double s = (fabs(W[1 + d]) + cs) * p->dx[d];"),
     "momentum_source_old_rho": ("pen[c][1] += dt * g * (0.5 * (rho_old + pen[c][0]));",
                                 "pen[c][1] += dt * g * rho_old;"),
-    "update_sign": ("for (int v = 0; v < NV; ++v) pen[c][v] -= dtdx * (F[c][v] - F[c - 1][v]);",
+    "fallback_disabled": ("hancock(W[c], Z, dtdx, gamma, kick, has_g, Wm[c], Wp[c]);",
+                          "(void)Z;"),
+    "fallback_without_kick": ("hancock(W[c], Z, dtdx, gamma, kick, has_g, Wm[c], Wp[c]);",
+                              "hancock(W[c], Z, dtdx, gamma, kick, 0, Wm[c], Wp[c]);"),
+    "fallback_density_unchecked": (
+        "if (Wm[c][0] <= 0.0 || Wm[c][4] <= 0.0 || Wp[c][0] <= 0.0 ||",
+        "if (Wm[c][4] <= 0.0 ||"),
+    "fallback_plus_pressure_unchecked": ("        Wp[c][4] <= 0.0) {", "        0) {"),
+    "fallback_minus_pressure_unchecked": ("Wm[c][4] <= 0.0 || ", ""),
+    "update_sign":("for (int v = 0; v < NV; ++v) pen[c][v] -= dtdx * (F[c][v] - F[c - 1][v]);",
                     "for (int v = 0; v < NV; ++v) pen[c][v] += dtdx * (F[c][v] - F[c - 1][v]);"),
 }
 

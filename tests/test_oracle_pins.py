@@ -159,6 +159,120 @@ def test_hllc_upwind_supersonic():
 
 
 # --------------------------------------------------------------------------
+# positivity fallback: a cell whose Hancock face state has rho <= 0 or
+# p <= 0 is reconstructed with zero slopes (first order)
+# --------------------------------------------------------------------------
+
+def _pencil(U, axis):
+    """The single pencil of a grid that is one cell wide across `axis`, as
+    (5, n) in the sweep frame (rho, m_axis, m_t1, m_t2, E), transverse
+    momenta in ascending axis order."""
+    line = [0, 0, 0]
+    line[2 - axis] = slice(None)
+    V = U[(slice(None),) + tuple(line)]
+    t = [a for a in range(3) if a != axis]
+    return np.array([V[0], V[1 + axis], V[1 + t[0]], V[1 + t[1]], V[4]])
+
+
+def _first_order_upwind_sweep(U1, dt, dx, gamma, g, left):
+    """One sweep of a pencil (sweep frame) of supersonic flow when every cell
+    is reconstructed with zero slopes: each face takes the physical Euler
+    flux of its upwind cell (Davis speeds all of one sign make HLLC the
+    upwind flux), with the normal velocity raised by the half kick dt g/2,
+    followed by the time-centred gravity source.  Outflow ends copy the edge
+    cells.  Returns the new pencil and the face fluxes (face i - 1/2 at
+    index i)."""
+    ext = np.concatenate([U1[:, :1], U1, U1[:, -1:]], axis=1)     # cells -1 .. n
+    rho = ext[0]
+    u, t1, t2 = ext[1] / rho, ext[2] / rho, ext[3] / rho
+    p = (gamma - 1.0) * (ext[4] - 0.5 * rho * (u * u + t1 * t1 + t2 * t2))
+    u = u + 0.5 * dt * g
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + t1 * t1 + t2 * t2)
+    F = np.array([rho * u, rho * u * u + p, rho * u * t1, rho * u * t2, u * (E + p)])
+    face = F[:, 1:] if left else F[:, :-1]
+    new = U1 - dt / dx * (face[:, 1:] - face[:, :-1])
+    new[1] += dt * g * (0.5 * (U1[0] + new[0]))
+    new[4] += dt * g * (0.5 * (face[0, :-1] + face[0, 1:]))
+    return new, face
+
+
+@pytest.mark.parametrize("grav", [0.0, -40.0])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("kind", ["rho_left", "rho_right", "p_left", "p_right"])
+def test_positivity_fallback_is_first_order_upwind(kind, axis, grav):
+    # Cell k of the staircase 100 | 10 | 1 has the MC slope -18 (2|b|) and,
+    # at Courant number 1/2 against the flow, a downstream-side face value
+    # 10 - 9 (1 + 1/2) < 0 in the stepped field: it must fall back, and it is
+    # the only cell with a nonzero slope, so the whole sweep becomes the
+    # textbook first-order upwind scheme.
+    P = ic.steep_supersonic(kind, axis=axis, grav=grav)
+    n = P.meta["n"]
+    dx = P.dx[axis]
+    dt = 0.5 * dx / 20.0
+    p = params_of(P)
+    U = P.U.copy()
+    F = oracle.sweep_flux(p, U, dt, axis)
+    fb = oracle.sweep(p, P.U.copy(), dt, axis)
+    assert fb == 1
+    want, face = _first_order_upwind_sweep(_pencil(P.U, axis), dt, dx, P.gamma, grav,
+                                           kind.endswith("_left"))
+    got_face = _pencil(F, axis)
+    for v in range(5):
+        tol = 1e-14 * max(np.abs(face[v]).max(), 1e-300)
+        assert np.abs(got_face[v] - face[v]).max() <= tol, (v, got_face[v], face[v])
+    got = _pencil(U, axis)
+    for v in range(5):
+        tol = 1e-14 * max(np.abs(want[v]).max(), 1e-300)
+        assert np.abs(got[v] - want[v]).max() <= tol, (v, got[v], want[v])
+    assert n == got.shape[1]
+
+
+@pytest.mark.parametrize("kind", ["rho_left", "p_right"])
+def test_no_fallback_when_face_states_stay_positive(kind):
+    # a gentler staircase (upstream plateau 20): cell k keeps its slope
+    # (MC = |a+b|/2 = 9.5, face value 10 - 4.75 (1 + 1/2) > 0), so there is
+    # no fallback and the sweep is not the first-order one
+    P = ic.steep_supersonic(kind)
+    U = P.U.copy()
+    k, left = P.meta["k"], kind.endswith("_left")
+    up = slice(0, k) if left else slice(k + 1, None)
+    field = 0 if kind.startswith("rho") else 4
+    W = U[:, 0, 0, :]
+    if field == 0:
+        rho_up = 20.0
+        W[1, up] *= rho_up / W[0, up]
+        W[4, up] = 1.0 / (P.gamma - 1.0) + 0.5 * W[1, up] ** 2 / rho_up
+        W[0, up] = rho_up
+    else:
+        W[4, up] += (20.0 - 100.0) / (P.gamma - 1.0)
+    dx = P.dx[0]
+    dt = 0.5 * dx / 20.0
+    p = params_of(P)
+    V = U.copy()
+    assert oracle.sweep(p, V, dt, 0) == 0
+    want, _ = _first_order_upwind_sweep(_pencil(U, 0), dt, dx, P.gamma, 0.0, left)
+    assert np.abs(_pencil(V, 0)[0] - want[0]).max() > 1e-3 * np.abs(want[0]).max()
+
+
+def test_two_rarefactions_reach_fallback_and_stay_positive_and_symmetric():
+    # rho = 1, p = 0.4, u = -10 | +10 (vacuum forms between the fans):
+    # the near-vacuum centre drives Hancock face states negative; the run
+    # falls back, keeps rho and p positive, and stays mirror symmetric
+    P = ic.two_rarefactions(64)
+    U = P.U.copy()
+    t, steps, fb = oracle.run(params_of(P), U, 10 ** 6, t_end=P.t_end)
+    assert abs(t - P.t_end) <= 1e-16 and fb > 0
+    rho = U[0, 0, 0]
+    m = U[1, 0, 0]
+    E = U[4, 0, 0]
+    p = (P.gamma - 1.0) * (E - 0.5 * m * m / rho)
+    assert rho.min() > 0 and p.min() > 0
+    assert np.abs(rho - rho[::-1]).max() <= 1e-13 * rho.max()
+    assert np.abs(m + m[::-1]).max() <= 1e-13 * np.abs(m).max()
+    assert np.abs(E - E[::-1]).max() <= 1e-13 * E.max()
+
+
+# --------------------------------------------------------------------------
 # Sod shock tube
 # --------------------------------------------------------------------------
 
