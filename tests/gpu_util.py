@@ -100,3 +100,26 @@ def oracle_box_step(U_in, corner, m, P, dt, step, bc_axes_periodic=(True, True, 
     p = oracle.make_params(box.shape[1:], P.dx, P.gamma, P.cfl, (1,) * 6, P.grav)
     oracle.step(p, box, dt, step)
     return box[:, 2:-2, 2:-2, 2:-2]
+
+
+def max_fp32_errors(got, want):
+    """Per-cell (max-norm) errors of an FP32 result against the FP64 oracle:
+    (e_rho, e_m, e_E) with e_q = max_i |q32 - q64| / max_i |q64| for rho and
+    E, and for the momentum the largest component difference over the
+    largest momentum magnitude max_i |m_i| (one scale for the three
+    components, as in the L1 measure)."""
+    e_rho = float(np.abs(got[0] - want[0]).max() / np.abs(want[0]).max())
+    e_E = float(np.abs(got[4] - want[4]).max() / np.abs(want[4]).max())
+    m_scale = float(np.sqrt((want[1:4] ** 2).sum(axis=0)).max())
+    e_m = float(np.abs(got[1:4] - want[1:4]).max() / max(m_scale, 1e-300))
+    return e_rho, e_m, e_E
+
+
+def sub_box_dev(dev, z0, y0, x0, m):
+    """sub_box of a device state tensor, gathered on the device (only the
+    (5, m, m, m) block crosses to the host)."""
+    t = torch()
+    nz, ny, nx = dev.shape[1:]
+    idx = [t.tensor(np.arange(a, a + m) % n, device=dev.device) for a, n in
+           ((z0, nz), (y0, ny), (x0, nx))]
+    return dev.index_select(1, idx[0]).index_select(2, idx[1]).index_select(3, idx[2])

@@ -13,8 +13,8 @@ import pytest
 
 import hydro_ic as ic
 import oracle
-from gpu_util import (grid_scale, host, l1_fp32_errors, oracle_box_step, params_of,
-                      rel_err, say, sub_box, torch)
+from gpu_util import (grid_scale, host, l1_fp32_errors, max_fp32_errors, oracle_box_step, params_of,
+                      rel_err, say, sub_box, sub_box_dev, torch)
 from paper_1510_05061_amd import hydro
 
 pytestmark = pytest.mark.gpu
@@ -60,9 +60,12 @@ def test_kh256_fp32_step_l1():
     g, dev = _grid(P, hydro.FP32, U=U32)
     g.step(dt)
     oracle.step(p, U64, dt, 0)
-    e = l1_fp32_errors(host(dev), U64)
-    say(f"  L1 (rho, m, E) {e}")
+    out = host(dev)
+    e = l1_fp32_errors(out, U64)
+    mx = max_fp32_errors(out, U64)
+    say(f"  L1 (rho, m, E) {e} max {mx}")
     assert max(e) <= 2e-6
+    assert max(mx) <= 1e-5
     g.close()
 
 
@@ -111,38 +114,159 @@ def test_rt_full_sampled_blocks_and_invariants():
     g.close()
 
 
-def test_turbulence768_fp32_sampled_blocks():
+def test_rt_full_fp32_sampled_blocks_and_walls():
+    """The RT workload as bench.py runs it (FP32 state, reflecting z walls,
+    gravity, autotuned kernels, graph step), one step from the FP32-rounded
+    initial state against the oracle on sampled interior blocks and on
+    full-height columns through both walls.  rho and E: L1 per block within
+    the one-step bound 2e-6 and per cell within 1e-5 of the grid's largest
+    value.  The layer starts near rest (|m| <= 0.02), and the rounding of
+    its momentum comes from the momentum flux rho u^2 + p ~ p; so momentum
+    is measured per cell against the acoustic scale max(rho) max(c) (also
+    1e-5), not against its own tiny magnitude."""
+    say("rt full fp32")
+    P = ic.rt()
+    U32 = P.U.astype(np.float32)
+    U64 = U32.astype(np.float64)
+    p = params_of(P, nthreads=THREADS)
+    dt = oracle.cfl_dt(p, U64)
+    g, dev = _grid(P, hydro.FP32, U=U32)
+    say(f"  config {g.config}")
+    g.step(dt)
+    out = host(dev)
+    rho_max = float(np.abs(U64[0]).max())
+    E_max = float(np.abs(U64[4]).max())
+    pr = (P.gamma - 1.0) * (U64[4] - 0.5 * (U64[1] ** 2 + U64[2] ** 2 + U64[3] ** 2) / U64[0])
+    m_acoustic = rho_max * float(np.sqrt(P.gamma * pr / U64[0]).max())
+    del pr
+
+    def check(got, want, where):
+        e = l1_fp32_errors(got, want)
+        assert e[0] <= 2e-6 and e[2] <= 2e-6, (where, e)
+        mx = (np.abs(got[0] - want[0]).max() / rho_max,
+              np.abs(got[1:4] - want[1:4]).max() / m_acoustic,
+              np.abs(got[4] - want[4]).max() / E_max)
+        assert max(mx) <= 1e-5, (where, mx)
+
+    rng = np.random.default_rng(3)
+    m = 12
+    for _ in range(6):
+        corner = (int(rng.integers(4, 512 - m - 4)), int(rng.integers(0, 256)),
+                  int(rng.integers(0, 256)))
+        want = oracle_box_step(U64, corner, m, P, dt, 0)
+        check(sub_box(out, *corner, m), want, corner)
+    for x0, y0 in ((9, 250), (131, 60)):
+        col = np.ascontiguousarray(
+            U64[:, :, (np.arange(y0 - 2, y0 + 14) % 256)[:, None],
+                (np.arange(x0 - 2, x0 + 14) % 256)[None, :]])
+        q = oracle.make_params(col.shape[1:], P.dx, P.gamma, P.cfl,
+                               (1, 1, 1, 1, ic.REFLECT, ic.REFLECT), P.grav)
+        oracle.step(q, col, dt, 0)
+        want = col[:, :, 2:-2, 2:-2]
+        got = np.ascontiguousarray(
+            out[:, :, (np.arange(y0, y0 + 12) % 256)[:, None],
+                (np.arange(x0, x0 + 12) % 256)[None, :]])
+        check(got, want, (x0, y0))
+        # the wall rows themselves (first and last two z layers)
+        for zs in (slice(0, 2), slice(-2, None)):
+            check(got[:, zs], want[:, zs], ((x0, y0), zs))
+    assert g.error() == hydro.HYDRO_OK
+    g.close()
+
+
+@pytest.fixture(scope="module")
+def turb768():
+    """The 768^3 turbulence initial state in FP64 (18 GB on the host), built
+    once for the tests of both precisions."""
+    say("building the 768^3 turbulence state")
+    P = ic.turbulence(768)
+    yield P
+    del P
+
+
+def _turb_blocks(P, U_in, dev, dt, corners, m, nsteps):
+    """Oracle steps of (m + 4 nsteps)^3 boxes of U_in around each sampled
+    corner (the centre m^3 is exact after nsteps steps) beside the same
+    blocks gathered from the device state."""
+    g = 2 * nsteps
+    for corner in corners:
+        block_in = sub_box(U_in, corner[0] - g, corner[1] - g, corner[2] - g, m + 2 * g)
+        block_in = block_in.astype(np.float64)
+        q = oracle.make_params(block_in.shape[1:], P.dx, P.gamma, P.cfl, (1,) * 6)
+        for s in range(nsteps):
+            oracle.step(q, block_in, dt, s)
+        want = block_in[:, g:-g, g:-g, g:-g]
+        got = sub_box_dev(dev, *corner, m).cpu().numpy().astype(np.float64)
+        yield corner, got, want
+
+
+def test_turbulence768_fp32_sampled_blocks(turb768):
     """Two steps (both Strang orders; the second ends with the x sweep, which
     folds the CFL maximum) at one dt from the oracle; 12^3 blocks checked
     against the oracle run on a (12+8)^3 box of the input (the centre is
     exact after two steps)."""
     say("turbulence 768 fp32")
-    P = ic.turbulence(768, dtype=np.float32)
+    P = turb768
+    U32 = P.U.astype(np.float32)
     p = oracle.make_params(P.shape, P.dx, P.gamma, P.cfl, P.bc, P.grav, nthreads=THREADS)
-    U64 = P.U.astype(np.float64)
-    dt = oracle.cfl_dt(p, U64)
-    del U64
-    g, dev = _grid(P, hydro.FP32, U=P.U)
+    dt = oracle.cfl_dt(p, U32.astype(np.float64))
+    g, dev = _grid(P, hydro.FP32, U=U32)
+    say(f"  config {g.config}")
     g.step(dt)
     g.step(dt)
-    t = torch()
-    t.cuda.synchronize()
-    out = dev.cpu().numpy()          # float32 host copy (9 GB)
+    torch().cuda.synchronize()
     rng = np.random.default_rng(1)
-    m = 12
-    for _ in range(8):
-        corner = tuple(int(v) for v in rng.integers(0, 768, size=3))
-        block_in = sub_box(P.U, corner[0] - 4, corner[1] - 4, corner[2] - 4, m + 8)
-        block_in = block_in.astype(np.float64)
-        q = oracle.make_params(block_in.shape[1:], P.dx, P.gamma, P.cfl, (1,) * 6)
-        oracle.step(q, block_in, dt, 0)
-        oracle.step(q, block_in, dt, 1)
-        want = block_in[:, 4:-4, 4:-4, 4:-4]
-        got = sub_box(out, *corner, m).astype(np.float64)
+    corners = [tuple(int(v) for v in rng.integers(0, 768, size=3)) for _ in range(8)]
+    for corner, got, want in _turb_blocks(P, U32, dev, dt, corners, 12, 2):
         e = l1_fp32_errors(got, want)
         assert max(e) <= 4e-6, (corner, e)
     assert g.error() == hydro.HYDRO_OK
     g.close()
+    del dev, U32
+    torch().cuda.empty_cache()
+
+
+def test_turbulence768_fp64_tuned_and_wide_x_lane_runs(turb768):
+    """The FP64 path at 768^3 in the autotuned configuration bench.py times
+    and with x lane runs of 4 cells over three waves per pencil
+    (x:v=4,b=192): two steps at the oracle's dt, sampled 12^3 blocks against
+    the oracle to 1e-12 of the grid's scale, and the two configurations bit
+    for bit equal on the sampled blocks."""
+    P = turb768
+    p = oracle.make_params(P.shape, P.dx, P.gamma, P.cfl, P.bc, P.grav, nthreads=THREADS)
+    dt = oracle.cfl_dt(p, P.U)
+    scale = grid_scale(P.U)
+    t = torch()
+    src = t.from_numpy(P.U).to("cuda:0")
+    rng = np.random.default_rng(5)
+    corners = [tuple(int(v) for v in rng.integers(0, 768, size=3)) for _ in range(6)]
+    first = None
+    for cfg in (None, "x:v=4,b=192"):
+        dev = src.clone()
+        g = hydro.Grid(dev, P.dx, P.gamma, P.cfl, P.bc, P.grav)
+        if cfg:
+            g.config = cfg
+        say(f"turbulence 768 fp64 {g.config}")
+        assert abs(g.cfl_dt() - dt) <= 1e-14 * dt
+        g.step(dt)
+        g.step(dt)
+        t.cuda.synchronize()
+        blocks = []
+        for corner, got, want in _turb_blocks(P, P.U, dev, dt, corners, 12, 2):
+            err = rel_err(got, want, scale)
+            assert max(err) <= 1e-12, (g.config, corner, err)
+            blocks.append(got)
+        if first is None:
+            first = blocks
+        else:
+            for a, b in zip(first, blocks):
+                np.testing.assert_array_equal(a, b)
+        assert g.error() == hydro.HYDRO_OK
+        g.close()
+        del dev
+        t.cuda.empty_cache()
+    del src
+    t.cuda.empty_cache()
 
 
 def test_batch4096_fp32_sampled_patches():
