@@ -359,7 +359,8 @@ struct hydro_ctx {
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
   DevScalars* scal = nullptr;
-  double* partials = nullptr;
+  double* partials = nullptr;          // totals partials (fused and standalone)
+  double* tslice = nullptr;            // first level of the totals reduction
   double* profile_partials = nullptr;  // single grid: slab profile partial sums
   PatchDev single{};
   // batch
@@ -374,6 +375,7 @@ struct hydro_ctx {
   double t_host = 0.0;
   double t_end = 0.0;
   bool dt_valid = false;
+  bool totals_valid = false;  // scal->totals hold the totals of the current state
   Config cfg;
   Config items_cfg;          // configuration the batch work lists were built for
   bool active[3] = {false, false, false};
@@ -407,6 +409,7 @@ LaunchSweep sweep_launch(const hydro_ctx* c, int axis, int do_cfl) {
   L.bc_hi = c->desc.bc[2 * axis + 1];
   L.do_cfl = do_cfl;
   L.grav = c->desc.grav[axis];
+  for (int a = 0; a < 3; ++a) L.gvec[a] = c->desc.grav[a];
   L.gamma = c->desc.gamma;
   L.scal = c->scal;
   L.cfg = c->cfg.ax[axis];
@@ -510,7 +513,25 @@ std::vector<StepOp> step_ops(const hydro_ctx* c, int parity) {
     else
       ops.push_back(StepOp{sweep_launch(c, seq[i], cfl), seq[i]});
   }
+  // the last sweep also folds the FP64 totals of the updated cells
+  if (!ops.empty()) ops.back().L.tpart = c->partials;
   return ops;
+}
+
+// The end of a step after its sweep launches `ops`: the fixed-order sum of
+// the totals partials the last sweep wrote, then t += dt and the next dt.
+// With nothing to sweep the CFL maximum and the totals come from standalone
+// reductions of the state.
+hipError_t finish_step_launches(const hydro_ctx* c, const std::vector<StepOp>& ops,
+                                hipStream_t st) {
+  if (ops.empty()) {
+    hipError_t e = launch_cfl(reduce_launch(c), st);
+    if (e == hipSuccess) e = launch_totals(reduce_launch(c), st);
+    if (e != hipSuccess) return e;
+    return launch_finish_step(c->scal, st);
+  }
+  return launch_totals_finish(c->partials, sweep_parts(ops.back().L), c->tslice, c->scal, 1,
+                              st);
 }
 
 // The launches of a step, then the step bookkeeping.
@@ -521,12 +542,7 @@ hipError_t enqueue_step_kernels(const hydro_ctx* c, int parity, hipStream_t st) 
     hipError_t e = launch_sweep(op.L, st);
     if (e != hipSuccess) return e;
   }
-  if (ops.empty()) {
-    // nothing to sweep: still fold the CFL of the state so dt stays defined
-    hipError_t e = launch_cfl(reduce_launch(c), st);
-    if (e != hipSuccess) return e;
-  }
-  return launch_finish_step(c->scal, st);
+  return finish_step_launches(c, ops, st);
 }
 
 void destroy_graphs(hydro_ctx* c) {
@@ -940,29 +956,46 @@ int read_scalars(hydro_ctx* c, DevScalars* out) {
   return HYDRO_OK;
 }
 
-// Single-grid workspace: scalars, reduction partials, then the partial
-// sums of the slab profiles (kProfileChunksX per slab of the longest axis,
-// 5 values each).
-size_t grid_totals_bytes(int64_t cells) {
-  return align_up(size_t(chunks_for(cells)) * 6 * sizeof(double), 256);
+// Totals partials of a single grid: the most workgroups any valid
+// configuration launches for a sweep (x: one pencil per workgroup; y, z: 64
+// columns per tile), and at least the standalone reduction's chunks.
+int64_t grid_parts(const int32_t n[3]) {
+  int64_t m = kMaxChunks;
+  if (n[0] > 1) m = std::max<int64_t>(m, int64_t(n[1]) * n[2]);
+  if (n[1] > 1) m = std::max<int64_t>(m, (int64_t(n[0]) * n[2] + 63) / 64);
+  if (n[2] > 1) m = std::max<int64_t>(m, (int64_t(n[0]) * n[1] + 63) / 64);
+  return m;
+}
+
+// Single-grid workspace: scalars, totals partials and the first level of
+// their reduction, then the partial sums of the slab profiles
+// (kProfileChunksX per slab of the longest axis, 5 values each).
+size_t grid_totals_bytes(const int32_t n[3]) {
+  return align_up(size_t(grid_parts(n)) * 6 * sizeof(double), 256) +
+         align_up(size_t(kTotalsSlices) * 6 * sizeof(double), 256);
 }
 size_t grid_workspace_bytes(const int32_t n[3]) {
-  const int64_t cells = int64_t(n[0]) * n[1] * n[2];
   const int64_t nmax = std::max(n[0], std::max(n[1], n[2]));
-  return kScalarBytes + grid_totals_bytes(cells) +
+  return kScalarBytes + grid_totals_bytes(n) +
          align_up(size_t(nmax) * kProfileChunksX * 5 * sizeof(double), 256);
 }
 
 // layout of a batch workspace
 struct BatchLayout {
-  size_t partials, patches, items[4], total;
+  size_t partials, slice, patches, items[4], total;
 };
 
+// totals partials: one per work item of any sweep launch, and at least the
+// standalone reduction's chunks
 BatchLayout batch_layout(int32_t n, const int32_t items[4]) {
   BatchLayout L;
   size_t o = kScalarBytes;
   L.partials = o;
-  o += align_up(size_t(n) * kBatchChunks * 6 * sizeof(double), 256);
+  int64_t parts = int64_t(n) * kBatchChunks;
+  for (int a = 0; a < 4; ++a) parts = std::max<int64_t>(parts, items[a]);
+  o += align_up(size_t(parts) * 6 * sizeof(double), 256);
+  L.slice = o;
+  o += align_up(size_t(kTotalsSlices) * 6 * sizeof(double), 256);
   L.patches = o;
   o += align_up(size_t(n) * sizeof(PatchDev), 256);
   for (int a = 0; a < 4; ++a) {
@@ -1092,8 +1125,9 @@ int hydro_init(const hydro_desc* d, void* state, size_t state_bytes, void* works
   c->stream = static_cast<hipStream_t>(stream);
   c->scal = reinterpret_cast<DevScalars*>(c->ws);
   c->partials = reinterpret_cast<double*>(c->ws + kScalarBytes);
-  c->profile_partials = reinterpret_cast<double*>(
-      c->ws + kScalarBytes + grid_totals_bytes(int64_t(n[0]) * n[1] * n[2]));
+  c->tslice = reinterpret_cast<double*>(
+      c->ws + kScalarBytes + align_up(size_t(grid_parts(n)) * 6 * sizeof(double), 256));
+  c->profile_partials = reinterpret_cast<double*>(c->ws + kScalarBytes + grid_totals_bytes(n));
   c->single = P;
   for (int a = 0; a < 3; ++a) c->active[a] = n[a] > 1;
   c->cfg.ax[0] = default_x({P}, c->fp64);
@@ -1199,6 +1233,7 @@ int hydro_batch_init(const hydro_patch* p, int32_t n, const hydro_desc* common, 
   max_items(c->patches, cap);
   BatchLayout L = batch_layout(n, cap);
   c->partials = reinterpret_cast<double*>(c->ws + L.partials);
+  c->tslice = reinterpret_cast<double*>(c->ws + L.slice);
   c->d_patches = reinterpret_cast<PatchDev*>(c->ws + L.patches);
   for (int a = 0; a < 4; ++a) c->d_items[a] = reinterpret_cast<WorkItem*>(c->ws + L.items[a]);
   c->single = c->patches[0];
@@ -1261,6 +1296,7 @@ static int step_common(hydro_ctx* c, double dt, bool want_batch) {
   }
   c->step += 1;
   c->dt_valid = true;
+  c->totals_valid = true;
   return HYDRO_OK;
 }
 
@@ -1282,6 +1318,7 @@ int hydro_sweep(hydro_ctx* c, int axis, double dt, int fold_cfl) {
     HIP_TRY(launch_sweep(sweep_launch(c, axis, fold_cfl ? 1 : 0), c->stream));
   }
   if (c->batch) HIP_TRY(launch_reset_tickets(c->scal, c->stream));
+  c->totals_valid = false;
   if (fold_cfl) {
     // the device dt becomes the CFL dt of the swept state (t is left alone)
     HIP_TRY(launch_finish_cfl(c->scal, c->stream));
@@ -1307,7 +1344,24 @@ int hydro_cfl_dt(hydro_ctx* c, double* dt) {
 
 int hydro_totals(hydro_ctx* c, double out[6]) {
   if (!c || !out) return fail(HYDRO_EINVAL, "null argument");
-  HIP_TRY(launch_totals(reduce_launch(c), c->stream));
+  if (!items_current(c)) return fail(HYDRO_ESTATE, "batch work lists out of date");
+  if (!c->totals_valid) {
+    // the last sweep of the step before the current one (odd order, ending
+    // with x, before the first step), replayed with dt = 0 and no stores:
+    // its partition of the sums, hence the bits a step folds
+    std::vector<StepOp> ops = step_ops(c, int((c->step + 1) & 1));
+    if (ops.empty()) {
+      HIP_TRY(launch_totals(reduce_launch(c), c->stream));
+    } else {
+      LaunchSweep L = ops.back().L;
+      L.do_cfl = 0;
+      L.totals_only = 1;
+      HIP_TRY(launch_sweep(L, c->stream));
+      HIP_TRY(launch_totals_finish(c->partials, sweep_parts(L), c->tslice, c->scal, 0,
+                                   c->stream));
+    }
+    c->totals_valid = true;
+  }
   DevScalars s;
   int rc = read_scalars(c, &s);
   if (rc) return rc;
@@ -1435,6 +1489,8 @@ int hydro_burn(hydro_ctx* c, void* X, size_t x_bytes, const hydro_network* net, 
     }
   }
   HIP_TRY(launch_burn(L, c->stream));
+  c->totals_valid = false;
+  c->dt_valid = false;
   return HYDRO_OK;
 }
 
@@ -1520,6 +1576,8 @@ int amr_links(hydro_ctx* c, const hydro_amr_link* links, int32_t n, int op, int 
     L.cells = most;
     HIP_TRY(launch_amr(L, c->stream));
   }
+  c->totals_valid = false;
+  c->dt_valid = false;
   return HYDRO_OK;
 }
 
@@ -1675,6 +1733,7 @@ int level_sweeps(hydro_ctx* c, const hydro_ctx* coarse, const hydro_ctx* fine,
   HIP_TRY(launch_finish_step(c->scal, c->stream));
   c->step += 1;
   c->dt_valid = false;
+  c->totals_valid = false;
   return HYDRO_OK;
 }
 
@@ -1782,6 +1841,7 @@ int hydro_set_time(hydro_ctx* c, double t, int64_t step) {
   c->t_host = t;
   c->step = step;
   c->dt_valid = false;
+  c->totals_valid = false;
   return HYDRO_OK;
 }
 
@@ -1801,6 +1861,7 @@ int hydro_set_t_end(hydro_ctx* c, double t_end) {
 int hydro_state_changed(hydro_ctx* c) {
   if (!c) return fail(HYDRO_EINVAL, "null context");
   c->dt_valid = false;
+  c->totals_valid = false;
   return HYDRO_OK;
 }
 
@@ -1891,18 +1952,15 @@ int hydro_profile_step(hydro_ctx* c, double dt, double ms[4]) {
     }
     ms[op.slot] = double(t);
   }
-  if (rc == HYDRO_OK) {
-    if (ops.empty() && launch_cfl(reduce_launch(c), c->stream) != hipSuccess)
-      rc = fail(HYDRO_EDEVICE, "cfl launch failed");
-    else if (launch_finish_step(c->scal, c->stream) != hipSuccess)
-      rc = fail(HYDRO_EDEVICE, "step bookkeeping launch failed");
-  }
+  if (rc == HYDRO_OK && finish_step_launches(c, ops, c->stream) != hipSuccess)
+    rc = fail(HYDRO_EDEVICE, "step bookkeeping launch failed");
   for (int i = 0; i < 2; ++i) (void)hipEventDestroy(ev[i]);
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(c->stream));
   ms[3] = ms[0] + ms[1] + ms[2];
   c->step += 1;
   c->dt_valid = true;
+  c->totals_valid = true;
   return HYDRO_OK;
 }
 

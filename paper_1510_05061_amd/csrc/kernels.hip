@@ -47,6 +47,9 @@ struct SweepArgs {
   double grav_y;             // fused plane sweeps: gravity along y
   double gamma;
   DevScalars* scal;
+  double* tpart;             // totals partials (null: no totals)
+  double gvec[3];            // gravity vector (totals: phi = -g . x)
+  int32_t tonly;             // totals of the current state: dt = 0, no stores
 };
 
 // plane indices of (normal, transverse 1, transverse 2) momenta per axis
@@ -196,6 +199,106 @@ __device__ void finish_block(DevScalars* scal, T smax, bool bad, bool do_cfl, T*
   }
 }
 
+// --------------------------------------------------------------------------
+// FP64 conserved totals folded into the last sweep of a step
+// --------------------------------------------------------------------------
+//
+// Each thread sums, in the order it updates its cells, the lab-frame
+// rho, mx, my, mz, E and E + rho phi of every updated cell times the cell
+// volume, phi = -(g . x) at the cell centre (origin at the low corner of the
+// grid or patch).  A workgroup then reduces its threads' sums in a fixed
+// tree into one partial per workgroup (direct launches) or per work item
+// (persistent launches), so the summation order depends only on the launch
+// configuration, never on scheduling: the totals are bitwise reproducible.
+
+// Per-thread sums in registers.
+struct TotR {
+  double s[6];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int v = 0; v < 6; ++v) s[v] = 0.0;
+  }
+  __device__ __forceinline__ void add(int v, double x) { s[v] += x; }
+  __device__ __forceinline__ double get(int v) const { return s[v]; }
+};
+
+// Per-thread sums in LDS, for kernels whose registers are spoken for: the
+// six sums of thread t at p[kTotStride t + v].  One address register and an
+// immediate offset per slot; a stride of 7 doubles (14 banks) puts the 64-bit
+// slots of 16 consecutive lanes on 32 distinct banks.  Each thread adds only
+// into its own slots, with LDS atomic adds that return nothing: no
+// registers are held and the wave does not wait.
+constexpr int kTotStride = 7;
+struct TotL {
+  double* p;
+  __device__ __forceinline__ double* slot() const { return p + kTotStride * threadIdx.x; }
+  __device__ __forceinline__ void zero() {
+    double* q = slot();
+#pragma unroll
+    for (int v = 0; v < 6; ++v) q[v] = 0.0;
+  }
+  __device__ __forceinline__ void add(int v, double x) { atomicAdd(slot() + v, x); }
+  __device__ __forceinline__ double get(int v) const { return slot()[v]; }
+};
+
+__device__ __forceinline__ double cell_volume(const PatchDev& P) {
+  return P.dx[0] * P.dx[1] * P.dx[2];
+}
+
+__device__ __forceinline__ bool has_grav(const double g[3]) {
+  return g[0] != 0.0 || g[1] != 0.0 || g[2] != 0.0;
+}
+
+// Cell (i, j, k) of patch P (interior indices along x, y, z) with its
+// updated state S in the frame of sweep axis AXIS: adds q for q = rho, mx,
+// my, mz, E and, with gravity, E + rho phi (the cell volume multiplies each
+// thread's sums once, in tot_block).
+template <class T, int AXIS, class Acc>
+__device__ __forceinline__ void tot_add(Acc& t, const Cons<T>& S, const PatchDev& P,
+                                        const double g[3], int i, int j, int k) {
+  constexpr int vn = AXIS + 1, vt1 = AXIS == 0 ? 2 : 1, vt2 = AXIS == 2 ? 2 : 3;
+  t.add(0, double(S.r));
+  t.add(vn, double(S.mn));
+  t.add(vt1, double(S.mt1));
+  t.add(vt2, double(S.mt2));
+  t.add(4, double(S.e));
+  if (has_grav(g)) {  // else E + rho phi = E (tot_block)
+    const double xc = (double(i) + 0.5) * P.dx[0];
+    const double yc = (double(j) + 0.5) * P.dx[1];
+    const double zc = (double(k) + 0.5) * P.dx[2];
+    const double phi = -(g[0] * xc + g[1] * yc + g[2] * zc);
+    t.add(5, double(S.e) + double(S.r) * phi);
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// The workgroup's sums, each thread's times the cell volume `vol`, in a
+// fixed tree (lanes, then waves in order), into out[0..5]; every thread of
+// the workgroup calls this.  `red` holds 6 doubles per wave (LDS).  The
+// sums are cleared for the next work item.
+template <class Acc>
+__device__ void tot_block(Acc& t, double vol, double* out, double* red, bool grav) {
+  const int wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int v = 0; v < 6; ++v) {
+    const double w = wave_sum(t.get(grav || v < 5 ? v : 4) * vol);  // phi = 0: E + rho phi is E
+    if ((threadIdx.x & 63) == 0) red[wid * 6 + v] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double a = red[threadIdx.x];
+    for (int w = 1; w < nw; ++w) a += red[w * 6 + threadIdx.x];
+    out[threadIdx.x] = a;
+  }
+  __syncthreads();
+  t.zero();
+}
+
 template <class T>
 __device__ __forceinline__ Prim<T> shfl_prim(const Prim<T>& W, int src) {
   Prim<T> r;
@@ -333,10 +436,11 @@ __device__ __forceinline__ void lanerun_update(Cons<T> (&U)[V], int gl, int last
 //    in-place update is race-free.
 // Outflow and reflecting ends build their ghost cells from the edge lanes'
 // own cells.
-template <class T, int V, bool MULTI>
+template <class T, int V, bool MULTI, bool TOT>
 __device__ void xsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t tile,
                             const SweepConst<T>& k, EdgeSlots<T>* slots, T& smax,
-                            bool& bad) {
+                            bool& bad, TotR& tot) {
+  const bool store = !(TOT && a.tonly);
   const int N = P.n[0];
   const int LPP = N / V;                 // lanes per pencil
   const int tid = threadIdx.x;
@@ -367,8 +471,10 @@ __device__ void xsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t ti
   act = act && q < npen;
   const Planes<T, 0> pl(a.pool, P);
   uint32_t off = 0;  // byte offset of this lane's first cell inside a plane
+  unsigned y = 0, z = 0;
   if (act) {
-    const unsigned z = unsigned(q) / unsigned(P.n[1]), y = unsigned(q) - z * unsigned(P.n[1]);
+    z = unsigned(q) / unsigned(P.n[1]);
+    y = unsigned(q) - z * unsigned(P.n[1]);
     off = uint32_t((int64_t(y) * P.sy + int64_t(z) * P.sz + gl * V) * int64_t(sizeof(T)));
   }
 
@@ -398,7 +504,11 @@ __device__ void xsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t ti
     inv_widths<T>(P, id);
     lanerun_update<T, V, 0>(U, gl, last, srcL, srcR, a.bc_lo, a.bc_hi, k, id, act,
                             a.do_cfl != 0, smax, bad);
-    if (act) {
+    if (TOT && act) {
+#pragma unroll
+      for (int c = 0; c < V; ++c) tot_add<T, 0>(tot, U[c], P, a.gvec, gl * V + c, y, z);
+    }
+    if (act && store) {
       T r[V], mn[V], mt1[V], mt2[V], e[V];
 #pragma unroll
       for (int c = 0; c < V; ++c) {
@@ -522,12 +632,15 @@ __device__ void xsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t ti
       update(U[c], F[c], c == V - 1 ? FR : F[c + 1], k);
       r[c] = U[c].r; mn[c] = U[c].mn; mt1[c] = U[c].mt1; mt2[c] = U[c].mt2; e[c] = U[c].e;
       if (a.do_cfl) smax = fmax_(smax, cell_speed<T, 0>(U[c], k, id, bad));
+      if (TOT) tot_add<T, 0>(tot, U[c], P, a.gvec, gl * V + c, y, z);
     }
-    store_run<T, V>(pl.r, off, r);
-    store_run<T, V>(pl.n, off, mn);
-    store_run<T, V>(pl.t1, off, mt1);
-    store_run<T, V>(pl.t2, off, mt2);
-    store_run<T, V>(pl.e, off, e);
+    if (store) {
+      store_run<T, V>(pl.r, off, r);
+      store_run<T, V>(pl.n, off, mn);
+      store_run<T, V>(pl.t1, off, mt1);
+      store_run<T, V>(pl.t2, off, mt2);
+      store_run<T, V>(pl.e, off, e);
+    }
   }
 }
 
@@ -551,17 +664,23 @@ __device__ __forceinline__ int item_at(const SweepArgs<T>& a, int i, unsigned in
   return int(blockIdx.x) + i * int(gridDim.x);
 }
 
-template <class T, int V, bool MULTI, bool PERSIST>
+template <class T, int V, bool MULTI, bool PERSIST, bool TOT>
 __global__ void __launch_bounds__(512) sweep_x_kernel(SweepArgs<T> a) {
   __shared__ EdgeSlots<T> slots[MULTI ? 8 : 1];
   __shared__ int item_s;
   __shared__ T red[8];
-  const double dt = a.scal->dt;
+  __shared__ double tred[TOT ? 48 : 1];
+  const double dt = (TOT && a.tonly) ? 0.0 : a.scal->dt;
+  const bool grav = has_grav(a.gvec);
   T smax = T(0);
   bool bad = false;
+  TotR tot;
+  tot.zero();
   if (!PERSIST) {
     SweepConst<T> k = make_const<T>(dt, a.single.dx[0], a.gamma, a.grav);
-    xsweep_tile<T, V, MULTI>(a, a.single, blockIdx.x, k, slots, smax, bad);
+    xsweep_tile<T, V, MULTI, TOT>(a, a.single, blockIdx.x, k, slots, smax, bad, tot);
+    if (TOT)
+      tot_block(tot, cell_volume(a.single), a.tpart + 6 * int64_t(blockIdx.x), tred, grav);
   } else {
     for (int i = 0;; ++i) {
       const int it = item_at(a, i, &a.scal->tickets[0], &item_s);
@@ -569,7 +688,8 @@ __global__ void __launch_bounds__(512) sweep_x_kernel(SweepArgs<T> a) {
       const WorkItem w = a.items[it];
       const PatchDev P = a.patches[w.patch];
       SweepConst<T> k = make_const<T>(dt, P.dx[0], a.gamma, a.grav);
-      xsweep_tile<T, V, MULTI>(a, P, w.tile, k, slots, smax, bad);
+      xsweep_tile<T, V, MULTI, TOT>(a, P, w.tile, k, slots, smax, bad, tot);
+      if (TOT) tot_block(tot, cell_volume(P), a.tpart + 6 * int64_t(it), tred, grav);
       if (MULTI) __syncthreads();
     }
   }
@@ -685,11 +805,12 @@ __device__ __forceinline__ void get_run(const T* line, int slot, Run<T, V>& R) {
 // the wrap flux of the first chunk for its high end.  Every value of a
 // pencil is loaded before the wave stores over it, and no other wave touches
 // the pencil, so the update is in place without barriers.
-template <class T, int V>
+template <class T, int V, bool TOT>
 __device__ void xmarch_pencils(const SweepArgs<T>& a, const PatchDev& P, int q0, int qs,
                                int qend, const SweepConst<T>& k, const T id[3], T* line,
-                               T& smax, bool& bad) {
+                               T& smax, bool& bad, TotL& tot) {
   if (q0 >= qend) return;
+  const bool store = !(TOT && a.tonly);
   const int N = P.n[0];
   const int LPP = N / V;
   const int C = (LPP + 63) >> 6;
@@ -708,6 +829,7 @@ __device__ void xmarch_pencils(const SweepArgs<T>& a, const PatchDev& P, int q0,
   load_runs<T, V>(pl, row_of(q0) + uint32_t(l) * runb, l < LPP, nxt);
   for (int q = q0; q < qend; q += qs) {
     const uint32_t row = row_of(q);
+    const int qz = int(unsigned(q) / ny), qy = q - qz * int(ny);  // the pencil's (y, z)
     const int qn = q + qs;  // next pencil of this wave
     Prim<T> Wt1, Wt2;  // original cells N-1 and N-2 (periodic low end)
     if (per) {
@@ -819,7 +941,8 @@ __device__ void xmarch_pencils(const SweepArgs<T>& a, const PatchDev& P, int q0,
         Cons<T> Ud = Uheld;
         update(Ud, Fheld, lane_cons(F[0], 0), k);
         if (a.do_cfl && l == 0) smax = fmax_(smax, cell_speed<T, 0>(Ud, k, id, bad));
-        if (l < LPL) {
+        if (TOT && l == 0) tot_add<T, 0>(tot, Ud, P, a.gvec, j * 64 * V - 1, qy, qz);
+        if (l < LPL && store) {
           Run<T, V> o;
           get_run<T, V>(line, l, o);
           if (l == LPL - 1) {
@@ -849,6 +972,8 @@ __device__ void xmarch_pencils(const SweepArgs<T>& a, const PatchDev& P, int q0,
           update(U[c], F[c], c == V - 1 ? FR : F[c + 1], k);
           if (a.do_cfl && !(hold && c == V - 1))
             smax = fmax_(smax, cell_speed<T, 0>(U[c], k, id, bad));
+          if (TOT && !(hold && c == V - 1))
+            tot_add<T, 0>(tot, U[c], P, a.gvec, gl * V + c, qy, qz);
         }
         Run<T, V> o;
 #pragma unroll
@@ -856,7 +981,9 @@ __device__ void xmarch_pencils(const SweepArgs<T>& a, const PatchDev& P, int q0,
           o.r[c] = U[c].r; o.n[c] = U[c].mn; o.t1[c] = U[c].mt1; o.t2[c] = U[c].mt2;
           o.e[c] = U[c].e;
         }
-        if (lastc || l < 64 - LPL) {
+        if (!store) {
+          // totals of the current state: nothing is written
+        } else if (lastc || l < 64 - LPL) {
           store_run<T, V>(pl.r, off, o.r);
           store_run<T, V>(pl.n, off, o.n);
           store_run<T, V>(pl.t1, off, o.t1);
@@ -870,16 +997,24 @@ __device__ void xmarch_pencils(const SweepArgs<T>& a, const PatchDev& P, int q0,
   }
 }
 
-template <class T, int V, bool PERSIST>
-__global__ void __launch_bounds__(512) sweep_xm_kernel(SweepArgs<T> a) {
+// Direct FP32 launches: at least three waves per SIMD (168 registers),
+// which the totals instantiation would otherwise miss by one register.
+template <class T, int V, bool PERSIST, bool TOT>
+__global__ void __launch_bounds__(512, sizeof(T) == 4 && !PERSIST ? 3 : 1)
+    sweep_xm_kernel(SweepArgs<T> a) {
   __shared__ int item_s;
   __shared__ T red[8];
   __shared__ T lines[8][5 * kLineBytes / sizeof(T)];  // per wave
-  const double dt = a.scal->dt;
+  __shared__ double tred[TOT ? 48 : 1];
+  extern __shared__ __align__(16) unsigned char dyn_lds[];  // TOT: per-thread totals (TotL)
+  const double dt = (TOT && a.tonly) ? 0.0 : a.scal->dt;
+  const bool grav = has_grav(a.gvec);
   const int nw = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   T smax = T(0);
   bool bad = false;
+  TotL tot{reinterpret_cast<double*>(dyn_lds)};
+  if (TOT) tot.zero();
   if (!PERSIST) {
     const PatchDev& P = a.single;
     SweepConst<T> k = make_const<T>(dt, P.dx[0], a.gamma, a.grav);
@@ -887,8 +1022,10 @@ __global__ void __launch_bounds__(512) sweep_xm_kernel(SweepArgs<T> a) {
     inv_widths<T>(P, id);
     // grid-stride over pencils: wave w of workgroup b takes pencils
     // b nw + w, (b + G) nw + w, ... for a grid of G workgroups
-    xmarch_pencils<T, V>(a, P, int(blockIdx.x) * nw + wave, int(gridDim.x) * nw,
-                         P.n[1] * P.n[2], k, id, lines[wave], smax, bad);
+    xmarch_pencils<T, V, TOT>(a, P, int(blockIdx.x) * nw + wave, int(gridDim.x) * nw,
+                              P.n[1] * P.n[2], k, id, lines[wave], smax, bad, tot);
+    if (TOT)
+      tot_block(tot, cell_volume(a.single), a.tpart + 6 * int64_t(blockIdx.x), tred, grav);
   } else {
     for (int i = 0;; ++i) {
       const int it = item_at(a, i, &a.scal->tickets[0], &item_s);
@@ -899,8 +1036,9 @@ __global__ void __launch_bounds__(512) sweep_xm_kernel(SweepArgs<T> a) {
       T id[3];
       inv_widths<T>(P, id);
       const int npen = P.n[1] * P.n[2];
-      xmarch_pencils<T, V>(a, P, w.tile * nw + wave, npen, npen, k, id, lines[wave], smax,
-                           bad);
+      xmarch_pencils<T, V, TOT>(a, P, w.tile * nw + wave, npen, npen, k, id, lines[wave], smax,
+                                bad, tot);
+      if (TOT) tot_block(tot, cell_volume(P), a.tpart + 6 * int64_t(it), tred, grav);
     }
   }
   finish_block(a.scal, smax, bad, a.do_cfl != 0, red);
@@ -1085,16 +1223,38 @@ __device__ void plane_sweep(const SweepArgs<T>& a, const PatchDev& P, int z, T* 
   }
 }
 
+// The FP64 totals of plane z of patch P, held in LDS after its last sweep:
+// thread t takes the cells t, t + blockDim.x, ... of the plane (x fastest).
+template <class T, int V>
+__device__ void plane_totals(const SweepArgs<T>& a, const PatchDev& P, int z, const T* lds,
+                             TotR& tot) {
+  constexpr int PP = kPlanePitch;
+  const int nx = P.n[0], cells = P.n[0] * P.n[1];
+  for (int c = threadIdx.x; c < cells; c += blockDim.x) {
+    const int y = c / nx, x = c - y * nx;
+    const T* p = lds + 5 * y * PP + plane_col<V>(x, y);
+    const Cons<T> U{p[0], p[PP], p[2 * PP], p[3 * PP], p[4 * PP]};  // x frame: lab order
+    tot_add<T, 0>(tot, U, P, a.gvec, x, y, z);
+  }
+}
+
 // XFIRST: x then y (even steps); else y then x (odd steps), where the x
-// sweep is the last of the step and folds the CFL maximum.
-template <class T, int V, bool XFIRST>
+// sweep is the last of the step and folds the CFL maximum.  TOT (the last
+// launch of a step): the plane's second sweep leaves its result in LDS,
+// plane_totals adds it to the totals and the plane is copied out.
+template <class T, int V, bool XFIRST, bool TOT>
 __global__ void __launch_bounds__(512) sweep_plane_kernel(SweepArgs<T> a) {
   extern __shared__ __align__(16) unsigned char dyn_lds[];
+  __shared__ double tred[TOT ? 48 : 1];
   T* lds = reinterpret_cast<T*>(dyn_lds);
   int* slot = reinterpret_cast<int*>(dyn_lds);  // free between items
-  const double dt = a.scal->dt;
+  const double dt = (TOT && a.tonly) ? 0.0 : a.scal->dt;
+  const bool store = !(TOT && a.tonly);
+  const bool grav = has_grav(a.gvec);
   T smax = T(0);
   bool bad = false;
+  TotR tot;
+  tot.zero();
   for (int i = 0;; ++i) {
     const int it = item_at(a, i, &a.scal->tickets[3], slot);
     if (it >= a.nitems) break;
@@ -1107,16 +1267,25 @@ __global__ void __launch_bounds__(512) sweep_plane_kernel(SweepArgs<T> a) {
       __syncthreads();
       plane_sweep<T, V, 1, false, false>(a, P, z, lds, a.do_cfl != 0, dt, smax, bad);
       __syncthreads();
-      plane_copy<T, V, false>(a, P, z, lds);
+      if (TOT) plane_totals<T, V>(a, P, z, lds, tot);
+      if (store) plane_copy<T, V, false>(a, P, z, lds);
     } else {
       // pool -> LDS; y: LDS -> LDS; x: LDS -> registers -> pool
       plane_copy<T, V, true>(a, P, z, lds);
       __syncthreads();
       plane_sweep<T, V, 1, false, false>(a, P, z, lds, false, dt, smax, bad);
       __syncthreads();
-      plane_sweep<T, V, 0, false, true>(a, P, z, lds, a.do_cfl != 0, dt, smax, bad);
+      if (TOT) {
+        plane_sweep<T, V, 0, false, false>(a, P, z, lds, a.do_cfl != 0, dt, smax, bad);
+        __syncthreads();
+        plane_totals<T, V>(a, P, z, lds, tot);
+        if (store) plane_copy<T, V, false>(a, P, z, lds);
+      } else {
+        plane_sweep<T, V, 0, false, true>(a, P, z, lds, a.do_cfl != 0, dt, smax, bad);
+      }
     }
     __syncthreads();  // the LDS is free again (the next ticket lands in it)
+    if (TOT) tot_block(tot, cell_volume(P), a.tpart + 6 * int64_t(it), tred, grav);
   }
   finish_block(a.scal, smax, bad, a.do_cfl != 0, lds);
 }
@@ -1152,9 +1321,10 @@ __device__ __forceinline__ int edge_slot(int c, int L, int N, int* seg) {
 //    read from memory once.
 //  * LDSH = false: each thread loads its halo cells from memory before the
 //    barrier (the owner loads them again when it marches there).
-template <class T, int AXIS, bool LDSH>
+template <class T, int AXIS, bool LDSH, bool TOT>
 __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t tile,
-                              const SweepConst<T>& k, T* tab, T& smax, bool& bad) {
+                              const SweepConst<T>& k, T* tab, T& smax, bool& bad, TotL& tot) {
+  const bool store = !(TOT && a.tonly);
   constexpr int TA = AXIS == 1 ? 2 : 1;   // the other transverse axis
   const int N = P.n[AXIS];
   const int nx = P.n[0];
@@ -1171,10 +1341,18 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
   const bool act = (seg < S) && (col < ncol) && (ja < jb);
   const Planes<T, AXIS> pl(a.pool, P);
   uint32_t cb = 0;  // byte offset of the column's cell 0 inside a plane
+  int cx = 0, ct = 0;  // the column's x and its index along the other transverse axis
   if (act) {
     const unsigned t = unsigned(col) / unsigned(nx), x = unsigned(col) - t * unsigned(nx);
     cb = uint32_t((int64_t(x) + int64_t(t) * st) * int64_t(sizeof(T)));
+    cx = int(x);
+    ct = int(t);
   }
+  // the updated cell c of the column into the totals
+  auto total = [&](const Cons<T>& U, int c) {
+    if (AXIS == 1) tot_add<T, 1>(tot, U, P, a.gvec, cx, c, ct);
+    else tot_add<T, 2>(tot, U, P, a.gvec, cx, ct, c);
+  };
 
   // halo cell h (ja-2, ja-1, jb, jb+1) after the boundary conditions: the
   // interior cell it copies, and whether it is mirrored
@@ -1193,6 +1371,18 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
     return j;
   };
 
+  // halo h from the LDSH table (primitives of segment edge cells)
+  auto table_halo = [&](int h) {
+    bool mir;
+    int os;
+    const int e = edge_slot(halo_cell(h, mir), L, N, &os);
+    const T* t = tab + ((os * 4 + e) * 5) * Q + l;
+    Prim<T> W;
+    W.r = t[0]; W.u = t[Q]; W.t1 = t[2 * Q]; W.t2 = t[3 * Q]; W.p = t[4 * Q];
+    W.ri = rcp(W.r);  // as to_prim computes it
+    return mir ? mirror(W) : W;
+  };
+
   Prim<T> H[4];
   Cons<T> E[4];  // LDSH: own cells ja, ja+1, jb-2, jb-1 (clamped into the segment)
   if (LDSH) {
@@ -1208,17 +1398,11 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
     }
     __syncthreads();  // the table is full, and no cell has been written
     if (!act) return;
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      bool mir;
-      int os;
-      const int e = edge_slot(halo_cell(h, mir), L, N, &os);
-      const T* t = tab + ((os * 4 + e) * 5) * Q + l;
-      Prim<T> W;
-      W.r = t[0]; W.u = t[Q]; W.t1 = t[2 * Q]; W.t2 = t[3 * Q]; W.p = t[4 * Q];
-      W.ri = rcp(W.r);  // as to_prim computes it
-      H[h] = mir ? mirror(W) : W;
-    }
+    // the halos before the segment now; those after it are read from the
+    // table again at the end of the march (the table stays intact until the
+    // tile ends), so they hold no registers during the march
+    H[0] = table_halo(0);
+    H[1] = table_halo(1);
   } else {
     if (act) {
 #pragma unroll
@@ -1255,7 +1439,7 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
     U1 = LDSH ? E[1] : pl.load(b + sd);
     W1 = to_prim(U1, k);
   } else {
-    W1 = H[2];
+    W1 = LDSH ? table_halo(2) : H[2];
   }
   Prim<T> WpPrev, WmC, WpC, dummy;
   face_states(H[0], H[1], W0, k, kick_lo, dummy, WpPrev);   // cell ja-1
@@ -1263,15 +1447,16 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
   Cons<T> Fl = hllc(WpPrev, WmC, k);
   WpPrev = WpC;
 
-  // one step of the march with cell j+2 in U2
-  auto advance = [&](const Cons<T>& U2) {
+  // one step of the march with cell j+2 in U2 (cell j updated)
+  auto advance = [&](const Cons<T>& U2, int j) {
     const Prim<T> W2 = to_prim(U2, k);
     Prim<T> Wm1, Wp1;
     face_states(W0, W1, W2, k, k.kick, Wm1, Wp1);  // cell j+1
     const Cons<T> Fr = hllc(WpPrev, Wm1, k);
     update(U0, Fl, Fr, k);
-    pl.store(b, U0);
+    if (store) pl.store(b, U0);
     if (a.do_cfl) smax = fmax_(smax, cell_speed<T, AXIS>(U0, k, id, bad));
+    if (TOT) total(U0, j);
     b += sd;
     U0 = U1;
     U1 = U2;
@@ -1310,11 +1495,13 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
       for (int d = 0; d + 1 < D; ++d) Pq[d] = Pq[d + 1];
       oa = min(oa + sd, bmax);  // cell j+2+D, clamped
       Pq[D - 1] = pl.load(oa);
-      advance(U2);
+      advance(U2, j);
     }
   }
   if (LDSH) {
-    for (; j < jb - 2; ++j) advance(j + 2 == jb - 2 ? E[2] : E[3]);
+    for (; j < jb - 2; ++j) advance(j + 2 == jb - 2 ? E[2] : E[3], j);
+    H[2] = table_halo(2);
+    H[3] = table_halo(3);
   }
   for (; j < jb; ++j) {
     const Prim<T> W2 = (j + 2 == jb) ? H[2] : H[3];
@@ -1322,8 +1509,9 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
     face_states(W0, W1, W2, k, (j + 1 == jb) ? kick_hi : k.kick, Wm1, Wp1);  // cell j+1
     const Cons<T> Fr = hllc(WpPrev, Wm1, k);
     update(U0, Fl, Fr, k);
-    pl.store(b, U0);
+    if (store) pl.store(b, U0);
     if (a.do_cfl) smax = fmax_(smax, cell_speed<T, AXIS>(U0, k, id, bad));
+    if (TOT) total(U0, j);
     b += sd;
     U0 = U1;
     W0 = W1;
@@ -1339,19 +1527,29 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
 #define HYDRO_COL_WAVES 4
 #endif
 constexpr int kColWaves = HYDRO_COL_WAVES;
-template <class T, int AXIS, bool PERSIST, bool LDSH>
-__global__ void __launch_bounds__(512, sizeof(T) == 4 ? kColWaves : 1)
+// Dynamic LDS: with TOT the per-thread totals (kTotStride doubles a
+// thread) first, then with LDSH the halo table.
+// FP32: kColWaves waves per SIMD; the persistent totals instantiation (the
+// batch's last z sweep) takes three, whose registers hold it without spills.
+template <class T, int AXIS, bool PERSIST, bool LDSH, bool TOT>
+__global__ void __launch_bounds__(512, sizeof(T) == 4 ? (PERSIST && TOT ? 3 : kColWaves) : 1)
     sweep_col_kernel(SweepArgs<T> a) {
   __shared__ int item_s;
   __shared__ T red[8];
-  extern __shared__ __align__(16) unsigned char dyn_lds[];  // halo table (LDSH)
-  T* tab = reinterpret_cast<T*>(dyn_lds);
-  const double dt = a.scal->dt;
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  __shared__ double tred[TOT ? 48 : 1];
+  TotL tot{reinterpret_cast<double*>(dyn_lds)};
+  T* tab = reinterpret_cast<T*>(dyn_lds + (TOT ? 8 * kTotStride * blockDim.x : 0));
+  const double dt = (TOT && a.tonly) ? 0.0 : a.scal->dt;
+  const bool grav = has_grav(a.gvec);
   T smax = T(0);
   bool bad = false;
+  if (TOT) tot.zero();
   if (!PERSIST) {
     SweepConst<T> k = make_const<T>(dt, a.single.dx[AXIS], a.gamma, a.grav);
-    colsweep_tile<T, AXIS, LDSH>(a, a.single, blockIdx.x, k, tab, smax, bad);
+    colsweep_tile<T, AXIS, LDSH, TOT>(a, a.single, blockIdx.x, k, tab, smax, bad, tot);
+    if (TOT)
+      tot_block(tot, cell_volume(a.single), a.tpart + 6 * int64_t(blockIdx.x), tred, grav);
   } else {
     for (int i = 0;; ++i) {
       const int it = item_at(a, i, &a.scal->tickets[AXIS], &item_s);
@@ -1359,8 +1557,9 @@ __global__ void __launch_bounds__(512, sizeof(T) == 4 ? kColWaves : 1)
       const WorkItem w = a.items[it];
       const PatchDev P = a.patches[w.patch];
       SweepConst<T> k = make_const<T>(dt, P.dx[AXIS], a.gamma, a.grav);
-      colsweep_tile<T, AXIS, LDSH>(a, P, w.tile, k, tab, smax, bad);
+      colsweep_tile<T, AXIS, LDSH, TOT>(a, P, w.tile, k, tab, smax, bad, tot);
       __syncthreads();
+      if (TOT) tot_block(tot, cell_volume(P), a.tpart + 6 * int64_t(it), tred, grav);
     }
   }
   finish_block(a.scal, smax, bad, a.do_cfl != 0, red);
@@ -1403,11 +1602,6 @@ __global__ void __launch_bounds__(256) cfl_kernel(ReduceArgs<T> a) {
     smax = fmax_(smax, cell_speed<T, 0>(U, k, id, bad));
   }
   finish_block(a.scal, smax, bad, true, red);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
 }
 
 // Partial sums of rho, mx, my, mz, E and E + rho*phi (phi = -g.x at cell
@@ -1498,6 +1692,56 @@ __global__ void finish_step_kernel(DevScalars* s) {
   s->tickets[0] = s->tickets[1] = s->tickets[2] = s->tickets[3] = 0u;
 }
 
+// The FP64 totals from n per-workgroup partials, in a fixed order: workgroup
+// b of R sums the partials [b n / R, (b + 1) n / R) (thread-strided, then a
+// fixed wave and workgroup tree) into slice b; the last workgroup to finish
+// (counted in s->tdone) sums the R slices in order into s->totals.  With
+// `finish` it then ends the step: t += dt and the next dt from the folded
+// CFL maximum.  The tickets are reset either way.
+__global__ void __launch_bounds__(256) totals_finish_kernel(const double* part, int64_t n,
+                                                            double* slice, DevScalars* s,
+                                                            int finish) {
+  __shared__ double red[4 * 6];
+  __shared__ int last;
+  const int R = int(gridDim.x), b = int(blockIdx.x);
+  const int64_t lo = n * b / R, hi = n * (b + 1) / R;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
+#pragma unroll
+    for (int v = 0; v < 6; ++v) acc[v] += part[i * 6 + v];
+  const int wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < 6; ++v) {
+    const double w = wave_sum(acc[v]);
+    if ((threadIdx.x & 63) == 0) red[wid * 6 + v] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double a = red[threadIdx.x];
+    for (int w = 1; w < int(blockDim.x >> 6); ++w) a += red[w * 6 + threadIdx.x];
+    slice[b * 6 + threadIdx.x] = a;
+  }
+  __threadfence();  // the slice is visible device-wide before the count
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&s->tdone, 1u) == unsigned(R - 1);
+  __syncthreads();
+  if (!last) return;
+  __threadfence();  // every other slice is visible to this workgroup
+  if (threadIdx.x < 6) {
+    double a = slice[threadIdx.x];
+    for (int r = 1; r < R; ++r) a += slice[r * 6 + threadIdx.x];
+    s->totals[threadIdx.x] = a;
+  }
+  if (threadIdx.x == 0) {
+    s->tdone = 0u;
+    if (finish) {
+      s->t += s->dt;
+      next_dt(s);
+    }
+    s->tickets[0] = s->tickets[1] = s->tickets[2] = s->tickets[3] = 0u;
+  }
+}
+
 // after a standalone CFL reduction: dt from the current state
 __global__ void finish_cfl_kernel(DevScalars* s) {
   next_dt(s);
@@ -1511,6 +1755,7 @@ __global__ void init_scalars_kernel(DevScalars* s, double cfl, double t, double 
   s->cfl = cfl;
   s->smax_bits = 0ull;
   s->error = 0u;
+  s->tdone = 0u;
   s->tickets[0] = s->tickets[1] = s->tickets[2] = s->tickets[3] = 0u;
   s->saved[0] = s->saved[1] = 0.0;
   for (int v = 0; v < 6; ++v) s->totals[v] = 0.0;
@@ -1564,6 +1809,9 @@ static SweepArgs<T> to_args(const LaunchSweep& L) {
   a.grav_y = L.grav_y;
   a.gamma = L.gamma;
   a.scal = L.scal;
+  a.tpart = L.tpart;
+  for (int i = 0; i < 3; ++i) a.gvec[i] = L.gvec[i];
+  a.tonly = L.totals_only;
   return a;
 }
 
@@ -1595,98 +1843,129 @@ int64_t col_tiles(const PatchDev& P, int axis, const SweepCfg& c) {
   return (ncol + c.q - 1) / c.q;
 }
 
-template <class T, int V, bool MULTI, bool PERSIST>
+template <class T, int V, bool MULTI, bool PERSIST, bool TOT>
 static hipError_t launch_x_vw(const LaunchSweep& L, hipStream_t st, dim3 grid) {
-  hipLaunchKernelGGL((sweep_x_kernel<T, V, MULTI, PERSIST>), grid, dim3(L.cfg.block), 0, st,
-                     to_args<T>(L));
+  hipLaunchKernelGGL((sweep_x_kernel<T, V, MULTI, PERSIST, TOT>), grid, dim3(L.cfg.block), 0,
+                     st, to_args<T>(L));
   return hipGetLastError();
 }
 
-template <class T, int V, bool PERSIST>
+template <class T, int V, bool PERSIST, bool TOT>
 static hipError_t launch_x_v(const LaunchSweep& L, hipStream_t st, dim3 grid) {
   if (L.xmode == kXMarch) {
     if constexpr (sizeof(T) == 8 && V == 4) {
       return hipErrorInvalidValue;  // not built: the FP64 V=4 march spills registers
     } else {
-      hipLaunchKernelGGL((sweep_xm_kernel<T, V, PERSIST>), grid, dim3(L.cfg.block), 0, st,
+      const size_t tl = TOT ? size_t(L.cfg.block) * kTotStride * sizeof(double) : 0;
+      hipLaunchKernelGGL((sweep_xm_kernel<T, V, PERSIST, TOT>), grid, dim3(L.cfg.block), tl, st,
                          to_args<T>(L));
       return hipGetLastError();
     }
   }
-  return L.xmode == kXPacked ? launch_x_vw<T, V, false, PERSIST>(L, st, grid)
-                             : launch_x_vw<T, V, true, PERSIST>(L, st, grid);
+  return L.xmode == kXPacked ? launch_x_vw<T, V, false, PERSIST, TOT>(L, st, grid)
+                             : launch_x_vw<T, V, true, PERSIST, TOT>(L, st, grid);
 }
 
-template <class T, bool PERSIST>
+template <class T, bool PERSIST, bool TOT>
 static hipError_t launch_x(const LaunchSweep& L, hipStream_t st, dim3 grid) {
   switch (L.cfg.v) {
-    case 1: return launch_x_v<T, 1, PERSIST>(L, st, grid);
-    case 2: return launch_x_v<T, 2, PERSIST>(L, st, grid);
-    case 4: return launch_x_v<T, 4, PERSIST>(L, st, grid);
+    case 1: return launch_x_v<T, 1, PERSIST, TOT>(L, st, grid);
+    case 2: return launch_x_v<T, 2, PERSIST, TOT>(L, st, grid);
+    case 4: return launch_x_v<T, 4, PERSIST, TOT>(L, st, grid);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <class T, bool PERSIST>
+template <class T, bool PERSIST, bool TOT>
 static hipError_t launch_col(const LaunchSweep& L, hipStream_t st, dim3 grid) {
   const int threads = L.cfg.q * L.cfg.s;
   dim3 block(threads);
   // halos through LDS while the table (20 values per thread) fits in 64 KiB
   const size_t tab = size_t(threads) * 20 * sizeof(T);
   const bool ldsh = tab <= 65536;
+  const size_t tl = TOT ? size_t(threads) * kTotStride * sizeof(double) : 0;  // totals (TotL)
   const SweepArgs<T> a = to_args<T>(L);
   if (L.axis == 1) {
     if (ldsh)
-      hipLaunchKernelGGL((sweep_col_kernel<T, 1, PERSIST, true>), grid, block, tab, st, a);
+      hipLaunchKernelGGL((sweep_col_kernel<T, 1, PERSIST, true, TOT>), grid, block, tl + tab, st,
+                         a);
     else
-      hipLaunchKernelGGL((sweep_col_kernel<T, 1, PERSIST, false>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((sweep_col_kernel<T, 1, PERSIST, false, TOT>), grid, block, tl, st, a);
   } else {
     if (ldsh)
-      hipLaunchKernelGGL((sweep_col_kernel<T, 2, PERSIST, true>), grid, block, tab, st, a);
+      hipLaunchKernelGGL((sweep_col_kernel<T, 2, PERSIST, true, TOT>), grid, block, tl + tab, st,
+                         a);
     else
-      hipLaunchKernelGGL((sweep_col_kernel<T, 2, PERSIST, false>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((sweep_col_kernel<T, 2, PERSIST, false, TOT>), grid, block, tl, st, a);
   }
   return hipGetLastError();
 }
 
-template <class T, int V>
+template <class T, int V, bool TOT>
 static hipError_t launch_plane_v(const LaunchSweep& L, hipStream_t st) {
   const SweepArgs<T> a = to_args<T>(L);
   const size_t lds = size_t(L.plane_lds);
   if (L.plane == kPlaneXY)
-    hipLaunchKernelGGL((sweep_plane_kernel<T, V, true>), dim3(L.nblocks), dim3(L.cfg.block),
-                       lds, st, a);
+    hipLaunchKernelGGL((sweep_plane_kernel<T, V, true, TOT>), dim3(L.nblocks),
+                       dim3(L.cfg.block), lds, st, a);
   else
-    hipLaunchKernelGGL((sweep_plane_kernel<T, V, false>), dim3(L.nblocks), dim3(L.cfg.block),
-                       lds, st, a);
+    hipLaunchKernelGGL((sweep_plane_kernel<T, V, false, TOT>), dim3(L.nblocks),
+                       dim3(L.cfg.block), lds, st, a);
   return hipGetLastError();
 }
 
-template <class T>
+template <class T, bool TOT>
 static hipError_t launch_plane(const LaunchSweep& L, hipStream_t st) {
   if (L.plane_lds <= 0 || L.plane_lds > kPlaneLdsBytes || !L.persistent)
     return hipErrorInvalidValue;
   switch (L.cfg.v) {
-    case 1: return launch_plane_v<T, 1>(L, st);
-    case 2: return launch_plane_v<T, 2>(L, st);
-    case 4: return launch_plane_v<T, 4>(L, st);
+    case 1: return launch_plane_v<T, 1, TOT>(L, st);
+    case 2: return launch_plane_v<T, 2, TOT>(L, st);
+    case 4: return launch_plane_v<T, 4, TOT>(L, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <class T>
-static hipError_t launch_sweep_t(const LaunchSweep& L, hipStream_t st) {
-  if (L.plane != kPlaneNone) return launch_plane<T>(L, st);
+// TOT: the launch also folds the FP64 totals of the cells it updates (the
+// last sweep of a step), a separate instantiation of each kernel so that the
+// other sweeps keep their registers.
+template <class T, bool TOT>
+static hipError_t launch_sweep_tt(const LaunchSweep& L, hipStream_t st) {
+  if (L.plane != kPlaneNone) return launch_plane<T, TOT>(L, st);
   if (L.persistent) {
     dim3 grid(L.nblocks);
-    return L.axis == 0 ? launch_x<T, true>(L, st, grid) : launch_col<T, true>(L, st, grid);
+    return L.axis == 0 ? launch_x<T, true, TOT>(L, st, grid)
+                       : launch_col<T, true, TOT>(L, st, grid);
   }
-  if (L.axis == 0) return launch_x<T, false>(L, st, dim3(unsigned(x_grid(L.single, L.cfg))));
-  return launch_col<T, false>(L, st, dim3(unsigned(col_tiles(L.single, L.axis, L.cfg))));
+  if (L.axis == 0)
+    return launch_x<T, false, TOT>(L, st, dim3(unsigned(x_grid(L.single, L.cfg))));
+  return launch_col<T, false, TOT>(L, st, dim3(unsigned(col_tiles(L.single, L.axis, L.cfg))));
+}
+
+template <class T>
+static hipError_t launch_sweep_t(const LaunchSweep& L, hipStream_t st) {
+  if (L.totals_only && !L.tpart) return hipErrorInvalidValue;
+  return L.tpart ? launch_sweep_tt<T, true>(L, st) : launch_sweep_tt<T, false>(L, st);
 }
 
 hipError_t launch_sweep(const LaunchSweep& L, hipStream_t st) {
   return L.fp64 ? launch_sweep_t<double>(L, st) : launch_sweep_t<float>(L, st);
+}
+
+int64_t sweep_parts(const LaunchSweep& L) {
+  if (L.plane != kPlaneNone || L.persistent) return L.nitems;
+  if (L.axis == 0) return x_grid(L.single, L.cfg);
+  return col_tiles(L.single, L.axis, L.cfg);
+}
+
+hipError_t launch_totals_finish(const double* part, int64_t n, double* slice, DevScalars* s,
+                                int finish, hipStream_t st) {
+  // about 8 partials per thread in each slice, at most kTotalsSlices slices
+  int64_t R = (n + 2047) / 2048;
+  R = R < 1 ? 1 : (R > kTotalsSlices ? kTotalsSlices : R);
+  hipLaunchKernelGGL(totals_finish_kernel, dim3(unsigned(R)), dim3(256), 0, st, part, n, slice,
+                     s, finish);
+  return hipGetLastError();
 }
 
 

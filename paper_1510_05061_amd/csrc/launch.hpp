@@ -37,7 +37,24 @@ struct LaunchSweep {
   int32_t plane_lds;   // fused plane sweeps: LDS bytes of the largest plane
   int32_t bc_lo_y, bc_hi_y;  // fused plane sweeps: boundary conditions along y
   double grav_y;             // fused plane sweeps: gravity along y
+  // FP64 conserved totals of the updated cells (the last sweep of a step):
+  // 6 sums per workgroup (direct launches) or per work item (persistent),
+  // at tpart + 6 * index; null: none
+  double* tpart;
+  double gvec[3];            // gravity vector (totals: phi = -g . x)
+  int32_t totals_only;       // dt = 0 and nothing stored: totals of the current state
 };
+
+// Partial sums a sweep launch writes (grid size or work items).
+int64_t sweep_parts(const LaunchSweep& L);
+
+// Sums n partials (6 doubles each) in a fixed order into scal->totals, using
+// `slice` (6 * kTotalsSlices doubles) for the first level; with finish set it
+// then ends a step (t += dt, next dt from the folded CFL maximum).  Always
+// resets the persistent-sweep tickets.
+constexpr int kTotalsSlices = 256;
+hipError_t launch_totals_finish(const double* part, int64_t n, double* slice, DevScalars* s,
+                                int finish, hipStream_t st);
 
 struct LaunchReduce {
   const void* pool;

@@ -31,7 +31,7 @@ struct DevScalars {
   double cfl;                    // Courant number
   unsigned long long smax_bits;  // running max of signal speed / dx (FP64 bits)
   unsigned int error;            // sticky error bits (kErr*)
-  unsigned int pad0;
+  unsigned int tdone;            // totals reduction: workgroups finished
   unsigned int tickets[4];       // persistent-sweep work tickets
   double saved[2];               // dt, t saved around timing runs
   double totals[6];              // last FP64 totals

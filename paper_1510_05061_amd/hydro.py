@@ -603,6 +603,9 @@ class Batch:
     def set_time(self, t, step):
         hydro_set_time(self.ctx, t, step)
 
+    def state_changed(self):
+        hydro_state_changed(self.ctx)
+
     def error(self):
         return hydro_get_error(self.ctx)
 
