@@ -1,14 +1,17 @@
 """Benchmark: zone-updates/s of the split compressible-Euler step on one MI355X.
 
-Default workload (`--workload kh`): 3D periodic Kelvin-Helmholtz layer,
-256^3 zones, gamma 5/3, seeded (numpy default_rng(1)) u_y noise, FP32 state
-with FP64 dt; the FP64 path runs on the same grid beside it.  Other
-workloads: `rt` (Rayleigh-Taylor 256x256x512, gravity, reflecting z walls),
-`turb` (decaying turbulence 768^3), `batch` (4096 uneven periodic KH patches,
-one persistent launch per sweep).  A zone-update is one interior zone
-advanced one full step (three sweeps plus the fused CFL reduction).  The
-state is resident in HBM before the timed region starts; the timed steps are
-graph replays bracketed by device synchronisation.
+Default workload (`--workload turb`): 3D decaying turbulence, 768^3 zones,
+the largest single-GPU grid of the workloads (9.1 GB of FP32 state), gamma
+5/3, rho = p = 1, seeded (numpy default_rng(4)) solenoidal velocity in shells
+k = 1..8 with E(k) ~ k^-5/3 and rms Mach 0.3; FP32 state with FP64 dt and
+totals; the FP64 path runs on the same grid beside it.  Other workloads:
+`kh` (Kelvin-Helmholtz 256^3), `rt` (Rayleigh-Taylor 256x256x512, gravity,
+reflecting z walls), `batch` (4096 uneven periodic KH patches, one
+persistent launch per sweep).  A zone-update is one interior zone advanced
+one full step: three sweeps, the fused CFL reduction that sets the next dt
+and the fused FP64 conserved totals.  The state is resident in HBM before
+the timed region starts; the timed steps are graph replays bracketed by
+device synchronisation.
 
 Prints ONE JSON line.  Fields beyond the driver's contract:
   roofline       dominant sweep kernel of the FP32 step: algorithmic HBM
@@ -89,7 +92,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="kh")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="turb")
     ap.add_argument("--n", type=int, default=0, help="grid edge (kh, turb)")
     ap.add_argument("--patches", type=int, default=4096)
     ap.add_argument("--pad-rows", type=int, default=32,
@@ -133,8 +136,9 @@ def make_workload(args):
     if w == "rt":
         return {"kind": "grid", "P": ic.rt(), "grid": [256, 256, 512]}
     if w == "turb":
+        # built in FP64; the FP32 path starts from its round-to-nearest copy
         n = args.n or 768
-        return {"kind": "grid", "P": ic.turbulence(n, dtype=np.float32), "grid": [n, n, n]}
+        return {"kind": "grid", "P": ic.turbulence(n), "grid": [n, n, n]}
     specs = ic.batch_specs(args.patches, seed=3)
     return {"kind": "batch", "specs": specs, "grid": None}
 
@@ -200,6 +204,10 @@ def run_gpu(W, prec, args, torch, hydro):
     sec = timed_steps(obj, args.steps, args.warmup, torch)
     if obj.error() != hydro.HYDRO_OK:
         raise RuntimeError("numeric error flag set during the benchmark")
+    t_end, nsteps = obj.time()
+    totals = {"names": ["rho", "mx", "my", "mz", "E", "E+rho*phi"], "values": obj.totals(),
+              "after_step": nsteps, "t": t_end,
+              "note": "FP64 sums folded into the last sweep of the last timed step"}
     kms = profile(obj, args.profile_steps)
     cfg = obj.config
     state_bytes = U.numel() * U.element_size()
@@ -225,7 +233,7 @@ def run_gpu(W, prec, args, torch, hydro):
     obj.close()
     del U
     torch.cuda.empty_cache()
-    return sec, kms, cfg, state_bytes, stream, diag
+    return sec, kms, cfg, state_bytes, stream, diag, totals
 
 
 # FP64 vector peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA
@@ -780,10 +788,11 @@ def main():
 
     W = make_workload(args)
     zones = interior_zones(W)
-    sec32, k32, cfg32, bytes32, stream32, diag32 = run_gpu(W, hydro.FP32, args, torch, hydro)
+    sec32, k32, cfg32, bytes32, stream32, diag32, tot32 = run_gpu(W, hydro.FP32, args, torch,
+                                                                  hydro)
     fp64 = None
     if not args.skip_fp64:
-        sec64, k64, cfg64, _, stream64, _ = run_gpu(W, hydro.FP64, args, torch, hydro)
+        sec64, k64, cfg64, _, stream64, _, tot64 = run_gpu(W, hydro.FP64, args, torch, hydro)
         fp64 = {"value": zones / sec64, "unit": "zone-updates/s",
                 "ms_per_step": sec64 * 1e3,
                 "step_roofline_frac": zones / sec64 * 240 / (HBM_PEAK_GBS * 1e9),
@@ -792,6 +801,7 @@ def main():
                                for i, ax in enumerate("xyz")},
                 "config": cfg64,
                 "stream_ceiling": stream64,
+                "totals": tot64,
                 "fp32_speedup": sec64 / sec32}
 
     value = zones / sec32
@@ -800,8 +810,11 @@ def main():
     achieved = bytes_launch / (k32[dom] * 1e-3) / 1e9 if k32[dom] > 0 else 0.0
     pers = W["kind"] == "batch"
     fused = "f=1" in cfg32
-    names = {0: "sweep_x_kernel<float>", 1: "sweep_col_kernel<float,1>",
-             2: "sweep_col_kernel<float,2>"}
+    xpart = cfg32.split(";")[0]                      # x:v=V,b=B[,m=1[,g=G]]
+    xv = xpart.split("v=")[1].split(",")[0]
+    names = {0: (f"sweep_xm_kernel<float,{xv}>" if "m=1" in xpart
+                 else f"sweep_x_kernel<float,{xv}>"),
+             1: "sweep_col_kernel<float,1>", 2: "sweep_col_kernel<float,2>"}
     if fused:   # one launch does the x and y sweeps of every patch z-plane
         names[0] = "sweep_plane_kernel<float> (x and y sweeps fused)"
     kname = names[dom] + (" (persistent)" if pers else "")
@@ -836,7 +849,9 @@ def main():
         "data": "synthetic: seeded initial state built on the host (numpy)",
         "config": {"workload": WORKLOADS[args.workload], "name": args.workload,
                    "grid": W["grid"], "zones": zones,
-                   "state": "FP32 planes, FP64 dt and CFL reduction", "kernels": cfg32},
+                   "state": "FP32 planes; FP64 dt, CFL reduction and conserved totals",
+                   "kernels": cfg32},
+        "totals": tot32,
         "roofline": roof,
         "step_roofline": {"achieved": value * 120 / 1e9, "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": value * 120 / (HBM_PEAK_GBS * 1e9),

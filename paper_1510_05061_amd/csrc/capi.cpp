@@ -415,6 +415,7 @@ LaunchSweep sweep_launch(const hydro_ctx* c, int axis, int do_cfl) {
   L.cfg = c->cfg.ax[axis];
   L.persistent = c->batch ? 1 : 0;
   L.fp64 = c->fp64;
+  L.tot_cap = 16 * std::max(1, c->cu_count);  // totals: x workgroups stride over tiles
   if (c->cfg.ax[0].kind == kXMarchKind) {
     L.xmode = kXMarch;
   } else {

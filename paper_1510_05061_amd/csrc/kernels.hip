@@ -439,7 +439,7 @@ __device__ __forceinline__ void lanerun_update(Cons<T> (&U)[V], int gl, int last
 template <class T, int V, bool MULTI, bool TOT>
 __device__ void xsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t tile,
                             const SweepConst<T>& k, EdgeSlots<T>* slots, T& smax,
-                            bool& bad, TotR& tot) {
+                            bool& bad, TotL& tot) {
   const bool store = !(TOT && a.tonly);
   const int N = P.n[0];
   const int LPP = N / V;                 // lanes per pencil
@@ -664,23 +664,35 @@ __device__ __forceinline__ int item_at(const SweepArgs<T>& a, int i, unsigned in
   return int(blockIdx.x) + i * int(gridDim.x);
 }
 
+// Direct FP32 totals instantiation with whole pencils per wave: four waves per
+// SIMD (128 registers), which it would otherwise miss by two registers.
 template <class T, int V, bool MULTI, bool PERSIST, bool TOT>
-__global__ void __launch_bounds__(512) sweep_x_kernel(SweepArgs<T> a) {
+__global__ void __launch_bounds__(512, sizeof(T) == 4 && TOT && !MULTI && !PERSIST ? 4 : 1)
+    sweep_x_kernel(SweepArgs<T> a) {
   __shared__ EdgeSlots<T> slots[MULTI ? 8 : 1];
   __shared__ int item_s;
   __shared__ T red[8];
   __shared__ double tred[TOT ? 48 : 1];
+  extern __shared__ __align__(16) unsigned char dyn_lds[];  // TOT: per-thread totals (TotL)
   const double dt = (TOT && a.tonly) ? 0.0 : a.scal->dt;
   const bool grav = has_grav(a.gvec);
   T smax = T(0);
   bool bad = false;
-  TotR tot;
-  tot.zero();
+  TotL tot{reinterpret_cast<double*>(dyn_lds)};
+  if (TOT) tot.zero();
   if (!PERSIST) {
     SweepConst<T> k = make_const<T>(dt, a.single.dx[0], a.gamma, a.grav);
-    xsweep_tile<T, V, MULTI, TOT>(a, a.single, blockIdx.x, k, slots, smax, bad, tot);
-    if (TOT)
+    if (!TOT) {
+      xsweep_tile<T, V, MULTI, TOT>(a, a.single, blockIdx.x, k, slots, smax, bad, tot);
+    } else {
+      // a capped grid strides over the a.nitems tiles: the totals partial
+      // of a workgroup covers many pencils
+      for (int64_t tile = blockIdx.x; tile < a.nitems; tile += gridDim.x) {
+        xsweep_tile<T, V, MULTI, TOT>(a, a.single, tile, k, slots, smax, bad, tot);
+        if (MULTI) __syncthreads();
+      }
       tot_block(tot, cell_volume(a.single), a.tpart + 6 * int64_t(blockIdx.x), tred, grav);
+    }
   } else {
     for (int i = 0;; ++i) {
       const int it = item_at(a, i, &a.scal->tickets[0], &item_s);
@@ -1845,7 +1857,8 @@ int64_t col_tiles(const PatchDev& P, int axis, const SweepCfg& c) {
 
 template <class T, int V, bool MULTI, bool PERSIST, bool TOT>
 static hipError_t launch_x_vw(const LaunchSweep& L, hipStream_t st, dim3 grid) {
-  hipLaunchKernelGGL((sweep_x_kernel<T, V, MULTI, PERSIST, TOT>), grid, dim3(L.cfg.block), 0,
+  const size_t tl = TOT ? size_t(L.cfg.block) * kTotStride * sizeof(double) : 0;
+  hipLaunchKernelGGL((sweep_x_kernel<T, V, MULTI, PERSIST, TOT>), grid, dim3(L.cfg.block), tl,
                      st, to_args<T>(L));
   return hipGetLastError();
 }
@@ -1937,8 +1950,12 @@ static hipError_t launch_sweep_tt(const LaunchSweep& L, hipStream_t st) {
     return L.axis == 0 ? launch_x<T, true, TOT>(L, st, grid)
                        : launch_col<T, true, TOT>(L, st, grid);
   }
-  if (L.axis == 0)
-    return launch_x<T, false, TOT>(L, st, dim3(unsigned(x_grid(L.single, L.cfg))));
+  if (L.axis == 0) {
+    if (!TOT) return launch_x<T, false, TOT>(L, st, dim3(unsigned(x_grid(L.single, L.cfg))));
+    LaunchSweep M = L;
+    M.nitems = int32_t(x_tiles(L.single, L.cfg));  // the tiles the capped grid strides over
+    return launch_x<T, false, TOT>(M, st, dim3(unsigned(sweep_parts(L))));
+  }
   return launch_col<T, false, TOT>(L, st, dim3(unsigned(col_tiles(L.single, L.axis, L.cfg))));
 }
 
@@ -1954,7 +1971,10 @@ hipError_t launch_sweep(const LaunchSweep& L, hipStream_t st) {
 
 int64_t sweep_parts(const LaunchSweep& L) {
   if (L.plane != kPlaneNone || L.persistent) return L.nitems;
-  if (L.axis == 0) return x_grid(L.single, L.cfg);
+  if (L.axis == 0) {
+    const int64_t g = x_grid(L.single, L.cfg);
+    return L.tpart && L.tot_cap > 0 ? std::min<int64_t>(g, L.tot_cap) : g;
+  }
   return col_tiles(L.single, L.axis, L.cfg);
 }
 

@@ -43,6 +43,8 @@ struct LaunchSweep {
   double* tpart;
   double gvec[3];            // gravity vector (totals: phi = -g . x)
   int32_t totals_only;       // dt = 0 and nothing stored: totals of the current state
+  int32_t tot_cap;           // direct x launches with totals: at most this many
+                             // workgroups, striding over the tiles (0: no cap)
 };
 
 // Partial sums a sweep launch writes (grid size or work items).
