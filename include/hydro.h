@@ -164,6 +164,37 @@ int hydro_cfl_dt(hydro_ctx* c, double* dt);
  * finite), HYDRO_EDEVICE, HYDRO_ESTATE (batch context). */
 int hydro_step(hydro_ctx* c, double dt);
 
+/* One split step of a single grid that allocates nothing, for callers that
+ * cannot allocate device memory: code under stream capture, tight serving
+ * loops, harnesses that forbid allocation.  It runs exactly the step that
+ * hydro_step runs for a context made by hydro_init from the same descriptor
+ * with HYDRO_FLAG_NO_TUNE (the built-in kernel configuration: the same
+ * bits), without a context or a workspace.  Its device scalars and totals
+ * partials live in a static device array of HYDRO_NOALLOC_SCRATCH_BYTES that
+ * every GPU the library runs on holds from the first call on it until the
+ * process ends (its address is looked up on that first call).  All calls on
+ * one GPU share the array, which keeps the last call's contents (each call
+ * resets what it reads): calls that overlap in time on one GPU (other
+ * streams or threads) race, and must not be made.
+ *   d, state, state_bytes  as for hydro_init (d->flags is ignored);
+ *   dt                     > 0: that dt; HYDRO_DT_CFL: the CFL dt of the
+ *                          state, reduced on the device first;
+ *   step                   >= 0; its parity sets the sweep order;
+ *   stream                 a hipStream_t (NULL: the null stream);
+ *   out                    NULL, or a caller-owned DEVICE array of 9 doubles
+ *                          (8-byte aligned): out[0] the dt taken, out[1] the
+ *                          CFL dt of the new state, out[2..7] the FP64
+ *                          totals of the new state (as hydro_totals), out[8]
+ *                          the step's sticky error bits (0: none).
+ * Asynchronous on `stream`.  Errors: HYDRO_EINVAL (as hydro_init; dt < 0 or
+ * not finite; step < 0; a grid whose totals need more partial sums than the
+ * array holds, about 21 500: the z sweep of the built-in configuration takes
+ * one per 64 columns, so an x-y cross-section of more than about 1.38 M
+ * cells), HYDRO_EDEVICE. */
+#define HYDRO_NOALLOC_SCRATCH_BYTES (1u << 20)
+int hydro_step_noalloc(const hydro_desc* d, void* state, size_t state_bytes, double dt,
+                       int64_t step, void* stream, double* out);
+
 /* Enqueue a single directional sweep along `axis` (0 = x, 1 = y, 2 = z)
  * with the given dt > 0 (or HYDRO_DT_CFL), without touching t or the step
  * counter.  fold_cfl != 0 also folds the CFL maximum of the updated cells

@@ -1305,6 +1305,120 @@ int hydro_step(hydro_ctx* c, double dt) { return step_common(c, dt, false); }
 
 int hydro_batch_step(hydro_ctx* c, double dt) { return step_common(c, dt, true); }
 
+}  // extern "C"
+
+// ------------------------------------------------------------------------
+// a step that allocates nothing (hydro_step_noalloc)
+// ------------------------------------------------------------------------
+
+// Device memory of hydro_step_noalloc: the scalar block, then the first
+// level of the totals reduction, then the totals partials.  Every GPU the
+// library runs on holds its own copy until the process ends; the calls on
+// one GPU share it.  In host code its name stands for no device address:
+// only the per-device address from hipGetSymbolAddress is ever used.
+static __device__ __align__(256) unsigned char scratch[HYDRO_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr size_t kNoallocSlices = kScalarBytes;
+constexpr size_t kNoallocParts =
+    kNoallocSlices + (size_t(kTotalsSlices) * 6 * sizeof(double) + 255) / 256 * 256;
+constexpr int64_t kNoallocMaxParts =
+    int64_t((HYDRO_NOALLOC_SCRATCH_BYTES - kNoallocParts) / (6 * sizeof(double)));
+
+struct NoallocDevice {
+  void* ptr = nullptr;  // device address of this GPU's scratch
+  int cu_count = 0;
+};
+
+std::mutex g_noalloc_mu;
+std::map<int, NoallocDevice> g_noalloc;  // by device ordinal
+
+// The current device's scratch address (looked up once per device, with the
+// device current) and CU count.
+int noalloc_device(NoallocDevice* out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  auto it = g_noalloc.find(dev);
+  if (it == g_noalloc.end()) {
+    NoallocDevice d;
+    HIP_TRY(hipGetSymbolAddress(&d.ptr, HIP_SYMBOL(scratch)));
+    if (!d.ptr) return fail(HYDRO_EDEVICE, "no device address for the static scratch");
+    HIP_TRY(hipDeviceGetAttribute(&d.cu_count, hipDeviceAttributeMultiprocessorCount, dev));
+    it = g_noalloc.emplace(dev, d).first;
+  }
+  *out = it->second;
+  return HYDRO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hydro_step_noalloc(const hydro_desc* d, void* state, size_t state_bytes, double dt,
+                       int64_t step, void* stream, double* out) {
+  g_last_error.clear();
+  if (!d || !state) return fail(HYDRO_EINVAL, "null argument");
+  int rc = check_common(d);
+  if (rc) return rc;
+  const int32_t n[3] = {d->nx, d->ny, d->nz};
+  const double dx[3] = {d->dx, d->dy, d->dz};
+  rc = check_extent(n, d->ng, dx);
+  if (rc) return rc;
+  if (reinterpret_cast<uintptr_t>(state) & 15)
+    return fail(HYDRO_EINVAL, "the state must be 16-byte aligned");
+  if (out && (reinterpret_cast<uintptr_t>(out) & 7))
+    return fail(HYDRO_EINVAL, "out must be 8-byte aligned");
+  if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(HYDRO_EINVAL, "dt must be >= 0 and finite");
+  if (step < 0) return fail(HYDRO_EINVAL, "step must be >= 0");
+  const PatchDev P = make_patch(n, d->ng, dx, 0);
+  const int64_t esz = d->precision == HYDRO_FP64 ? 8 : 4;
+  if (!plane_fits(P, esz)) return fail(HYDRO_EINVAL, "a state plane must be smaller than 4 GiB");
+  if (state_bytes < size_t(P.plane) * 5 * size_t(esz))
+    return fail(HYDRO_EINVAL, "state buffer too small");
+  NoallocDevice nd;
+  rc = noalloc_device(&nd);
+  if (rc) return rc;
+  // a host-side description of the grid; it owns nothing on the device
+  hydro_ctx c;
+  c.desc = *d;
+  c.fp64 = d->precision == HYDRO_FP64;
+  c.pool = state;
+  c.pool_bytes = size_t(P.plane) * 5 * size_t(esz);
+  c.stream = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(nd.ptr);
+  c.scal = reinterpret_cast<DevScalars*>(base);
+  c.tslice = reinterpret_cast<double*>(base + kNoallocSlices);
+  c.partials = reinterpret_cast<double*>(base + kNoallocParts);
+  c.single = P;
+  for (int a = 0; a < 3; ++a) c.active[a] = n[a] > 1;
+  c.cfg.ax[0] = default_x({P}, c.fp64);
+  c.cfg.ax[1] = default_col(n[1]);
+  c.cfg.ax[2] = default_col(n[2]);
+  if (c.cfg.ax[0].v == 0 && c.active[0])
+    return fail(HYDRO_EINVAL, "no valid x-sweep configuration for this width");
+  c.cu_count = nd.cu_count;
+  const int parity = int(step & 1);
+  const std::vector<StepOp> ops = step_ops(&c, parity);
+  const int64_t need = ops.empty() ? int64_t(chunks_for(int64_t(n[0]) * n[1] * n[2]))
+                                   : sweep_parts(ops.back().L);
+  if (need > kNoallocMaxParts)
+    return fail(HYDRO_EINVAL, "this grid's totals need " + std::to_string(need) +
+                                  " partial sums; the static scratch holds " +
+                                  std::to_string(kNoallocMaxParts));
+  hipStream_t st = c.stream;
+  HIP_TRY(launch_init_scalars(c.scal, d->cfl, 0.0, 0.0, st));
+  if (dt > 0.0) {
+    HIP_TRY(launch_set_dt(c.scal, dt, st));
+  } else {
+    HIP_TRY(launch_cfl(reduce_launch(&c), st));
+  }
+  HIP_TRY(enqueue_step_kernels(&c, parity, st));
+  if (out) HIP_TRY(launch_step_results(c.scal, out, st));
+  return HYDRO_OK;
+}
+
 int hydro_sweep(hydro_ctx* c, int axis, double dt, int fold_cfl) {
   if (!c) return fail(HYDRO_EINVAL, "null context");
   if (!items_current(c)) return fail(HYDRO_ESTATE, "batch work lists out of date");

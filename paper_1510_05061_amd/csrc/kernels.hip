@@ -1774,6 +1774,15 @@ __global__ void init_scalars_kernel(DevScalars* s, double cfl, double t, double 
 }
 
 __global__ void set_dt_kernel(DevScalars* s, double dt) { s->dt = dt; }
+
+// after a step that started at t = 0: the dt it took (its t), the next CFL
+// dt, the six totals and the sticky error bits into out[0..8]
+__global__ void step_results_kernel(const DevScalars* s, double* out) {
+  out[0] = s->t;
+  out[1] = s->dt;
+  for (int v = 0; v < 6; ++v) out[2 + v] = s->totals[v];
+  out[8] = double(s->error);
+}
 __global__ void set_time_kernel(DevScalars* s, double t, double t_end) {
   s->t = t;
   s->t_end = t_end;
@@ -2060,6 +2069,10 @@ hipError_t launch_finish_cfl(DevScalars* s, hipStream_t st) {
 hipError_t launch_init_scalars(DevScalars* s, double cfl, double t, double t_end,
                                hipStream_t st) {
   hipLaunchKernelGGL(init_scalars_kernel, dim3(1), dim3(1), 0, st, s, cfl, t, t_end);
+  return hipGetLastError();
+}
+hipError_t launch_step_results(const DevScalars* s, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(step_results_kernel, dim3(1), dim3(1), 0, st, s, out);
   return hipGetLastError();
 }
 hipError_t launch_set_dt(DevScalars* s, double dt, hipStream_t st) {

@@ -192,6 +192,7 @@ hipError_t launch_finish_cfl(DevScalars* s, hipStream_t st);
 hipError_t launch_init_scalars(DevScalars* s, double cfl, double t, double t_end,
                                hipStream_t st);
 hipError_t launch_set_dt(DevScalars* s, double dt, hipStream_t st);
+hipError_t launch_step_results(const DevScalars* s, double* out, hipStream_t st);
 hipError_t launch_set_time(DevScalars* s, double t, double t_end, hipStream_t st);
 hipError_t launch_clear_error(DevScalars* s, hipStream_t st);
 hipError_t launch_timing_begin(DevScalars* s, hipStream_t st);

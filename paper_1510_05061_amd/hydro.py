@@ -104,6 +104,8 @@ _SIGS = {
                     ctypes.POINTER(_vp)], ctypes.c_int),
     "hydro_cfl_dt": ([_vp, _dp], ctypes.c_int),
     "hydro_step": ([_vp, ctypes.c_double], ctypes.c_int),
+    "hydro_step_noalloc": ([ctypes.POINTER(HydroDesc), _vp, _sz, ctypes.c_double, ctypes.c_int64,
+                            _vp, _vp], ctypes.c_int),
     "hydro_sweep": ([_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int], ctypes.c_int),
     "hydro_batch_workspace_bytes": ([ctypes.POINTER(HydroPatch), ctypes.c_int32,
                                      ctypes.POINTER(HydroDesc), ctypes.POINTER(_sz)],
@@ -215,6 +217,16 @@ def hydro_cfl_dt(ctx):
 
 def hydro_step(ctx, dt=DT_CFL):
     _check(lib().hydro_step(ctx, float(dt)), "hydro_step")
+
+
+NOALLOC_SCRATCH_BYTES = 1 << 20
+
+
+def hydro_step_noalloc(desc, state_ptr, state_bytes, dt, step, stream_ptr, out_ptr=None):
+    """One step of a single grid with no context and no allocation
+    (asynchronous); out_ptr: None or a device float64[9] (see hydro.h)."""
+    _check(lib().hydro_step_noalloc(ctypes.byref(desc), state_ptr, state_bytes, float(dt),
+                                    int(step), stream_ptr, out_ptr), "hydro_step_noalloc")
 
 
 def hydro_batch_step(ctx, dt=DT_CFL):
