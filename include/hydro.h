@@ -81,6 +81,10 @@ typedef enum hydro_precision { HYDRO_FP32 = 0, HYDRO_FP64 = 1 } hydro_precision;
 #define HYDRO_FLAG_NO_GRAPH 0x1u /* launch kernels one by one, no hipGraph */
 #define HYDRO_FLAG_NO_TUNE 0x2u  /* skip the autotuner and its cache; use the
                                     built-in default configuration */
+#define HYDRO_BATCH_PER_PATCH_DT 0x4u /* batches: every patch keeps its own
+                                    time and steps with its own CFL dt (a
+                                    suite of independent runs) instead of
+                                    one dt, the minimum over patches */
 
 /* dt argument of hydro_step / hydro_batch_step: use the CFL dt held on the
  * device (no host synchronisation). */
@@ -217,10 +221,25 @@ int hydro_batch_init(const hydro_patch* p, int32_t n, const hydro_desc* common, 
                      hydro_ctx** out);
 
 /* Enqueue one split step of every patch of the batch: one persistent
- * launch per sweep direction over the whole work list, with one global dt
- * (the minimum over patches: an AMR level without subcycling).  dt as in
- * hydro_step.  Asynchronous. */
+ * launch per sweep direction over the whole work list.  By default with one
+ * global dt, the minimum over patches (an AMR level without subcycling);
+ * with HYDRO_BATCH_PER_PATCH_DT each patch with its own dt, patch p
+ * advancing its own time by its own CFL dt (the suites of independent runs
+ * of the paper's section "Capabilities needed"; each patch then takes the
+ * steps it would take as a single grid, bit for bit).  dt > 0: that dt for
+ * every patch; HYDRO_DT_CFL: the CFL dt on the device (per patch with the
+ * flag).  The step counter, and so the sweep order, is shared.
+ * Asynchronous. */
 int hydro_batch_step(hydro_ctx* c, double dt);
+
+/* Time and next dt of every patch of a batch (host arrays of n doubles;
+ * without HYDRO_BATCH_PER_PATCH_DT every entry holds the batch's one t and
+ * dt).  With the flag, hydro_get_time reports the earliest patch time and
+ * hydro_cfl_dt the smallest patch dt, hydro_set_time sets every patch's
+ * time, and hydro_set_t_end caps each patch's dt so that its own time lands
+ * on t_end.  Synchronous.  Errors: HYDRO_EINVAL, HYDRO_ESTATE (single-grid
+ * context), HYDRO_EDEVICE. */
+int hydro_batch_times(hydro_ctx* c, double* t, double* dt);
 
 /* FP64 totals of the current state: sum over cells of (rho, mx, my, mz, E,
  * E + rho*phi) times the cell volume, phi = -(g . x) at cell centres with

@@ -376,6 +376,14 @@ struct hydro_ctx {
   double t_end = 0.0;
   bool dt_valid = false;
   bool totals_valid = false;  // scal->totals hold the totals of the current state
+  // HYDRO_BATCH_PER_PATCH_DT: patch p has its own time pt[p] and dt pdt[p],
+  // and its sweeps fold their CFL maximum into psmax[p]; pp_live turns this
+  // off while the tuner times sweeps with dt = 0
+  bool per_patch = false;
+  bool pp_live = false;
+  double* pt = nullptr;
+  double* pdt = nullptr;
+  unsigned long long* psmax = nullptr;
   Config cfg;
   Config items_cfg;          // configuration the batch work lists were built for
   bool active[3] = {false, false, false};
@@ -416,6 +424,10 @@ LaunchSweep sweep_launch(const hydro_ctx* c, int axis, int do_cfl) {
   L.persistent = c->batch ? 1 : 0;
   L.fp64 = c->fp64;
   L.tot_cap = 16 * std::max(1, c->cu_count);  // totals: x workgroups stride over tiles
+  if (c->pp_live) {
+    L.pdt = c->pdt;
+    L.psmax = c->psmax;
+  }
   if (c->cfg.ax[0].kind == kXMarchKind) {
     L.xmode = kXMarch;
   } else {
@@ -443,6 +455,7 @@ LaunchReduce reduce_launch(const hydro_ctx* c) {
   L.scal = c->scal;
   L.partials = c->partials;
   L.fp64 = c->fp64;
+  if (c->pp_live) L.psmax = c->psmax;
   return L;
 }
 
@@ -525,14 +538,33 @@ std::vector<StepOp> step_ops(const hydro_ctx* c, int parity) {
 // reductions of the state.
 hipError_t finish_step_launches(const hydro_ctx* c, const std::vector<StepOp>& ops,
                                 hipStream_t st) {
+  hipError_t e = hipSuccess;
   if (ops.empty()) {
-    hipError_t e = launch_cfl(reduce_launch(c), st);
+    // nothing to sweep: the CFL maximum and the totals of the state itself
+    LaunchReduce R = reduce_launch(c);
+    R.fold_only = 1;
+    e = launch_cfl(R, st);
     if (e == hipSuccess) e = launch_totals(reduce_launch(c), st);
-    if (e != hipSuccess) return e;
-    return launch_finish_step(c->scal, st);
+    if (e == hipSuccess && !c->pp_live) e = launch_finish_step(c->scal, st);
+  } else {
+    e = launch_totals_finish(c->partials, sweep_parts(ops.back().L), c->tslice, c->scal,
+                             c->pp_live ? 0 : 1, st);
   }
-  return launch_totals_finish(c->partials, sweep_parts(ops.back().L), c->tslice, c->scal, 1,
-                              st);
+  // a dt per patch: each patch's t advances by its dt, then its next dt
+  if (e == hipSuccess && c->pp_live)
+    e = launch_patch_dt(c->pt, c->pdt, c->psmax, c->npatch, c->scal, 1, st);
+  return e;
+}
+
+// dt of the next step on the device: `dt` (> 0) for every patch, or the CFL
+// dt of the current state (one, or one per patch)
+hipError_t set_step_dt(const hydro_ctx* c, double dt, hipStream_t st) {
+  if (dt > 0.0)
+    return c->pp_live ? launch_fill(c->pdt, c->npatch, dt, st) : launch_set_dt(c->scal, dt, st);
+  hipError_t e = launch_cfl(reduce_launch(c), st);
+  if (e == hipSuccess && c->pp_live)
+    e = launch_patch_dt(c->pt, c->pdt, c->psmax, c->npatch, c->scal, 0, st);
+  return e;
 }
 
 // The launches of a step, then the step bookkeeping.
@@ -942,6 +974,12 @@ int common_init(hydro_ctx* c) {
   rc = choose_config(c);
   if (rc) return rc;
   HIP_TRY(launch_init_scalars(c->scal, c->desc.cfl, 0.0, 0.0, c->stream));
+  if (c->per_patch) {
+    c->pp_live = true;
+    HIP_TRY(launch_fill(c->pt, c->npatch, 0.0, c->stream));
+    HIP_TRY(launch_fill(c->pdt, c->npatch, 0.0, c->stream));
+    HIP_TRY(launch_fill(reinterpret_cast<double*>(c->psmax), c->npatch, 0.0, c->stream));
+  }
   rc = capture_graphs(c);
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(c->stream));
@@ -983,7 +1021,7 @@ size_t grid_workspace_bytes(const int32_t n[3]) {
 
 // layout of a batch workspace
 struct BatchLayout {
-  size_t partials, slice, patches, items[4], total;
+  size_t partials, slice, patches, items[4], pt, pdt, psmax, total;
 };
 
 // totals partials: one per work item of any sweep launch, and at least the
@@ -1003,6 +1041,13 @@ BatchLayout batch_layout(int32_t n, const int32_t items[4]) {
     L.items[a] = o;
     o += align_up(size_t(std::max(1, items[a])) * sizeof(WorkItem), 256);
   }
+  // time, dt and CFL maximum per patch (HYDRO_BATCH_PER_PATCH_DT)
+  L.pt = o;
+  o += align_up(size_t(n) * sizeof(double), 256);
+  L.pdt = o;
+  o += align_up(size_t(n) * sizeof(double), 256);
+  L.psmax = o;
+  o += align_up(size_t(n) * sizeof(unsigned long long), 256);
   L.total = o;
   return L;
 }
@@ -1235,6 +1280,10 @@ int hydro_batch_init(const hydro_patch* p, int32_t n, const hydro_desc* common, 
   BatchLayout L = batch_layout(n, cap);
   c->partials = reinterpret_cast<double*>(c->ws + L.partials);
   c->tslice = reinterpret_cast<double*>(c->ws + L.slice);
+  c->pt = reinterpret_cast<double*>(c->ws + L.pt);
+  c->pdt = reinterpret_cast<double*>(c->ws + L.pdt);
+  c->psmax = reinterpret_cast<unsigned long long*>(c->ws + L.psmax);
+  c->per_patch = (common->flags & HYDRO_BATCH_PER_PATCH_DT) != 0;
   c->d_patches = reinterpret_cast<PatchDev*>(c->ws + L.patches);
   for (int a = 0; a < 4; ++a) c->d_items[a] = reinterpret_cast<WorkItem*>(c->ws + L.items[a]);
   c->single = c->patches[0];
@@ -1284,11 +1333,7 @@ static int step_common(hydro_ctx* c, double dt, bool want_batch) {
   if (c->batch != want_batch)
     return fail(HYDRO_ESTATE, want_batch ? "not a batch context" : "batch context: use hydro_batch_step");
   if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(HYDRO_EINVAL, "dt must be >= 0 and finite");
-  if (dt > 0.0) {
-    HIP_TRY(launch_set_dt(c->scal, dt, c->stream));
-  } else if (!c->dt_valid) {
-    HIP_TRY(launch_cfl(reduce_launch(c), c->stream));
-  }
+  if (dt > 0.0 || !c->dt_valid) HIP_TRY(set_step_dt(c, dt, c->stream));
   const int parity = int(c->step & 1);
   if (c->graph[parity]) {
     HIP_TRY(hipGraphLaunch(c->graph[parity], c->stream));
@@ -1424,11 +1469,7 @@ int hydro_sweep(hydro_ctx* c, int axis, double dt, int fold_cfl) {
   if (!items_current(c)) return fail(HYDRO_ESTATE, "batch work lists out of date");
   if (axis < 0 || axis > 2) return fail(HYDRO_EINVAL, "axis must be 0, 1 or 2");
   if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(HYDRO_EINVAL, "dt must be >= 0 and finite");
-  if (dt > 0.0) {
-    HIP_TRY(launch_set_dt(c->scal, dt, c->stream));
-  } else if (!c->dt_valid) {
-    HIP_TRY(launch_cfl(reduce_launch(c), c->stream));
-  }
+  if (dt > 0.0 || !c->dt_valid) HIP_TRY(set_step_dt(c, dt, c->stream));
   if (c->active[axis] && (!c->batch || c->nitems[axis] > 0)) {
     HIP_TRY(launch_sweep(sweep_launch(c, axis, fold_cfl ? 1 : 0), c->stream));
   }
@@ -1436,7 +1477,10 @@ int hydro_sweep(hydro_ctx* c, int axis, double dt, int fold_cfl) {
   c->totals_valid = false;
   if (fold_cfl) {
     // the device dt becomes the CFL dt of the swept state (t is left alone)
-    HIP_TRY(launch_finish_cfl(c->scal, c->stream));
+    if (c->pp_live)
+      HIP_TRY(launch_patch_dt(c->pt, c->pdt, c->psmax, c->npatch, c->scal, 0, c->stream));
+    else
+      HIP_TRY(launch_finish_cfl(c->scal, c->stream));
     c->dt_valid = true;
   } else {
     c->dt_valid = false;
@@ -1447,12 +1491,20 @@ int hydro_sweep(hydro_ctx* c, int axis, double dt, int fold_cfl) {
 int hydro_cfl_dt(hydro_ctx* c, double* dt) {
   if (!c || !dt) return fail(HYDRO_EINVAL, "null argument");
   *dt = 0.0;
-  HIP_TRY(launch_cfl(reduce_launch(c), c->stream));
+  HIP_TRY(set_step_dt(c, HYDRO_DT_CFL, c->stream));
   DevScalars s;
   int rc = read_scalars(c, &s);
   if (rc) return rc;
   c->dt_valid = true;
   if (s.error) return fail(HYDRO_ENUMERIC, "state holds rho <= 0, p <= 0 or a non-finite value");
+  if (c->pp_live) {  // the smallest patch dt
+    std::vector<double> d(size_t(c->npatch));
+    HIP_TRY(hipMemcpyAsync(d.data(), c->pdt, d.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *dt = *std::min_element(d.begin(), d.end());
+    return HYDRO_OK;
+  }
   *dt = s.dt;
   return HYDRO_OK;
 }
@@ -1726,6 +1778,8 @@ int check_level(const hydro_ctx* coarse, const hydro_ctx* fine, const hydro_amr_
                 int32_t n, int g) {
   if (!coarse || !fine || coarse == fine) return fail(HYDRO_EINVAL, "two distinct contexts needed");
   if (!coarse->batch || !fine->batch) return fail(HYDRO_ESTATE, "both levels must be batches");
+  if (coarse->per_patch || fine->per_patch)
+    return fail(HYDRO_EINVAL, "the level step takes one dt per level (no HYDRO_BATCH_PER_PATCH_DT)");
   if (coarse->fp64 != fine->fp64) return fail(HYDRO_EINVAL, "the levels differ in precision");
   if (coarse->stream != fine->stream) return fail(HYDRO_EINVAL, "the levels must share a stream");
   if (coarse->desc.gamma != fine->desc.gamma) return fail(HYDRO_EINVAL, "the levels differ in gamma");
@@ -1942,9 +1996,37 @@ int hydro_get_time(hydro_ctx* c, double* t, int64_t* step) {
   DevScalars s;
   int rc = read_scalars(c, &s);
   if (rc) return rc;
-  c->t_host = s.t;
-  if (t) *t = s.t;
+  double tt = s.t;
+  if (c->pp_live) {  // the earliest patch time
+    std::vector<double> pt(size_t(c->npatch));
+    HIP_TRY(hipMemcpyAsync(pt.data(), c->pt, pt.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    tt = *std::min_element(pt.begin(), pt.end());
+  }
+  c->t_host = tt;
+  if (t) *t = tt;
   if (step) *step = c->step;
+  return HYDRO_OK;
+}
+
+int hydro_batch_times(hydro_ctx* c, double* t, double* dt) {
+  if (!c || !t || !dt) return fail(HYDRO_EINVAL, "null argument");
+  if (!c->batch) return fail(HYDRO_ESTATE, "not a batch context");
+  const size_t n = size_t(c->npatch);
+  if (c->pp_live) {
+    HIP_TRY(hipMemcpyAsync(t, c->pt, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(dt, c->pdt, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return HYDRO_OK;
+  }
+  DevScalars s;
+  int rc = read_scalars(c, &s);
+  if (rc) return rc;
+  for (size_t i = 0; i < n; ++i) {
+    t[i] = s.t;
+    dt[i] = s.dt;
+  }
   return HYDRO_OK;
 }
 
@@ -1952,6 +2034,7 @@ int hydro_set_time(hydro_ctx* c, double t, int64_t step) {
   if (!c) return fail(HYDRO_EINVAL, "null context");
   if (!std::isfinite(t) || step < 0) return fail(HYDRO_EINVAL, "bad time or step");
   HIP_TRY(launch_set_time(c->scal, t, c->t_end, c->stream));
+  if (c->pp_live) HIP_TRY(launch_fill(c->pt, c->npatch, t, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->t_host = t;
   c->step = step;
@@ -2029,6 +2112,8 @@ int hydro_set_config(hydro_ctx* c, const char* text) {
 int hydro_time_sweeps(hydro_ctx* c, int reps, double ms[3]) {
   if (!c || !ms || reps < 1) return fail(HYDRO_EINVAL, "bad argument");
   HIP_TRY(launch_timing_begin(c->scal, c->stream));
+  const bool pp = c->pp_live;
+  c->pp_live = false;  // the timing runs take the one dt = 0 (state unchanged)
   int rc = HYDRO_OK;
   for (int a = 0; a < 3; ++a) {
     ms[a] = 0.0;
@@ -2036,6 +2121,7 @@ int hydro_time_sweeps(hydro_ctx* c, int reps, double ms[3]) {
     rc = time_sweep(c, a, reps, &ms[a]);
     if (rc) break;
   }
+  c->pp_live = pp;
   HIP_TRY(launch_timing_end(c->scal, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return rc;
@@ -2046,11 +2132,7 @@ int hydro_profile_step(hydro_ctx* c, double dt, double ms[4]) {
   if (!items_current(c)) return fail(HYDRO_ESTATE, "batch work lists out of date");
   if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(HYDRO_EINVAL, "dt must be >= 0 and finite");
   for (int i = 0; i < 4; ++i) ms[i] = 0.0;
-  if (dt > 0.0) {
-    HIP_TRY(launch_set_dt(c->scal, dt, c->stream));
-  } else if (!c->dt_valid) {
-    HIP_TRY(launch_cfl(reduce_launch(c), c->stream));
-  }
+  if (dt > 0.0 || !c->dt_valid) HIP_TRY(set_step_dt(c, dt, c->stream));
   const std::vector<StepOp> ops = step_ops(c, int(c->step & 1));
   hipEvent_t ev[2];
   for (int i = 0; i < 2; ++i) HIP_TRY(hipEventCreate(&ev[i]));

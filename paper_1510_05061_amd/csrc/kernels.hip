@@ -50,6 +50,8 @@ struct SweepArgs {
   double* tpart;             // totals partials (null: no totals)
   double gvec[3];            // gravity vector (totals: phi = -g . x)
   int32_t tonly;             // totals of the current state: dt = 0, no stores
+  const double* pdt;         // persistent: dt per patch (null: scal->dt)
+  unsigned long long* psmax; // persistent: CFL maximum per patch
 };
 
 // plane indices of (normal, transverse 1, transverse 2) momenta per axis
@@ -176,14 +178,11 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
-// Workgroup max of smax folded into the FP64 atomic, and the sticky error
-// (one atomic per wave that saw a bad cell: a wave vote, no LDS).  `red`
-// holds one T per wave.
+// Workgroup max of smax folded into the FP64 atomic at `dst` (the bit
+// pattern of a non-negative double orders like the value; NaN propagates as
+// the largest bits).  Every thread calls this; `red` holds one T per wave.
 template <class T>
-__device__ void finish_block(DevScalars* scal, T smax, bool bad, bool do_cfl, T* red) {
-  const bool wbad = __any(bad);
-  if (wbad && (threadIdx.x & 63) == 0) atomicOr(&scal->error, kErrState);
-  if (!do_cfl) return;
+__device__ void block_max_fold(T smax, unsigned long long* dst, T* red) {
   T m = wave_max(smax);
   const int wid = threadIdx.x >> 6;
   const int nw = (blockDim.x + 63) >> 6;
@@ -193,10 +192,40 @@ __device__ void finish_block(DevScalars* scal, T smax, bool bad, bool do_cfl, T*
     T b = red[0];
     for (int i = 1; i < nw; ++i) b = fmax_(b, red[i]);
     double d = double(b);
-    if (!(d >= 0.0)) d = __builtin_nan("");  // NaN propagates as the largest bits
+    if (!(d >= 0.0)) d = __builtin_nan("");
     unsigned long long bits = (unsigned long long)__double_as_longlong(d);
-    atomicMax(&scal->smax_bits, bits);
+    atomicMax(dst, bits);
   }
+}
+
+// The end of a persistent work item with a dt per patch: the item's CFL
+// maximum into its patch's slot (smax restarts at 0); `red` is free again
+// on return.
+template <class T>
+__device__ __forceinline__ void item_cfl(const SweepArgs<T>& a, int patch, T& smax, T* red) {
+  if (a.pdt && a.do_cfl) {
+    block_max_fold(smax, &a.psmax[patch], red);
+    __syncthreads();
+    smax = T(0);
+  }
+}
+
+// dt of a persistent work item on `patch`
+template <class T>
+__device__ __forceinline__ double item_dt(const SweepArgs<T>& a, int patch, double dt) {
+  return a.pdt && !a.tonly ? a.pdt[patch] : dt;
+}
+
+// Workgroup max of smax folded into the step's FP64 atomic (unless the
+// launch folds it per patch), and the sticky error (one atomic per wave
+// that saw a bad cell: a wave vote, no LDS).  `red` holds one T per wave.
+template <class T>
+__device__ void finish_block(DevScalars* scal, T smax, bool bad, bool do_cfl, T* red,
+                             unsigned long long* dst = nullptr) {
+  const bool wbad = __any(bad);
+  if (wbad && (threadIdx.x & 63) == 0) atomicOr(&scal->error, kErrState);
+  if (!do_cfl) return;
+  block_max_fold(smax, dst ? dst : &scal->smax_bits, red);
 }
 
 // --------------------------------------------------------------------------
@@ -699,13 +728,14 @@ __global__ void __launch_bounds__(512, sizeof(T) == 4 && TOT && !MULTI && !PERSI
       if (it >= a.nitems) break;
       const WorkItem w = a.items[it];
       const PatchDev P = a.patches[w.patch];
-      SweepConst<T> k = make_const<T>(dt, P.dx[0], a.gamma, a.grav);
+      SweepConst<T> k = make_const<T>(item_dt(a, w.patch, dt), P.dx[0], a.gamma, a.grav);
       xsweep_tile<T, V, MULTI, TOT>(a, P, w.tile, k, slots, smax, bad, tot);
       if (TOT) tot_block(tot, cell_volume(P), a.tpart + 6 * int64_t(it), tred, grav);
       if (MULTI) __syncthreads();
+      item_cfl(a, w.patch, smax, red);
     }
   }
-  finish_block(a.scal, smax, bad, a.do_cfl != 0, red);
+  finish_block(a.scal, smax, bad, a.do_cfl != 0 && !a.pdt, red);
 }
 
 // --------------------------------------------------------------------------
@@ -1044,16 +1074,17 @@ __global__ void __launch_bounds__(512, sizeof(T) == 4 && !PERSIST ? 3 : 1)
       if (it >= a.nitems) break;
       const WorkItem w = a.items[it];
       const PatchDev P = a.patches[w.patch];
-      SweepConst<T> k = make_const<T>(dt, P.dx[0], a.gamma, a.grav);
+      SweepConst<T> k = make_const<T>(item_dt(a, w.patch, dt), P.dx[0], a.gamma, a.grav);
       T id[3];
       inv_widths<T>(P, id);
       const int npen = P.n[1] * P.n[2];
       xmarch_pencils<T, V, TOT>(a, P, w.tile * nw + wave, npen, npen, k, id, lines[wave], smax,
                                 bad, tot);
       if (TOT) tot_block(tot, cell_volume(P), a.tpart + 6 * int64_t(it), tred, grav);
+      item_cfl(a, w.patch, smax, red);
     }
   }
-  finish_block(a.scal, smax, bad, a.do_cfl != 0, red);
+  finish_block(a.scal, smax, bad, a.do_cfl != 0 && !a.pdt, red);
 }
 
 // --------------------------------------------------------------------------
@@ -1260,7 +1291,7 @@ __global__ void __launch_bounds__(512) sweep_plane_kernel(SweepArgs<T> a) {
   __shared__ double tred[TOT ? 48 : 1];
   T* lds = reinterpret_cast<T*>(dyn_lds);
   int* slot = reinterpret_cast<int*>(dyn_lds);  // free between items
-  const double dt = (TOT && a.tonly) ? 0.0 : a.scal->dt;
+  const double dt0 = (TOT && a.tonly) ? 0.0 : a.scal->dt;
   const bool store = !(TOT && a.tonly);
   const bool grav = has_grav(a.gvec);
   T smax = T(0);
@@ -1273,6 +1304,7 @@ __global__ void __launch_bounds__(512) sweep_plane_kernel(SweepArgs<T> a) {
     const WorkItem w = a.items[it];
     const PatchDev P = a.patches[w.patch];
     const int z = w.tile;
+    const double dt = item_dt(a, w.patch, dt0);
     if (XFIRST) {
       // x: pool -> registers -> LDS; y: LDS -> LDS; then LDS -> pool
       plane_sweep<T, V, 0, true, false>(a, P, z, lds, false, dt, smax, bad);
@@ -1298,8 +1330,9 @@ __global__ void __launch_bounds__(512) sweep_plane_kernel(SweepArgs<T> a) {
     }
     __syncthreads();  // the LDS is free again (the next ticket lands in it)
     if (TOT) tot_block(tot, cell_volume(P), a.tpart + 6 * int64_t(it), tred, grav);
+    item_cfl(a, w.patch, smax, lds);
   }
-  finish_block(a.scal, smax, bad, a.do_cfl != 0, lds);
+  finish_block(a.scal, smax, bad, a.do_cfl != 0 && !a.pdt, lds);
 }
 
 // --------------------------------------------------------------------------
@@ -1568,13 +1601,14 @@ __global__ void __launch_bounds__(512, sizeof(T) == 4 ? (PERSIST && TOT ? 3 : kC
       if (it >= a.nitems) break;
       const WorkItem w = a.items[it];
       const PatchDev P = a.patches[w.patch];
-      SweepConst<T> k = make_const<T>(dt, P.dx[AXIS], a.gamma, a.grav);
+      SweepConst<T> k = make_const<T>(item_dt(a, w.patch, dt), P.dx[AXIS], a.gamma, a.grav);
       colsweep_tile<T, AXIS, LDSH, TOT>(a, P, w.tile, k, tab, smax, bad, tot);
       __syncthreads();
       if (TOT) tot_block(tot, cell_volume(P), a.tpart + 6 * int64_t(it), tred, grav);
+      item_cfl(a, w.patch, smax, red);
     }
   }
-  finish_block(a.scal, smax, bad, a.do_cfl != 0, red);
+  finish_block(a.scal, smax, bad, a.do_cfl != 0 && !a.pdt, red);
 }
 
 // --------------------------------------------------------------------------
@@ -1590,6 +1624,7 @@ struct ReduceArgs {
   double grav[3];
   DevScalars* scal;
   double* partials;         // totals: [patch][chunk][6]
+  unsigned long long* psmax;  // CFL maximum per patch (null: scal->smax_bits)
 };
 
 template <class T>
@@ -1613,7 +1648,7 @@ __global__ void __launch_bounds__(256) cfl_kernel(ReduceArgs<T> a) {
     Cons<T> U = pl.load(off);
     smax = fmax_(smax, cell_speed<T, 0>(U, k, id, bad));
   }
-  finish_block(a.scal, smax, bad, true, red);
+  finish_block(a.scal, smax, bad, true, red, a.psmax ? &a.psmax[blockIdx.y] : nullptr);
 }
 
 // Partial sums of rho, mx, my, mz, E and E + rho*phi (phi = -g.x at cell
@@ -1833,6 +1868,8 @@ static SweepArgs<T> to_args(const LaunchSweep& L) {
   a.tpart = L.tpart;
   for (int i = 0; i < 3; ++i) a.gvec[i] = L.gvec[i];
   a.tonly = L.totals_only;
+  a.pdt = L.pdt;
+  a.psmax = L.psmax;
   return a;
 }
 
@@ -2008,9 +2045,13 @@ static ReduceArgs<T> to_rargs(const LaunchReduce& L) {
   for (int i = 0; i < 3; ++i) a.grav[i] = L.grav[i];
   a.scal = L.scal;
   a.partials = L.partials;
+  a.psmax = L.psmax;
   return a;
 }
 
+// The CFL maximum of the state: with L.psmax one per patch (turned into dt
+// per patch by launch_patch_dt), else one, turned into scal->dt here unless
+// L.fold_only (a step without sweeps: its bookkeeping takes the maximum).
 hipError_t launch_cfl(const LaunchReduce& L, hipStream_t st) {
   dim3 grid(L.chunks, L.npatch);
   if (L.fp64)
@@ -2018,7 +2059,7 @@ hipError_t launch_cfl(const LaunchReduce& L, hipStream_t st) {
   else
     hipLaunchKernelGGL(cfl_kernel<float>, grid, dim3(256), 0, st, to_rargs<float>(L));
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || L.psmax || L.fold_only) return e;
   hipLaunchKernelGGL(finish_cfl_kernel, dim3(1), dim3(1), 0, st, L.scal);
   return hipGetLastError();
 }
@@ -2071,6 +2112,49 @@ hipError_t launch_init_scalars(DevScalars* s, double cfl, double t, double t_end
   hipLaunchKernelGGL(init_scalars_kernel, dim3(1), dim3(1), 0, st, s, cfl, t, t_end);
   return hipGetLastError();
 }
+// Per-patch time steps (one thread per patch): with advance, t += dt
+// first; then the next dt from the patch's folded CFL maximum, capped by
+// t_end - t, as next_dt does for a single dt.
+__global__ void patch_dt_kernel(double* t, double* dt, unsigned long long* psmax, int32_t n,
+                                DevScalars* s, int advance) {
+  const int p = int(blockIdx.x * blockDim.x + threadIdx.x);
+  if (p >= n) return;
+  double tp = t[p];
+  if (advance) {
+    tp += dt[p];
+    t[p] = tp;
+  }
+  const double smax = __longlong_as_double((long long)psmax[p]);
+  double d = s->cfl / smax;
+  if (!(smax > 0.0) || !(smax < __builtin_huge_val())) {
+    atomicOr(&s->error, kErrSpeed);
+    d = 0.0;
+  }
+  if (s->t_end > 0.0) d = fmin(d, fmax(0.0, s->t_end - tp));
+  dt[p] = d;
+  psmax[p] = 0ull;
+}
+
+__global__ void fill_kernel(double* a, int64_t n, double v) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    a[i] = v;
+}
+
+hipError_t launch_patch_dt(double* t, double* dt, unsigned long long* psmax, int32_t n,
+                           DevScalars* s, int advance, hipStream_t st) {
+  hipLaunchKernelGGL(patch_dt_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, t, dt,
+                     psmax, n, s, advance);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* a, int64_t n, double v, hipStream_t st) {
+  const int64_t b = std::min<int64_t>((n + 255) / 256, 1024);
+  if (b < 1) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(unsigned(b)), dim3(256), 0, st, a, n, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_step_results(const DevScalars* s, double* out, hipStream_t st) {
   hipLaunchKernelGGL(step_results_kernel, dim3(1), dim3(1), 0, st, s, out);
   return hipGetLastError();

@@ -45,6 +45,10 @@ struct LaunchSweep {
   int32_t totals_only;       // dt = 0 and nothing stored: totals of the current state
   int32_t tot_cap;           // direct x launches with totals: at most this many
                              // workgroups, striding over the tiles (0: no cap)
+  // persistent launches with a dt per patch (null: one dt in DevScalars):
+  // patch p steps by pdt[p] and folds its CFL maximum into psmax[p]
+  const double* pdt;
+  unsigned long long* psmax;
 };
 
 // Partial sums a sweep launch writes (grid size or work items).
@@ -69,6 +73,8 @@ struct LaunchReduce {
   DevScalars* scal;
   double* partials;
   int32_t fp64;
+  unsigned long long* psmax;  // CFL maximum per patch (null: one in DevScalars)
+  int32_t fold_only;          // CFL: leave the maximum folded (no dt from it yet)
 };
 
 // In-situ diagnostics (diag.hip).
@@ -193,6 +199,12 @@ hipError_t launch_init_scalars(DevScalars* s, double cfl, double t, double t_end
                                hipStream_t st);
 hipError_t launch_set_dt(DevScalars* s, double dt, hipStream_t st);
 hipError_t launch_step_results(const DevScalars* s, double* out, hipStream_t st);
+// Per-patch time steps: with advance, t[p] += dt[p] first; then dt[p] =
+// cfl / psmax[p] capped by t_end - t[p] (DevScalars), and psmax[p] = 0.
+hipError_t launch_patch_dt(double* t, double* dt, unsigned long long* psmax, int32_t n,
+                           DevScalars* s, int advance, hipStream_t st);
+// a[0..n) = v (a fill kernel: safe to capture in a graph)
+hipError_t launch_fill(double* a, int64_t n, double v, hipStream_t st);
 hipError_t launch_set_time(DevScalars* s, double t, double t_end, hipStream_t st);
 hipError_t launch_clear_error(DevScalars* s, hipStream_t st);
 hipError_t launch_timing_begin(DevScalars* s, hipStream_t st);

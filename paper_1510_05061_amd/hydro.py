@@ -21,7 +21,7 @@ HYDRO_OK, HYDRO_EINVAL, HYDRO_EDEVICE, HYDRO_ENUMERIC, HYDRO_ESTATE = range(5)
 PERIODIC, OUTFLOW, REFLECT = 0, 1, 2
 FP32, FP64 = 0, 1
 Q_RHO, Q_PRESSURE, Q_SPEED, Q_MACH = 0, 1, 2, 3
-FLAG_NO_GRAPH, FLAG_NO_TUNE = 0x1, 0x2
+FLAG_NO_GRAPH, FLAG_NO_TUNE, BATCH_PER_PATCH_DT = 0x1, 0x2, 0x4
 DT_CFL = 0.0
 
 
@@ -114,6 +114,7 @@ _SIGS = {
                           ctypes.POINTER(HydroDesc), _vp, _sz, _vp, _sz, _vp,
                           ctypes.POINTER(_vp)], ctypes.c_int),
     "hydro_batch_step": ([_vp, ctypes.c_double], ctypes.c_int),
+    "hydro_batch_times": ([_vp, _dp, _dp], ctypes.c_int),
     "hydro_totals": ([_vp, _dp], ctypes.c_int),
     "hydro_diag_pdf": ([_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                         _vp], ctypes.c_int),
@@ -231,6 +232,14 @@ def hydro_step_noalloc(desc, state_ptr, state_bytes, dt, step, stream_ptr, out_p
 
 def hydro_batch_step(ctx, dt=DT_CFL):
     _check(lib().hydro_batch_step(ctx, float(dt)), "hydro_batch_step")
+
+
+def hydro_batch_times(ctx, n):
+    """(t, dt) lists of the n patches of a batch."""
+    t = (ctypes.c_double * n)()
+    dt = (ctypes.c_double * n)()
+    _check(lib().hydro_batch_times(ctx, t, dt), "hydro_batch_times")
+    return list(t), list(dt)
 
 
 def hydro_sweep(ctx, axis, dt, fold_cfl=False):
@@ -585,6 +594,10 @@ class Batch:
     def step(self, dt=DT_CFL):
         hydro_batch_step(self.ctx, dt)
 
+    def times(self):
+        """(t, dt) lists per patch (see hydro_batch_times)."""
+        return hydro_batch_times(self.ctx, len(self.patches))
+
     def sweep(self, axis, dt, fold_cfl=False):
         hydro_sweep(self.ctx, axis, dt, fold_cfl)
 
@@ -614,6 +627,9 @@ class Batch:
 
     def set_time(self, t, step):
         hydro_set_time(self.ctx, t, step)
+
+    def set_t_end(self, t_end):
+        hydro_set_t_end(self.ctx, t_end)
 
     def state_changed(self):
         hydro_state_changed(self.ctx)

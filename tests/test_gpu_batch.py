@@ -1,7 +1,8 @@
 """Batched patches: one persistent launch per sweep over a patch list must
 give, patch by patch, the bits of the single-grid path, parity with the
 oracle, the global dt as the minimum over patches, and untouched stored
-ghost layers."""
+ghost layers; with a dt per patch (HYDRO_BATCH_PER_PATCH_DT) every patch
+takes the steps and reaches the times of its own single-grid run."""
 import numpy as np
 import pytest
 
@@ -141,3 +142,84 @@ def test_cached_autotune_config_runs_the_whole_batch(tmp_path):
         np.testing.assert_array_equal(outs[1][0], outs[2][0])
     finally:
         del os.environ["HYDRO_TUNE_CACHE"]
+
+
+def _mixed_speed_batch(count, prec, flags):
+    """A batch whose patches differ in signal speed (shear and density
+    ratio from the seeded specs): with a dt per patch each takes its own."""
+    return _batch(count, prec, seed=11, pad_rows=32, flags=flags)
+
+
+@pytest.mark.parametrize("prec,cfg", [(hydro.FP64, ""), (hydro.FP32, ""),
+                                      (hydro.FP32, "p:f=1;w:v=4,b=256")])
+def test_per_patch_dt_equals_single_grids_bitwise(prec, cfg):
+    say(f"per-patch dt {prec} {cfg}")
+    b, dev, pool, patches = _mixed_speed_batch(
+        10, prec, hydro.FLAG_NO_TUNE | hydro.BATCH_PER_PATCH_DT)
+    if cfg:
+        b.config = cfg
+    steps = 5
+    dt_min = b.cfl_dt()
+    for _ in range(steps):
+        b.step()
+    out = host(dev)
+    tb, dtb = b.times()
+    assert b.time()[0] == min(tb)
+    for i, p in enumerate(patches):
+        g, sd = _single(pool, p, prec)
+        for _ in range(steps):
+            g.step()
+        np.testing.assert_array_equal(ic.patch_view(out, p), host(sd))
+        t, s = g.time()
+        assert tb[i] == t and s == steps
+        assert dtb[i] == g.cfl_dt()          # the next dt of the patch
+        g.close()
+    assert len(set(tb)) == len(tb)           # every patch at its own time
+    assert min(dtb) >= 0 and dt_min > 0
+    assert b.error() == hydro.HYDRO_OK
+    b.close()
+
+
+def test_per_patch_dt_fp64_matches_oracle_runs():
+    say("per-patch dt vs oracle")
+    b, dev, pool, patches = _mixed_speed_batch(
+        6, hydro.FP64, hydro.FLAG_NO_TUNE | hydro.BATCH_PER_PATCH_DT)
+    steps = 3
+    for _ in range(steps):
+        b.step()
+    out = host(dev)
+    tb, _ = b.times()
+    for i, p in enumerate(patches):
+        ng = p[4]
+        u = np.ascontiguousarray(ic.patch_view(pool, p)[:, ng:-ng, ng:-ng, ng:-ng])
+        prm = oracle.make_params(u.shape[1:], p[5], GAMMA, 0.8)
+        t, s, _ = oracle.run(prm, u, steps)
+        got = ic.patch_view(out, p)[:, ng:-ng, ng:-ng, ng:-ng]
+        err = rel_err(got, u)
+        assert max(err) <= 1e-12, (i, err)
+        assert abs(tb[i] - t) <= 1e-14 * t
+    b.close()
+
+
+def test_per_patch_dt_lands_every_patch_on_t_end():
+    say("per-patch dt t_end")
+    b, dev, pool, patches = _mixed_speed_batch(
+        8, hydro.FP64, hydro.FLAG_NO_TUNE | hydro.BATCH_PER_PATCH_DT)
+    t_end = 3.5 * b.cfl_dt()     # about four steps for the patch with the smallest dt
+    b.set_t_end(t_end)
+    steps = 0
+    while b.time()[0] < t_end:
+        b.step()
+        steps += 1
+        assert steps <= 50
+    tb, dtb = b.times()
+    assert all(t == t_end for t in tb) and all(d == 0.0 for d in dtb)
+    out = host(dev)
+    for p in patches[:3]:
+        g, sd = _single(pool, p, hydro.FP64)
+        g.set_t_end(t_end)
+        for _ in range(steps):
+            g.step()
+        np.testing.assert_array_equal(ic.patch_view(out, p), host(sd))
+        g.close()
+    b.close()
