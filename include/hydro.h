@@ -138,10 +138,12 @@ const char* hydro_last_error(void);
 
 /* Bytes of device workspace hydro_init needs for this descriptor.  The
  * workspace holds the device scalars (dt, t, CFL maximum, error flag, work
- * tickets) and reduction partials. */
+ * tickets) and reduction partials (the FP64 totals of each step). */
 int hydro_workspace_bytes(const hydro_desc* d, size_t* bytes);
 
-/* Bind a context to caller-owned device buffers.  `state` is the grid
+/* The star as a fluid on a grid (paper, introduction): a context binds the
+ * zone update to one grid.
+ * Bind a context to caller-owned device buffers.  `state` is the grid
  * (layout above) of `state_bytes` bytes (at least 5 planes), `workspace` at
  * least hydro_workspace_bytes bytes (16-byte aligned), `stream` a
  * hipStream_t (NULL: the null stream).  Validates the
@@ -153,14 +155,20 @@ int hydro_workspace_bytes(const hydro_desc* d, size_t* bytes);
 int hydro_init(const hydro_desc* d, void* state, size_t state_bytes, void* workspace,
                size_t ws_bytes, void* stream, hydro_ctx** out);
 
-/* Compute dt = cfl / max signal speed from the current state (capped so
+/* The global reduction every timestep needs (paper, section "Capabilities
+ * needed": global communication each timestep), here the CFL maximum.
+ * Compute dt = cfl / max signal speed from the current state (capped so
  * that t does not pass t_end when a final time is set), store it on the
  * device for the next HYDRO_DT_CFL step and return it in *dt.  Synchronous.
  * Returns HYDRO_ENUMERIC (and *dt = 0) when the sticky error flag is set or
  * the state holds rho <= 0, p <= 0 or a non-finite value. */
 int hydro_cfl_dt(hydro_ctx* c, double* dt);
 
-/* Enqueue one full split step of the grid.  dt > 0 uses exactly that dt;
+/* The zone update of the fluid (paper, introduction), with the
+ * nearest-neighbour data of every sweep and the step's global reductions
+ * (section "Capabilities needed": the CFL maximum for the next dt and the
+ * FP64 conserved totals, both folded into the last sweep).
+ * Enqueue one full split step of the grid.  dt > 0 uses exactly that dt;
  * dt == HYDRO_DT_CFL uses the CFL dt on the device (computed from the
  * current state before the first such step, then by the last sweep of each
  * step).  Advances t by dt and the step counter by one; the counter's parity
@@ -210,7 +218,11 @@ int hydro_sweep(hydro_ctx* c, int axis, double dt, int fold_cfl);
 int hydro_batch_workspace_bytes(const hydro_patch* p, int32_t n, const hydro_desc* common,
                                 size_t* bytes);
 
-/* Bind a context to a batch of n independent patches stored in the
+/* Many independent grids in one launch per sweep: the suites of runs of
+ * the paper's capacity-computing argument (section "Capabilities needed";
+ * section "Increasing computing power": suites of simulations), and the
+ * patches of adaptively refined levels.
+ * Bind a context to a batch of n independent patches stored in the
  * caller-owned `pool` of `pool_bytes` bytes (offsets in p[]; every patch
  * must lie inside the pool and patches must not overlap).  `common` gives gamma, cfl, grav,
  * bc, precision and flags (its nx..dz are ignored).  The patch table and
@@ -241,10 +253,19 @@ int hydro_batch_step(hydro_ctx* c, double dt);
  * context), HYDRO_EDEVICE. */
 int hydro_batch_times(hydro_ctx* c, double* t, double* dt);
 
-/* FP64 totals of the current state: sum over cells of (rho, mx, my, mz, E,
+/* The conserved totals, a global reduction of every timestep (paper,
+ * section "Capabilities needed"), kept in FP64.
+ * FP64 totals of the current state: sum over cells of (rho, mx, my, mz, E,
  * E + rho*phi) times the cell volume, phi = -(g . x) at cell centres with
- * the origin at the low corner of the grid (of each patch).  Fixed
- * summation order: bitwise reproducible for a given shape.  Synchronous. */
+ * the origin at the low corner of the grid (of each patch).  Every step
+ * folds them into its last sweep: each workgroup (or batch work item) sums
+ * the cells it updates and a final kernel adds those partial sums in a
+ * fixed order, so the result is bitwise reproducible for a configuration.
+ * After a step this returns the folded totals; after anything else that may
+ * change the state (hydro_state_changed, hydro_sweep, hydro_set_time,
+ * hydro_burn, AMR operators) it recomputes them with the same partition (the
+ * last sweep of the previous step's order, run with dt = 0 and nothing
+ * stored), so both give the same bits.  Synchronous. */
 int hydro_totals(hydro_ctx* c, double out[6]);
 
 /* In-situ diagnostics.  Large runs need their analysis done in situ (the
@@ -413,6 +434,14 @@ int hydro_amr_prolong(hydro_ctx* c, const hydro_amr_link* links, int32_t n, int 
  * it is as large as the pool), the registers and the link table.  Asynchronous.  Errors: HYDRO_EINVAL, HYDRO_ESTATE
  * (not batches, work lists out of date), HYDRO_EDEVICE. */
 #define HYDRO_AMR_NO_REFLUX 0x1u
+
+/* The largest stable coarse dt of the two-level step: min(coarse CFL dt,
+ * 2 x fine CFL dt), each the CFL dt of its batch's current state (as
+ * hydro_cfl_dt, which it also stores on each context's device), since the
+ * fine level takes two substeps of dt/2.  Synchronous.  Errors:
+ * HYDRO_EINVAL, HYDRO_ESTATE (not batches), HYDRO_ENUMERIC, HYDRO_EDEVICE. */
+int hydro_amr_cfl_dt(hydro_ctx* coarse, hydro_ctx* fine, double* dt);
+
 int hydro_amr_step_workspace_bytes(const hydro_ctx* coarse, const hydro_ctx* fine,
                                    int32_t fine_ng, size_t* bytes);
 int hydro_amr_step(hydro_ctx* coarse, hydro_ctx* fine, const hydro_amr_link* links, int32_t n,

@@ -1908,6 +1908,19 @@ int level_sweeps(hydro_ctx* c, const hydro_ctx* coarse, const hydro_ctx* fine,
 
 }  // namespace
 
+int hydro_amr_cfl_dt(hydro_ctx* coarse, hydro_ctx* fine, double* dt) {
+  if (!coarse || !fine || !dt) return fail(HYDRO_EINVAL, "null argument");
+  *dt = 0.0;
+  if (!coarse->batch || !fine->batch) return fail(HYDRO_ESTATE, "both levels must be batches");
+  double dc = 0.0, df = 0.0;
+  int rc = hydro_cfl_dt(coarse, &dc);
+  if (rc) return rc;
+  rc = hydro_cfl_dt(fine, &df);
+  if (rc) return rc;
+  *dt = std::min(dc, 2.0 * df);  // two fine substeps of dt/2 per coarse step
+  return HYDRO_OK;
+}
+
 int hydro_amr_step_workspace_bytes(const hydro_ctx* coarse, const hydro_ctx* fine,
                                    int32_t fine_ng, size_t* bytes) {
   if (!coarse || !fine || !bytes) return fail(HYDRO_EINVAL, "null argument");

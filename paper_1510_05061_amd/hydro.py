@@ -125,6 +125,7 @@ _SIGS = {
     "hydro_amr_restrict": ([_vp, ctypes.POINTER(HydroAmrLink), ctypes.c_int32], ctypes.c_int),
     "hydro_amr_prolong": ([_vp, ctypes.POINTER(HydroAmrLink), ctypes.c_int32, ctypes.c_int],
                           ctypes.c_int),
+    "hydro_amr_cfl_dt": ([_vp, _vp, _dp], ctypes.c_int),
     "hydro_amr_step_workspace_bytes": ([_vp, _vp, ctypes.c_int32, ctypes.POINTER(_sz)],
                                        ctypes.c_int),
     "hydro_amr_step": ([_vp, _vp, ctypes.POINTER(HydroAmrLink), ctypes.c_int32, ctypes.c_int32,
@@ -293,6 +294,12 @@ def hydro_amr_prolong(ctx, links, ghosts_only=False):
 AMR_NO_REFLUX = 0x1
 
 
+def hydro_amr_cfl_dt(coarse_ctx, fine_ctx):
+    dt = ctypes.c_double(0.0)
+    _check(lib().hydro_amr_cfl_dt(coarse_ctx, fine_ctx, ctypes.byref(dt)), "hydro_amr_cfl_dt")
+    return dt.value
+
+
 def hydro_amr_step_workspace_bytes(coarse_ctx, fine_ctx, fine_ng):
     n = _sz(0)
     _check(lib().hydro_amr_step_workspace_bytes(coarse_ctx, fine_ctx, fine_ng, ctypes.byref(n)),
@@ -326,8 +333,8 @@ class AmrLevels:
                        self.workspace.numel())
 
     def cfl_dt(self):
-        """Largest stable coarse dt: min(coarse CFL dt, 2 x fine CFL dt)."""
-        return min(self.coarse.cfl_dt(), 2.0 * self.fine.cfl_dt())
+        """Largest stable coarse dt (see hydro_amr_cfl_dt)."""
+        return hydro_amr_cfl_dt(self.coarse.ctx, self.fine.ctx)
 
 
 def _pdf(obj, quantity, lo, hi, nbins, out):

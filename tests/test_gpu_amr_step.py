@@ -336,6 +336,9 @@ def test_two_coarse_patches_one_with_stored_ghosts():
             pf = oracle.make_params(fines[k].shape[1:], tuple(h / 2 for h in dxs[c]), GAMMA)
             dt = min(dt, 2 * oracle.cfl_dt(pf, fines[k]))
             k += 1
+    # the library's level dt (hydro_amr_cfl_dt) is the same minimum
+    level_dt = lv.cfl_dt()
+    assert abs(level_dt - dt) <= 1e-14 * dt, (level_dt, dt)
     dt *= 0.5
     lv.step(dt)
     got_pool = tc.cpu().numpy()
