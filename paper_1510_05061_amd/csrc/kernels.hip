@@ -1219,9 +1219,9 @@ __device__ __forceinline__ void pool_run(const SweepArgs<T>& a, const PatchDev& 
 // x-first step straight from the pool (GSRC); the result goes to LDS, or
 // for the x sweep of a y-first step straight to the pool (GDST): a row run
 // is a coalesced vector access, so those two sweeps skip a copy through LDS.
-template <class T, int V, int AXIS, bool GSRC, bool GDST>
+template <class T, int V, int AXIS, bool GSRC, bool GDST, bool TOT = false>
 __device__ void plane_sweep(const SweepArgs<T>& a, const PatchDev& P, int z, T* lds,
-                            bool do_cfl, double dt, T& smax, bool& bad) {
+                            bool do_cfl, double dt, T& smax, bool& bad, TotR* tot = nullptr) {
   const int nx = P.n[0], ny = P.n[1];
   const int n = AXIS == 0 ? nx : ny;      // pencil length
   const int m = AXIS == 0 ? ny : nx;      // pencils
@@ -1257,11 +1257,18 @@ __device__ void plane_sweep(const SweepArgs<T>& a, const PatchDev& P, int z, T* 
       pool_run<T, V, false>(a, P, z, gl * V, pen + mstep, Un);
     lanerun_update<T, V, AXIS>(U, act ? gl : 0, last, srcL, srcR, blo, bhi, k, id, act, do_cfl,
                                smax, bad);
+    if (TOT && act) {
+#pragma unroll
+      for (int c = 0; c < V; ++c)
+        tot_add<T, AXIS>(*tot, U[c], P, a.gvec, AXIS == 0 ? gl * V + c : pen,
+                         AXIS == 0 ? pen : gl * V + c, z);
+    }
     if (act) {
-      if (GDST)
-        pool_run<T, V, true>(a, P, z, gl * V, pen, U);
-      else
+      if (GDST) {
+        if (!(TOT && a.tonly)) pool_run<T, V, true>(a, P, z, gl * V, pen, U);
+      } else {
         plane_run<T, V, AXIS, true>(lds, AXIS == 0 ? gl * V : pen, AXIS == 0 ? pen : gl * V, U);
+      }
     }
   }
 }
@@ -1283,12 +1290,15 @@ __device__ void plane_totals(const SweepArgs<T>& a, const PatchDev& P, int z, co
 
 // XFIRST: x then y (even steps); else y then x (odd steps), where the x
 // sweep is the last of the step and folds the CFL maximum.  TOT (the last
-// launch of a step): the plane's second sweep leaves its result in LDS,
-// plane_totals adds it to the totals and the plane is copied out.
+// launch of a step): y then x adds each updated cell to the totals as it
+// stores it; x then y (a batch without z, whose plane launch is last on
+// every step) adds the plane in LDS with plane_totals before copying it out.
+// The plane takes up to half the LDS of a CU, so two workgroups share one:
+// no static LDS beside it (the totals reduction uses the plane's LDS once
+// the plane has been copied out).
 template <class T, int V, bool XFIRST, bool TOT>
 __global__ void __launch_bounds__(512) sweep_plane_kernel(SweepArgs<T> a) {
   extern __shared__ __align__(16) unsigned char dyn_lds[];
-  __shared__ double tred[TOT ? 48 : 1];
   T* lds = reinterpret_cast<T*>(dyn_lds);
   int* slot = reinterpret_cast<int*>(dyn_lds);  // free between items
   const double dt0 = (TOT && a.tonly) ? 0.0 : a.scal->dt;
@@ -1319,17 +1329,13 @@ __global__ void __launch_bounds__(512) sweep_plane_kernel(SweepArgs<T> a) {
       __syncthreads();
       plane_sweep<T, V, 1, false, false>(a, P, z, lds, false, dt, smax, bad);
       __syncthreads();
-      if (TOT) {
-        plane_sweep<T, V, 0, false, false>(a, P, z, lds, a.do_cfl != 0, dt, smax, bad);
-        __syncthreads();
-        plane_totals<T, V>(a, P, z, lds, tot);
-        if (store) plane_copy<T, V, false>(a, P, z, lds);
-      } else {
-        plane_sweep<T, V, 0, false, true>(a, P, z, lds, a.do_cfl != 0, dt, smax, bad);
-      }
+      // x: LDS -> registers -> pool (with TOT adding each cell to the totals)
+      plane_sweep<T, V, 0, false, true, TOT>(a, P, z, lds, a.do_cfl != 0, dt, smax, bad, &tot);
     }
     __syncthreads();  // the LDS is free again (the next ticket lands in it)
-    if (TOT) tot_block(tot, cell_volume(P), a.tpart + 6 * int64_t(it), tred, grav);
+    if (TOT)
+      tot_block(tot, cell_volume(P), a.tpart + 6 * int64_t(it),
+                reinterpret_cast<double*>(dyn_lds), grav);
     item_cfl(a, w.patch, smax, lds);
   }
   finish_block(a.scal, smax, bad, a.do_cfl != 0 && !a.pdt, lds);
@@ -1937,13 +1943,21 @@ static hipError_t launch_x(const LaunchSweep& L, hipStream_t st, dim3 grid) {
 
 template <class T, bool PERSIST, bool TOT>
 static hipError_t launch_col(const LaunchSweep& L, hipStream_t st, dim3 grid) {
-  const int threads = L.cfg.q * L.cfg.s;
+  int s = L.cfg.s;
+  // the persistent FP32 totals instantiation holds three waves per SIMD
+  // (its register bound): workgroups of at most 256 threads, so that three
+  // of them share a CU (fewer segments per column; the same work items and
+  // the same state bits)
+  if (TOT && PERSIST && sizeof(T) == 4)
+    while (L.cfg.q * s > 256 && s % 2 == 0) s /= 2;
+  const int threads = L.cfg.q * s;
   dim3 block(threads);
   // halos through LDS while the table (20 values per thread) fits in 64 KiB
   const size_t tab = size_t(threads) * 20 * sizeof(T);
   const bool ldsh = tab <= 65536;
   const size_t tl = TOT ? size_t(threads) * kTotStride * sizeof(double) : 0;  // totals (TotL)
-  const SweepArgs<T> a = to_args<T>(L);
+  SweepArgs<T> a = to_args<T>(L);
+  a.s = s;
   if (L.axis == 1) {
     if (ldsh)
       hipLaunchKernelGGL((sweep_col_kernel<T, 1, PERSIST, true, TOT>), grid, block, tl + tab, st,
