@@ -300,9 +300,34 @@ __device__ __forceinline__ void tot_add(Acc& t, const Cons<T>& S, const PatchDev
   }
 }
 
+// v of every lane moved by the DPP pattern CTRL (one row of 16 lanes; every
+// source lane lies in the destination's row), as two 32-bit moves.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = unsigned(__builtin_amdgcn_update_dpp(0, int(unsigned(b)), CTRL, 0xF, 0xF, false));
+  const unsigned hi = unsigned(__builtin_amdgcn_update_dpp(0, int(unsigned(b >> 32)), CTRL, 0xF, 0xF, false));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(unsigned(b)), lane));
+  const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(unsigned(b >> 32)), lane));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a full wave, in a fixed tree: within each row of
+// 16 lanes by register moves across lanes (pairs, quads, halves of a row,
+// rows: each step adds a lane and its mirror, so every lane of a row ends
+// with the same row sum), then the four row sums as (r0 + r1) + (r2 + r3).
+// No LDS round trips: the reduction is four dependent adds and a few moves.
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
 // The workgroup's sums, each thread's times the cell volume `vol`, in a
