@@ -353,6 +353,33 @@ __device__ void tot_block(Acc& t, double vol, double* out, double* red, bool gra
   t.zero();
 }
 
+// LDS bytes per thread that tot_block_wide needs
+constexpr int kTotWideBytes = 48;
+
+// tot_block for kernels that reduce once per work item and have a large LDS
+// area free at that point: every thread stores its six sums (times `vol`)
+// at red[v B + t] (B threads); wave w then adds variable v = w, w + nw, ...
+// over the threads in a fixed order (lane l takes t = l, l + 64, ...) and
+// reduces its lanes with wave_sum.  About a quarter of tot_block's
+// instructions per item, since only six waves reduce and each reduces one
+// value.  `red` holds kTotWideBytes per thread.
+template <class Acc>
+__device__ void tot_block_wide(Acc& t, double vol, double* out, double* red, bool grav) {
+  const int B = blockDim.x, nw = B >> 6;
+  const int wid = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int v = 0; v < 6; ++v) red[v * B + threadIdx.x] = t.get(grav || v < 5 ? v : 4) * vol;
+  __syncthreads();
+  for (int v = wid; v < 6; v += nw) {  // wave-uniform
+    double a = 0.0;
+    for (int j = l; j < B; j += 64) a += red[v * B + j];
+    a = wave_sum(a);
+    if (l == 0) out[v] = a;
+  }
+  __syncthreads();
+  t.zero();
+}
+
 template <class T>
 __device__ __forceinline__ Prim<T> shfl_prim(const Prim<T>& W, int src) {
   Prim<T> r;
@@ -1359,8 +1386,8 @@ __global__ void __launch_bounds__(512) sweep_plane_kernel(SweepArgs<T> a) {
     }
     __syncthreads();  // the LDS is free again (the next ticket lands in it)
     if (TOT)
-      tot_block(tot, cell_volume(P), a.tpart + 6 * int64_t(it),
-                reinterpret_cast<double*>(dyn_lds), grav);
+      tot_block_wide(tot, cell_volume(P), a.tpart + 6 * int64_t(it),
+                     reinterpret_cast<double*>(dyn_lds), grav);
     item_cfl(a, w.patch, smax, lds);
   }
   finish_block(a.scal, smax, bad, a.do_cfl != 0 && !a.pdt, lds);
@@ -2002,7 +2029,8 @@ static hipError_t launch_col(const LaunchSweep& L, hipStream_t st, dim3 grid) {
 template <class T, int V, bool TOT>
 static hipError_t launch_plane_v(const LaunchSweep& L, hipStream_t st) {
   const SweepArgs<T> a = to_args<T>(L);
-  const size_t lds = size_t(L.plane_lds);
+  // with totals the plane's LDS also takes the per-item reduction
+  const size_t lds = std::max(size_t(L.plane_lds), TOT ? size_t(kTotWideBytes) * L.cfg.block : 0);
   if (L.plane == kPlaneXY)
     hipLaunchKernelGGL((sweep_plane_kernel<T, V, true, TOT>), dim3(L.nblocks),
                        dim3(L.cfg.block), lds, st, a);
