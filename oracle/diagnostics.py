@@ -35,6 +35,13 @@ Kinetic-energy spectrum along x: the x-line DFTs of the velocity m / rho,
 their power summed over components, averaged over lines and folded onto
 k = 0 .. nx//2 so that the spectrum sums to the mean specific kinetic
 energy (spectrum_x).
+
+Shell kinetic-energy spectrum (spectrum_shell): the three-dimensional DFT of
+the velocity m / rho over the grid, its power summed over components and
+over the integer wavevectors of each shell K = round(|k|), scaled so that
+the shells sum to the mean specific kinetic energy (Parseval).  The shells
+are those that set the turbulence initial data's spectrum (E(K) ~ K^(-5/3)
+over shells 1..8), so the diagnostic reads that spectrum back.
 """
 import numpy as np
 
@@ -125,3 +132,45 @@ def spectrum_x(U):
     if n % 2 == 0:
         E[n // 2] *= 0.5
     return E
+
+
+def wavenumbers(n):
+    """Signed integer wavenumbers of a DFT of length n in numpy's order:
+    0, 1, .., then the negative ones (-n/2 at index n/2 for even n)."""
+    return np.rint(np.fft.fftfreq(n) * n).astype(np.int64)
+
+
+def shell_index(m2):
+    """Shell K = round(sqrt(m2)) of integer wavevectors with |k|^2 = m2
+    (int64 array).  sqrt of an integer is never a half-integer, so the
+    rounding has no ties; K is the integer with K - 1/2 <= |k| < K + 1/2."""
+    return np.rint(np.sqrt(np.asarray(m2, dtype=np.float64))).astype(np.int64)
+
+
+def shell_count(shape):
+    """Number of shells K = 0 .. K_max of a (nz, ny, nx) grid: K_max is the
+    shell of the corner wavevector (nx//2, ny//2, nz//2)."""
+    nz, ny, nx = shape
+    return int(shell_index((nx // 2) ** 2 + (ny // 2) ** 2 + (nz // 2) ** 2)) + 1
+
+
+def spectrum_shell(U):
+    """Shell kinetic-energy spectrum of the velocity u = m / rho over the
+    grid: with u_hat_c the unnormalised three-dimensional DFT of component c
+    (numpy's fftn over the grid, N = nx ny nz cells) and k the signed integer
+    wavevector of each coefficient,
+        E[K] = sum over k with round(|k|) = K of sum_c |u_hat_c(k)|^2 / (2 N^2),
+    K = 0 .. K_max (shell_count), so that by Parseval
+    sum_K E[K] = (1/2) <|u|^2>, the mean specific kinetic energy."""
+    U = np.asarray(U, dtype=np.float64)
+    nz, ny, nx = U.shape[1:]
+    with np.errstate(all="ignore"):
+        u = U[1:4] / U[0]
+    F = np.fft.fftn(u, axes=(1, 2, 3))
+    P = (F.real * F.real + F.imag * F.imag).sum(axis=0)
+    kz, ky, kx = (wavenumbers(n) for n in (nz, ny, nx))
+    m2 = kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2
+    K = shell_index(m2)
+    nb = shell_count((nz, ny, nx))
+    N = float(nx) * ny * nz
+    return np.bincount(K.ravel(), weights=P.ravel(), minlength=nb) / (2.0 * N * N)

@@ -178,3 +178,126 @@ def test_spectrum_parseval_and_velocity_not_momentum():
     np.testing.assert_allclose(E.sum(), 0.5 * (u * u).sum(axis=0).mean(), rtol=1e-13)
     np.testing.assert_allclose(E, D.spectrum_x(cons(1.0, u[0], u[1], u[2], 1.0)), rtol=1e-12,
                                atol=1e-15)
+
+
+# ------------------------------------------------------ shell spectrum
+
+def _field(u, rho=1.0):
+    """Conserved state of velocity field u (3, nz, ny, nx) and density rho."""
+    return cons(rho, u[0], u[1], u[2], 1.0)
+
+
+def _grid(shape):
+    nz, ny, nx = shape
+    return np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+
+
+def test_shell_index_is_the_nearest_integer_of_the_norm():
+    # K - 1/2 <= |k| < K + 1/2, i.e. (2K - 1)^2 <= 4 m2 < (2K + 1)^2, in
+    # integers, for every |k|^2 of wavevectors up to 512 per axis
+    m2 = np.arange(0, 3 * 512 * 512 + 1, dtype=np.int64)
+    K = D.shell_index(m2)
+    lo_ok = (K == 0) | ((2 * K - 1) ** 2 <= 4 * m2)     # K - 1/2 <= 0 needs no check
+    assert np.all(lo_ok) and np.all(4 * m2 < (2 * K + 1) ** 2)
+    assert D.shell_count((768, 768, 768)) == 666      # round(sqrt(3) 384) = 665
+    assert D.shell_count((1, 1, 16)) == 9 and D.shell_count((6, 4, 12)) == 8  # corner (6, 2, 3): |k| = 7
+
+
+@pytest.mark.parametrize("shape,k", [((8, 12, 16), (3, 2, 1)), ((6, 9, 12), (5, -4, 2)),
+                                     ((16, 16, 16), (0, 7, -7)), ((4, 6, 10), (2, -2, 1))])
+def test_shell_spectrum_single_mode(shape, k):
+    # u = A e cos(2 pi k . x / n + phi) with e a unit vector: all the energy
+    # A^2 / 4 in the shell round(|k|) (no component at a Nyquist frequency)
+    nz, ny, nx = shape
+    kx, ky, kz = k
+    z, y, x = _grid(shape)
+    A, phi = 0.8, 0.3
+    wave = A * np.cos(2 * np.pi * (kx * x / nx + ky * y / ny + kz * z / nz) + phi)
+    e = np.array([0.6, 0.0, -0.8])
+    E = D.spectrum_shell(_field(e[:, None, None, None] * wave, rho=1.3))
+    assert E.shape == (D.shell_count(shape),)
+    K = int(round(np.sqrt(kx * kx + ky * ky + kz * kz)))
+    np.testing.assert_allclose(E[K], A * A / 4.0, rtol=1e-13)
+    assert np.all(np.abs(np.delete(E, K)) < 1e-28)
+
+
+def test_shell_spectrum_uniform_flow_and_nyquist_corner():
+    shape = (6, 8, 10)
+    E = D.spectrum_shell(_field(np.broadcast_to(np.array([0.3, -0.4, 1.2])[:, None, None, None],
+                                                (3,) + shape)))
+    np.testing.assert_allclose(E[0], 0.5 * (0.09 + 0.16 + 1.44), rtol=1e-14)
+    assert np.all(np.abs(E[1:]) < 1e-28)
+    # (-1)^(x+y+z): the corner wavevector (5, 4, 3), |k| = sqrt(50): shell 7,
+    # and <u^2> = 1/4 for amplitude 1/2 (no cosine factor at Nyquist)
+    z, y, x = _grid(shape)
+    alt = 0.5 * (-1.0) ** (x + y + z)
+    E = D.spectrum_shell(_field(np.stack([0 * alt, alt, 0 * alt])))
+    assert E.shape == (8,)
+    np.testing.assert_allclose(E[7], 0.5 * 0.25, rtol=1e-14)
+    assert np.all(np.abs(E[:7]) < 1e-28)
+
+
+def test_shell_spectrum_brute_force_dft():
+    # the definition written out: a direct triple-sum DFT per wavevector,
+    # signed wavenumbers and shells taken by integer comparisons
+    rng = np.random.default_rng(21)
+    shape = (3, 4, 6)
+    nz, ny, nx = shape
+    u = rng.normal(size=(3,) + shape)
+    rho = rng.uniform(0.5, 2.0, size=shape)
+    z, y, x = _grid(shape)
+    nb = D.shell_count(shape)
+    want = np.zeros(nb)
+    for jz in range(nz):
+        for jy in range(ny):
+            for jx in range(nx):
+                ph = np.exp(-2j * np.pi * (jx * x / nx + jy * y / ny + jz * z / nz))
+                power = sum(abs(np.sum(u[c] * ph)) ** 2 for c in range(3))
+                kvec = [j if 2 * j <= n else j - n for j, n in ((jx, nx), (jy, ny), (jz, nz))]
+                m2 = sum(q * q for q in kvec)
+                K = 0
+                while not (4 * m2 < (2 * K + 1) ** 2):
+                    K += 1
+                want[K] += power
+    want /= 2.0 * (nx * ny * nz) ** 2
+    np.testing.assert_allclose(D.spectrum_shell(_field(u, rho)), want, rtol=1e-12, atol=1e-16)
+
+
+def test_shell_spectrum_parseval_and_axis_permutation():
+    # sum_K E[K] = <|u|^2> / 2; on a cube, swapping the x and z axes (and the
+    # x and z velocity components) maps each wavevector to one of equal norm
+    rng = np.random.default_rng(22)
+    n = 12
+    u = rng.normal(size=(3, n, n, n))
+    rho = rng.uniform(0.5, 2.0, size=(n, n, n))
+    E = D.spectrum_shell(cons(rho, u[0], u[1], u[2], 1.0))
+    np.testing.assert_allclose(E.sum(), 0.5 * (u * u).sum(axis=0).mean(), rtol=1e-13)
+    ut = np.stack([u[2], u[1], u[0]]).transpose(0, 3, 2, 1)
+    Et = D.spectrum_shell(cons(rho.transpose(2, 1, 0), ut[0], ut[1], ut[2], 1.0))
+    np.testing.assert_allclose(Et, E, rtol=1e-12, atol=1e-18)
+
+
+def test_shell_spectrum_of_x_only_flow_is_the_x_spectrum():
+    # a velocity that varies along x alone has its power on (kx, 0, 0),
+    # shell |kx|: the shell spectrum equals the x-line spectrum
+    rng = np.random.default_rng(23)
+    nx = 16
+    line = rng.normal(size=(3, nx))
+    u = np.broadcast_to(line[:, None, None, :], (3, 4, 6, nx))
+    E3 = D.spectrum_shell(_field(u))
+    E1 = D.spectrum_x(_field(u))
+    np.testing.assert_allclose(E3[:nx // 2 + 1], E1, rtol=1e-12, atol=1e-18)
+    assert np.all(np.abs(E3[nx // 2 + 1:]) < 1e-28)
+
+
+def test_shell_spectrum_reads_back_the_turbulence_initial_spectrum():
+    # the turbulence initial data puts vrms^2 K^(-5/3) / sum_K' K'^(-5/3)
+    # of <|v|^2> into each shell K = 1..8 (rho = 1): half of it is E[K]
+    n, mach, gamma = 24, 0.3, 5.0 / 3.0
+    P = ic.turbulence(n, mach=mach, gamma=gamma)
+    E = D.spectrum_shell(P.U)
+    vrms2 = mach * mach * gamma
+    K = np.arange(1, 9)
+    want = 0.5 * vrms2 * K ** (-5.0 / 3.0) / np.sum(K ** (-5.0 / 3.0))
+    np.testing.assert_allclose(E[1:9], want, rtol=1e-10)
+    assert abs(E[0]) < 1e-20 and np.all(np.abs(E[9:]) < 1e-20)
