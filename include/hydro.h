@@ -322,6 +322,28 @@ int hydro_diag_profile(hydro_ctx* c, int axis, double rho_lo, double rho_hi, dou
  * stream.  Errors: HYDRO_EINVAL, HYDRO_ESTATE (batch context), HYDRO_EDEVICE. */
 int hydro_diag_spectrum(hydro_ctx* c, double* out);
 
+/* Shell kinetic-energy spectrum of a single grid (in-situ analysis, the
+ * paper's discussion of the capabilities needed at the exascale; the shells
+ * are those of the turbulence initial data's spectrum).  With u_hat_c the
+ * unnormalised three-dimensional DFT of the velocity component u_c = m_c/rho
+ * over the grid (N = nx ny nz cells, FP64) and k the signed integer
+ * wavevector of each coefficient (k_i in (-n_i/2, n_i/2]), `out` (a
+ * caller-owned DEVICE array of nshells doubles, 8-byte aligned) receives
+ *   out[K] = sum over k with round(|k|) = K of sum_c |u_hat_c(k)|^2 / (2 N^2),
+ * K = 0 .. nshells - 1, where nshells - 1 is the shell of the corner
+ * wavevector (nx/2, ny/2, nz/2) (integer halves); sum_K out[K] = <|u|^2>/2
+ * (Parseval).  Every extent must be 2^a 3^b with 1 <= n <= 1024
+ * (HYDRO_EINVAL otherwise).  `work` is a caller-owned DEVICE buffer of at
+ * least the bytes hydro_diag_spectrum3d_workspace_bytes reports (256-byte
+ * aligned; about 28 bytes per cell: the three half spectra, their power and
+ * the partial spectra); its contents are overwritten and need not be kept
+ * between calls.  Sums run in a fixed order: bitwise reproducible for a
+ * shape.  Asynchronous on the context's stream (the state and `work` must
+ * stay valid until it completes).  Errors: HYDRO_EINVAL, HYDRO_ESTATE
+ * (batch context), HYDRO_EDEVICE. */
+int hydro_diag_spectrum3d_workspace_bytes(hydro_ctx* c, size_t* bytes, int32_t* nshells);
+int hydro_diag_spectrum3d(hydro_ctx* c, void* work, size_t work_bytes, double* out);
+
 /* Operator-split reactive source: a self-contained toy network.  The
  * paper's explosion models carry nuclear networks of 10-20 nuclei without
  * rates; this chain has the same shape of work, a stiff ODE per zone.

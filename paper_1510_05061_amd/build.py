@@ -23,7 +23,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=off",
           f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
-SOURCES = ["kernels.hip", "diag.hip", "burn.hip", "amr.hip", "capi.cpp"]
+SOURCES = ["kernels.hip", "diag.hip", "spec3.hip", "burn.hip", "amr.hip", "capi.cpp"]
 
 
 def hipcc():

@@ -1620,6 +1620,38 @@ int hydro_diag_spectrum(hydro_ctx* c, double* out) {
   return HYDRO_OK;
 }
 
+int hydro_diag_spectrum3d_workspace_bytes(hydro_ctx* c, size_t* bytes, int32_t* nshells) {
+  if (!c || !bytes) return fail(HYDRO_EINVAL, "null argument");
+  if (c->batch) return fail(HYDRO_ESTATE, "the shell spectrum is defined for single grids");
+  if (!spec3_shape_ok(c->single))
+    return fail(HYDRO_EINVAL, "every extent must be 2^a 3^b, from 1 to 1024");
+  int nb = 0;
+  *bytes = spec3_workspace_bytes(c->single, &nb);
+  if (nshells) *nshells = nb;
+  return HYDRO_OK;
+}
+
+int hydro_diag_spectrum3d(hydro_ctx* c, void* work, size_t work_bytes, double* out) {
+  if (!c || !work || !out) return fail(HYDRO_EINVAL, "null argument");
+  if (c->batch) return fail(HYDRO_ESTATE, "the shell spectrum is defined for single grids");
+  if (!spec3_shape_ok(c->single))
+    return fail(HYDRO_EINVAL, "every extent must be 2^a 3^b, from 1 to 1024");
+  if (reinterpret_cast<uintptr_t>(out) & 7) return fail(HYDRO_EINVAL, "out must be 8-byte aligned");
+  if (reinterpret_cast<uintptr_t>(work) & 255)
+    return fail(HYDRO_EINVAL, "the workspace must be 256-byte aligned");
+  if (work_bytes < spec3_workspace_bytes(c->single, nullptr))
+    return fail(HYDRO_EINVAL, "workspace too small (hydro_diag_spectrum3d_workspace_bytes)");
+  LaunchSpec3 L{};
+  L.pool = c->pool;
+  L.single = c->single;
+  L.fp64 = c->fp64;
+  L.cu_count = c->cu_count;
+  L.work = work;
+  L.out = out;
+  HIP_TRY(launch_diag_spectrum3d(L, c->stream));
+  return HYDRO_OK;
+}
+
 int hydro_burn(hydro_ctx* c, void* X, size_t x_bytes, const hydro_network* net, double dt,
                int32_t nsub) {
   if (!c || !X || !net) return fail(HYDRO_EINVAL, "null argument");

@@ -17,33 +17,13 @@
 
 #include <algorithm>
 
+#include "fft.hpp"
 #include "launch.hpp"
 
 namespace hydro {
 
 constexpr int kDiagBlock = 256;
 constexpr int kDiagCells = 4;   // cells per thread in flight (loads before arithmetic)
-
-// Unsigned 32-bit division by an invariant d >= 1 with one multiply-high
-// (Granlund and Montgomery, "Division by invariant integers using
-// multiplication", PLDI 1994, the unsigned algorithm of their figure 4.1):
-// l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1, and for every n
-// q = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0) with t = mulhi(m, n).
-struct FastDiv {
-  uint32_t d, m, s1, s2;
-  __host__ __device__ FastDiv() : d(1), m(1), s1(0), s2(0) {}
-  __host__ __device__ explicit FastDiv(uint32_t div) : d(div) {
-    uint32_t l = 0;
-    while ((uint64_t(1) << l) < div) ++l;
-    m = uint32_t(((uint64_t(1) << 32) * ((uint64_t(1) << l) - div)) / div + 1);
-    s1 = l < 1 ? l : 1;
-    s2 = l > 1 ? l - 1 : 0;
-  }
-  __device__ __forceinline__ uint32_t div(uint32_t n) const {
-    const uint32_t t = __umulhi(m, n);
-    return (t + ((n - t) >> s1)) >> s2;
-  }
-};
 
 template <class T, int Q>
 __device__ __forceinline__ double diag_quantity(const T* p0, int64_t plane, int64_t o,
@@ -338,14 +318,6 @@ struct SpecArgs {
   FastDiv nsd[kSpecMaxStages];  // division by Ns
   FastDiv md[kSpecMaxStages];   // division by n / R (butterflies per complex line)
 };
-
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-// -i a
-__device__ __forceinline__ double2 cmi(double2 a) { return make_double2(a.y, -a.x); }
 
 // One butterfly of a stage: R inputs j + r step (twiddled), R-point DFT,
 // outputs at base + r Ns.

@@ -191,6 +191,22 @@ hipError_t launch_burn(const LaunchBurn& L, hipStream_t st);
 hipError_t launch_diag_pdf(const LaunchDiag& L, hipStream_t st);
 hipError_t launch_diag_profile(const LaunchDiag& L, hipStream_t st);
 hipError_t launch_diag_spectrum(const LaunchDiag& L, hipStream_t st);
+
+// Shell kinetic-energy spectrum of a single grid (spec3.hip).
+constexpr int kSpec3BinBlocks = 2048;  // binning workgroups (partial spectra)
+struct LaunchSpec3 {
+  const void* pool;
+  PatchDev single;
+  int32_t fp64;
+  int32_t cu_count;
+  void* work;   // spec3_workspace_bytes(single) bytes, 256-byte aligned
+  double* out;  // device, one value per shell
+};
+// every extent 2^a 3^b, from 1 to 1024
+bool spec3_shape_ok(const PatchDev& P);
+// workspace bytes; *nb receives the number of shells
+size_t spec3_workspace_bytes(const PatchDev& P, int* nb);
+hipError_t launch_diag_spectrum3d(const LaunchSpec3& L, hipStream_t st);
 hipError_t launch_cfl(const LaunchReduce& L, hipStream_t st);
 hipError_t launch_totals(const LaunchReduce& L, hipStream_t st);
 hipError_t launch_finish_step(DevScalars* s, hipStream_t st);

@@ -121,6 +121,9 @@ _SIGS = {
     "hydro_diag_profile": ([_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, _vp],
                            ctypes.c_int),
     "hydro_diag_spectrum": ([_vp, _vp], ctypes.c_int),
+    "hydro_diag_spectrum3d_workspace_bytes": ([_vp, ctypes.POINTER(_sz),
+                                               ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "hydro_diag_spectrum3d": ([_vp, _vp, _sz, _vp], ctypes.c_int),
     "hydro_fill_ghosts": ([_vp], ctypes.c_int),
     "hydro_amr_restrict": ([_vp, ctypes.POINTER(HydroAmrLink), ctypes.c_int32], ctypes.c_int),
     "hydro_amr_prolong": ([_vp, ctypes.POINTER(HydroAmrLink), ctypes.c_int32, ctypes.c_int],
@@ -268,6 +271,21 @@ def hydro_diag_profile(ctx, axis, rho_lo, rho_hi, out_ptr):
 def hydro_diag_spectrum(ctx, out_ptr):
     """Asynchronous; out_ptr: device float64[nx // 2 + 1]."""
     _check(lib().hydro_diag_spectrum(ctx, out_ptr), "hydro_diag_spectrum")
+
+
+def hydro_diag_spectrum3d_workspace_bytes(ctx):
+    """(workspace bytes, number of shells) of the shell spectrum."""
+    b = _sz(0)
+    nb = ctypes.c_int32(0)
+    _check(lib().hydro_diag_spectrum3d_workspace_bytes(ctx, ctypes.byref(b), ctypes.byref(nb)),
+           "hydro_diag_spectrum3d_workspace_bytes")
+    return int(b.value), int(nb.value)
+
+
+def hydro_diag_spectrum3d(ctx, work_ptr, work_bytes, out_ptr):
+    """Asynchronous; work_ptr: device workspace; out_ptr: device float64[nshells]."""
+    _check(lib().hydro_diag_spectrum3d(ctx, work_ptr, int(work_bytes), out_ptr),
+           "hydro_diag_spectrum3d")
 
 
 def hydro_burn(ctx, x_ptr, x_bytes, net, dt, nsub):
@@ -520,6 +538,24 @@ class Grid:
                               device=self.state.device)
         hydro_diag_spectrum(self.ctx, ctypes.c_void_p(out.data_ptr()))
         return out
+
+    def spectrum3d(self, out=None, work=None):
+        """Device float64 tensor of the shell spectrum (see
+        hydro_diag_spectrum3d).  `work` (a device uint8 tensor of at least
+        spectrum3d_workspace()[0] bytes) is allocated when not given."""
+        torch = _torch()
+        nbytes, nb = hydro_diag_spectrum3d_workspace_bytes(self.ctx)
+        if work is None:
+            work = torch.empty(nbytes, dtype=torch.uint8, device=self.state.device)
+        if out is None:
+            out = torch.empty(nb, dtype=torch.float64, device=self.state.device)
+        hydro_diag_spectrum3d(self.ctx, ctypes.c_void_p(work.data_ptr()), work.numel(),
+                              ctypes.c_void_p(out.data_ptr()))
+        return out
+
+    def spectrum3d_workspace(self):
+        """(bytes, shells) of the shell spectrum."""
+        return hydro_diag_spectrum3d_workspace_bytes(self.ctx)
 
     def time(self):
         return hydro_get_time(self.ctx)

@@ -227,3 +227,93 @@ def test_spectrum_of_the_768_turbulence_state():
     assert E[9:].sum() < 1e-10 * E.sum()
     assert E[1:9].min() > 0.0
     g.close()
+
+
+# ------------------------------------------------------ shell spectrum
+
+def _shell_tol(ref):
+    """Both sides transform in FP64; each coefficient carries an error of a
+    few eps log2 N of the field's norm, so every shell differs from the
+    oracle by far less than 1e-12 of the total energy (rtol covers the
+    large shells)."""
+    return dict(rtol=1e-10, atol=1e-12 * float(np.abs(ref).sum()))
+
+
+SHELL_SHAPES = [(8, 12, 16), (12, 18, 24), (36, 32, 48), (16, 16, 16), (1, 4, 8), (6, 1, 9),
+                (3, 2, 1), (9, 27, 3), (4, 2, 1024), (2, 1024, 4), (1024, 2, 3), (24, 96, 256)]
+
+
+@pytest.mark.parametrize("prec", [hydro.FP32, hydro.FP64])
+@pytest.mark.parametrize("shape", SHELL_SHAPES)
+def test_shell_spectrum_matches_oracle(prec, shape):
+    say(f"shell spectrum prec={prec} shape={shape}")
+    g, U, P = _state(shape, seed=31 + sum(shape), ng=2 if shape[2] % 2 else 0, prec=prec,
+                     special=False)
+    E = g.spectrum3d().cpu().numpy()
+    ref = D.spectrum_shell(U)
+    assert E.shape == ref.shape == (D.shell_count(shape),)
+    np.testing.assert_allclose(E, ref, **_shell_tol(ref))
+    nbytes, nb = g.spectrum3d_workspace()
+    assert nb == len(ref)
+    # fixed order: a second call into a used workspace gives the same bits
+    work = torch().full((nbytes,), 0xA5, dtype=torch().uint8, device="cuda:0")
+    np.testing.assert_array_equal(E, g.spectrum3d(work=work).cpu().numpy())
+    np.testing.assert_array_equal(E, g.spectrum3d(work=work).cpu().numpy())
+    g.close()
+
+
+def test_shell_spectrum_single_mode_and_errors():
+    shape = (12, 16, 24)
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    A, k = 0.4, (5, -3, 2)
+    wave = A * np.cos(2 * np.pi * (k[0] * x / nx + k[1] * y / ny + k[2] * z / nz))
+    rho = np.full(shape, 1.7)
+    U = np.stack([rho, 0 * rho, rho * wave, 0 * rho, 2.5 + 0.5 * rho * wave * wave])
+    dev = torch().from_numpy(U.copy()).to("cuda:0")
+    g = hydro.Grid(dev, (1.0 / nx,) * 3, 1.4, flags=hydro.FLAG_NO_TUNE)
+    say("shell spectrum single mode")
+    E = g.spectrum3d().cpu().numpy()
+    K = int(round(np.sqrt(25 + 9 + 4)))
+    np.testing.assert_allclose(E[K], A * A / 4.0, rtol=1e-13)
+    assert np.abs(np.delete(E, K)).max() < 1e-15 * E[K]
+    nbytes, nb = g.spectrum3d_workspace()
+    out = torch().empty(nb, dtype=torch().float64, device="cuda:0")
+    work = torch().empty(nbytes, dtype=torch().uint8, device="cuda:0")
+    wp, op = ctypes.c_void_p(work.data_ptr()), ctypes.c_void_p(out.data_ptr())
+    for args in ((wp, nbytes - 1, op), (ctypes.c_void_p(work.data_ptr() + 8), nbytes - 8, op),
+                 (wp, nbytes, ctypes.c_void_p(out.data_ptr() + 4)), (None, nbytes, op)):
+        with pytest.raises(hydro.HydroError) as e:
+            hydro.hydro_diag_spectrum3d(g.ctx, *args)
+        assert e.value.status == hydro.HYDRO_EINVAL
+    g.close()
+    # an extent that is not 2^a 3^b
+    P = ic.smooth_random((8, 10, 8), 3)
+    g = hydro.Grid(torch().from_numpy(P.U.copy()).to("cuda:0"), P.dx, P.gamma,
+                   flags=hydro.FLAG_NO_TUNE)
+    with pytest.raises(hydro.HydroError) as e:
+        g.spectrum3d_workspace()
+    assert e.value.status == hydro.HYDRO_EINVAL
+    g.close()
+
+
+@pytest.mark.parametrize("prec", [hydro.FP32, hydro.FP64])
+def test_shell_spectrum_reads_back_the_turbulence_initial_spectrum(prec):
+    # closed form of the initial data (rho = 1, modes only on shells 1..8):
+    # E[K] = vrms^2 K^(-5/3) / (2 sum_K' K'^(-5/3)); in FP32 the state's
+    # rounding (relative 6e-8 per value) spreads ~1e-15 of the energy into
+    # every other shell
+    n = 96
+    P = ic.turbulence(n)
+    dt = np.float64 if prec == hydro.FP64 else np.float32
+    dev = torch().from_numpy(P.U.astype(dt)).to("cuda:0")
+    g = hydro.Grid(dev, P.dx, P.gamma, flags=hydro.FLAG_NO_TUNE)
+    say(f"shell spectrum turbulence {n}^3 prec={prec}")
+    E = g.spectrum3d().cpu().numpy()
+    vrms2 = 0.3 * 0.3 * (5.0 / 3.0)
+    K = np.arange(1, 9)
+    want = 0.5 * vrms2 * K ** (-5.0 / 3.0) / np.sum(K ** (-5.0 / 3.0))
+    np.testing.assert_allclose(E[1:9], want, rtol=1e-10 if prec == hydro.FP64 else 1e-6)
+    rest = np.concatenate([E[:1], E[9:]])
+    assert rest.max() < (1e-25 if prec == hydro.FP64 else 1e-12) * E.sum()
+    g.close()

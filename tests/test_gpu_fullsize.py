@@ -269,6 +269,35 @@ def test_turbulence768_fp64_tuned_and_wide_x_lane_runs(turb768):
     t.cuda.empty_cache()
 
 
+
+@pytest.mark.parametrize("prec", [hydro.FP64, hydro.FP32])
+def test_turbulence768_shell_spectrum(turb768, prec):
+    """The shell spectrum at full size: the initial data's closed form
+    (rho = 1, every shell K = 1..8 holding vrms^2 K^(-5/3) / sum_K' K'^(-5/3)
+    of <|v|^2>, nothing elsewhere) and Parseval against <|u|^2> / 2 reduced
+    by torch from the device state."""
+    P = turb768
+    t = torch()
+    dt = np.float64 if prec == hydro.FP64 else np.float32
+    dev = t.from_numpy(P.U.astype(dt, copy=False)).to("cuda:0")
+    g = hydro.Grid(dev, P.dx, P.gamma, P.cfl, P.bc, P.grav, flags=hydro.FLAG_NO_TUNE)
+    say(f"turbulence 768 shell spectrum prec={prec}")
+    E = g.spectrum3d().cpu().numpy()
+    assert E.shape == (666,)
+    r = dev[0].double()
+    half_u2 = 0.5 * sum(((dev[c].double() / r) ** 2).mean() for c in (1, 2, 3)).item()
+    del r
+    np.testing.assert_allclose(E.sum(), half_u2, rtol=1e-12 if prec == hydro.FP64 else 1e-10)
+    vrms2 = 0.3 * 0.3 * (5.0 / 3.0)
+    K = np.arange(1, 9)
+    want = 0.5 * vrms2 * K ** (-5.0 / 3.0) / np.sum(K ** (-5.0 / 3.0))
+    np.testing.assert_allclose(E[1:9], want, rtol=1e-10 if prec == hydro.FP64 else 1e-6)
+    rest = np.concatenate([E[:1], E[9:]])
+    assert rest.max() < (1e-20 if prec == hydro.FP64 else 1e-12) * E.sum()
+    g.close()
+    del dev
+    t.cuda.empty_cache()
+
 def test_batch4096_fp32_sampled_patches():
     say("batch 4096 fp32")
     specs = ic.batch_specs(4096, seed=3)
