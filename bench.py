@@ -458,7 +458,39 @@ def diag_timing(obj, W, name, torch, hydro, reps=10):
             es.update({"kmax": len(E) - 1, "total": float(E.sum()),
                        "E_k1_to_16": [float(v) for v in E[1:17]]})
             res["spectrum_x"] = es
+        if all(_fft_len_ok(n) for n in W["grid"]):
+            res["spectrum_shell"] = shell_spectrum_timing(obj, W, zones, timed, torch)
     return res
+
+
+def _fft_len_ok(n):
+    m = n
+    for f in (2, 3):
+        while m % f == 0:
+            m //= f
+    return m == 1 and 1 <= n <= 1024
+
+
+def shell_spectrum_timing(obj, W, zones, timed, torch):
+    """The shell kinetic-energy spectrum (hydro_diag_spectrum3d): four
+    passes, whose algorithmic HBM bytes are the state's density and momentum
+    (4 words per zone), the three half spectra (nx/2 + 1 complex FP64 values
+    per x-line and component) written, read and written, and read, and
+    their power (one FP64 value per half-spectrum point) written and read."""
+    nx, ny, nz = W["grid"]
+    nbytes, nb = obj.spectrum3d_workspace()
+    work = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    out = torch.empty(nb, dtype=torch.float64, device="cuda:0")
+    ms = timed(lambda: obj.spectrum3d(out=out, work=work))
+    esz = obj.state.element_size()
+    half = (nx // 2 + 1) * ny * nz
+    alg = zones * 4 * esz + half * (3 * 16 * 4 + 8 * 2)
+    gbs = alg / (ms * 1e-3) / 1e9
+    E = out.cpu().numpy()
+    del work
+    return {"mean_ms": ms, "bytes": alg, "gbs": gbs, "frac": gbs / HBM_PEAK_GBS,
+            "workspace_bytes": nbytes, "shells": nb, "total": float(E.sum()),
+            "E_K1_to_16": [float(v) for v in E[1:17]]}
 
 
 def per_patch_loop(W, prec, npatch, steps, torch, hydro):
