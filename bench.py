@@ -20,13 +20,14 @@ Prints ONE JSON line.  Fields beyond the driver's contract:
                  on the stream it runs on (hydro_profile_step), against the
                  8 TB/s HBM peak; `traffic` from rocprofv3 counters when the
                  committed counter summary matches the current kernel source.
-                 When the dominant kernel is the fused x+y launch of a batch
-                 (two sweeps per HBM pass, arithmetic-bound) it is reported
-                 as bound "alu": algorithmic flops over its duration against
-                 the FP32 vector peak without packed FP32 (78.6 TFLOP/s);
+                 When the dominant kernel is a fused x+y launch (batch
+                 planes or single-grid windows: two sweeps per HBM pass,
+                 arithmetic-bound) it is reported as bound "alu":
+                 algorithmic flops over its duration against the FP32 vector
+                 peak without packed FP32 (78.6 TFLOP/s);
   step_roofline  the whole step against the same peak (120 B per FP32
                  zone-update, the three-sweep method's algorithmic bytes);
-                 when a batch step fuses the x and y sweeps it moves 80 B per
+                 when a step fuses the x and y sweeps it moves 80 B per
                  zone-update, given as hbm_bytes_per_zone_update and
                  hbm_achieved;
   fp64           the FP64 path on the same workload and the FP32 speedup;
@@ -181,6 +182,9 @@ def build_obj(W, prec, args, torch, hydro, flags=None):
     dtype = np.float32 if prec == hydro.FP32 else np.float64
     if flags is None:
         flags = hydro.FLAG_NO_TUNE if args.no_tune else 0
+        if W["kind"] == "grid":
+            # let the tuner keep the fused x+y step where it is faster (FP32)
+            flags |= hydro.FLAG_FUSE_XY
     if W["kind"] == "grid":
         P = W["P"]
         U = torch.from_numpy(np.ascontiguousarray(P.U.astype(dtype, copy=False))).to("cuda:0")
@@ -847,8 +851,10 @@ def main():
     names = {0: (f"sweep_xm_kernel<float,{xv}>" if "m=1" in xpart
                  else f"sweep_x_kernel<float,{xv}>"),
              1: "sweep_col_kernel<float,1>", 2: "sweep_col_kernel<float,2>"}
-    if fused:   # one launch does the x and y sweeps of every patch z-plane
+    if fused and pers:   # one launch does the x and y sweeps of every patch z-plane
         names[0] = "sweep_plane_kernel<float> (x and y sweeps fused)"
+    elif fused:          # one launch does the x and y sweeps, 64 x 64 windows per z-plane
+        names[0] = "sweep_window_kernel<float> (x and y sweeps fused)"
     kname = names[dom] + (" (persistent)" if pers else "")
     hbm_per_zu = 80 if fused else 120
     traffic = counter_traffic(args.workload, names[dom].split(" (")[0], "fp32")

@@ -232,6 +232,8 @@ std::string cfg_text(const Config& cf) {
   if (cf.batch_blocks) {
     o << ";p:g=" << cf.batch_blocks << ",d=" << cf.batch_dyn << ",f=" << cf.batch_fuse;
     if (cf.batch_fuse) o << ";w:v=" << cf.plane.v << ",b=" << cf.plane.block;
+  } else if (cf.batch_fuse) {
+    o << ";p:f=1;w:v=" << cf.plane.v << ",b=" << cf.plane.block;  // single grid, fused x+y
   }
   return o.str();
 }
@@ -367,6 +369,11 @@ struct hydro_ctx {
   int32_t npatch = 0;
   std::vector<PatchDev> patches;
   PatchDev* d_patches = nullptr;
+  // single grid, fused x+y step (HYDRO_FLAG_FUSE_XY): the windows of a
+  // z-plane and a second buffer laid out like the state (null: not eligible)
+  WinDev* d_wins = nullptr;
+  int32_t nwin = 0;
+  void* shadow = nullptr;
   WorkItem* d_items[4] = {nullptr, nullptr, nullptr, nullptr};  // x, y, z, planes
   int32_t nitems[4] = {0, 0, 0, 0};
   int64_t max_patch_cells = 0;
@@ -495,6 +502,34 @@ LaunchSweep plane_launch(const hydro_ctx* c, bool xfirst, int do_cfl) {
   return L;
 }
 
+// The fused x+y step of a single grid applies (see fuse_eligible) with a
+// window kernel of V = 1 or 2 cells per lane.
+bool win_ok(const hydro_ctx* c, const Config& cf) {
+  if (c->batch || !c->shadow || c->fp64) return false;
+  const int v = cf.plane.v;
+  if (v != 1 && v != 2) return false;
+  return cf.plane.block >= 64 && cf.plane.block <= kMaxBlock && cf.plane.block % 64 == 0;
+}
+
+// The fused x and y sweeps of a single grid, window by window, from src to
+// dst (x first on even steps): two resident workgroups per CU take the
+// windows of every z-plane round robin.
+LaunchSweep window_launch(const hydro_ctx* c, bool xfirst, int do_cfl, void* src, void* dst) {
+  LaunchSweep L = sweep_launch(c, 0, do_cfl);
+  L.plane = xfirst ? kWinXY : kWinYX;
+  L.cfg = c->cfg.plane;
+  L.pool = src;
+  L.dst = dst;
+  L.wins = c->d_wins;
+  L.nwin = c->nwin;
+  L.nitems = c->nwin * c->single.n[2];
+  L.nblocks = 2 * std::max(1, c->cu_count);
+  L.bc_lo_y = c->desc.bc[2];
+  L.bc_hi_y = c->desc.bc[3];
+  L.grav_y = c->desc.grav[1];
+  return L;
+}
+
 // One launch of a step and the profile slot it reports in (0: x, or x and y
 // fused; 1: y; 2: z).
 struct StepOp {
@@ -520,6 +555,26 @@ std::vector<StepOp> step_ops(const hydro_ctx* c, int parity) {
     seq.push_back(ax);
   }
   std::vector<StepOp> ops;
+  if (!c->batch && c->cfg.batch_fuse && win_ok(c, c->cfg)) {
+    // single grid, x and y fused: x+y from the state into the second buffer
+    // and z back (even steps), or z into it and y+x back (odd steps)
+    void* st = c->pool;
+    void* sh = c->shadow;
+    if (parity == 0) {
+      ops.push_back(StepOp{window_launch(c, true, 0, st, sh), 0});
+      LaunchSweep Z = sweep_launch(c, 2, 1);
+      Z.pool = sh;
+      Z.dst = st;
+      ops.push_back(StepOp{Z, 2});
+    } else {
+      LaunchSweep Z = sweep_launch(c, 2, 0);
+      Z.dst = sh;
+      ops.push_back(StepOp{Z, 2});
+      ops.push_back(StepOp{window_launch(c, false, 1, sh, st), 0});
+    }
+    ops.back().L.tpart = c->partials;
+    return ops;
+  }
   for (size_t i = 0; i < seq.size(); ++i) {
     const int cfl = i + 1 == seq.size() ? 1 : 0;
     if (seq[i] < 0)
@@ -860,6 +915,48 @@ int choose_config(hydro_ctx* c) {
     cache[key] = part;
     dirty = true;
   }
+  if (!c->batch && c->shadow) {
+    // single grid with the fused x+y step available: keep it when whole
+    // steps (an even and an odd one, as they will run) are faster than with
+    // the separate sweeps
+    const std::string key = shape_key(c, 4);
+    auto it = cache.find(key);
+    Config tmp = c->cfg;
+    if (it != cache.end() && parse_cfg(it->second, tmp) && (!tmp.batch_fuse || win_ok(c, tmp))) {
+      c->cfg.batch_fuse = tmp.batch_fuse;
+      c->cfg.plane = tmp.plane;
+    } else {
+      if (launch_timing_begin(c->scal, c->stream) != hipSuccess)
+        return fail(HYDRO_EDEVICE, "timing setup failed");
+      std::vector<SweepCfg> wins;  // candidate i > 0: window configuration i - 1
+      for (int v : {1, 2})
+        for (int b : {256, 512}) {
+          Config trial = c->cfg;
+          trial.plane.v = v;
+          trial.plane.block = b;
+          if (win_ok(c, trial)) wins.push_back(trial.plane);
+        }
+      const SweepCfg keep = c->cfg.plane;
+      int bi = 0;
+      int rc = fastest_of(
+          "fuse", int(wins.size()) + 1, 3,
+          [&](int i) {
+            c->cfg.batch_fuse = i > 0 ? 1 : 0;
+            if (i > 0) c->cfg.plane = wins[size_t(i - 1)];
+            return HYDRO_OK;
+          },
+          [&](double* ms) { return time_steps(c, 2, ms); }, &bi);
+      if (launch_timing_end(c->scal, c->stream) != hipSuccess)
+        return fail(HYDRO_EDEVICE, "timing teardown failed");
+      if (rc) return rc;
+      c->cfg.plane = bi > 0 ? wins[size_t(bi - 1)] : keep;
+      c->cfg.batch_fuse = bi > 0 ? 1 : 0;
+      std::ostringstream o;
+      o << "p:f=" << c->cfg.batch_fuse << ";w:v=" << c->cfg.plane.v << ",b=" << c->cfg.plane.block;
+      cache[key] = o.str();
+      dirty = true;
+    }
+  }
   if (c->batch) {
     // fuse the x and y sweeps per patch z-plane when that is faster than the
     // two sweeps: the fastest valid plane configuration (both Strang orders
@@ -998,8 +1095,16 @@ int read_scalars(hydro_ctx* c, DevScalars* out) {
 // Totals partials of a single grid: the most workgroups any valid
 // configuration launches for a sweep (x: one pencil per workgroup; y, z: 64
 // columns per tile), and at least the standalone reduction's chunks.
+// Windows of the fused x+y step along an axis of n cells: written chunks of
+// kWinEdge - 2 kWinHalo cells.
+int32_t win_count(int32_t n) {
+  const int w = kWinEdge - 2 * kWinHalo;
+  return n >= kWinEdge ? (n + w - 1) / w : 0;
+}
+
 int64_t grid_parts(const int32_t n[3]) {
   int64_t m = kMaxChunks;
+  m = std::max<int64_t>(m, int64_t(win_count(n[0])) * win_count(n[1]) * n[2]);
   if (n[0] > 1) m = std::max<int64_t>(m, int64_t(n[1]) * n[2]);
   if (n[1] > 1) m = std::max<int64_t>(m, (int64_t(n[0]) * n[2] + 63) / 64);
   if (n[2] > 1) m = std::max<int64_t>(m, (int64_t(n[0]) * n[1] + 63) / 64);
@@ -1017,6 +1122,57 @@ size_t grid_workspace_bytes(const int32_t n[3]) {
   const int64_t nmax = std::max(n[0], std::max(n[1], n[2]));
   return kScalarBytes + grid_totals_bytes(n) +
          align_up(size_t(nmax) * kProfileChunksX * 5 * sizeof(double), 256);
+}
+
+// The fused x+y step of a single grid applies to FP32 grids with x and y
+// extents even and >= kWinEdge and an active z axis, whose rows allow runs
+// of two cells (even strides).
+bool fuse_eligible(const hydro_desc& d) {
+  if (!(d.flags & HYDRO_FLAG_FUSE_XY) || d.precision != HYDRO_FP32) return false;
+  if (d.nx < kWinEdge || d.ny < kWinEdge || d.nx % 2 || d.ny % 2 || d.nz < 2) return false;
+  int32_t n[3] = {d.nx, d.ny, d.nz};
+  double dx[3] = {d.dx, d.dy, d.dz};
+  const PatchDev P = make_patch(n, d.ng, dx, 0);
+  return P.base0 % 2 == 0 && P.sy % 2 == 0 && P.sz % 2 == 0 && P.plane % 2 == 0;
+}
+
+// Workspace of the fused step after the grid's own: the window table, then
+// the second state buffer.
+size_t fuse_bytes(const hydro_desc& d) {
+  if (!fuse_eligible(d)) return 0;
+  int32_t n[3] = {d.nx, d.ny, d.nz};
+  double dx[3] = {d.dx, d.dy, d.dz};
+  const PatchDev P = make_patch(n, d.ng, dx, 0);
+  const size_t nwin = size_t(win_count(d.nx)) * win_count(d.ny);
+  return align_up(nwin * sizeof(WinDev), 256) + align_up(size_t(P.plane) * 5 * 4, 256);
+}
+
+// The windows of a z-plane: along each axis, written chunks [w i, w (i+1))
+// (the last one shorter), w = kWinEdge - 2 kWinHalo; a window starts
+// kWinHalo cells before its chunk, wrapped on a periodic axis, or clamped
+// into the domain on a non-periodic one, where its pencil ends at a domain
+// edge take the boundary condition (elsewhere the ends are discarded).
+std::vector<WinDev> build_windows(const int32_t n[3], const int32_t bc[6]) {
+  struct Span { int32_t start, lo, hi, blo, bhi; };
+  auto spans = [&](int axis) {
+    std::vector<Span> out;
+    const int N = n[axis], w = kWinEdge - 2 * kWinHalo;
+    const bool per = bc[2 * axis] == HYDRO_BC_PERIODIC;
+    for (int o = 0; o < N; o += w) {
+      const int e = std::min(N, o + w);
+      const int start = per ? o - kWinHalo : std::max(0, std::min(o - kWinHalo, N - kWinEdge));
+      Span sp{start, o - start, e - start, HYDRO_BC_PERIODIC, HYDRO_BC_PERIODIC};
+      if (!per && start == 0) sp.blo = bc[2 * axis];
+      if (!per && start + kWinEdge == N) sp.bhi = bc[2 * axis + 1];
+      out.push_back(sp);
+    }
+    return out;
+  };
+  std::vector<WinDev> wins;
+  for (const Span& y : spans(1))
+    for (const Span& x : spans(0))
+      wins.push_back(WinDev{x.start, y.start, x.lo, x.hi, y.lo, y.hi, x.blo, x.bhi, y.blo, y.bhi});
+  return wins;
 }
 
 // layout of a batch workspace
@@ -1137,7 +1293,7 @@ int hydro_workspace_bytes(const hydro_desc* d, size_t* bytes) {
   double dx[3] = {d->dx, d->dy, d->dz};
   rc = check_extent(n, d->ng, dx);
   if (rc) return rc;
-  *bytes = grid_workspace_bytes(n);
+  *bytes = grid_workspace_bytes(n) + fuse_bytes(*d);
   return HYDRO_OK;
 }
 
@@ -1182,6 +1338,19 @@ int hydro_init(const hydro_desc* d, void* state, size_t state_bytes, void* works
   if (c->cfg.ax[0].v == 0 && c->active[0]) {
     delete c;
     return fail(HYDRO_EINVAL, "no valid x-sweep configuration for this width");
+  }
+  if (fuse_eligible(*d)) {
+    const std::vector<WinDev> wins = build_windows(n, d->bc);
+    char* f = c->ws + grid_workspace_bytes(n);
+    c->d_wins = reinterpret_cast<WinDev*>(f);
+    c->nwin = int32_t(wins.size());
+    c->shadow = f + align_up(wins.size() * sizeof(WinDev), 256);
+    if (hipMemcpyAsync(c->d_wins, wins.data(), wins.size() * sizeof(WinDev),
+                       hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+      delete c;
+      return fail(HYDRO_EDEVICE, "window table upload failed");
+    }
   }
   rc = common_init(c);
   if (rc) {
@@ -1523,6 +1692,9 @@ int hydro_totals(hydro_ctx* c, double out[6]) {
       LaunchSweep L = ops.back().L;
       L.do_cfl = 0;
       L.totals_only = 1;
+      // the state itself (a fused step's last launch reads the second buffer)
+      L.pool = c->pool;
+      if (L.dst) L.dst = c->pool;
       HIP_TRY(launch_sweep(L, c->stream));
       HIP_TRY(launch_totals_finish(c->partials, sweep_parts(L), c->tslice, c->scal, 0,
                                    c->stream));
@@ -2143,8 +2315,11 @@ int hydro_set_config(hydro_ctx* c, const char* text) {
     if (c->active[a] && !col_cfg_ok(cf.ax[a])) return fail(HYDRO_EINVAL, "invalid column config");
   if (c->batch && (cf.batch_blocks < 1 || cf.batch_blocks > 65536))
     return fail(HYDRO_EINVAL, "invalid persistent grid size");
-  if (cf.batch_fuse && !plane_ok(c, cf))
+  if (cf.batch_fuse && c->batch && !plane_ok(c, cf))
     return fail(HYDRO_EINVAL, "fused plane sweeps do not apply to these patches");
+  if (cf.batch_fuse && !c->batch && !win_ok(c, cf))
+    return fail(HYDRO_EINVAL, "the fused x+y step does not apply (HYDRO_FLAG_FUSE_XY, FP32, "
+                              "even x and y extents >= 64, active z; w:v=1 or 2)");
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->cfg = cf;
   if (c->batch) {

@@ -52,6 +52,9 @@ struct SweepArgs {
   int32_t tonly;             // totals of the current state: dt = 0, no stores
   const double* pdt;         // persistent: dt per patch (null: scal->dt)
   unsigned long long* psmax; // persistent: CFL maximum per patch
+  T* dst;                    // out-of-place result (null: pool, in place)
+  const WinDev* wins;        // window sweeps: the windows of a z-plane
+  int32_t nwin;
 };
 
 // plane indices of (normal, transverse 1, transverse 2) momenta per axis
@@ -1182,38 +1185,117 @@ __device__ __forceinline__ void copy_run(T* dst, const T* src) {
     *reinterpret_cast<vec*>(dst + h * H) = *reinterpret_cast<const vec*>(src + h * H);
 }
 
-// Plane z of patch P between the pool and LDS (LOAD: pool -> LDS).  LDS row
-// r holds variable r mod 5 of y = r / 5.
-template <class T, int V, bool LOAD>
-__device__ void plane_copy(const SweepArgs<T>& a, const PatchDev& P, int z, T* lds) {
-  const int nx = P.n[0], ny = P.n[1];
-  const int nq = nx / V;   // runs per row (<= 64)
+// A row run: V consecutive elements of each of the five variables from g
+// (variable 0 at g, variable v at g + v plane), rotated into the x frame,
+// between registers and memory.
+template <class T, int V, bool WRITE>
+__device__ __forceinline__ void row_run(T* g, int64_t plane, Cons<T> (&U)[V]) {
+  T* p[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) p[v] = g + int64_t(v) * plane;
+  T r[V], mn[V], mt1[V], mt2[V], e[V];
+  if (WRITE) {
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+      r[c] = U[c].r; mn[c] = U[c].mn; mt1[c] = U[c].mt1; mt2[c] = U[c].mt2; e[c] = U[c].e;
+    }
+    copy_run<T, V>(p[0], r); copy_run<T, V>(p[1], mn); copy_run<T, V>(p[2], mt1);
+    copy_run<T, V>(p[3], mt2); copy_run<T, V>(p[4], e);
+  } else {
+    copy_run<T, V>(r, p[0]); copy_run<T, V>(mn, p[1]); copy_run<T, V>(mt1, p[2]);
+    copy_run<T, V>(mt2, p[3]); copy_run<T, V>(e, p[4]);
+#pragma unroll
+    for (int c = 0; c < V; ++c) U[c] = Cons<T>{r[c], mn[c], mt1[c], mt2[c], e[c]};
+  }
+}
+
+// Where the pencils of a fused plane sweep live in memory, as the plane
+// functions below see them: a rectangle of n(0) x n(1) cells of one z-plane
+// whose part [lo(0), hi(0)) x [lo(1), hi(1)) is written.  at(base, x, y)
+// is cell (x, y) of variable 0 in a buffer laid out like the state;
+// gx, gy give a cell's grid coordinates (totals).
+//  * PatchPlane: the whole z-plane of a batch patch, read and written in
+//    place, with the launch's boundary conditions at the pencil ends.
+//  * WindowPlane: a window of a single grid's z-plane (WinDev), read from
+//    the pool and written to a.dst, wrapped around periodic axes.
+template <class T>
+struct PatchPlane {
+  const SweepArgs<T>& a;
+  const PatchDev& P;
+  int z;
+  __device__ int n(int axis) const { return P.n[axis]; }
+  __device__ int bc_lo(int axis) const { return axis == 0 ? a.bc_lo : a.bc_lo_y; }
+  __device__ int bc_hi(int axis) const { return axis == 0 ? a.bc_hi : a.bc_hi_y; }
+  __device__ int lo(int) const { return 0; }
+  __device__ int hi(int axis) const { return P.n[axis]; }
+  __device__ int gx(int x) const { return x; }
+  __device__ int gy(int y) const { return y; }
+  __device__ T* src() const { return a.pool; }
+  __device__ T* dst() const { return a.pool; }
+  __device__ int64_t plane() const { return P.plane; }
+  __device__ T* at(T* base, int x, int y) const {
+    return base + P.base0 + int64_t(z) * P.sz + int64_t(y) * P.sy + x;
+  }
+};
+
+template <class T>
+struct WindowPlane {
+  const SweepArgs<T>& a;
+  const PatchDev& G;
+  const WinDev& w;
+  int z;
+  __device__ static int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+  __device__ int n(int) const { return kWinEdge; }
+  __device__ int bc_lo(int axis) const { return axis == 0 ? w.bx_lo : w.by_lo; }
+  __device__ int bc_hi(int axis) const { return axis == 0 ? w.bx_hi : w.by_hi; }
+  __device__ int lo(int axis) const { return axis == 0 ? w.ox0 : w.oy0; }
+  __device__ int hi(int axis) const { return axis == 0 ? w.ox1 : w.oy1; }
+  __device__ int gx(int x) const { return wrap(w.x0 + x, G.n[0]); }
+  __device__ int gy(int y) const { return wrap(w.y0 + y, G.n[1]); }
+  __device__ T* src() const { return a.pool; }
+  __device__ T* dst() const { return a.dst; }
+  __device__ int64_t plane() const { return G.plane; }
+  __device__ T* at(T* base, int x, int y) const {
+    return base + G.base0 + int64_t(z) * G.sz + int64_t(gy(y)) * G.sy + gx(x);
+  }
+};
+
+// The plane between memory and LDS (LOAD: every cell from m.src(), else the
+// written part to m.dst()).  LDS row r holds variable r mod 5 of y = r / 5.
+template <class T, int V, bool LOAD, class M>
+__device__ void plane_copy(const M& m, T* lds) {
+  const int nx = m.n(0), ny = m.n(1);
+  const int nq = nx / V;    // runs per row (<= 64)
   const int rpw = 64 / nq;  // rows per wave
   const int l = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int r = l / nq, q = l - r * nq;
   if (r >= rpw) return;
-  T* g = a.pool + P.base0 + int64_t(z) * P.sz + q * V;
-  const int rows = 5 * ny, step = nw * rpw;
-  auto gaddr = [&](int row) {
-    const int y = row / 5, v = row - 5 * y;
-    return g + int64_t(v) * P.plane + int64_t(y) * P.sy;
-  };
+  const int64_t pl = m.plane();
+  const int step = nw * rpw;
   auto laddr = [&](int row) { return lds + row * kPlanePitch + plane_col<V>(q * V, row / 5); };
   if (LOAD) {
+    T* base = m.src();
+    const int rows = 5 * ny;
     // B runs in flight per lane before the first LDS write
     constexpr int B = int(128 / (V * sizeof(T))) < 8 ? int(128 / (V * sizeof(T))) : 8;
     for (int row0 = wave * rpw + r; row0 < rows; row0 += B * step) {
       T buf[B][V];
 #pragma unroll
-      for (int b = 0; b < B; ++b)
-        if (row0 + b * step < rows) copy_run<T, V>(buf[b], gaddr(row0 + b * step));
+      for (int b = 0; b < B; ++b) {
+        const int row = row0 + b * step, y = row / 5;
+        if (row < rows) copy_run<T, V>(buf[b], m.at(base, q * V, y) + int64_t(row - 5 * y) * pl);
+      }
 #pragma unroll
       for (int b = 0; b < B; ++b)
         if (row0 + b * step < rows) copy_run<T, V>(laddr(row0 + b * step), buf[b]);
     }
   } else {
-    for (int row = wave * rpw + r; row < rows; row += step)
-      copy_run<T, V>(gaddr(row), laddr(row));
+    T* base = m.dst();
+    if (q * V < m.lo(0) || q * V >= m.hi(0)) return;
+    for (int row = 5 * m.lo(1) + wave * rpw + r; row < 5 * m.hi(1); row += step) {
+      const int y = row / 5;
+      copy_run<T, V>(m.at(base, q * V, y) + int64_t(row - 5 * y) * pl, laddr(row));
+    }
   }
 }
 
@@ -1239,44 +1321,20 @@ __device__ __forceinline__ void plane_run(T* lds, int x0, int y0, Cons<T> (&U)[V
   }
 }
 
-// A row run (V cells from (x0, y) of plane z, rotated into the x frame)
-// between registers and the pool.
-template <class T, int V, bool WRITE>
-__device__ __forceinline__ void pool_run(const SweepArgs<T>& a, const PatchDev& P, int z, int x0,
-                                         int y, Cons<T> (&U)[V]) {
-  T* g = a.pool + P.base0 + int64_t(z) * P.sz + int64_t(y) * P.sy + x0;
-  T* p[5];
-#pragma unroll
-  for (int v = 0; v < 5; ++v) p[v] = g + int64_t(v) * P.plane;
-  T r[V], mn[V], mt1[V], mt2[V], e[V];
-  if (WRITE) {
-#pragma unroll
-    for (int c = 0; c < V; ++c) {
-      r[c] = U[c].r; mn[c] = U[c].mn; mt1[c] = U[c].mt1; mt2[c] = U[c].mt2; e[c] = U[c].e;
-    }
-    copy_run<T, V>(p[0], r); copy_run<T, V>(p[1], mn); copy_run<T, V>(p[2], mt1);
-    copy_run<T, V>(p[3], mt2); copy_run<T, V>(p[4], e);
-  } else {
-    copy_run<T, V>(r, p[0]); copy_run<T, V>(mn, p[1]); copy_run<T, V>(mt1, p[2]);
-    copy_run<T, V>(mt2, p[3]); copy_run<T, V>(e, p[4]);
-#pragma unroll
-    for (int c = 0; c < V; ++c) U[c] = Cons<T>{r[c], mn[c], mt1[c], mt2[c], e[c]};
-  }
-}
-
-// One sweep along AXIS (0: x, 1: y) of the plane.  Pencils of n cells take
-// n/V lanes; a wave holds 64/(n/V) pencils, laid out so that the lanes of
-// equal place in their pencils sit together (for AXIS 1 they then read
-// consecutive x).  The input comes from LDS, or for the x sweep of an
-// x-first step straight from the pool (GSRC); the result goes to LDS, or
-// for the x sweep of a y-first step straight to the pool (GDST): a row run
-// is a coalesced vector access, so those two sweeps skip a copy through LDS.
-template <class T, int V, int AXIS, bool GSRC, bool GDST, bool TOT = false>
-__device__ void plane_sweep(const SweepArgs<T>& a, const PatchDev& P, int z, T* lds,
-                            bool do_cfl, double dt, T& smax, bool& bad, TotR* tot = nullptr) {
-  const int nx = P.n[0], ny = P.n[1];
-  const int n = AXIS == 0 ? nx : ny;      // pencil length
-  const int m = AXIS == 0 ? ny : nx;      // pencils
+// One sweep along AXIS (0: x, 1: y) of the pencils [p0, p1) of the plane
+// (rows for AXIS 0, columns for AXIS 1).  Pencils of n cells take n/V
+// lanes; a wave holds 64/(n/V) pencils, laid out so that the lanes of equal
+// place in their pencils sit together (for AXIS 1 they then read consecutive
+// x).  The input comes from LDS, or for the x sweep of an x-first step
+// straight from memory (GSRC); the result goes to LDS, or for the x sweep of
+// a y-first step straight to memory (GDST, the written part only): a row
+// run is a coalesced vector access, so those two sweeps skip a copy through
+// LDS.  Only runs in the written part fold the CFL maximum and the totals.
+template <class T, int V, int AXIS, bool GSRC, bool GDST, bool TOT = false, class M>
+__device__ void plane_sweep(const SweepArgs<T>& a, const M& m, const PatchDev& P, int p0, int p1,
+                            T* lds, bool do_cfl, double dt, T& smax, bool& bad,
+                            TotR* tot = nullptr) {
+  const int n = m.n(AXIS);                // pencil length
   const int LPP = n / V, ppw = 64 / LPP;  // lanes per pencil, pencils per wave
   const int l = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int gl = l / ppw, col = l - gl * ppw, last = LPP - 1;
@@ -1285,14 +1343,17 @@ __device__ void plane_sweep(const SweepArgs<T>& a, const PatchDev& P, int z, T* 
   const SweepConst<T> k = make_const<T>(dt, P.dx[AXIS], a.gamma, AXIS == 0 ? a.grav : a.grav_y);
   T id[3];
   inv_widths<T>(P, id);
-  const int blo = AXIS == 0 ? a.bc_lo : a.bc_lo_y, bhi = AXIS == 0 ? a.bc_hi : a.bc_hi_y;
+  const int blo = m.bc_lo(AXIS), bhi = m.bc_hi(AXIS);
   const int mstep = nw * ppw;
+  // the written part: runs along the pencil, and pencils
+  const int rlo = m.lo(AXIS), rhi = m.hi(AXIS), plo = m.lo(1 - AXIS), phi = m.hi(1 - AXIS);
   Cons<T> Un[V];  // GSRC: the next pass's runs, loaded one pass ahead
-  if (GSRC && gl < LPP && wave * ppw + col < m)
-    pool_run<T, V, false>(a, P, z, gl * V, wave * ppw + col, Un);
-  for (int m0 = wave * ppw; m0 < m; m0 += mstep) {  // wave-uniform
+  if (GSRC && gl < LPP && p0 + wave * ppw + col < p1)
+    row_run<T, V, false>(m.at(m.src(), gl * V, p0 + wave * ppw + col), m.plane(), Un);
+  for (int m0 = p0 + wave * ppw; m0 < p1; m0 += mstep) {  // wave-uniform
     const int pen = m0 + col;
-    const bool act = gl < LPP && pen < m;
+    const bool act = gl < LPP && pen < p1;
+    const bool wr = act && gl * V >= rlo && gl * V < rhi && pen >= plo && pen < phi;
     Cons<T> U[V];
     if (act) {
       if (GSRC) {
@@ -1305,56 +1366,82 @@ __device__ void plane_sweep(const SweepArgs<T>& a, const PatchDev& P, int z, T* 
 #pragma unroll
       for (int c = 0; c < V; ++c) U[c] = Cons<T>{T(1), T(0), T(0), T(0), T(1)};
     }
-    if (GSRC && gl < LPP && pen + mstep < m)
-      pool_run<T, V, false>(a, P, z, gl * V, pen + mstep, Un);
-    lanerun_update<T, V, AXIS>(U, act ? gl : 0, last, srcL, srcR, blo, bhi, k, id, act, do_cfl,
+    if (GSRC && gl < LPP && pen + mstep < p1)
+      row_run<T, V, false>(m.at(m.src(), gl * V, pen + mstep), m.plane(), Un);
+    lanerun_update<T, V, AXIS>(U, act ? gl : 0, last, srcL, srcR, blo, bhi, k, id, wr, do_cfl,
                                smax, bad);
-    if (TOT && act) {
+    if (TOT && wr) {
 #pragma unroll
       for (int c = 0; c < V; ++c)
-        tot_add<T, AXIS>(*tot, U[c], P, a.gvec, AXIS == 0 ? gl * V + c : pen,
-                         AXIS == 0 ? pen : gl * V + c, z);
+        tot_add<T, AXIS>(*tot, U[c], P, a.gvec, m.gx(AXIS == 0 ? gl * V + c : pen),
+                         m.gy(AXIS == 0 ? pen : gl * V + c), m.z);
     }
-    if (act) {
-      if (GDST) {
-        if (!(TOT && a.tonly)) pool_run<T, V, true>(a, P, z, gl * V, pen, U);
-      } else {
-        plane_run<T, V, AXIS, true>(lds, AXIS == 0 ? gl * V : pen, AXIS == 0 ? pen : gl * V, U);
-      }
+    if (GDST) {
+      if (wr && !(TOT && a.tonly)) row_run<T, V, true>(m.at(m.dst(), gl * V, pen), m.plane(), U);
+    } else if (act) {
+      plane_run<T, V, AXIS, true>(lds, AXIS == 0 ? gl * V : pen, AXIS == 0 ? pen : gl * V, U);
     }
   }
 }
 
-// The FP64 totals of plane z of patch P, held in LDS after its last sweep:
-// thread t takes the cells t, t + blockDim.x, ... of the plane (x fastest).
-template <class T, int V>
-__device__ void plane_totals(const SweepArgs<T>& a, const PatchDev& P, int z, const T* lds,
+// The FP64 totals of the written part of the plane, held in LDS after its
+// last sweep: thread t takes the cells t, t + blockDim.x, ... (x fastest).
+template <class T, int V, class M>
+__device__ void plane_totals(const SweepArgs<T>& a, const M& m, const PatchDev& P, const T* lds,
                              TotR& tot) {
   constexpr int PP = kPlanePitch;
-  const int nx = P.n[0], cells = P.n[0] * P.n[1];
+  const int x0 = m.lo(0), y0 = m.lo(1), wx = m.hi(0) - x0;
+  const int cells = wx * (m.hi(1) - y0);
   for (int c = threadIdx.x; c < cells; c += blockDim.x) {
-    const int y = c / nx, x = c - y * nx;
+    const int yy = c / wx, x = x0 + c - yy * wx, y = y0 + yy;
     const T* p = lds + 5 * y * PP + plane_col<V>(x, y);
     const Cons<T> U{p[0], p[PP], p[2 * PP], p[3 * PP], p[4 * PP]};  // x frame: lab order
-    tot_add<T, 0>(tot, U, P, a.gvec, x, y, z);
+    tot_add<T, 0>(tot, U, P, a.gvec, m.gx(x), m.gy(y), m.z);
   }
 }
 
-// XFIRST: x then y (even steps); else y then x (odd steps), where the x
-// sweep is the last of the step and folds the CFL maximum.  TOT (the last
-// launch of a step): y then x adds each updated cell to the totals as it
-// stores it; x then y (a batch without z, whose plane launch is last on
-// every step) adds the plane in LDS with plane_totals before copying it out.
-// The plane takes up to half the LDS of a CU, so two workgroups share one:
-// no static LDS beside it (the totals reduction uses the plane's LDS once
-// the plane has been copied out).
+// One plane of a fused step: XFIRST, x then y (even steps); else y then x
+// (odd steps).  The second sweep runs only on the pencils of the written
+// part; the first on all of them (the second needs its halo).  TOT (the
+// last launch of a step): y then x adds each written cell to the totals as
+// it stores it; x then y adds the written part in LDS with plane_totals
+// before copying it out.  `P` gives the cell widths and gravity frame.
+template <class T, int V, bool XFIRST, bool TOT, class M>
+__device__ __forceinline__ void plane_item(const SweepArgs<T>& a, const M& m, const PatchDev& P,
+                                           T* lds, double dt, T& smax, bool& bad, TotR& tot) {
+  const bool store = !(TOT && a.tonly);
+  if (XFIRST) {
+    // x: memory -> registers -> LDS; y: LDS -> LDS; then LDS -> memory
+    plane_sweep<T, V, 0, true, false>(a, m, P, 0, m.n(1), lds, false, dt, smax, bad);
+    __syncthreads();
+    plane_sweep<T, V, 1, false, false>(a, m, P, m.lo(0), m.hi(0), lds, a.do_cfl != 0, dt, smax,
+                                       bad);
+    __syncthreads();
+    if (TOT) plane_totals<T, V>(a, m, P, lds, tot);
+    if (store) plane_copy<T, V, false>(m, lds);
+  } else {
+    // memory -> LDS; y: LDS -> LDS; x: LDS -> registers -> memory
+    plane_copy<T, V, true>(m, lds);
+    __syncthreads();
+    plane_sweep<T, V, 1, false, false>(a, m, P, 0, m.n(0), lds, false, dt, smax, bad);
+    __syncthreads();
+    // (with TOT adding each written cell to the totals)
+    plane_sweep<T, V, 0, false, true, TOT>(a, m, P, m.lo(1), m.hi(1), lds, a.do_cfl != 0, dt,
+                                           smax, bad, &tot);
+  }
+  __syncthreads();  // the LDS is free again
+}
+
+// The fused x and y sweeps of batch patch z-planes (persistent; XFIRST as
+// in plane_item).  The plane takes up to half the LDS of a CU, so two
+// workgroups share one: no static LDS beside it (the totals reduction and
+// the next ticket use the plane's LDS once the plane has been copied out).
 template <class T, int V, bool XFIRST, bool TOT>
 __global__ void __launch_bounds__(512) sweep_plane_kernel(SweepArgs<T> a) {
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   T* lds = reinterpret_cast<T*>(dyn_lds);
   int* slot = reinterpret_cast<int*>(dyn_lds);  // free between items
   const double dt0 = (TOT && a.tonly) ? 0.0 : a.scal->dt;
-  const bool store = !(TOT && a.tonly);
   const bool grav = has_grav(a.gvec);
   T smax = T(0);
   bool bad = false;
@@ -1365,32 +1452,55 @@ __global__ void __launch_bounds__(512) sweep_plane_kernel(SweepArgs<T> a) {
     if (it >= a.nitems) break;
     const WorkItem w = a.items[it];
     const PatchDev P = a.patches[w.patch];
-    const int z = w.tile;
-    const double dt = item_dt(a, w.patch, dt0);
-    if (XFIRST) {
-      // x: pool -> registers -> LDS; y: LDS -> LDS; then LDS -> pool
-      plane_sweep<T, V, 0, true, false>(a, P, z, lds, false, dt, smax, bad);
-      __syncthreads();
-      plane_sweep<T, V, 1, false, false>(a, P, z, lds, a.do_cfl != 0, dt, smax, bad);
-      __syncthreads();
-      if (TOT) plane_totals<T, V>(a, P, z, lds, tot);
-      if (store) plane_copy<T, V, false>(a, P, z, lds);
-    } else {
-      // pool -> LDS; y: LDS -> LDS; x: LDS -> registers -> pool
-      plane_copy<T, V, true>(a, P, z, lds);
-      __syncthreads();
-      plane_sweep<T, V, 1, false, false>(a, P, z, lds, false, dt, smax, bad);
-      __syncthreads();
-      // x: LDS -> registers -> pool (with TOT adding each cell to the totals)
-      plane_sweep<T, V, 0, false, true, TOT>(a, P, z, lds, a.do_cfl != 0, dt, smax, bad, &tot);
-    }
-    __syncthreads();  // the LDS is free again (the next ticket lands in it)
+    const PatchPlane<T> m{a, P, w.tile};
+    plane_item<T, V, XFIRST, TOT>(a, m, P, lds, item_dt(a, w.patch, dt0), smax, bad, tot);
     if (TOT)
       tot_block_wide(tot, cell_volume(P), a.tpart + 6 * int64_t(it),
                      reinterpret_cast<double*>(dyn_lds), grav);
     item_cfl(a, w.patch, smax, lds);
   }
   finish_block(a.scal, smax, bad, a.do_cfl != 0 && !a.pdt, lds);
+}
+
+// Item i of n, remapped so that neighbouring items run on one XCD: the
+// dispatcher places workgroup b on XCD b mod 8, and round robin over a grid
+// of a multiple of 8 workgroups hands item i to XCD i mod 8, so XCD x gets
+// the contiguous items x q + min(x, r) .. (n = 8 q + r).  Neighbouring
+// windows share the cache lines of their overlap.
+__device__ __forceinline__ int xcd_item(int i, int n) {
+  const int q = n >> 3, r = n & 7, x = i & 7, k = i >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
+
+// The fused x and y sweeps of a single grid, window by window (WinDev):
+// work item it is window it mod nwin of z-plane it / nwin, taken round
+// robin (xcd_item order) by a grid of resident workgroups (every item
+// costs the same).  The
+// windows overlap (each reads two cells past its written part), so the
+// result goes to a.dst, a buffer laid out like the state.  Four waves per
+// SIMD (at most 128 registers): the LDS holds two workgroups of eight waves
+// per CU.
+template <class T, int V, bool XFIRST, bool TOT>
+__global__ void __launch_bounds__(512, 4) sweep_window_kernel(SweepArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  T* lds = reinterpret_cast<T*>(dyn_lds);
+  const double dt = (TOT && a.tonly) ? 0.0 : a.scal->dt;
+  const bool grav = has_grav(a.gvec);
+  T smax = T(0);
+  bool bad = false;
+  TotR tot;
+  tot.zero();
+  for (int i = blockIdx.x; i < a.nitems; i += gridDim.x) {
+    const int it = xcd_item(i, a.nitems);
+    const int z = it / a.nwin;
+    const WinDev w = a.wins[it - z * a.nwin];
+    const WindowPlane<T> m{a, a.single, w, z};
+    plane_item<T, V, XFIRST, TOT>(a, m, a.single, lds, dt, smax, bad, tot);
+    if (TOT)
+      tot_block_wide(tot, cell_volume(a.single), a.tpart + 6 * int64_t(it),
+                     reinterpret_cast<double*>(dyn_lds), grav);
+  }
+  finish_block(a.scal, smax, bad, a.do_cfl != 0, lds);
 }
 
 // --------------------------------------------------------------------------
@@ -1443,6 +1553,7 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
   const int jb = min(N, ja + L);
   const bool act = (seg < S) && (col < ncol) && (ja < jb);
   const Planes<T, AXIS> pl(a.pool, P);
+  const Planes<T, AXIS> pd(a.dst ? a.dst : a.pool, P);  // the result (out of place: a.dst)
   uint32_t cb = 0;  // byte offset of the column's cell 0 inside a plane
   int cx = 0, ct = 0;  // the column's x and its index along the other transverse axis
   if (act) {
@@ -1557,7 +1668,7 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
     face_states(W0, W1, W2, k, k.kick, Wm1, Wp1);  // cell j+1
     const Cons<T> Fr = hllc(WpPrev, Wm1, k);
     update(U0, Fl, Fr, k);
-    if (store) pl.store(b, U0);
+    if (store) pd.store(b, U0);
     if (a.do_cfl) smax = fmax_(smax, cell_speed<T, AXIS>(U0, k, id, bad));
     if (TOT) total(U0, j);
     b += sd;
@@ -1612,7 +1723,7 @@ __device__ void colsweep_tile(const SweepArgs<T>& a, const PatchDev& P, int64_t 
     face_states(W0, W1, W2, k, (j + 1 == jb) ? kick_hi : k.kick, Wm1, Wp1);  // cell j+1
     const Cons<T> Fr = hllc(WpPrev, Wm1, k);
     update(U0, Fl, Fr, k);
-    if (store) pl.store(b, U0);
+    if (store) pd.store(b, U0);
     if (a.do_cfl) smax = fmax_(smax, cell_speed<T, AXIS>(U0, k, id, bad));
     if (TOT) total(U0, j);
     b += sd;
@@ -1928,6 +2039,9 @@ static SweepArgs<T> to_args(const LaunchSweep& L) {
   a.tonly = L.totals_only;
   a.pdt = L.pdt;
   a.psmax = L.psmax;
+  a.dst = static_cast<T*>(L.dst);
+  a.wins = L.wins;
+  a.nwin = L.nwin;
   return a;
 }
 
@@ -2052,11 +2166,42 @@ static hipError_t launch_plane(const LaunchSweep& L, hipStream_t st) {
   }
 }
 
+template <class T, int V, bool TOT>
+static hipError_t launch_window_v(const LaunchSweep& L, hipStream_t st) {
+  const SweepArgs<T> a = to_args<T>(L);
+  const size_t lds = std::max(size_t(kPlaneLdsBytes), TOT ? size_t(kTotWideBytes) * L.cfg.block : 0);
+  if (L.plane == kWinXY)
+    hipLaunchKernelGGL((sweep_window_kernel<T, V, true, TOT>), dim3(L.nblocks),
+                       dim3(L.cfg.block), lds, st, a);
+  else
+    hipLaunchKernelGGL((sweep_window_kernel<T, V, false, TOT>), dim3(L.nblocks),
+                       dim3(L.cfg.block), lds, st, a);
+  return hipGetLastError();
+}
+
+// Window sweeps: FP32 (a 64 x 64 FP32 plane is the LDS share of a
+// workgroup), V = 1 or 2 (window origins are even cells).
+template <class T, bool TOT>
+static hipError_t launch_window(const LaunchSweep& L, hipStream_t st) {
+  if constexpr (sizeof(T) != 4) {
+    return hipErrorInvalidValue;
+  } else {
+    if (!L.wins || !L.dst || L.nwin < 1 || L.nblocks < 1 || L.nitems % L.nwin)
+      return hipErrorInvalidValue;
+    switch (L.cfg.v) {
+      case 1: return launch_window_v<T, 1, TOT>(L, st);
+      case 2: return launch_window_v<T, 2, TOT>(L, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+}
+
 // TOT: the launch also folds the FP64 totals of the cells it updates (the
 // last sweep of a step), a separate instantiation of each kernel so that the
 // other sweeps keep their registers.
 template <class T, bool TOT>
 static hipError_t launch_sweep_tt(const LaunchSweep& L, hipStream_t st) {
+  if (L.plane == kWinXY || L.plane == kWinYX) return launch_window<T, TOT>(L, st);
   if (L.plane != kPlaneNone) return launch_plane<T, TOT>(L, st);
   if (L.persistent) {
     dim3 grid(L.nblocks);

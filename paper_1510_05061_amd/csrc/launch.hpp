@@ -13,6 +13,8 @@ namespace hydro {
 constexpr int kPlaneNone = 0;  // one sweep along `axis`
 constexpr int kPlaneXY = 1;    // fused x then y sweeps of patch z-planes
 constexpr int kPlaneYX = 2;    // fused y then x sweeps of patch z-planes
+constexpr int kWinXY = 3;      // fused x then y sweeps of single-grid windows
+constexpr int kWinYX = 4;      // fused y then x sweeps of single-grid windows
 
 struct LaunchSweep {
   // pool: state or patch pool; patches/items: device tables (persistent)
@@ -49,6 +51,12 @@ struct LaunchSweep {
   // patch p steps by pdt[p] and folds its CFL maximum into psmax[p]
   const double* pdt;
   unsigned long long* psmax;
+  // out-of-place sweeps (single grid, fused x+y step): results go to dst,
+  // laid out like pool (null: in place); only the z march and the window
+  // sweeps take one
+  void* dst;
+  const WinDev* wins;  // window sweeps: the windows of a z-plane
+  int32_t nwin;
 };
 
 // Partial sums a sweep launch writes (grid size or work items).

@@ -47,6 +47,22 @@ struct WorkItem {
   int32_t tile;
 };
 
+// A window of the fused x+y sweeps of a single grid: kWinEdge x kWinEdge
+// cells of a z-plane whose inner part is written.  The sweeps need two
+// cells on each side of a written cell, so a window reaches two cells past
+// its written part, except where it meets a domain edge that is not
+// periodic (there the pencil ends apply that boundary condition).
+constexpr int kWinEdge = 64;
+constexpr int kWinHalo = 2;
+struct WinDev {
+  int32_t x0, y0;          // cell (0, 0) of the window in the grid (wrapped on
+                           // periodic axes: x0 may be -2)
+  int32_t ox0, ox1;        // written columns [ox0, ox1), window-relative
+  int32_t oy0, oy1;        // written rows [oy0, oy1)
+  int32_t bx_lo, bx_hi;    // pencil-end conditions along x (hydro_bc; periodic
+  int32_t by_lo, by_hi;    // where the window's end is not a domain edge)
+};
+
 // Kinds of sweep kernel (SweepCfg::kind).
 constexpr int kLaneRunKind = 0;   // x: lane runs, whole pencils per workgroup
 constexpr int kColumnKind = 1;    // y, z: column march

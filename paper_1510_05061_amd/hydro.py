@@ -21,7 +21,7 @@ HYDRO_OK, HYDRO_EINVAL, HYDRO_EDEVICE, HYDRO_ENUMERIC, HYDRO_ESTATE = range(5)
 PERIODIC, OUTFLOW, REFLECT = 0, 1, 2
 FP32, FP64 = 0, 1
 Q_RHO, Q_PRESSURE, Q_SPEED, Q_MACH = 0, 1, 2, 3
-FLAG_NO_GRAPH, FLAG_NO_TUNE, BATCH_PER_PATCH_DT = 0x1, 0x2, 0x4
+FLAG_NO_GRAPH, FLAG_NO_TUNE, BATCH_PER_PATCH_DT, FLAG_FUSE_XY = 0x1, 0x2, 0x4, 0x8
 DT_CFL = 0.0
 
 
