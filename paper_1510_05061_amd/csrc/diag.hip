@@ -294,88 +294,38 @@ __global__ void __launch_bounds__(kDiagBlock) profile_final_kernel(const double*
 // One-dimensional kinetic-energy spectrum along x
 // --------------------------------------------------------------------------
 //
-// A workgroup owns whole x-lines (y, z): lines blockIdx.x, blockIdx.x +
-// gridDim.x, ...  For each it widens rho and m to FP64, forms u = m / rho
-// (IEEE division), packs two complex lines z1 = ux + i uy and z2 = uz, and
-// transforms both in LDS with a mixed-radix Stockham FFT (radices 4, 2, 3;
-// the autosort formulation of Govindaraju et al., SC 2008: stage s with
-// radix R and span Ns maps element j + r N/R, twiddled by W^(r (j mod Ns)
-// N/(Ns R)), through an R-point DFT to (j div Ns) Ns R + (j mod Ns) + r Ns;
-// the output lands in natural order).  For a real pair packed as a + i b,
+// A workgroup owns groups of P whole x-lines (y, z): groups blockIdx.x,
+// blockIdx.x + gridDim.x, ...  For each line it widens rho and m to FP64,
+// forms u = m / rho (IEEE division), packs two complex lines z1 = ux + i uy
+// and z2 = uz, and transforms all 2P in LDS with the in-place mixed-radix
+// Stockham FFT of fft.hpp (radices 16, 4, 2, 3; output in natural order).
+// For a real pair packed as a + i b,
 // |A(k)|^2 + |B(k)|^2 = (|Z(k)|^2 + |Z(N-k)|^2) / 2, so the power summed over
 // the three components needs no unpacking.  Thread t accumulates k = t,
 // t + 256, ... over its workgroup's lines (fixed order), writes its
 // partial spectrum, and one workgroup sums the partials in a fixed order.
 
-constexpr int kSpecMaxStages = 12;
+// x-lines per pass: the two complex lines of every x-line of a pass fill at
+// most kSpecElems complex values of LDS
+constexpr int kSpecElems = 4096;
+constexpr int kSpecBlock = 512;  // threads of the spectrum kernel
 
-struct SpecArgs {
-  int n;                       // line length nx
-  int nst;                     // stages
-  int rad[kSpecMaxStages];     // radix of each stage
-  int ns[kSpecMaxStages];      // span Ns of each stage (product of the earlier radices)
-  int tw[kSpecMaxStages];      // twiddle step n / (Ns R)
-  FastDiv nsd[kSpecMaxStages];  // division by Ns
-  FastDiv md[kSpecMaxStages];   // division by n / R (butterflies per complex line)
-};
-
-// One butterfly of a stage: R inputs j + r step (twiddled), R-point DFT,
-// outputs at base + r Ns.
-template <int R>
-__device__ __forceinline__ void fft_butterfly(const double2* src, double2* dst,
-                                              const double2* W, int n, int jj, int ns,
-                                              const FastDiv& nsd, int tw) {
-  const int step = n / R;
-  const int q = int(nsd.div(uint32_t(jj))), k = jj - q * ns;
-  double2 v[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const double2 x = src[jj + r * step];
-    v[r] = r == 0 ? x : cmul(x, W[r * k * tw]);
-  }
-  double2 b[R];
-  if constexpr (R == 2) {
-    b[0] = cadd(v[0], v[1]);
-    b[1] = csub(v[0], v[1]);
-  } else if constexpr (R == 4) {
-    const double2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
-    const double2 s13 = cadd(v[1], v[3]), d13 = cmi(csub(v[1], v[3]));  // -i (v1 - v3)
-    b[0] = cadd(s02, s13);
-    b[1] = cadd(d02, d13);
-    b[2] = csub(s02, s13);
-    b[3] = csub(d02, d13);
-  } else {  // R == 3: w = exp(-2 pi i / 3) = -1/2 - i sqrt(3)/2
-    const double h = 0.86602540378443864676;  // sqrt(3) / 2
-    const double2 t1 = cadd(v[1], v[2]);
-    const double2 t2 = make_double2(v[0].x - 0.5 * t1.x, v[0].y - 0.5 * t1.y);
-    const double2 dd = csub(v[1], v[2]);
-    const double2 t3 = make_double2(h * dd.y, -h * dd.x);  // -i h (v1 - v2)
-    b[0] = cadd(v[0], t1);
-    b[1] = cadd(t2, t3);
-    b[2] = csub(t2, t3);
-  }
-  const int base = q * ns * R + k;
-#pragma unroll
-  for (int r = 0; r < R; ++r) dst[base + r * ns] = b[r];
-}
-
-// P x-lines per pass (P = 2 for lines of up to 256 cells, so that every
-// thread has a butterfly in each stage and a pass pays for its barriers
-// once for two lines).
 template <class T, int P>
-__global__ void __launch_bounds__(kDiagBlock) spectrum_kernel(DiagArgs<T> a, SpecArgs sp) {
+// Short lines (P >= 4) keep their registers (two waves per SIMD); long
+// lines (P = 2) take four waves per SIMD, which measured faster (768^3:
+// 5.5 against 6.7 ms) despite a few spilled registers.
+__global__ void __launch_bounds__(kSpecBlock, P >= 4 ? 2 : 4) spectrum_kernel(DiagArgs<T> a, FftPlan sp) {
   extern __shared__ double2 sbuf[];
   const PatchDev& Pd = a.single;
   const int n = sp.n;
-  double2* W = sbuf;                  // W[t] = exp(-2 pi i t / n)
-  double2* bufA = sbuf + n;           // 2P complex lines
-  double2* bufB = sbuf + (1 + 2 * P) * n;
-  for (int t = threadIdx.x; t < n; t += kDiagBlock) {
+  double2* W = sbuf;       // W[t] = exp(-2 pi i t / n)
+  double2* buf = sbuf + n;  // 2P complex lines (fft_pad slots), transformed in place
+  for (int t = threadIdx.x; t < n; t += kSpecBlock) {
     double sn, cs;
     sincospi(-2.0 * double(t) / double(n), &sn, &cs);
     W[t] = make_double2(cs, sn);
   }
-  constexpr int KPT = (kSpecMaxLen / 2 + 1 + kDiagBlock - 1) / kDiagBlock;  // k per thread
+  constexpr int KPT = (kSpecMaxLen / 2 + 1 + kSpecBlock - 1) / kSpecBlock;  // k per thread
   double acc[KPT];
 #pragma unroll
   for (int i = 0; i < KPT; ++i) acc[i] = 0.0;
@@ -385,15 +335,15 @@ __global__ void __launch_bounds__(kDiagBlock) spectrum_kernel(DiagArgs<T> a, Spe
   // this thread's cells c = t + 256 i of the pass (line c / n of the group,
   // x = c mod n), fetched one pass ahead so that the next pass's loads are
   // in flight during the current transform
-  constexpr int XPT = kSpecMaxLen / kDiagBlock;
+  constexpr int XPT = kSpecElems / 2 / kSpecBlock;
   T fr[XPT], fm[XPT][3];
   auto fetch = [&](int grp) {
 #pragma unroll
     for (int i = 0; i < XPT; ++i) {
-      const int c = threadIdx.x + i * kDiagBlock;
-      const int lp = P == 1 ? 0 : (c >= n ? 1 : 0);
+      const int c = threadIdx.x + i * kSpecBlock;
+      const int lp = c / n;
       const int x = c - lp * n, line = grp * P + lp;
-      if (c < P * n && line < lines) {
+      if (lp < P && line < lines) {
         const int z = line / ny, y = line - z * ny;
         const int64_t o = int64_t(y) * Pd.sy + int64_t(z) * Pd.sz + x;
         fr[i] = p0[o];
@@ -404,56 +354,37 @@ __global__ void __launch_bounds__(kDiagBlock) spectrum_kernel(DiagArgs<T> a, Spe
   };
   if (int(blockIdx.x) < groups) fetch(blockIdx.x);
   for (int grp = blockIdx.x; grp < groups; grp += gridDim.x) {
-    __syncthreads();  // the previous pass's buffers and the twiddles
+    __syncthreads();  // the previous pass's buffer and the twiddles
 #pragma unroll
     for (int i = 0; i < XPT; ++i) {
-      const int c = threadIdx.x + i * kDiagBlock;
-      const int lp = P == 1 ? 0 : (c >= n ? 1 : 0);
+      const int c = threadIdx.x + i * kSpecBlock;
+      const int lp = c / n;
       const int x = c - lp * n;
-      if (c < P * n) {
+      if (lp < P) {
         double2 z1 = make_double2(0.0, 0.0), z2 = z1;  // a missing last line: zeros
         if (grp * P + lp < lines) {
           const double r = double(fr[i]);
           z1 = make_double2(double(fm[i][0]) / r, double(fm[i][1]) / r);
           z2 = make_double2(double(fm[i][2]) / r, 0.0);
         }
-        bufA[2 * lp * n + x] = z1;
-        bufA[(2 * lp + 1) * n + x] = z2;
+        buf[fft_pad(2 * lp * n + x)] = z1;
+        buf[fft_pad((2 * lp + 1) * n + x)] = z2;
       }
     }
     if (grp + int(gridDim.x) < groups) fetch(grp + gridDim.x);
-    double2* src = bufA;
-    double2* dst = bufB;
-    for (int s = 0; s < sp.nst; ++s) {
-      __syncthreads();
-      const int R = sp.rad[s], ns = sp.ns[s], tw = sp.tw[s];
-      const FastDiv nsd = sp.nsd[s], md = sp.md[s];
-      const int m = n / R;
-      for (int j = threadIdx.x; j < 2 * P * m; j += kDiagBlock) {
-        const int l = int(md.div(uint32_t(j)));  // complex line of the pass
-        const int jj = j - l * m;
-        if (R == 4)
-          fft_butterfly<4>(src + l * n, dst + l * n, W, n, jj, ns, nsd, tw);
-        else if (R == 2)
-          fft_butterfly<2>(src + l * n, dst + l * n, W, n, jj, ns, nsd, tw);
-        else
-          fft_butterfly<3>(src + l * n, dst + l * n, W, n, jj, ns, nsd, tw);
-      }
-      double2* t = src;
-      src = dst;
-      dst = t;
-    }
     __syncthreads();
+    fft_lines_inplace<kSpecElems, kSpecBlock>(buf, 2 * P, n, sp, W);
 #pragma unroll
     for (int lp = 0; lp < P; ++lp) {
       if (grp * P + lp >= lines) break;
-      const double2* z = src + 2 * lp * n;
+      const int z = 2 * lp * n;
 #pragma unroll
       for (int i = 0; i < KPT; ++i) {
-        const int k = threadIdx.x + i * kDiagBlock;
+        const int k = threadIdx.x + i * kSpecBlock;
         if (k <= n / 2) {
           const int km = k == 0 ? 0 : n - k;
-          const double2 a1 = z[k], b1 = z[km], a2 = z[n + k], b2 = z[n + km];
+          const double2 a1 = buf[fft_pad(z + k)], b1 = buf[fft_pad(z + km)];
+          const double2 a2 = buf[fft_pad(z + n + k)], b2 = buf[fft_pad(z + n + km)];
           acc[i] += 0.5 * ((a1.x * a1.x + a1.y * a1.y) + (b1.x * b1.x + b1.y * b1.y)) +
                     0.5 * ((a2.x * a2.x + a2.y * a2.y) + (b2.x * b2.x + b2.y * b2.y));
         }
@@ -463,7 +394,7 @@ __global__ void __launch_bounds__(kDiagBlock) spectrum_kernel(DiagArgs<T> a, Spe
   const int nk = n / 2 + 1;
 #pragma unroll
   for (int i = 0; i < KPT; ++i) {
-    const int k = threadIdx.x + i * kDiagBlock;
+    const int k = threadIdx.x + i * kSpecBlock;
     if (k < nk) a.partials[int64_t(blockIdx.x) * nk + k] = acc[i];
   }
 }
@@ -564,26 +495,18 @@ static hipError_t launch_profile_t(const LaunchDiag& L, hipStream_t st) {
 template <class T>
 static hipError_t launch_spectrum_t(const LaunchDiag& L, hipStream_t st) {
   const DiagArgs<T> a = to_dargs<T>(L);
-  SpecArgs sp{};
-  sp.n = L.single.n[0];
-  int m = sp.n;
-  while (m % 4 == 0 && sp.nst < kSpecMaxStages) { sp.rad[sp.nst++] = 4; m /= 4; }
-  while (m % 2 == 0 && sp.nst < kSpecMaxStages) { sp.rad[sp.nst++] = 2; m /= 2; }
-  while (m % 3 == 0 && sp.nst < kSpecMaxStages) { sp.rad[sp.nst++] = 3; m /= 3; }
-  if (m != 1) return hipErrorInvalidValue;
-  for (int s = 0, ns = 1; s < sp.nst; ns *= sp.rad[s], ++s) {
-    sp.ns[s] = ns;
-    sp.tw[s] = sp.n / (ns * sp.rad[s]);
-    sp.nsd[s] = FastDiv(uint32_t(ns));
-    sp.md[s] = FastDiv(uint32_t(sp.n / sp.rad[s]));
-  }
-  if (sp.n <= kDiagBlock) {  // two lines per pass
-    const size_t lds = size_t(9) * sp.n * sizeof(double2);
-    hipLaunchKernelGGL((spectrum_kernel<T, 2>), dim3(unsigned(L.chunks)), dim3(kDiagBlock), lds,
+  FftPlan sp;
+  if (!make_fft_plan(L.single.n[0], sp)) return hipErrorInvalidValue;
+  // x-lines per pass: 8 (an FP64 state: 4, for its prefetch registers) for
+  // lines of up to 256 cells, else 2 (2P n <= kSpecElems)
+  constexpr int PS = sizeof(T) == 8 ? 4 : 8;
+  if (sp.n <= 256) {
+    const size_t lds = size_t(sp.n + fft_lds(2 * PS * sp.n)) * sizeof(double2);
+    hipLaunchKernelGGL((spectrum_kernel<T, PS>), dim3(unsigned(L.chunks)), dim3(kSpecBlock), lds,
                        st, a, sp);
   } else {
-    const size_t lds = size_t(5) * sp.n * sizeof(double2);
-    hipLaunchKernelGGL((spectrum_kernel<T, 1>), dim3(unsigned(L.chunks)), dim3(kDiagBlock), lds,
+    const size_t lds = size_t(sp.n + fft_lds(2 * 2 * sp.n)) * sizeof(double2);
+    hipLaunchKernelGGL((spectrum_kernel<T, 2>), dim3(unsigned(L.chunks)), dim3(kSpecBlock), lds,
                        st, a, sp);
   }
   hipError_t e = hipGetLastError();

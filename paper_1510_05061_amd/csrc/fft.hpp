@@ -39,10 +39,47 @@ __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 cmi(double2 a) { return make_double2(a.y, -a.x); }
 __device__ __forceinline__ double2 conj2(double2 a) { return make_double2(a.x, -a.y); }
 
-// Forward R-point DFT (R = 2, 3, 4) of v in place, W_R = exp(-2 pi i / R).
+// W_16^e = exp(-2 pi i e / 16) times a, for the internal twiddles of the
+// 16-point DFT (e = b c, b and c in 0..3)
+template <int E>
+__device__ __forceinline__ double2 w16(double2 a) {
+  constexpr double C1 = 0.92387953251128675613;  // cos(pi/8)
+  constexpr double S1 = 0.38268343236508977173;  // sin(pi/8)
+  constexpr double H = 0.70710678118654752440;   // cos(pi/4)
+  if constexpr (E == 0) return a;
+  else if constexpr (E == 1) return cmul(a, make_double2(C1, -S1));
+  else if constexpr (E == 2) return cmul(a, make_double2(H, -H));
+  else if constexpr (E == 3) return cmul(a, make_double2(S1, -C1));
+  else if constexpr (E == 4) return cmi(a);
+  else if constexpr (E == 6) return cmul(a, make_double2(-H, -H));
+  else return cmul(a, make_double2(-C1, S1));  // E == 9
+}
+
+// Forward R-point DFT (R = 2, 3, 4, 16) of v in place, W_R = exp(-2 pi i / R).
+// R = 16 as 4 x 4: with r = 4a + b and k = c + 4d,
+// X[c + 4d] = sum_b W_4^(bd) W_16^(bc) sum_a x[4a + b] W_4^(ac).
 template <int R>
 __device__ __forceinline__ void dft_small(double2 (&v)[R]) {
-  if constexpr (R == 2) {
+  if constexpr (R == 16) {
+    double2 y[4][4];  // y[b][c]
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      double2 t[4] = {v[b], v[4 + b], v[8 + b], v[12 + b]};
+      dft_small<4>(t);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) y[b][c] = t[c];
+    }
+    y[1][1] = w16<1>(y[1][1]); y[1][2] = w16<2>(y[1][2]); y[1][3] = w16<3>(y[1][3]);
+    y[2][1] = w16<2>(y[2][1]); y[2][2] = w16<4>(y[2][2]); y[2][3] = w16<6>(y[2][3]);
+    y[3][1] = w16<3>(y[3][1]); y[3][2] = w16<6>(y[3][2]); y[3][3] = w16<9>(y[3][3]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double2 t[4] = {y[0][c], y[1][c], y[2][c], y[3][c]};
+      dft_small<4>(t);
+#pragma unroll
+      for (int d = 0; d < 4; ++d) v[c + 4 * d] = t[d];
+    }
+  } else if constexpr (R == 2) {
     const double2 a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
@@ -65,8 +102,9 @@ __device__ __forceinline__ void dft_small(double2 (&v)[R]) {
   }
 }
 
-// Stages of an FFT of length n = 4^a 2^b 3^c (radix 4 first, then 2, then
-// 3), built on the host.  Stage s has radix rad[s], span ns[s] (product of
+// Stages of an FFT of length n = 16^a 4^b 2^c 3^d (radix 16 first, then 4,
+// 2, 3: fewer stages mean fewer LDS round trips and barriers), built on the
+// host.  Stage s has radix rad[s], span ns[s] (product of
 // the earlier radices) and twiddle step tw[s] = n / (ns R).
 constexpr int kFftMaxStages = 12;
 struct FftPlan {
@@ -85,6 +123,7 @@ inline bool make_fft_plan(int n, FftPlan& p) {
   p.n = n;
   if (n < 1) return false;
   int m = n;
+  while (m % 16 == 0 && p.nst < kFftMaxStages) { p.rad[p.nst++] = 16; m /= 16; }
   while (m % 4 == 0 && p.nst < kFftMaxStages) { p.rad[p.nst++] = 4; m /= 4; }
   while (m % 2 == 0 && p.nst < kFftMaxStages) { p.rad[p.nst++] = 2; m /= 2; }
   while (m % 3 == 0 && p.nst < kFftMaxStages) { p.rad[p.nst++] = 3; m /= 3; }
@@ -98,6 +137,13 @@ inline bool make_fft_plan(int n, FftPlan& p) {
   return true;
 }
 
+// LDS slot of complex element o of an FFT buffer: one pad slot after every
+// 16 elements.  A radix-16 stage writes its outputs 16 elements apart (256
+// bytes, the same banks for every lane); with the pad they land 272 bytes
+// apart, on different banks.  A buffer of n elements takes fft_lds(n) slots.
+__host__ __device__ __forceinline__ int fft_pad(int o) { return o + (o >> 4); }
+__host__ __device__ __forceinline__ int fft_lds(int n) { return n + (n >> 4) + 1; }
+
 // One radix-R stage of the Stockham autosort FFT (Govindaraju et al., SC
 // 2008) over nl complex lines in LDS (line l at buf + l ls), in place:
 // butterfly j of a line takes the elements j + r n/R, twiddled by
@@ -105,7 +151,8 @@ inline bool make_fft_plan(int n, FftPlan& p) {
 // (j mod ns) + r ns.  Every thread first holds the inputs of its
 // butterflies (j = t, t + B, ... over the nl n/R of the stage, at most MAXB)
 // in registers; after a barrier it writes the outputs; a second barrier
-// ends the stage.  W[t] = exp(-2 pi i t / n) in LDS.  B = blockDim.x.
+// ends the stage.  Element o of the buffer sits at slot fft_pad(o).
+// W[t] = exp(-2 pi i t / n) in LDS.  B = blockDim.x.
 template <int R, int MAXB>
 __device__ __forceinline__ void fft_stage_inplace(double2* buf, int nl, int ls, int n, int ns,
                                                   int tw, const FastDiv& md, const FastDiv& nsd,
@@ -120,10 +167,10 @@ __device__ __forceinline__ void fft_stage_inplace(double2* buf, int nl, int ls, 
     if (j < nb) {
       const int l = int(md.div(uint32_t(j))), jj = j - l * m;
       const int q = int(nsd.div(uint32_t(jj))), k = jj - q * ns;
-      const double2* s = buf + l * ls + jj;
+      const int s = l * ls + jj;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const double2 x = s[r * m];
+        const double2 x = buf[fft_pad(s + r * m)];
         v[b][r] = r == 0 ? x : cmul(x, W[r * k * tw]);
       }
       dst[b] = l * ls + q * ns * R + k;
@@ -135,7 +182,7 @@ __device__ __forceinline__ void fft_stage_inplace(double2* buf, int nl, int ls, 
     if (dst[b] >= 0) {
       dft_small<R>(v[b]);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[dst[b] + r * ns] = v[b][r];
+      for (int r = 0; r < R; ++r) buf[fft_pad(dst[b] + r * ns)] = v[b][r];
     }
   }
   __syncthreads();
@@ -148,7 +195,10 @@ template <int EMAX, int BLOCK>
 __device__ void fft_lines_inplace(double2* buf, int nl, int ls, const FftPlan& p, const double2* W) {
   for (int s = 0; s < p.nst; ++s) {
     const int R = p.rad[s];
-    if (R == 4)
+    if (R == 16)
+      fft_stage_inplace<16, (EMAX + 16 * BLOCK - 1) / (16 * BLOCK)>(
+          buf, nl, ls, p.n, p.ns[s], p.tw[s], p.md[s], p.nsd[s], W);
+    else if (R == 4)
       fft_stage_inplace<4, (EMAX + 4 * BLOCK - 1) / (4 * BLOCK)>(buf, nl, ls, p.n, p.ns[s], p.tw[s],
                                                                 p.md[s], p.nsd[s], W);
     else if (R == 2)

@@ -1475,7 +1475,8 @@ __device__ __forceinline__ int xcd_item(int i, int n) {
 // The fused x and y sweeps of a single grid, window by window (WinDev):
 // work item it is window it mod nwin of z-plane it / nwin, taken round
 // robin (xcd_item order) by a grid of resident workgroups (every item
-// costs the same).  The
+// costs the same); with TOT each workgroup sums its items in registers and
+// writes one partial.  The
 // windows overlap (each reads two cells past its written part), so the
 // result goes to a.dst, a buffer laid out like the state.  Four waves per
 // SIMD (at most 128 registers): the LDS holds two workgroups of eight waves
@@ -1496,10 +1497,12 @@ __global__ void __launch_bounds__(512, 4) sweep_window_kernel(SweepArgs<T> a) {
     const WinDev w = a.wins[it - z * a.nwin];
     const WindowPlane<T> m{a, a.single, w, z};
     plane_item<T, V, XFIRST, TOT>(a, m, a.single, lds, dt, smax, bad, tot);
-    if (TOT)
-      tot_block_wide(tot, cell_volume(a.single), a.tpart + 6 * int64_t(it),
-                     reinterpret_cast<double*>(dyn_lds), grav);
   }
+  // the items of a workgroup are fixed by the grid size (round robin), so
+  // one partial per workgroup has a fixed summation order
+  if (TOT)
+    tot_block_wide(tot, cell_volume(a.single), a.tpart + 6 * int64_t(blockIdx.x),
+                   reinterpret_cast<double*>(dyn_lds), grav);
   finish_block(a.scal, smax, bad, a.do_cfl != 0, lds);
 }
 
@@ -2228,6 +2231,7 @@ hipError_t launch_sweep(const LaunchSweep& L, hipStream_t st) {
 }
 
 int64_t sweep_parts(const LaunchSweep& L) {
+  if (L.plane == kWinXY || L.plane == kWinYX) return L.nblocks;  // one per workgroup
   if (L.plane != kPlaneNone || L.persistent) return L.nitems;
   if (L.axis == 0) {
     const int64_t g = x_grid(L.single, L.cfg);

@@ -114,8 +114,8 @@ __global__ void __launch_bounds__(kS3Block) spec3_x_kernel(Spec3Args a, FftPlan 
           z1 = make_double2(double(m[i][0]) / rho, double(m[i][1]) / rho);
           z2 = make_double2(double(m[i][2]) / rho, 0.0);
         }
-        buf[2 * lp * nx + x] = z1;
-        buf[(2 * lp + 1) * nx + x] = z2;
+        buf[fft_pad(2 * lp * nx + x)] = z1;
+        buf[fft_pad((2 * lp + 1) * nx + x)] = z2;
       }
     }
     __syncthreads();
@@ -126,13 +126,13 @@ __global__ void __launch_bounds__(kS3Block) spec3_x_kernel(Spec3Args a, FftPlan 
       const int lp = int(a.dnh.div(uint32_t(e))), k = e - lp * nh, line = grp * G + lp;
       if (line >= lines) continue;
       const int z = int(a.dny.div(uint32_t(line))), y = line - z * ny;
-      const double2 zk = buf[2 * lp * nx + k];
-      const double2 zm = conj2(buf[2 * lp * nx + (k == 0 ? 0 : nx - k)]);
+      const double2 zk = buf[fft_pad(2 * lp * nx + k)];
+      const double2 zm = conj2(buf[fft_pad(2 * lp * nx + (k == 0 ? 0 : nx - k))]);
       const double2 s = cadd(zk, zm), d = cmi(csub(zk, zm));
       const int64_t o = (int64_t(z) * ny + y) * nh + k;
       a.U[o] = make_double2(0.5 * s.x, 0.5 * s.y);
       a.U[o + a.cplane] = make_double2(0.5 * d.x, 0.5 * d.y);
-      a.U[o + 2 * a.cplane] = buf[(2 * lp + 1) * nx + k];
+      a.U[o + 2 * a.cplane] = buf[fft_pad((2 * lp + 1) * nx + k)];
     }
   }
 }
@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(kS3Block) spec3_col_kernel(Spec3Args a, FftPla
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int e = threadIdx.x + i * kS3Block, t = e & (kS3T - 1), j = e / kS3T;
-      if (j < L) buf[t * ls + j] = v[i];
+      if (j < L) buf[fft_pad(t * ls + j)] = v[i];
     }
     __syncthreads();
     fft_lines_inplace<kS3ColElems, kS3Block>(buf, kS3T, ls, pl, W);
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(kS3Block) spec3_col_kernel(Spec3Args a, FftPla
     for (int i = 0; i < EPT; ++i) {
       const int e = threadIdx.x + i * kS3Block, t = e & (kS3T - 1), j = e / kS3T;
       if (j < L && kx0 + t < nh) {
-        const double2 u = buf[t * ls + j];
+        const double2 u = buf[fft_pad(t * ls + j)];
         if (ZP)
           pw[i] += u.x * u.x + u.y * u.y;
         else
@@ -330,14 +330,14 @@ static hipError_t launch_s3(const LaunchSpec3& L, hipStream_t st) {
   if (e != hipSuccess) return e;
   const int groups = (P.n[1] * P.n[2] + a.gx - 1) / a.gx;
   const int xgrid = std::min(groups, 8 * std::max(1, L.cu_count));
-  const size_t xlds = size_t(P.n[0] + 2 * a.gx * P.n[0]) * sizeof(double2);
+  const size_t xlds = size_t(P.n[0] + fft_lds(2 * a.gx * P.n[0])) * sizeof(double2);
   hipLaunchKernelGGL(spec3_x_kernel<T>, dim3(unsigned(xgrid)), dim3(kS3Block), xlds, st, a, px);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t ylds = size_t(P.n[1] + kS3T * (P.n[1] + 1)) * sizeof(double2);
+  const size_t ylds = size_t(P.n[1] + fft_lds(kS3T * (P.n[1] + 1))) * sizeof(double2);
   hipLaunchKernelGGL(spec3_col_kernel<false>, dim3(unsigned(3 * P.n[2] * a.ntk)), dim3(kS3Block),
                      ylds, st, a, py);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t zlds = size_t(P.n[2] + kS3T * (P.n[2] + 1)) * sizeof(double2);
+  const size_t zlds = size_t(P.n[2] + fft_lds(kS3T * (P.n[2] + 1))) * sizeof(double2);
   hipLaunchKernelGGL(spec3_col_kernel<true>, dim3(unsigned(P.n[1] * a.ntk)), dim3(kS3Block), zlds,
                      st, a, pz);
   if ((e = hipGetLastError()) != hipSuccess) return e;
