@@ -158,7 +158,9 @@ struct Config {
   int32_t batch_blocks = 0;  // persistent launches: workgroups
   int32_t batch_dyn = 1;     // persistent launches: ticket (1) or static (0) items
   int32_t batch_fuse = 0;    // batches: x and y sweeps fused per patch z-plane (1)
+  int32_t batch_zplane = 0;  // batches: z swept as lane runs over x-z planes in LDS (1)
   SweepCfg plane{kLaneRunKind, 4, 512, 0, 0, 0};  // fused plane kernel: V, threads
+  SweepCfg zplane{kLaneRunKind, 2, 512, 0, 0, 0};  // x-z plane kernel: V, threads
 };
 
 // A lane run of v cells is loaded and stored as one vector access, so every
@@ -231,7 +233,9 @@ std::string cfg_text(const Config& cf) {
   o << ";z:q=" << cf.ax[2].q << ",s=" << cf.ax[2].s;
   if (cf.batch_blocks) {
     o << ";p:g=" << cf.batch_blocks << ",d=" << cf.batch_dyn << ",f=" << cf.batch_fuse;
+    if (cf.batch_zplane) o << ",z=1";
     if (cf.batch_fuse) o << ";w:v=" << cf.plane.v << ",b=" << cf.plane.block;
+    if (cf.batch_zplane) o << ";u:v=" << cf.zplane.v << ",b=" << cf.zplane.block;
   } else if (cf.batch_fuse) {
     o << ";p:f=1;w:v=" << cf.plane.v << ",b=" << cf.plane.block;  // single grid, fused x+y
   }
@@ -275,10 +279,15 @@ bool parse_cfg(const std::string& text, Config& cf) {
         if (k == "v") cf.plane.v = int(v);
         else if (k == "b") cf.plane.block = int(v);
         else return false;
+      } else if (ax == 'u') {
+        if (k == "v") cf.zplane.v = int(v);
+        else if (k == "b") cf.zplane.block = int(v);
+        else return false;
       } else if (ax == 'p') {
         if (k == "g") cf.batch_blocks = int(v);
         else if (k == "d" && (v == 0 || v == 1)) cf.batch_dyn = int(v);
         else if (k == "f" && (v == 0 || v == 1)) cf.batch_fuse = int(v);
+        else if (k == "z" && (v == 0 || v == 1)) cf.batch_zplane = int(v);
         else return false;
       } else {
         return false;
@@ -374,8 +383,9 @@ struct hydro_ctx {
   WinDev* d_wins = nullptr;
   int32_t nwin = 0;
   void* shadow = nullptr;
-  WorkItem* d_items[4] = {nullptr, nullptr, nullptr, nullptr};  // x, y, z, planes
-  int32_t nitems[4] = {0, 0, 0, 0};
+  // x, y, z, z-planes (fused x+y), x-z planes (z in LDS)
+  WorkItem* d_items[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int32_t nitems[5] = {0, 0, 0, 0, 0};
   int64_t max_patch_cells = 0;
   // run state
   int64_t step = 0;
@@ -486,6 +496,45 @@ bool plane_ok(const hydro_ctx* c, const Config& cf) {
   return true;
 }
 
+// The z sweep over patch x-z planes in LDS applies when every patch has z
+// active and an x-z plane within a workgroup's LDS share, with lane runs of
+// V cells along x and z.
+bool zplane_ok(const hydro_ctx* c, const Config& cf) {
+  if (!c->batch || !c->active[2]) return false;
+  const int v = cf.zplane.v;
+  if (v != 1 && v != 2 && v != 4) return false;
+  if (cf.zplane.block < 64 || cf.zplane.block > kMaxBlock || cf.zplane.block % 64) return false;
+  const int esz = c->fp64 ? 8 : 4;
+  const int a = std::min(v, 16 / esz);
+  for (auto& P : c->patches) {
+    if (P.n[0] == 1 || P.n[2] == 1) return false;
+    if (P.n[0] % v || P.n[2] % v || P.n[0] / v > 64 || P.n[2] / v > 64) return false;
+    if (plane_lds_bytes(P, c->fp64, 2) == 0) return false;
+    if (P.base0 % a || P.sy % a || P.sz % a || P.plane % a) return false;
+  }
+  return true;
+}
+
+// The z sweep of every patch x-z plane in LDS (replaces the z march).
+LaunchSweep zplane_launch(const hydro_ctx* c, int do_cfl) {
+  LaunchSweep L = sweep_launch(c, 2, do_cfl);
+  L.plane = kZPlane;
+  L.cfg = c->cfg.zplane;
+  L.items = c->d_items[4];
+  L.nitems = c->nitems[4];
+  // the plane's first axis is x, its second z
+  L.bc_lo = c->desc.bc[0];
+  L.bc_hi = c->desc.bc[1];
+  L.grav = c->desc.grav[0];
+  L.bc_lo_y = c->desc.bc[4];
+  L.bc_hi_y = c->desc.bc[5];
+  L.grav_y = c->desc.grav[2];
+  int lds = 0;
+  for (auto& P : c->patches) lds = std::max(lds, plane_lds_bytes(P, c->fp64, 2));
+  L.plane_lds = lds;
+  return L;
+}
+
 // The fused x and y sweeps of every patch z-plane (x first on even steps).
 LaunchSweep plane_launch(const hydro_ctx* c, bool xfirst, int do_cfl) {
   LaunchSweep L = sweep_launch(c, 0, do_cfl);
@@ -575,10 +624,13 @@ std::vector<StepOp> step_ops(const hydro_ctx* c, int parity) {
     ops.back().L.tpart = c->partials;
     return ops;
   }
+  const bool zp = c->cfg.batch_zplane && c->nitems[4] > 0 && zplane_ok(c, c->cfg);
   for (size_t i = 0; i < seq.size(); ++i) {
     const int cfl = i + 1 == seq.size() ? 1 : 0;
     if (seq[i] < 0)
       ops.push_back(StepOp{plane_launch(c, parity == 0, cfl), 0});
+    else if (seq[i] == 2 && zp)
+      ops.push_back(StepOp{zplane_launch(c, cfl), 2});
     else
       ops.push_back(StepOp{sweep_launch(c, seq[i], cfl), seq[i]});
   }
@@ -1042,6 +1094,49 @@ int choose_config(hydro_ctx* c) {
       dirty = true;
     }
   }
+  if (c->batch && c->active[2]) {
+    // the z sweep over x-z planes in LDS against the z march, timed over the
+    // launches of one even and one odd step
+    const std::string key = shape_key(c, 5);
+    auto it = cache.find(key);
+    Config tmp = c->cfg;
+    if (it != cache.end() && parse_cfg(it->second, tmp) &&
+        (!tmp.batch_zplane || zplane_ok(c, tmp))) {
+      c->cfg.batch_zplane = tmp.batch_zplane;
+      c->cfg.zplane = tmp.zplane;
+    } else {
+      if (launch_timing_begin(c->scal, c->stream) != hipSuccess)
+        return fail(HYDRO_EDEVICE, "timing setup failed");
+      std::vector<SweepCfg> zps;  // candidate i > 0: x-z plane configuration i - 1
+      for (int v : {1, 2, 4})
+        for (int b : {256, 512}) {
+          Config trial = c->cfg;
+          trial.zplane.v = v;
+          trial.zplane.block = b;
+          if (zplane_ok(c, trial)) zps.push_back(trial.zplane);
+        }
+      const SweepCfg keep = c->cfg.zplane;
+      int bi = 0;
+      int rc = fastest_of(
+          "zplane", int(zps.size()) + 1, 3,
+          [&](int i) {
+            c->cfg.batch_zplane = i > 0 ? 1 : 0;
+            if (i > 0) c->cfg.zplane = zps[size_t(i - 1)];
+            return HYDRO_OK;
+          },
+          [&](double* ms) { return time_steps(c, 2, ms); }, &bi);
+      if (launch_timing_end(c->scal, c->stream) != hipSuccess)
+        return fail(HYDRO_EDEVICE, "timing teardown failed");
+      if (rc) return rc;
+      c->cfg.zplane = bi > 0 ? zps[size_t(bi - 1)] : keep;
+      c->cfg.batch_zplane = bi > 0 ? 1 : 0;
+      std::ostringstream o;
+      o << "p:z=" << c->cfg.batch_zplane << ";u:v=" << c->cfg.zplane.v << ",b="
+        << c->cfg.zplane.block;
+      cache[key] = o.str();
+      dirty = true;
+    }
+  }
   if (dirty) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto merged = cache_read();
@@ -1177,23 +1272,23 @@ std::vector<WinDev> build_windows(const int32_t n[3], const int32_t bc[6]) {
 
 // layout of a batch workspace
 struct BatchLayout {
-  size_t partials, slice, patches, items[4], pt, pdt, psmax, total;
+  size_t partials, slice, patches, items[5], pt, pdt, psmax, total;
 };
 
 // totals partials: one per work item of any sweep launch, and at least the
 // standalone reduction's chunks
-BatchLayout batch_layout(int32_t n, const int32_t items[4]) {
+BatchLayout batch_layout(int32_t n, const int32_t items[5]) {
   BatchLayout L;
   size_t o = kScalarBytes;
   L.partials = o;
   int64_t parts = int64_t(n) * kBatchChunks;
-  for (int a = 0; a < 4; ++a) parts = std::max<int64_t>(parts, items[a]);
+  for (int a = 0; a < 5; ++a) parts = std::max<int64_t>(parts, items[a]);
   o += align_up(size_t(parts) * 6 * sizeof(double), 256);
   L.slice = o;
   o += align_up(size_t(kTotalsSlices) * 6 * sizeof(double), 256);
   L.patches = o;
   o += align_up(size_t(n) * sizeof(PatchDev), 256);
-  for (int a = 0; a < 4; ++a) {
+  for (int a = 0; a < 5; ++a) {
     L.items[a] = o;
     o += align_up(size_t(std::max(1, items[a])) * sizeof(WorkItem), 256);
   }
@@ -1210,16 +1305,17 @@ BatchLayout batch_layout(int32_t n, const int32_t items[4]) {
 
 // The most tiles a patch list can need per axis under any valid config
 // (x: v = 1 with one pencil per workgroup; columns: 64 columns per tile),
-// and its z-planes (fused plane sweeps).
-void max_items(const std::vector<PatchDev>& ps, int32_t out[4]) {
-  int64_t acc[4] = {0, 0, 0, 0};
+// its z-planes (fused plane sweeps) and its x-z planes (z sweep in LDS).
+void max_items(const std::vector<PatchDev>& ps, int32_t out[5]) {
+  int64_t acc[5] = {0, 0, 0, 0, 0};
   for (auto& P : ps) {
     acc[0] += int64_t(P.n[1]) * P.n[2];
     acc[1] += (int64_t(P.n[0]) * P.n[2] + 63) / 64;
     acc[2] += (int64_t(P.n[0]) * P.n[1] + 63) / 64;
     acc[3] += P.n[2];
+    acc[4] += P.n[1];
   }
-  for (int a = 0; a < 4; ++a) out[a] = int32_t(std::min<int64_t>(acc[a], INT32_MAX));
+  for (int a = 0; a < 5; ++a) out[a] = int32_t(std::min<int64_t>(acc[a], INT32_MAX));
 }
 
 int rebuild_items(hydro_ctx* c) {
@@ -1231,11 +1327,19 @@ int rebuild_items(hydro_ctx* c) {
     const PatchDev &A = c->patches[a], &B = c->patches[b];
     return int64_t(A.n[0]) * A.n[1] * A.n[2] > int64_t(B.n[0]) * B.n[1] * B.n[2];
   });
-  int32_t cap[4];
+  int32_t cap[5];
   max_items(c->patches, cap);
-  for (int axis = 0; axis < 4; ++axis) {
+  for (int axis = 0; axis < 5; ++axis) {
     std::vector<WorkItem> items;
-    if (axis == 3) {
+    if (axis == 4) {
+      // x-z planes of the z sweep in LDS (patches with z active)
+      if (c->active[2])
+        for (int32_t p : order) {
+          const PatchDev& P = c->patches[p];
+          if (P.n[2] == 1) continue;
+          for (int32_t y = 0; y < P.n[1]; ++y) items.push_back(WorkItem{p, y});
+        }
+    } else if (axis == 3) {
       // z-planes of the fused plane sweeps (patches with both x and y active)
       if (c->active[0] && c->active[1])
         for (int32_t p : order) {
@@ -1381,7 +1485,7 @@ int hydro_batch_workspace_bytes(const hydro_patch* p, int32_t n, const hydro_des
       return fail(HYDRO_EINVAL, "patch " + std::to_string(i) + ": a plane must be smaller than 4 GiB");
     ps.push_back(P);
   }
-  int32_t cap[4];
+  int32_t cap[5];
   max_items(ps, cap);
   *bytes = batch_layout(n, cap).total;
   return HYDRO_OK;
@@ -1444,7 +1548,7 @@ int hydro_batch_init(const hydro_patch* p, int32_t n, const hydro_desc* common, 
   c->ws_bytes = ws_bytes;
   c->stream = static_cast<hipStream_t>(stream);
   c->scal = reinterpret_cast<DevScalars*>(c->ws);
-  int32_t cap[4];
+  int32_t cap[5];
   max_items(c->patches, cap);
   BatchLayout L = batch_layout(n, cap);
   c->partials = reinterpret_cast<double*>(c->ws + L.partials);
@@ -1454,7 +1558,7 @@ int hydro_batch_init(const hydro_patch* p, int32_t n, const hydro_desc* common, 
   c->psmax = reinterpret_cast<unsigned long long*>(c->ws + L.psmax);
   c->per_patch = (common->flags & HYDRO_BATCH_PER_PATCH_DT) != 0;
   c->d_patches = reinterpret_cast<PatchDev*>(c->ws + L.patches);
-  for (int a = 0; a < 4; ++a) c->d_items[a] = reinterpret_cast<WorkItem*>(c->ws + L.items[a]);
+  for (int a = 0; a < 5; ++a) c->d_items[a] = reinterpret_cast<WorkItem*>(c->ws + L.items[a]);
   c->single = c->patches[0];
   // batch defaults: 4 cells per lane where every width allows, whole
   // columns per thread (patches are short), 8 workgroups per CU
@@ -2317,6 +2421,8 @@ int hydro_set_config(hydro_ctx* c, const char* text) {
     return fail(HYDRO_EINVAL, "invalid persistent grid size");
   if (cf.batch_fuse && c->batch && !plane_ok(c, cf))
     return fail(HYDRO_EINVAL, "fused plane sweeps do not apply to these patches");
+  if (cf.batch_zplane && !zplane_ok(c, cf))
+    return fail(HYDRO_EINVAL, "the x-z plane z sweep does not apply to these patches");
   if (cf.batch_fuse && !c->batch && !win_ok(c, cf))
     return fail(HYDRO_EINVAL, "the fused x+y step does not apply (HYDRO_FLAG_FUSE_XY, FP32, "
                               "even x and y extents >= 64, active z; w:v=1 or 2)");

@@ -1209,13 +1209,14 @@ __device__ __forceinline__ void row_run(T* g, int64_t plane, Cons<T> (&U)[V]) {
   }
 }
 
-// Where the pencils of a fused plane sweep live in memory, as the plane
-// functions below see them: a rectangle of n(0) x n(1) cells of one z-plane
-// whose part [lo(0), hi(0)) x [lo(1), hi(1)) is written.  at(base, x, y)
-// is cell (x, y) of variable 0 in a buffer laid out like the state;
-// gx, gy give a cell's grid coordinates (totals).
+// Where the pencils of a plane sweep live in memory, as the plane functions
+// below see them: a rectangle of n(0) x n(1) cells of one plane whose part
+// [lo(0), hi(0)) x [lo(1), hi(1)) is written.  at(base, x, y) is cell (x, y)
+// of variable 0 in a buffer laid out like the state; cell(x, y) gives its
+// grid coordinates (totals).
 //  * PatchPlane: the whole z-plane of a batch patch, read and written in
 //    place, with the launch's boundary conditions at the pencil ends.
+//  * PatchZPlane: an x-z plane of a batch patch (below).
 //  * WindowPlane: a window of a single grid's z-plane (WinDev), read from
 //    the pool and written to a.dst, wrapped around periodic axes.
 template <class T>
@@ -1228,13 +1229,34 @@ struct PatchPlane {
   __device__ int bc_hi(int axis) const { return axis == 0 ? a.bc_hi : a.bc_hi_y; }
   __device__ int lo(int) const { return 0; }
   __device__ int hi(int axis) const { return P.n[axis]; }
-  __device__ int gx(int x) const { return x; }
-  __device__ int gy(int y) const { return y; }
+  __device__ int3 cell(int x, int y) const { return make_int3(x, y, z); }
   __device__ T* src() const { return a.pool; }
   __device__ T* dst() const { return a.pool; }
   __device__ int64_t plane() const { return P.plane; }
   __device__ T* at(T* base, int x, int y) const {
     return base + P.base0 + int64_t(z) * P.sz + int64_t(y) * P.sy + x;
+  }
+};
+
+// The x-z plane y = yr of a batch patch: the plane's second axis is z (the
+// z march of a batch as lane runs in LDS), with the launch's z boundary
+// conditions in bc_lo_y / bc_hi_y.
+template <class T>
+struct PatchZPlane {
+  const SweepArgs<T>& a;
+  const PatchDev& P;
+  int yr;
+  __device__ int n(int axis) const { return P.n[axis == 0 ? 0 : 2]; }
+  __device__ int bc_lo(int axis) const { return axis == 0 ? a.bc_lo : a.bc_lo_y; }
+  __device__ int bc_hi(int axis) const { return axis == 0 ? a.bc_hi : a.bc_hi_y; }
+  __device__ int lo(int) const { return 0; }
+  __device__ int hi(int axis) const { return n(axis); }
+  __device__ int3 cell(int x, int y) const { return make_int3(x, yr, y); }
+  __device__ T* src() const { return a.pool; }
+  __device__ T* dst() const { return a.pool; }
+  __device__ int64_t plane() const { return P.plane; }
+  __device__ T* at(T* base, int x, int y) const {
+    return base + P.base0 + int64_t(y) * P.sz + int64_t(yr) * P.sy + x;
   }
 };
 
@@ -1252,6 +1274,7 @@ struct WindowPlane {
   __device__ int hi(int axis) const { return axis == 0 ? w.ox1 : w.oy1; }
   __device__ int gx(int x) const { return wrap(w.x0 + x, G.n[0]); }
   __device__ int gy(int y) const { return wrap(w.y0 + y, G.n[1]); }
+  __device__ int3 cell(int x, int y) const { return make_int3(gx(x), gy(y), z); }
   __device__ T* src() const { return a.pool; }
   __device__ T* dst() const { return a.dst; }
   __device__ int64_t plane() const { return G.plane; }
@@ -1301,10 +1324,11 @@ __device__ void plane_copy(const M& m, T* lds) {
 
 // Reads (write = false) or writes the V cells of a run in LDS: the cells at
 // (x0 + c dx, y0 + c dy), c < V, of the five variables, rotated into the
-// frame of the sweep axis (AXIS 0: x, 1: y).
+// frame of the sweep axis AXIS (0: x, along the plane's first axis; 1 or 2:
+// y or z, along its second axis).
 template <class T, int V, int AXIS, bool WRITE>
 __device__ __forceinline__ void plane_run(T* lds, int x0, int y0, Cons<T> (&U)[V]) {
-  constexpr int vn = AXIS == 0 ? 1 : 2, vt1 = AXIS == 0 ? 2 : 1;
+  constexpr int vn = Rot<AXIS>::n, vt1 = Rot<AXIS>::t1, vt2 = Rot<AXIS>::t2;
   constexpr int P = kPlanePitch;
   // x0 and y0 are multiples of V, so the whole run shares one rotation and
   // a run of a row stays contiguous
@@ -1313,19 +1337,20 @@ __device__ __forceinline__ void plane_run(T* lds, int x0, int y0, Cons<T> (&U)[V
   for (int c = 0; c < V; ++c) {
     T* p = AXIS == 0 ? base + c : base + 5 * c * P;
     if (WRITE) {
-      p[0] = U[c].r; p[vn * P] = U[c].mn; p[vt1 * P] = U[c].mt1; p[3 * P] = U[c].mt2;
+      p[0] = U[c].r; p[vn * P] = U[c].mn; p[vt1 * P] = U[c].mt1; p[vt2 * P] = U[c].mt2;
       p[4 * P] = U[c].e;
     } else {
-      U[c] = Cons<T>{p[0], p[vn * P], p[vt1 * P], p[3 * P], p[4 * P]};
+      U[c] = Cons<T>{p[0], p[vn * P], p[vt1 * P], p[vt2 * P], p[4 * P]};
     }
   }
 }
 
-// One sweep along AXIS (0: x, 1: y) of the pencils [p0, p1) of the plane
-// (rows for AXIS 0, columns for AXIS 1).  Pencils of n cells take n/V
-// lanes; a wave holds 64/(n/V) pencils, laid out so that the lanes of equal
-// place in their pencils sit together (for AXIS 1 they then read consecutive
-// x).  The input comes from LDS, or for the x sweep of an x-first step
+// One sweep along AXIS (0: x, 1: y, 2: z) of the pencils [p0, p1) of the
+// plane (rows for AXIS 0, columns of the plane's second axis for AXIS 1 or
+// 2; the launch puts that axis's gravity in grav_y).  Pencils of n cells
+// take n/V lanes; a wave holds 64/(n/V) pencils, laid out so that the lanes
+// of equal place in their pencils sit together (along the second axis they
+// then read consecutive x).  The input comes from LDS, or for the x sweep of an x-first step
 // straight from memory (GSRC); the result goes to LDS, or for the x sweep of
 // a y-first step straight to memory (GDST, the written part only): a row
 // run is a coalesced vector access, so those two sweeps skip a copy through
@@ -1334,7 +1359,8 @@ template <class T, int V, int AXIS, bool GSRC, bool GDST, bool TOT = false, clas
 __device__ void plane_sweep(const SweepArgs<T>& a, const M& m, const PatchDev& P, int p0, int p1,
                             T* lds, bool do_cfl, double dt, T& smax, bool& bad,
                             TotR* tot = nullptr) {
-  const int n = m.n(AXIS);                // pencil length
+  constexpr int LA = AXIS == 0 ? 0 : 1;   // the plane axis the pencils run along
+  const int n = m.n(LA);                  // pencil length
   const int LPP = n / V, ppw = 64 / LPP;  // lanes per pencil, pencils per wave
   const int l = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int gl = l / ppw, col = l - gl * ppw, last = LPP - 1;
@@ -1343,10 +1369,10 @@ __device__ void plane_sweep(const SweepArgs<T>& a, const M& m, const PatchDev& P
   const SweepConst<T> k = make_const<T>(dt, P.dx[AXIS], a.gamma, AXIS == 0 ? a.grav : a.grav_y);
   T id[3];
   inv_widths<T>(P, id);
-  const int blo = m.bc_lo(AXIS), bhi = m.bc_hi(AXIS);
+  const int blo = m.bc_lo(LA), bhi = m.bc_hi(LA);
   const int mstep = nw * ppw;
   // the written part: runs along the pencil, and pencils
-  const int rlo = m.lo(AXIS), rhi = m.hi(AXIS), plo = m.lo(1 - AXIS), phi = m.hi(1 - AXIS);
+  const int rlo = m.lo(LA), rhi = m.hi(LA), plo = m.lo(1 - LA), phi = m.hi(1 - LA);
   Cons<T> Un[V];  // GSRC: the next pass's runs, loaded one pass ahead
   if (GSRC && gl < LPP && p0 + wave * ppw + col < p1)
     row_run<T, V, false>(m.at(m.src(), gl * V, p0 + wave * ppw + col), m.plane(), Un);
@@ -1372,9 +1398,10 @@ __device__ void plane_sweep(const SweepArgs<T>& a, const M& m, const PatchDev& P
                                smax, bad);
     if (TOT && wr) {
 #pragma unroll
-      for (int c = 0; c < V; ++c)
-        tot_add<T, AXIS>(*tot, U[c], P, a.gvec, m.gx(AXIS == 0 ? gl * V + c : pen),
-                         m.gy(AXIS == 0 ? pen : gl * V + c), m.z);
+      for (int c = 0; c < V; ++c) {
+        const int3 q = m.cell(LA == 0 ? gl * V + c : pen, LA == 0 ? pen : gl * V + c);
+        tot_add<T, AXIS>(*tot, U[c], P, a.gvec, q.x, q.y, q.z);
+      }
     }
     if (GDST) {
       if (wr && !(TOT && a.tonly)) row_run<T, V, true>(m.at(m.dst(), gl * V, pen), m.plane(), U);
@@ -1396,7 +1423,8 @@ __device__ void plane_totals(const SweepArgs<T>& a, const M& m, const PatchDev& 
     const int yy = c / wx, x = x0 + c - yy * wx, y = y0 + yy;
     const T* p = lds + 5 * y * PP + plane_col<V>(x, y);
     const Cons<T> U{p[0], p[PP], p[2 * PP], p[3 * PP], p[4 * PP]};  // x frame: lab order
-    tot_add<T, 0>(tot, U, P, a.gvec, m.gx(x), m.gy(y), m.z);
+    const int3 q = m.cell(x, y);
+    tot_add<T, 0>(tot, U, P, a.gvec, q.x, q.y, q.z);
   }
 }
 
@@ -1470,6 +1498,46 @@ __global__ void __launch_bounds__(512) sweep_plane_kernel(SweepArgs<T> a) {
 __device__ __forceinline__ int xcd_item(int i, int n) {
   const int q = n >> 3, r = n & 7, x = i & 7, k = i >> 3;
   return x * q + (x < r ? x : r) + k;
+}
+
+// The z sweep of a batch as lane runs in LDS: a work item is one x-z plane
+// (y = tile) of one patch (nx <= 64; <= 80 KiB), loaded whole (rows of x,
+// coalesced), swept along z (the column pencils of the plane), and stored
+// back.  Unlike the column march it recomputes nothing at segment edges
+// (patches are 16-64 cells along z).  Persistent like the plane kernel; TOT
+// adds the plane in LDS before copying it out.
+template <class T, int V, bool TOT>
+__global__ void __launch_bounds__(512) sweep_zplane_kernel(SweepArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  T* lds = reinterpret_cast<T*>(dyn_lds);
+  int* slot = reinterpret_cast<int*>(dyn_lds);  // free between items
+  const double dt0 = (TOT && a.tonly) ? 0.0 : a.scal->dt;
+  const bool store = !(TOT && a.tonly);
+  const bool grav = has_grav(a.gvec);
+  T smax = T(0);
+  bool bad = false;
+  TotR tot;
+  tot.zero();
+  for (int i = 0;; ++i) {
+    const int it = item_at(a, i, &a.scal->tickets[2], slot);
+    if (it >= a.nitems) break;
+    const WorkItem w = a.items[it];
+    const PatchDev P = a.patches[w.patch];
+    const PatchZPlane<T> m{a, P, w.tile};
+    plane_copy<T, V, true>(m, lds);
+    __syncthreads();
+    plane_sweep<T, V, 2, false, false>(a, m, P, 0, m.n(0), lds, a.do_cfl != 0,
+                                       item_dt(a, w.patch, dt0), smax, bad);
+    __syncthreads();
+    if (TOT) plane_totals<T, V>(a, m, P, lds, tot);
+    if (store) plane_copy<T, V, false>(m, lds);
+    __syncthreads();  // the LDS is free again
+    if (TOT)
+      tot_block_wide(tot, cell_volume(P), a.tpart + 6 * int64_t(it),
+                     reinterpret_cast<double*>(dyn_lds), grav);
+    item_cfl(a, w.patch, smax, lds);
+  }
+  finish_block(a.scal, smax, bad, a.do_cfl != 0 && !a.pdt, lds);
 }
 
 // The fused x and y sweeps of a single grid, window by window (WinDev):
@@ -2182,6 +2250,27 @@ static hipError_t launch_window_v(const LaunchSweep& L, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <class T, int V, bool TOT>
+static hipError_t launch_zplane_v(const LaunchSweep& L, hipStream_t st) {
+  const SweepArgs<T> a = to_args<T>(L);
+  const size_t lds = std::max(size_t(L.plane_lds), TOT ? size_t(kTotWideBytes) * L.cfg.block : 0);
+  hipLaunchKernelGGL((sweep_zplane_kernel<T, V, TOT>), dim3(L.nblocks), dim3(L.cfg.block), lds,
+                     st, a);
+  return hipGetLastError();
+}
+
+template <class T, bool TOT>
+static hipError_t launch_zplane(const LaunchSweep& L, hipStream_t st) {
+  if (L.plane_lds <= 0 || L.plane_lds > kPlaneLdsBytes || !L.persistent)
+    return hipErrorInvalidValue;
+  switch (L.cfg.v) {
+    case 1: return launch_zplane_v<T, 1, TOT>(L, st);
+    case 2: return launch_zplane_v<T, 2, TOT>(L, st);
+    case 4: return launch_zplane_v<T, 4, TOT>(L, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 // Window sweeps: FP32 (a 64 x 64 FP32 plane is the LDS share of a
 // workgroup), V = 1 or 2 (window origins are even cells).
 template <class T, bool TOT>
@@ -2205,6 +2294,7 @@ static hipError_t launch_window(const LaunchSweep& L, hipStream_t st) {
 template <class T, bool TOT>
 static hipError_t launch_sweep_tt(const LaunchSweep& L, hipStream_t st) {
   if (L.plane == kWinXY || L.plane == kWinYX) return launch_window<T, TOT>(L, st);
+  if (L.plane == kZPlane) return launch_zplane<T, TOT>(L, st);
   if (L.plane != kPlaneNone) return launch_plane<T, TOT>(L, st);
   if (L.persistent) {
     dim3 grid(L.nblocks);
@@ -2404,11 +2494,11 @@ hipError_t launch_reset_tickets(DevScalars* s, hipStream_t st) {
 // lanes; longer pencils span several waves of one workgroup
 bool x_wave_ok(int n, int v) { return n % v == 0 && n / v <= 64; }
 
-// LDS bytes of one z-plane of a patch in the fused plane sweeps (0 if it does
-// not fit in a workgroup's share)
-int plane_lds_bytes(const PatchDev& P, int fp64) {
+// LDS bytes of one z-plane (second axis 1) or x-z plane (second axis 2) of
+// a patch in the plane sweeps (0 if it does not fit in a workgroup's share)
+int plane_lds_bytes(const PatchDev& P, int fp64, int axis2) {
   if (P.n[0] > kPlanePitch) return 0;
-  const int64_t b = int64_t(5) * kPlanePitch * P.n[1] * (fp64 ? 8 : 4);
+  const int64_t b = int64_t(5) * kPlanePitch * P.n[axis2] * (fp64 ? 8 : 4);
   return b <= kPlaneLdsBytes ? int(b) : 0;
 }
 

@@ -15,6 +15,7 @@ constexpr int kPlaneXY = 1;    // fused x then y sweeps of patch z-planes
 constexpr int kPlaneYX = 2;    // fused y then x sweeps of patch z-planes
 constexpr int kWinXY = 3;      // fused x then y sweeps of single-grid windows
 constexpr int kWinYX = 4;      // fused y then x sweeps of single-grid windows
+constexpr int kZPlane = 5;     // z sweep of patch x-z planes in LDS (batches)
 
 struct LaunchSweep {
   // pool: state or patch pool; patches/items: device tables (persistent)
@@ -240,6 +241,6 @@ int64_t x_grid(const PatchDev& P, const SweepCfg& c);
 int64_t col_tiles(const PatchDev& P, int axis, const SweepCfg& c);
 bool x_wave_ok(int n, int v);
 int64_t x_pencils_per_tile(const PatchDev& P, const SweepCfg& c);
-int plane_lds_bytes(const PatchDev& P, int fp64);
+int plane_lds_bytes(const PatchDev& P, int fp64, int axis2 = 1);
 
 }  // namespace hydro

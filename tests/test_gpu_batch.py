@@ -223,3 +223,54 @@ def test_per_patch_dt_lands_every_patch_on_t_end():
         np.testing.assert_array_equal(ic.patch_view(out, p), host(sd))
         g.close()
     b.close()
+
+
+# --------------------------------------------------- z sweep over x-z planes
+
+ZP_CASES = [
+    ((ic.PERIODIC,) * 6, (0.0, 0.0, 0.0)),
+    ((ic.PERIODIC, ic.PERIODIC, ic.OUTFLOW, ic.OUTFLOW, ic.REFLECT, ic.REFLECT), (0.0, 0.0, -0.7)),
+    ((ic.OUTFLOW,) * 4 + (ic.OUTFLOW, ic.REFLECT), (0.2, 0.0, 0.4)),
+]
+
+
+@pytest.mark.parametrize("v,block", [(1, 256), (2, 512), (4, 256)])
+@pytest.mark.parametrize("bc,grav", ZP_CASES)
+@pytest.mark.parametrize("prec", [hydro.FP32, hydro.FP64])
+def test_zplane_z_sweep_equals_column_march_bitwise(prec, bc, grav, v, block):
+    # the z sweep as lane runs over x-z planes in LDS gives the bits of the
+    # z march, for every boundary kind at the z ends and gravity along z,
+    # over both Strang orders with the CFL dt; FP64 patches up to 32 cells
+    # along z fit the LDS share
+    say(f"zplane prec {prec} bc {bc} grav {grav} v {v} b {block}")
+    sizes = (16, 32) if prec == hydro.FP64 else (16, 32, 48, 64)
+    specs = ic.batch_specs(10, seed=8, sizes=sizes)
+    dt = np.float64 if prec == hydro.FP64 else np.float32
+    pool, patches = ic.batch_pool(specs, ng=4, dtype=dt, pad_rows=32)
+    runs = []
+    for cfg in (f"p:z=1;u:v={v},b={block}", "p:z=0"):
+        dev = torch().from_numpy(pool.copy()).to("cuda:0")
+        b = hydro.Batch(dev, patches, GAMMA, 0.8, bc, grav, flags=hydro.FLAG_NO_TUNE)
+        b.config = cfg
+        assert ("z=1" in b.config) == cfg.startswith("p:z=1"), b.config
+        for _ in range(4):
+            b.step()
+        assert b.error() == hydro.HYDRO_OK
+        runs.append((host(dev), b.time(), b.totals()))
+        b.close()
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert runs[0][1] == runs[1][1]
+    scale = np.abs(runs[1][2]).max() + 1.0
+    assert np.all(np.abs(np.array(runs[0][2]) - np.array(runs[1][2])) <= 1e-13 * scale)
+
+
+def test_zplane_rejected_where_a_plane_does_not_fit():
+    # FP64 x-z planes of 48 or 64 cells along z exceed a workgroup's LDS share
+    specs = ic.batch_specs(6, seed=9, sizes=(48, 64))
+    pool, patches = ic.batch_pool(specs, ng=4, dtype=np.float64, pad_rows=32)
+    dev = torch().from_numpy(pool).to("cuda:0")
+    b = hydro.Batch(dev, patches, GAMMA, flags=hydro.FLAG_NO_TUNE)
+    with pytest.raises(hydro.HydroError) as e:
+        b.config = "p:z=1;u:v=2,b=512"
+    assert e.value.status == hydro.HYDRO_EINVAL
+    b.close()

@@ -270,6 +270,44 @@ def test_turbulence768_fp64_tuned_and_wide_x_lane_runs(turb768):
 
 
 
+
+def test_turbulence768_fp32_fused_step(turb768):
+    """The benchmark's FP32 launch configuration: the fused x+y step (64 x 64
+    windows written to the second buffer, the z march writing back) in the
+    configuration its tuner keeps, two steps (both Strang orders) at the
+    oracle's dt.  The whole state equals the separate sweeps' bit for bit
+    (compared on the device), and sampled 12^3 blocks match the oracle."""
+    P = turb768
+    U32 = P.U.astype(np.float32)
+    p = oracle.make_params(P.shape, P.dx, P.gamma, P.cfl, P.bc, P.grav, nthreads=THREADS)
+    dt = oracle.cfl_dt(p, U32.astype(np.float64))
+    t = torch()
+    src = t.from_numpy(U32).to("cuda:0")
+    out = []
+    for flags, cfg in ((hydro.FLAG_NO_TUNE | hydro.FLAG_FUSE_XY,
+                        "x:v=4,b=256,m=1;y:q=256,s=2;z:q=128,s=4;p:f=1;w:v=2,b=512"),
+                       (hydro.FLAG_NO_TUNE, "x:v=4,b=256,m=1;y:q=256,s=2;z:q=128,s=4")):
+        dev = src.clone()
+        g = hydro.Grid(dev, P.dx, P.gamma, P.cfl, P.bc, P.grav, flags=flags)
+        g.config = cfg
+        say(f"turbulence 768 fp32 {g.config}")
+        g.step(dt)
+        g.step(dt)
+        t.cuda.synchronize()
+        assert g.error() == hydro.HYDRO_OK
+        out.append((dev, g.totals()))
+        g.close()
+    assert bool(t.equal(out[0][0], out[1][0]))
+    for v in range(6):
+        assert abs(out[0][1][v] - out[1][1][v]) <= 1e-12 * max(1.0, abs(out[1][1][v]))
+    rng = np.random.default_rng(7)
+    corners = [tuple(int(v) for v in rng.integers(0, 768, size=3)) for _ in range(4)]
+    for corner, got, want in _turb_blocks(P, U32, out[0][0], dt, corners, 12, 2):
+        e = l1_fp32_errors(got, want)
+        assert max(e) <= 4e-6, (corner, e)
+    del out, src
+    t.cuda.empty_cache()
+
 @pytest.mark.parametrize("prec", [hydro.FP64, hydro.FP32])
 def test_turbulence768_shell_spectrum(turb768, prec):
     """The shell spectrum at full size: the initial data's closed form
