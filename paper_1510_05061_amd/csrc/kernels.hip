@@ -1185,25 +1185,41 @@ __device__ __forceinline__ void copy_run(T* dst, const T* src) {
     *reinterpret_cast<vec*>(dst + h * H) = *reinterpret_cast<const vec*>(src + h * H);
 }
 
-// A row run: V consecutive elements of each of the five variables from g
-// (variable 0 at g, variable v at g + v plane), rotated into the x frame,
-// between registers and memory.
-template <class T, int V, bool WRITE>
-__device__ __forceinline__ void row_run(T* g, int64_t plane, Cons<T> (&U)[V]) {
-  T* p[5];
+// The five plane bases of a grid or patch (wave-uniform) for row runs
+// addressed by one 32-bit byte offset (planes stay below 4 GiB).
+template <class T>
+struct RowBases {
+  char* p[5];
+};
+
+template <class T>
+__device__ __forceinline__ RowBases<T> row_bases(T* buf, int64_t base0, int64_t plane) {
+  RowBases<T> b;
+  char* p0 = reinterpret_cast<char*>(buf + base0);
 #pragma unroll
-  for (int v = 0; v < 5; ++v) p[v] = g + int64_t(v) * plane;
+  for (int v = 0; v < 5; ++v) b.p[v] = p0 + v * plane * int64_t(sizeof(T));
+  return b;
+}
+
+// A row run: V consecutive elements of each of the five variables at
+// B.p[v] + off, rotated into the x frame, between registers and memory: a
+// wave-uniform base and one offset register per run, no 64-bit address
+// arithmetic per run.
+template <class T, int V, bool WRITE>
+__device__ __forceinline__ void row_run_off(const RowBases<T>& B, uint32_t off,
+                                            Cons<T> (&U)[V]) {
   T r[V], mn[V], mt1[V], mt2[V], e[V];
+  auto at = [&](int v) { return reinterpret_cast<T*>(B.p[v] + off); };
   if (WRITE) {
 #pragma unroll
     for (int c = 0; c < V; ++c) {
       r[c] = U[c].r; mn[c] = U[c].mn; mt1[c] = U[c].mt1; mt2[c] = U[c].mt2; e[c] = U[c].e;
     }
-    copy_run<T, V>(p[0], r); copy_run<T, V>(p[1], mn); copy_run<T, V>(p[2], mt1);
-    copy_run<T, V>(p[3], mt2); copy_run<T, V>(p[4], e);
+    copy_run<T, V>(at(0), r); copy_run<T, V>(at(1), mn); copy_run<T, V>(at(2), mt1);
+    copy_run<T, V>(at(3), mt2); copy_run<T, V>(at(4), e);
   } else {
-    copy_run<T, V>(r, p[0]); copy_run<T, V>(mn, p[1]); copy_run<T, V>(mt1, p[2]);
-    copy_run<T, V>(mt2, p[3]); copy_run<T, V>(e, p[4]);
+    copy_run<T, V>(r, at(0)); copy_run<T, V>(mn, at(1)); copy_run<T, V>(mt1, at(2));
+    copy_run<T, V>(mt2, at(3)); copy_run<T, V>(e, at(4));
 #pragma unroll
     for (int c = 0; c < V; ++c) U[c] = Cons<T>{r[c], mn[c], mt1[c], mt2[c], e[c]};
   }
@@ -1236,6 +1252,10 @@ struct PatchPlane {
   __device__ T* at(T* base, int x, int y) const {
     return base + P.base0 + int64_t(z) * P.sz + int64_t(y) * P.sy + x;
   }
+  __device__ RowBases<T> bases(T* buf) const { return row_bases(buf, P.base0, P.plane); }
+  __device__ uint32_t off(int x, int y) const {
+    return uint32_t(z * P.sz + y * P.sy + x) * uint32_t(sizeof(T));
+  }
 };
 
 // The x-z plane y = yr of a batch patch: the plane's second axis is z (the
@@ -1257,6 +1277,10 @@ struct PatchZPlane {
   __device__ int64_t plane() const { return P.plane; }
   __device__ T* at(T* base, int x, int y) const {
     return base + P.base0 + int64_t(y) * P.sz + int64_t(yr) * P.sy + x;
+  }
+  __device__ RowBases<T> bases(T* buf) const { return row_bases(buf, P.base0, P.plane); }
+  __device__ uint32_t off(int x, int y) const {
+    return uint32_t(y * P.sz + yr * P.sy + x) * uint32_t(sizeof(T));
   }
 };
 
@@ -1280,6 +1304,10 @@ struct WindowPlane {
   __device__ int64_t plane() const { return G.plane; }
   __device__ T* at(T* base, int x, int y) const {
     return base + G.base0 + int64_t(z) * G.sz + int64_t(gy(y)) * G.sy + gx(x);
+  }
+  __device__ RowBases<T> bases(T* buf) const { return row_bases(buf, G.base0, G.plane); }
+  __device__ uint32_t off(int x, int y) const {
+    return uint32_t(z * G.sz + gy(y) * G.sy + gx(x)) * uint32_t(sizeof(T));
   }
 };
 
@@ -1373,27 +1401,31 @@ __device__ void plane_sweep(const SweepArgs<T>& a, const M& m, const PatchDev& P
   const int mstep = nw * ppw;
   // the written part: runs along the pencil, and pencils
   const int rlo = m.lo(LA), rhi = m.hi(LA), plo = m.lo(1 - LA), phi = m.hi(1 - LA);
+  // rows in memory: wave-uniform plane bases and one byte offset per run
+  const RowBases<T> sb = m.bases(m.src());
   Cons<T> Un[V];  // GSRC: the next pass's runs, loaded one pass ahead
+#pragma unroll
+  for (int c = 0; c < V; ++c) Un[c] = Cons<T>{T(1), T(0), T(0), T(0), T(1)};
+  // lanes past the pencils (pen >= p1, or gl >= LPP when n/V does not divide
+  // 64) work on a valid clamped run: their results are neither stored nor
+  // folded, and shuffles never cross from them into an active pencil
+  const int glr = gl < LPP ? gl : LPP - 1;
   if (GSRC && gl < LPP && p0 + wave * ppw + col < p1)
-    row_run<T, V, false>(m.at(m.src(), gl * V, p0 + wave * ppw + col), m.plane(), Un);
+    row_run_off<T, V, false>(sb, m.off(gl * V, p0 + wave * ppw + col), Un);
   for (int m0 = p0 + wave * ppw; m0 < p1; m0 += mstep) {  // wave-uniform
     const int pen = m0 + col;
     const bool act = gl < LPP && pen < p1;
     const bool wr = act && gl * V >= rlo && gl * V < rhi && pen >= plo && pen < phi;
     Cons<T> U[V];
-    if (act) {
-      if (GSRC) {
+    if (GSRC) {
 #pragma unroll
-        for (int c = 0; c < V; ++c) U[c] = Un[c];
-      } else {
-        plane_run<T, V, AXIS, false>(lds, AXIS == 0 ? gl * V : pen, AXIS == 0 ? pen : gl * V, U);
-      }
+      for (int c = 0; c < V; ++c) U[c] = Un[c];
     } else {
-#pragma unroll
-      for (int c = 0; c < V; ++c) U[c] = Cons<T>{T(1), T(0), T(0), T(0), T(1)};
+      const int penr = pen < p1 ? pen : p1 - 1;
+      plane_run<T, V, AXIS, false>(lds, AXIS == 0 ? glr * V : penr, AXIS == 0 ? penr : glr * V, U);
     }
     if (GSRC && gl < LPP && pen + mstep < p1)
-      row_run<T, V, false>(m.at(m.src(), gl * V, pen + mstep), m.plane(), Un);
+      row_run_off<T, V, false>(sb, m.off(gl * V, pen + mstep), Un);
     lanerun_update<T, V, AXIS>(U, act ? gl : 0, last, srcL, srcR, blo, bhi, k, id, wr, do_cfl,
                                smax, bad);
     if (TOT && wr) {
@@ -1404,7 +1436,7 @@ __device__ void plane_sweep(const SweepArgs<T>& a, const M& m, const PatchDev& P
       }
     }
     if (GDST) {
-      if (wr && !(TOT && a.tonly)) row_run<T, V, true>(m.at(m.dst(), gl * V, pen), m.plane(), U);
+      if (wr && !(TOT && a.tonly)) row_run_off<T, V, true>(m.bases(m.dst()), m.off(gl * V, pen), U);
     } else if (act) {
       plane_run<T, V, AXIS, true>(lds, AXIS == 0 ? gl * V : pen, AXIS == 0 ? pen : gl * V, U);
     }
