@@ -26,7 +26,7 @@ def _batch(count, prec, seed=3, ng=4, flags=hydro.FLAG_NO_TUNE, pad_rows=0):
 
 
 def _single(pool, patch, prec):
-    view = np.ascontiguousarray(ic.patch_view(pool, patch))
+    view = np.array(ic.patch_view(pool, patch), order="C")  # a writable copy
     dev = torch().from_numpy(view).to("cuda:0")
     d = patch[5]
     g = hydro.Grid(dev, (d, d, d), GAMMA, ng=patch[4], flags=hydro.FLAG_NO_TUNE)
