@@ -30,7 +30,10 @@ Prints ONE JSON line.  Fields beyond the driver's contract:
                  when a step fuses the x and y sweeps it moves 80 B per
                  zone-update, given as hbm_bytes_per_zone_update and
                  hbm_achieved;
-  fp64           the FP64 path on the same workload and the FP32 speedup;
+  fp64           the FP64 path on the same workload and the FP32 speedup
+                 (240 B per FP64 zone-update for the roofline; a step that
+                 fuses the x and y sweeps moves 160 B: hbm_bytes_per_zone_update
+                 and hbm_achieved in GB/s);
   copy_ceiling   a plain device copy of the same bytes, for context;
   stream_ceiling an in-place read+write pass over the state with no
                  arithmetic (hydro_stream_ceiling): the memory-only ceiling;
@@ -183,7 +186,7 @@ def build_obj(W, prec, args, torch, hydro, flags=None):
     if flags is None:
         flags = hydro.FLAG_NO_TUNE if args.no_tune else 0
         if W["kind"] == "grid":
-            # let the tuner keep the fused x+y step where it is faster (FP32)
+            # let the tuner keep the fused x+y step where it is faster
             flags |= hydro.FLAG_FUSE_XY
     if W["kind"] == "grid":
         P = W["P"]
@@ -832,6 +835,8 @@ def main():
         fp64 = {"value": zones / sec64, "unit": "zone-updates/s",
                 "ms_per_step": sec64 * 1e3,
                 "step_roofline_frac": zones / sec64 * 240 / (HBM_PEAK_GBS * 1e9),
+                "hbm_bytes_per_zone_update": 160 if "f=1" in cfg64 else 240,
+                "hbm_achieved": zones / sec64 * (160 if "f=1" in cfg64 else 240) / 1e9,
                 "kernel_ms": {"x": k64[0], "y": k64[1], "z": k64[2]},
                 "kernel_gbs": {ax: (zones * 80 / (k64[i] * 1e-3) / 1e9 if k64[i] else 0.0)
                                for i, ax in enumerate("xyz")},

@@ -85,13 +85,15 @@ typedef enum hydro_precision { HYDRO_FP32 = 0, HYDRO_FP64 = 1 } hydro_precision;
                                     time and steps with its own CFL dt (a
                                     suite of independent runs) instead of
                                     one dt, the minimum over patches */
-#define HYDRO_FLAG_FUSE_XY 0x8u /* single FP32 grids with even x and y
-                                    extents >= 64 and an active z axis: allow
-                                    the fused x+y step, which sweeps x and y
-                                    together in 64 x 64 windows of each
-                                    z-plane held in LDS (one pass over HBM
-                                    for two sweeps, the windows overlapping by
-                                    two cells on each side).  The windows
+#define HYDRO_FLAG_FUSE_XY 0x8u /* single grids with even x and y extents,
+                                    x >= 64, y >= 64 (FP32) or 32 (FP64), and
+                                    an active z axis: allow the fused x+y
+                                    step, which sweeps x and y together in
+                                    windows of 64 x 64 FP32 or 64 x 32 FP64
+                                    cells of each z-plane held in LDS (one
+                                    pass over HBM for two sweeps, the windows
+                                    overlapping by two cells on each side).
+                                    The windows
                                     write to a second buffer laid out like the
                                     state, which the workspace then holds
                                     (hydro_workspace_bytes grows by the

@@ -554,7 +554,7 @@ LaunchSweep plane_launch(const hydro_ctx* c, bool xfirst, int do_cfl) {
 // The fused x+y step of a single grid applies (see fuse_eligible) with a
 // window kernel of V = 1 or 2 cells per lane.
 bool win_ok(const hydro_ctx* c, const Config& cf) {
-  if (c->batch || !c->shadow || c->fp64) return false;
+  if (c->batch || !c->shadow) return false;
   const int v = cf.plane.v;
   if (v != 1 && v != 2) return false;
   return cf.plane.block >= 64 && cf.plane.block <= kMaxBlock && cf.plane.block % 64 == 0;
@@ -1190,16 +1190,17 @@ int read_scalars(hydro_ctx* c, DevScalars* out) {
 // Totals partials of a single grid: the most workgroups any valid
 // configuration launches for a sweep (x: one pencil per workgroup; y, z: 64
 // columns per tile), and at least the standalone reduction's chunks.
-// Windows of the fused x+y step along an axis of n cells: written chunks of
-// kWinEdge - 2 kWinHalo cells.
-int32_t win_count(int32_t n) {
-  const int w = kWinEdge - 2 * kWinHalo;
-  return n >= kWinEdge ? (n + w - 1) / w : 0;
+// Windows of the fused x+y step along an axis of n cells for windows of
+// `edge` cells: written chunks of edge - 2 kWinHalo cells.
+int32_t win_count(int32_t n, int edge) {
+  const int w = edge - 2 * kWinHalo;
+  return n >= edge ? (n + w - 1) / w : 0;
 }
 
 int64_t grid_parts(const int32_t n[3]) {
   int64_t m = kMaxChunks;
-  m = std::max<int64_t>(m, int64_t(win_count(n[0])) * win_count(n[1]) * n[2]);
+  m = std::max<int64_t>(m, int64_t(win_count(n[0], kWinEdge)) * win_count(n[1], win_rows(true)) *
+                               n[2]);
   if (n[0] > 1) m = std::max<int64_t>(m, int64_t(n[1]) * n[2]);
   if (n[1] > 1) m = std::max<int64_t>(m, (int64_t(n[0]) * n[2] + 63) / 64);
   if (n[2] > 1) m = std::max<int64_t>(m, (int64_t(n[0]) * n[1] + 63) / 64);
@@ -1219,12 +1220,13 @@ size_t grid_workspace_bytes(const int32_t n[3]) {
          align_up(size_t(nmax) * kProfileChunksX * 5 * sizeof(double), 256);
 }
 
-// The fused x+y step of a single grid applies to FP32 grids with x and y
-// extents even and >= kWinEdge and an active z axis, whose rows allow runs
-// of two cells (even strides).
+// The fused x+y step of a single grid applies to grids with x and y extents
+// even and at least a window's (kWinEdge along x, win_rows() along y) and
+// an active z axis, whose rows allow runs of two cells (even strides).
 bool fuse_eligible(const hydro_desc& d) {
-  if (!(d.flags & HYDRO_FLAG_FUSE_XY) || d.precision != HYDRO_FP32) return false;
-  if (d.nx < kWinEdge || d.ny < kWinEdge || d.nx % 2 || d.ny % 2 || d.nz < 2) return false;
+  if (!(d.flags & HYDRO_FLAG_FUSE_XY)) return false;
+  const bool fp64 = d.precision == HYDRO_FP64;
+  if (d.nx < kWinEdge || d.ny < win_rows(fp64) || d.nx % 2 || d.ny % 2 || d.nz < 2) return false;
   int32_t n[3] = {d.nx, d.ny, d.nz};
   double dx[3] = {d.dx, d.dy, d.dz};
   const PatchDev P = make_patch(n, d.ng, dx, 0);
@@ -1238,27 +1240,31 @@ size_t fuse_bytes(const hydro_desc& d) {
   int32_t n[3] = {d.nx, d.ny, d.nz};
   double dx[3] = {d.dx, d.dy, d.dz};
   const PatchDev P = make_patch(n, d.ng, dx, 0);
-  const size_t nwin = size_t(win_count(d.nx)) * win_count(d.ny);
-  return align_up(nwin * sizeof(WinDev), 256) + align_up(size_t(P.plane) * 5 * 4, 256);
+  const bool fp64 = d.precision == HYDRO_FP64;
+  const size_t nwin = size_t(win_count(d.nx, kWinEdge)) * win_count(d.ny, win_rows(fp64));
+  return align_up(nwin * sizeof(WinDev), 256) +
+         align_up(size_t(P.plane) * 5 * (fp64 ? 8 : 4), 256);
 }
 
 // The windows of a z-plane: along each axis, written chunks [w i, w (i+1))
-// (the last one shorter), w = kWinEdge - 2 kWinHalo; a window starts
+// (the last one shorter), w = edge - 2 kWinHalo with edge = kWinEdge along
+// x and win_rows() along y; a window starts
 // kWinHalo cells before its chunk, wrapped on a periodic axis, or clamped
 // into the domain on a non-periodic one, where its pencil ends at a domain
 // edge take the boundary condition (elsewhere the ends are discarded).
-std::vector<WinDev> build_windows(const int32_t n[3], const int32_t bc[6]) {
+std::vector<WinDev> build_windows(const int32_t n[3], const int32_t bc[6], bool fp64) {
   struct Span { int32_t start, lo, hi, blo, bhi; };
   auto spans = [&](int axis) {
     std::vector<Span> out;
-    const int N = n[axis], w = kWinEdge - 2 * kWinHalo;
+    const int edge = axis == 0 ? kWinEdge : win_rows(fp64);
+    const int N = n[axis], w = edge - 2 * kWinHalo;
     const bool per = bc[2 * axis] == HYDRO_BC_PERIODIC;
     for (int o = 0; o < N; o += w) {
       const int e = std::min(N, o + w);
-      const int start = per ? o - kWinHalo : std::max(0, std::min(o - kWinHalo, N - kWinEdge));
+      const int start = per ? o - kWinHalo : std::max(0, std::min(o - kWinHalo, N - edge));
       Span sp{start, o - start, e - start, HYDRO_BC_PERIODIC, HYDRO_BC_PERIODIC};
       if (!per && start == 0) sp.blo = bc[2 * axis];
-      if (!per && start + kWinEdge == N) sp.bhi = bc[2 * axis + 1];
+      if (!per && start + edge == N) sp.bhi = bc[2 * axis + 1];
       out.push_back(sp);
     }
     return out;
@@ -1444,7 +1450,7 @@ int hydro_init(const hydro_desc* d, void* state, size_t state_bytes, void* works
     return fail(HYDRO_EINVAL, "no valid x-sweep configuration for this width");
   }
   if (fuse_eligible(*d)) {
-    const std::vector<WinDev> wins = build_windows(n, d->bc);
+    const std::vector<WinDev> wins = build_windows(n, d->bc, d->precision == HYDRO_FP64);
     char* f = c->ws + grid_workspace_bytes(n);
     c->d_wins = reinterpret_cast<WinDev*>(f);
     c->nwin = int32_t(wins.size());
@@ -2424,8 +2430,9 @@ int hydro_set_config(hydro_ctx* c, const char* text) {
   if (cf.batch_zplane && !zplane_ok(c, cf))
     return fail(HYDRO_EINVAL, "the x-z plane z sweep does not apply to these patches");
   if (cf.batch_fuse && !c->batch && !win_ok(c, cf))
-    return fail(HYDRO_EINVAL, "the fused x+y step does not apply (HYDRO_FLAG_FUSE_XY, FP32, "
-                              "even x and y extents >= 64, active z; w:v=1 or 2)");
+    return fail(HYDRO_EINVAL, "the fused x+y step does not apply (HYDRO_FLAG_FUSE_XY, even x "
+                              "and y extents >= 64 and 64 (FP32) or 32 (FP64), active z; "
+                              "w:v=1 or 2)");
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->cfg = cf;
   if (c->batch) {

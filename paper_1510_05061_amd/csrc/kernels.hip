@@ -1291,7 +1291,7 @@ struct WindowPlane {
   const WinDev& w;
   int z;
   __device__ static int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
-  __device__ int n(int) const { return kWinEdge; }
+  __device__ int n(int axis) const { return axis == 0 ? kWinEdge : win_rows(sizeof(T) == 8); }
   __device__ int bc_lo(int axis) const { return axis == 0 ? w.bx_lo : w.by_lo; }
   __device__ int bc_hi(int axis) const { return axis == 0 ? w.bx_hi : w.by_hi; }
   __device__ int lo(int axis) const { return axis == 0 ? w.ox0 : w.oy0; }
@@ -1582,7 +1582,7 @@ __global__ void __launch_bounds__(512) sweep_zplane_kernel(SweepArgs<T> a) {
 // SIMD (at most 128 registers): the LDS holds two workgroups of eight waves
 // per CU.
 template <class T, int V, bool XFIRST, bool TOT>
-__global__ void __launch_bounds__(512, 4) sweep_window_kernel(SweepArgs<T> a) {
+__global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 2) sweep_window_kernel(SweepArgs<T> a) {
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   T* lds = reinterpret_cast<T*>(dyn_lds);
   const double dt = (TOT && a.tonly) ? 0.0 : a.scal->dt;
@@ -2303,20 +2303,16 @@ static hipError_t launch_zplane(const LaunchSweep& L, hipStream_t st) {
   }
 }
 
-// Window sweeps: FP32 (a 64 x 64 FP32 plane is the LDS share of a
+// Window sweeps (a 64 x 64 FP32 or 64 x 32 FP64 plane is the LDS share of a
 // workgroup), V = 1 or 2 (window origins are even cells).
 template <class T, bool TOT>
 static hipError_t launch_window(const LaunchSweep& L, hipStream_t st) {
-  if constexpr (sizeof(T) != 4) {
+  if (!L.wins || !L.dst || L.nwin < 1 || L.nblocks < 1 || L.nitems % L.nwin)
     return hipErrorInvalidValue;
-  } else {
-    if (!L.wins || !L.dst || L.nwin < 1 || L.nblocks < 1 || L.nitems % L.nwin)
-      return hipErrorInvalidValue;
-    switch (L.cfg.v) {
-      case 1: return launch_window_v<T, 1, TOT>(L, st);
-      case 2: return launch_window_v<T, 2, TOT>(L, st);
-      default: return hipErrorInvalidValue;
-    }
+  switch (L.cfg.v) {
+    case 1: return launch_window_v<T, 1, TOT>(L, st);
+    case 2: return launch_window_v<T, 2, TOT>(L, st);
+    default: return hipErrorInvalidValue;
   }
 }
 

@@ -47,13 +47,16 @@ struct WorkItem {
   int32_t tile;
 };
 
-// A window of the fused x+y sweeps of a single grid: kWinEdge x kWinEdge
-// cells of a z-plane whose inner part is written.  The sweeps need two
-// cells on each side of a written cell, so a window reaches two cells past
-// its written part, except where it meets a domain edge that is not
-// periodic (there the pencil ends apply that boundary condition).
+// A window of the fused x+y sweeps of a single grid: kWinEdge cells along
+// x by win_rows() rows along y of a z-plane, whose inner part is written
+// (64 x 64 FP32 cells or 64 x 32 FP64 cells: 80 KiB of LDS either way).
+// The sweeps need two cells on each side of a written cell, so a window
+// reaches two cells past its written part, except where it meets a domain
+// edge that is not periodic (there the pencil ends apply that boundary
+// condition).
 constexpr int kWinEdge = 64;
 constexpr int kWinHalo = 2;
+constexpr int win_rows(bool fp64) { return fp64 ? 32 : 64; }
 struct WinDev {
   int32_t x0, y0;          // cell (0, 0) of the window in the grid (wrapped on
                            // periodic axes: x0 may be -2)

@@ -226,12 +226,13 @@ def test_turbulence768_fp32_sampled_blocks(turb768):
     torch().cuda.empty_cache()
 
 
-def test_turbulence768_fp64_tuned_and_wide_x_lane_runs(turb768):
+def test_turbulence768_fp64_tuned_fused_and_wide_x_lane_runs(turb768):
     """The FP64 path at 768^3 in the autotuned configuration bench.py times
-    and with x lane runs of 4 cells over three waves per pencil
+    (the fused x+y step allowed), the fused step forced (64 x 32 windows) and
+    separate sweeps with x lane runs of 4 cells over three waves per pencil
     (x:v=4,b=192): two steps at the oracle's dt, sampled 12^3 blocks against
-    the oracle to 1e-12 of the grid's scale, and the two configurations bit
-    for bit equal on the sampled blocks."""
+    the oracle to 1e-12 of the grid's scale, and the configurations bit for
+    bit equal on the sampled blocks."""
     P = turb768
     p = oracle.make_params(P.shape, P.dx, P.gamma, P.cfl, P.bc, P.grav, nthreads=THREADS)
     dt = oracle.cfl_dt(p, P.U)
@@ -241,9 +242,12 @@ def test_turbulence768_fp64_tuned_and_wide_x_lane_runs(turb768):
     rng = np.random.default_rng(5)
     corners = [tuple(int(v) for v in rng.integers(0, 768, size=3)) for _ in range(6)]
     first = None
-    for cfg in (None, "x:v=4,b=192"):
+    for flags, cfg in ((hydro.FLAG_FUSE_XY, None),
+                       (hydro.FLAG_NO_TUNE | hydro.FLAG_FUSE_XY,
+                        "x:v=4,b=192;y:q=256,s=1;z:q=256,s=1;p:f=1;w:v=2,b=256"),
+                       (0, "x:v=4,b=192")):
         dev = src.clone()
-        g = hydro.Grid(dev, P.dx, P.gamma, P.cfl, P.bc, P.grav)
+        g = hydro.Grid(dev, P.dx, P.gamma, P.cfl, P.bc, P.grav, flags=flags)
         if cfg:
             g.config = cfg
         say(f"turbulence 768 fp64 {g.config}")
