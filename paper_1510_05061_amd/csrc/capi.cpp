@@ -420,6 +420,8 @@ bool items_current(const hydro_ctx* c) {
   return !c->batch || std::memcmp(c->items_cfg.ax, c->cfg.ax, sizeof(c->cfg.ax)) == 0;
 }
 
+constexpr int64_t kTotCellsPerBlock = 24576;
+
 LaunchSweep sweep_launch(const hydro_ctx* c, int axis, int do_cfl) {
   LaunchSweep L{};
   L.pool = c->pool;
@@ -440,7 +442,18 @@ LaunchSweep sweep_launch(const hydro_ctx* c, int axis, int do_cfl) {
   L.cfg = c->cfg.ax[axis];
   L.persistent = c->batch ? 1 : 0;
   L.fp64 = c->fp64;
-  L.tot_cap = 16 * std::max(1, c->cu_count);  // totals: x workgroups stride over tiles
+  // totals: the direct x launches stride their workgroups over the tiles so
+  // that one partial covers many pencils: about kTotCellsPerBlock cells per
+  // workgroup (measured best from 16.8 M to 453 M cells), as a power of two
+  // from 2 to 64 workgroups per CU (the same number on every CU)
+  {
+    const int cu = std::max(1, c->cu_count);
+    const double cells = double(c->single.n[0]) * c->single.n[1] * c->single.n[2];
+    const double per_cu = cells / (double(kTotCellsPerBlock) * cu);
+    int m = 2;
+    while (m < 64 && per_cu > 1.4142135623730951 * m) m *= 2;  // nearest power of two
+    L.tot_cap = m * cu;
+  }
   if (c->pp_live) {
     L.pdt = c->pdt;
     L.psmax = c->psmax;
