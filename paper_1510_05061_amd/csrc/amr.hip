@@ -145,7 +145,8 @@ __global__ void __launch_bounds__(kAmrBlock) fill_ghosts_kernel(AmrArgs<T> a) {
   }
 }
 
-// Coarse cells covered by the fine patch of link blockIdx.y.
+// Coarse cells covered by the fine patch of link blockIdx.y, variable
+// blockIdx.z.
 template <class T>
 __global__ void __launch_bounds__(kAmrBlock) restrict_kernel(AmrArgs<T> a) {
   const AmrLink L = link_of(a);
@@ -162,8 +163,8 @@ __global__ void __launch_bounds__(kAmrBlock) restrict_kernel(AmrArgs<T> a) {
     const int64_t fb = int64_t(2 * i) + int64_t(2 * j) * F.sy + int64_t(2 * k) * F.sz;
     const int64_t cb = int64_t(L.ox + int(i)) + int64_t(L.oy + int(j)) * C.sy +
                        int64_t(L.oz + int(k)) * C.sz;
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
+    {
+      const int v = int(blockIdx.z);
       const T* f = f0 + fb + v * F.plane;
       double s = 0.0;
       bool first = true;
@@ -188,9 +189,11 @@ __device__ __forceinline__ double mc_slope(double a, double b) {
   return a * b > 0.0 ? copysign(m, a) : 0.0;
 }
 
-// Fine cells (interior, or the stored ghost shell) of link blockIdx.y, one
-// coarse parent per thread: the parent's value and its three limited slopes
-// are formed once and give each of its children that is written.
+// Fine cells (interior, or the stored ghost shell) of link blockIdx.y and
+// variable blockIdx.z, one coarse parent per thread: the parent's value and
+// its three limited slopes are formed once and give each of its children
+// that is written (the variables in parallel: five times the threads of a
+// loop over them, for a latency-bound gather).
 template <class T, bool COLD>
 __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
   const AmrLink L = link_of(a);
@@ -200,8 +203,23 @@ __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
   // parents of the fine cells -g .. n + g - 1 along each axis
   const int lo = (-g) >> 1;
   const unsigned px = unsigned(((nx + g - 1) >> 1) - lo + 1);
-  const unsigned pxy = px * unsigned(((ny + g - 1) >> 1) - lo + 1);
-  const unsigned total = pxy * unsigned(((nz + g - 1) >> 1) - lo + 1);
+  const unsigned py = unsigned(((ny + g - 1) >> 1) - lo + 1);
+  const unsigned pz = unsigned(((nz + g - 1) >> 1) - lo + 1);
+  const unsigned pxy = px * py;
+  // ghosts only: the parents outside the block of parents [0, (n + 1) / 2)
+  // along some axis (the others have every child in the interior), as three
+  // parts: whole planes below and above the block along z; within the
+  // block's z range, whole rows below and above it along y; within both,
+  // the cells below and above it along x
+  const unsigned ix = unsigned((nx + 1) >> 1), iy = unsigned((ny + 1) >> 1),
+                 iz = unsigned((nz + 1) >> 1);
+  const unsigned oz = pz - iz, oy = py - iy, ox = px - ix;
+  const unsigned nz_part = oz * pxy, ny_part = iz * oy * px;
+  const unsigned total = a.ghosts_only ? pxy * pz - ix * iy * iz : pxy * pz;
+  // t-th parent outside the block [0, I) along an axis: lo .. -1, then I ..
+  auto outside = [&](unsigned t, unsigned I) {
+    return int(t) < -lo ? lo + int(t) : int(I) + int(t) + lo;
+  };
   T* f0 = a.fpool + F.base0;
   const T* c0 = a.pool + C.base0;
   const T* o0 = COLD ? a.cold + C.base0 : nullptr;
@@ -209,17 +227,38 @@ __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
   if (blockIdx.x * kAmrBlock >= total) return;
   for (unsigned c = blockIdx.x * kAmrBlock + threadIdx.x; c < total;
        c += gridDim.x * kAmrBlock) {
-    const unsigned kk = c / pxy, rem = c - kk * pxy;
-    const unsigned jj = rem / px;
-    const int pk = int(kk) + lo, pj = int(jj) + lo, pi = int(rem - jj * px) + lo;
-    // a parent whose children are all interior has none in the ghost shell
-    if (a.ghosts_only && pi >= 0 && 2 * pi < nx && pj >= 0 && 2 * pj < ny && pk >= 0 &&
-        2 * pk < nz)
-      continue;
+    int pi, pj, pk;
+    if (!a.ghosts_only) {
+      const unsigned kk = c / pxy, rem = c - kk * pxy;
+      const unsigned jj = rem / px;
+      pk = int(kk) + lo;
+      pj = int(jj) + lo;
+      pi = int(rem - jj * px) + lo;
+    } else if (c < nz_part) {
+      const unsigned kk = c / pxy, rem = c - kk * pxy;
+      const unsigned jj = rem / px;
+      pk = outside(kk, iz);
+      pj = int(jj) + lo;
+      pi = int(rem - jj * px) + lo;
+    } else if (c < nz_part + ny_part) {
+      const unsigned d = c - nz_part, row = oy * px;
+      const unsigned kk = d / row, rem = d - kk * row;
+      const unsigned jj = rem / px;
+      pk = int(kk);
+      pj = outside(jj, iy);
+      pi = int(rem - jj * px) + lo;
+    } else {
+      const unsigned d = c - nz_part - ny_part, row = iy * ox;
+      const unsigned kk = d / row, rem = d - kk * row;
+      const unsigned jj = rem / ox;
+      pk = int(kk);
+      pj = int(jj);
+      pi = outside(rem - jj * ox, ix);
+    }
     const int64_t pc = int64_t(L.ox + pi) + int64_t(L.oy + pj) * C.sy +
                        int64_t(L.oz + pk) * C.sz;
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
+    {
+      const int v = int(blockIdx.z);
       const T* q = c0 + pc + v * C.plane;
       const T* qo = COLD ? o0 + pc + v * C.plane : nullptr;
       // coarse value at offset d, interpolated in time when a start copy is given
@@ -251,9 +290,9 @@ __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
   }
 }
 
-// Copy of the coarse cells within a.margin of the box link blockIdx.y
-// covers (every cell its ghost prolongation reads), into a.cold at the
-// pool's offsets.  Boxes of neighbouring links may overlap; they copy the
+// Copy of the coarse cells (variable blockIdx.z) within a.margin of the box
+// link blockIdx.y covers (every cell its ghost prolongation reads), into
+// a.cold at the pool's offsets.  Boxes of neighbouring links may overlap; they copy the
 // same values.
 template <class T>
 __global__ void __launch_bounds__(kAmrBlock) snapshot_kernel(AmrArgs<T> a) {
@@ -270,8 +309,8 @@ __global__ void __launch_bounds__(kAmrBlock) snapshot_kernel(AmrArgs<T> a) {
     const unsigned jj = rem / bx;
     const int64_t cell = int64_t(L.ox - m + int(rem - jj * bx)) +
                          int64_t(L.oy - m + int(jj)) * C.sy + int64_t(L.oz - m + int(kk)) * C.sz;
-#pragma unroll
-    for (int v = 0; v < 5; ++v) o0[cell + v * C.plane] = c0[cell + v * C.plane];
+    const int64_t vc = cell + int64_t(blockIdx.z) * C.plane;  // variable blockIdx.z
+    o0[vc] = c0[vc];
   }
 }
 
@@ -543,17 +582,19 @@ static hipError_t launch_amr_t(const LaunchAmr& L, hipStream_t st) {
     const unsigned nx = L.patches ? std::min(amr_blocks(L.cells), 32u) : amr_blocks(L.cells);
     hipLaunchKernelGGL(fill_ghosts_kernel<T>, dim3(nx, ny), dim3(kAmrBlock), 0, st, a);
   } else if (L.op == kAmrRestrict) {
-    hipLaunchKernelGGL(restrict_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
+    hipLaunchKernelGGL(restrict_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks), 5u),
                        dim3(kAmrBlock), 0, st, a);
   } else if (L.op == kAmrProlong) {
     if (L.cold)
-      hipLaunchKernelGGL((prolong_kernel<T, true>), dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
-                         dim3(kAmrBlock), 0, st, a);
+      hipLaunchKernelGGL((prolong_kernel<T, true>),
+                         dim3(amr_blocks(L.cells), unsigned(L.nlinks), 5u), dim3(kAmrBlock), 0,
+                         st, a);
     else
-      hipLaunchKernelGGL((prolong_kernel<T, false>), dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
-                         dim3(kAmrBlock), 0, st, a);
+      hipLaunchKernelGGL((prolong_kernel<T, false>),
+                         dim3(amr_blocks(L.cells), unsigned(L.nlinks), 5u), dim3(kAmrBlock), 0,
+                         st, a);
   } else if (L.op == kAmrSnapshot) {
-    hipLaunchKernelGGL(snapshot_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
+    hipLaunchKernelGGL(snapshot_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks), 5u),
                        dim3(kAmrBlock), 0, st, a);
   } else if (L.op == kAmrFlux) {
     hipLaunchKernelGGL(flux_reg_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks), 2u),

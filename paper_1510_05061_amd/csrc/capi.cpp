@@ -2039,6 +2039,20 @@ int check_link(const hydro_ctx* c, const hydro_amr_link& k, bool prolong, bool g
   return HYDRO_OK;
 }
 
+// Coarse parents a prolongation visits for a fine patch of interior
+// extents n: all of them (g = 0), or with g ghost layers only those with a
+// child in the ghost shell (the parents outside the block [0, (n + 1) / 2)
+// along some axis), as the kernel enumerates them.
+int64_t prolong_parents(const int64_t n[3], int64_t g) {
+  const int64_t lo = (-g) >> 1;
+  int64_t box = 1, inner = 1;
+  for (int a = 0; a < 3; ++a) {
+    box *= ((n[a] + g - 1) >> 1) - lo + 1;
+    inner *= (n[a] + 1) >> 1;
+  }
+  return g > 0 ? box - inner : box;
+}
+
 int amr_links(hydro_ctx* c, const hydro_amr_link* links, int32_t n, int op, int ghosts_only) {
   if (!c || (!links && n > 0) || n < 0) return fail(HYDRO_EINVAL, "bad arguments");
   if (!c->batch) return fail(HYDRO_ESTATE, "AMR links join patches of a batch");
@@ -2061,10 +2075,10 @@ int amr_links(hydro_ctx* c, const hydro_amr_link* links, int32_t n, int op, int 
       L.links[i] = AmrLink{k.fine, k.coarse, k.ox, k.oy, k.oz, 0};
       const PatchDev& F = c->patches[size_t(k.fine)];
       // restriction: coarse cells; prolongation: parents of the written cells
-      const int64_t g = (op == kAmrProlong && ghosts_only) ? F.ng : 0;
+      const int64_t nf[3] = {F.n[0], F.n[1], F.n[2]};
       const int64_t cells = op == kAmrRestrict
                                 ? int64_t(F.n[0] / 2) * (F.n[1] / 2) * (F.n[2] / 2)
-                                : (F.n[0] / 2 + g) * (F.n[1] / 2 + g) * (F.n[2] / 2 + g);
+                                : prolong_parents(nf, ghosts_only ? F.ng : 0);
       most = std::max(most, cells);
     }
     L.cells = most;
@@ -2191,7 +2205,7 @@ int level_launch(const hydro_ctx* coarse, const hydro_ctx* fine, const hydro_amr
     if (op == kAmrRestrict) cells = (nf[0] / 2) * (nf[1] / 2) * (nf[2] / 2);
     else if (op == kAmrSnapshot)
       cells = (nf[0] / 2 + 2 * mg) * (nf[1] / 2 + 2 * mg) * (nf[2] / 2 + 2 * mg);
-    else if (op == kAmrProlong) cells = (nf[0] / 2 + g) * (nf[1] / 2 + g) * (nf[2] / 2 + g);
+    else if (op == kAmrProlong) cells = prolong_parents(nf, g);
     else cells = std::max({nf[1] * nf[2], nf[0] * nf[2], nf[0] * nf[1]}) / 4;
     most = std::max(most, cells);
   }
