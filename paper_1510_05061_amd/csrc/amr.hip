@@ -145,8 +145,7 @@ __global__ void __launch_bounds__(kAmrBlock) fill_ghosts_kernel(AmrArgs<T> a) {
   }
 }
 
-// Coarse cells covered by the fine patch of link blockIdx.y, variable
-// blockIdx.z.
+// Coarse cells covered by the fine patch of link blockIdx.y.
 template <class T>
 __global__ void __launch_bounds__(kAmrBlock) restrict_kernel(AmrArgs<T> a) {
   const AmrLink L = link_of(a);
@@ -163,8 +162,8 @@ __global__ void __launch_bounds__(kAmrBlock) restrict_kernel(AmrArgs<T> a) {
     const int64_t fb = int64_t(2 * i) + int64_t(2 * j) * F.sy + int64_t(2 * k) * F.sz;
     const int64_t cb = int64_t(L.ox + int(i)) + int64_t(L.oy + int(j)) * C.sy +
                        int64_t(L.oz + int(k)) * C.sz;
-    {
-      const int v = int(blockIdx.z);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
       const T* f = f0 + fb + v * F.plane;
       double s = 0.0;
       bool first = true;
@@ -290,9 +289,9 @@ __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
   }
 }
 
-// Copy of the coarse cells (variable blockIdx.z) within a.margin of the box
-// link blockIdx.y covers (every cell its ghost prolongation reads), into
-// a.cold at the pool's offsets.  Boxes of neighbouring links may overlap; they copy the
+// Copy of the coarse cells within a.margin of the box link blockIdx.y
+// covers (every cell its ghost prolongation reads), into a.cold at the
+// pool's offsets.  Boxes of neighbouring links may overlap; they copy the
 // same values.
 template <class T>
 __global__ void __launch_bounds__(kAmrBlock) snapshot_kernel(AmrArgs<T> a) {
@@ -309,8 +308,8 @@ __global__ void __launch_bounds__(kAmrBlock) snapshot_kernel(AmrArgs<T> a) {
     const unsigned jj = rem / bx;
     const int64_t cell = int64_t(L.ox - m + int(rem - jj * bx)) +
                          int64_t(L.oy - m + int(jj)) * C.sy + int64_t(L.oz - m + int(kk)) * C.sz;
-    const int64_t vc = cell + int64_t(blockIdx.z) * C.plane;  // variable blockIdx.z
-    o0[vc] = c0[vc];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) o0[cell + v * C.plane] = c0[cell + v * C.plane];
   }
 }
 
@@ -582,7 +581,7 @@ static hipError_t launch_amr_t(const LaunchAmr& L, hipStream_t st) {
     const unsigned nx = L.patches ? std::min(amr_blocks(L.cells), 32u) : amr_blocks(L.cells);
     hipLaunchKernelGGL(fill_ghosts_kernel<T>, dim3(nx, ny), dim3(kAmrBlock), 0, st, a);
   } else if (L.op == kAmrRestrict) {
-    hipLaunchKernelGGL(restrict_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks), 5u),
+    hipLaunchKernelGGL(restrict_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
                        dim3(kAmrBlock), 0, st, a);
   } else if (L.op == kAmrProlong) {
     if (L.cold)
@@ -594,7 +593,7 @@ static hipError_t launch_amr_t(const LaunchAmr& L, hipStream_t st) {
                          dim3(amr_blocks(L.cells), unsigned(L.nlinks), 5u), dim3(kAmrBlock), 0,
                          st, a);
   } else if (L.op == kAmrSnapshot) {
-    hipLaunchKernelGGL(snapshot_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks), 5u),
+    hipLaunchKernelGGL(snapshot_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
                        dim3(kAmrBlock), 0, st, a);
   } else if (L.op == kAmrFlux) {
     hipLaunchKernelGGL(flux_reg_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks), 2u),
