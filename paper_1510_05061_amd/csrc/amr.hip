@@ -188,12 +188,13 @@ __device__ __forceinline__ double mc_slope(double a, double b) {
   return a * b > 0.0 ? copysign(m, a) : 0.0;
 }
 
-// Fine cells (interior, or the stored ghost shell) of link blockIdx.y and
-// variable blockIdx.z, one coarse parent per thread: the parent's value and
-// its three limited slopes are formed once and give each of its children
-// that is written (the variables in parallel: five times the threads of a
-// loop over them, for a latency-bound gather).
-template <class T, bool COLD>
+// Fine cells (interior, or the stored ghost shell) of link blockIdx.y, one
+// coarse parent per thread: the parent's value and its three limited slopes
+// are formed once and give each of its children that is written.  SHELL (a
+// thin ghost shell): only the parents with a ghost child, and variable
+// blockIdx.z per thread; else the whole box of parents, all five variables
+// per thread (their loads issued together).
+template <class T, bool COLD, bool SHELL>
 __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
   const AmrLink L = link_of(a);
   const PatchDev F = fine_patch(a.fpatches, L.fine, a.finset), C = a.patches[L.coarse];
@@ -214,7 +215,7 @@ __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
                  iz = unsigned((nz + 1) >> 1);
   const unsigned oz = pz - iz, oy = py - iy, ox = px - ix;
   const unsigned nz_part = oz * pxy, ny_part = iz * oy * px;
-  const unsigned total = a.ghosts_only ? pxy * pz - ix * iy * iz : pxy * pz;
+  const unsigned total = SHELL ? pxy * pz - ix * iy * iz : pxy * pz;
   // t-th parent outside the block [0, I) along an axis: lo .. -1, then I ..
   auto outside = [&](unsigned t, unsigned I) {
     return int(t) < -lo ? lo + int(t) : int(I) + int(t) + lo;
@@ -227,12 +228,16 @@ __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
   for (unsigned c = blockIdx.x * kAmrBlock + threadIdx.x; c < total;
        c += gridDim.x * kAmrBlock) {
     int pi, pj, pk;
-    if (!a.ghosts_only) {
+    if (!SHELL) {
       const unsigned kk = c / pxy, rem = c - kk * pxy;
       const unsigned jj = rem / px;
       pk = int(kk) + lo;
       pj = int(jj) + lo;
       pi = int(rem - jj * px) + lo;
+      // a parent whose children are all interior has none in the ghost shell
+      if (a.ghosts_only && pi >= 0 && 2 * pi < nx && pj >= 0 && 2 * pj < ny && pk >= 0 &&
+          2 * pk < nz)
+        continue;
     } else if (c < nz_part) {
       const unsigned kk = c / pxy, rem = c - kk * pxy;
       const unsigned jj = rem / px;
@@ -256,8 +261,9 @@ __global__ void __launch_bounds__(kAmrBlock) prolong_kernel(AmrArgs<T> a) {
     }
     const int64_t pc = int64_t(L.ox + pi) + int64_t(L.oy + pj) * C.sy +
                        int64_t(L.oz + pk) * C.sz;
-    {
-      const int v = int(blockIdx.z);
+    const int v0 = SHELL ? int(blockIdx.z) : 0;
+#pragma unroll
+    for (int v = v0; v < (SHELL ? v0 + 1 : 5); ++v) {
       const T* q = c0 + pc + v * C.plane;
       const T* qo = COLD ? o0 + pc + v * C.plane : nullptr;
       // coarse value at offset d, interpolated in time when a start copy is given
@@ -584,14 +590,19 @@ static hipError_t launch_amr_t(const LaunchAmr& L, hipStream_t st) {
     hipLaunchKernelGGL(restrict_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
                        dim3(kAmrBlock), 0, st, a);
   } else if (L.op == kAmrProlong) {
-    if (L.cold)
-      hipLaunchKernelGGL((prolong_kernel<T, true>),
-                         dim3(amr_blocks(L.cells), unsigned(L.nlinks), 5u), dim3(kAmrBlock), 0,
-                         st, a);
-    else
-      hipLaunchKernelGGL((prolong_kernel<T, false>),
-                         dim3(amr_blocks(L.cells), unsigned(L.nlinks), 5u), dim3(kAmrBlock), 0,
-                         st, a);
+    const dim3 grid(amr_blocks(L.cells), unsigned(L.nlinks), L.shell ? 5u : 1u);
+    if (L.shell && !L.ghosts_only) return hipErrorInvalidValue;
+    if (L.cold) {
+      if (L.shell)
+        hipLaunchKernelGGL((prolong_kernel<T, true, true>), grid, dim3(kAmrBlock), 0, st, a);
+      else
+        hipLaunchKernelGGL((prolong_kernel<T, true, false>), grid, dim3(kAmrBlock), 0, st, a);
+    } else {
+      if (L.shell)
+        hipLaunchKernelGGL((prolong_kernel<T, false, true>), grid, dim3(kAmrBlock), 0, st, a);
+      else
+        hipLaunchKernelGGL((prolong_kernel<T, false, false>), grid, dim3(kAmrBlock), 0, st, a);
+    }
   } else if (L.op == kAmrSnapshot) {
     hipLaunchKernelGGL(snapshot_kernel<T>, dim3(amr_blocks(L.cells), unsigned(L.nlinks)),
                        dim3(kAmrBlock), 0, st, a);

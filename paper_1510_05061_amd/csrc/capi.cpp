@@ -2039,19 +2039,25 @@ int check_link(const hydro_ctx* c, const hydro_amr_link& k, bool prolong, bool g
   return HYDRO_OK;
 }
 
-// Coarse parents a prolongation visits for a fine patch of interior
-// extents n: all of them (g = 0), or with g ghost layers only those with a
-// child in the ghost shell (the parents outside the block [0, (n + 1) / 2)
-// along some axis), as the kernel enumerates them.
-int64_t prolong_parents(const int64_t n[3], int64_t g) {
+// Coarse parents of a prolongation for a fine patch of interior extents n
+// and g ghost layers written (0: the interior): the box of every parent of a
+// written cell, and the shell of those outside the block [0, (n + 1) / 2)
+// along some axis (the parents with a ghost child).
+void prolong_parents(const int64_t n[3], int64_t g, int64_t* box, int64_t* shell) {
   const int64_t lo = (-g) >> 1;
-  int64_t box = 1, inner = 1;
+  int64_t b = 1, inner = 1;
   for (int a = 0; a < 3; ++a) {
-    box *= ((n[a] + g - 1) >> 1) - lo + 1;
+    b *= ((n[a] + g - 1) >> 1) - lo + 1;
     inner *= (n[a] + 1) >> 1;
   }
-  return g > 0 ? box - inner : box;
+  *box = b;
+  *shell = g > 0 ? b - inner : 0;
 }
+
+// A ghost prolongation walks only the shell's parents where they are at
+// most 40 % of the box (2 ghost layers on 32^3 patches: 30 %, faster; 4
+// layers: 49 %, slower than the whole box).
+bool prolong_shell(int64_t box, int64_t shell) { return shell > 0 && 10 * shell <= 4 * box; }
 
 int amr_links(hydro_ctx* c, const hydro_amr_link* links, int32_t n, int op, int ghosts_only) {
   if (!c || (!links && n > 0) || n < 0) return fail(HYDRO_EINVAL, "bad arguments");
@@ -2069,17 +2075,25 @@ int amr_links(hydro_ctx* c, const hydro_amr_link* links, int32_t n, int op, int 
     L.npatch = c->npatch;
     L.ghosts_only = ghosts_only;
     L.nlinks = std::min<int32_t>(kAmrLinksPerLaunch, n - b);
-    int64_t most = 0;
+    int64_t most = 0, box = 0, shell = 0;
     for (int32_t i = 0; i < L.nlinks; ++i) {
       const hydro_amr_link& k = links[b + i];
       L.links[i] = AmrLink{k.fine, k.coarse, k.ox, k.oy, k.oz, 0};
       const PatchDev& F = c->patches[size_t(k.fine)];
       // restriction: coarse cells; prolongation: parents of the written cells
-      const int64_t nf[3] = {F.n[0], F.n[1], F.n[2]};
-      const int64_t cells = op == kAmrRestrict
-                                ? int64_t(F.n[0] / 2) * (F.n[1] / 2) * (F.n[2] / 2)
-                                : prolong_parents(nf, ghosts_only ? F.ng : 0);
-      most = std::max(most, cells);
+      if (op == kAmrRestrict) {
+        most = std::max(most, int64_t(F.n[0] / 2) * (F.n[1] / 2) * (F.n[2] / 2));
+      } else {
+        const int64_t nf[3] = {F.n[0], F.n[1], F.n[2]};
+        int64_t pb, ps;
+        prolong_parents(nf, ghosts_only ? F.ng : 0, &pb, &ps);
+        box = std::max(box, pb);
+        shell = std::max(shell, ps);
+      }
+    }
+    if (op == kAmrProlong) {
+      L.shell = ghosts_only && prolong_shell(box, shell) ? 1 : 0;
+      most = L.shell ? shell : box;
     }
     L.cells = most;
     HIP_TRY(launch_amr(L, c->stream));
@@ -2197,17 +2211,29 @@ int level_launch(const hydro_ctx* coarse, const hydro_ctx* fine, const hydro_amr
   L.nlinks = n;
   L.dlinks = dlinks;
   int64_t most = 0;  // most work items of one link (grid sizing)
+  int64_t pbox = 0, pshell = 0;
   for (int32_t i = 0; i < n; ++i) {
     const PatchDev& F = fine->patches[size_t(links[i].fine)];
     const int64_t nf[3] = {F.n[0] - 2 * g, F.n[1] - 2 * g, F.n[2] - 2 * g};
     int64_t cells = 0;
     const int64_t mg = (g + 1) / 2 + 1;  // snapshot margin
-    if (op == kAmrRestrict) cells = (nf[0] / 2) * (nf[1] / 2) * (nf[2] / 2);
-    else if (op == kAmrSnapshot)
+    if (op == kAmrRestrict) {
+      cells = (nf[0] / 2) * (nf[1] / 2) * (nf[2] / 2);
+    } else if (op == kAmrSnapshot) {
       cells = (nf[0] / 2 + 2 * mg) * (nf[1] / 2 + 2 * mg) * (nf[2] / 2 + 2 * mg);
-    else if (op == kAmrProlong) cells = prolong_parents(nf, g);
-    else cells = std::max({nf[1] * nf[2], nf[0] * nf[2], nf[0] * nf[1]}) / 4;
+    } else if (op == kAmrProlong) {
+      int64_t pb, ps;
+      prolong_parents(nf, g, &pb, &ps);
+      pbox = std::max(pbox, pb);
+      pshell = std::max(pshell, ps);
+    } else {
+      cells = std::max({nf[1] * nf[2], nf[0] * nf[2], nf[0] * nf[1]}) / 4;
+    }
     most = std::max(most, cells);
+  }
+  if (op == kAmrProlong) {
+    L.shell = prolong_shell(pbox, pshell) ? 1 : 0;  // the level step fills ghosts only
+    most = L.shell ? pshell : pbox;
   }
   L.cells = most;
   fill(L);

@@ -161,6 +161,8 @@ struct LaunchAmr {
   AmrLink links[kAmrLinksPerLaunch];
   int32_t nlinks;
   int32_t ghosts_only;               // prolongation: the fine ghost shell only
+  int32_t shell;                     // ghost prolongation: walk the shell's parents only
+                                     // (a thin shell), a variable per grid layer
   int64_t cells;                     // most cells one workgroup row walks (grid sizing)
   // Fine side of the links (null: the coarse pool and table).  finset > 0:
   // each fine table entry is a whole stored box without ghosts whose outer
