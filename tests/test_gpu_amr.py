@@ -136,6 +136,30 @@ def test_prolong(prec, ghosts_only):
     b.close()
 
 
+@pytest.mark.parametrize("prec", [hydro.FP64, hydro.FP32])
+@pytest.mark.parametrize("ng", [2, 4])
+def test_prolong_ghost_shell_of_a_large_patch(prec, ng):
+    """Ghost prolongation of a fine patch of 28 x 24 x 20 cells at coarse
+    (4, 4, 4) of a 22 x 20 x 18 coarse patch.  With 2 ghost layers the
+    parents with a ghost child are 37.5 % of the box of parents, so the
+    launch walks only those (a grid layer per variable); with 4 they are
+    58 % and it walks the whole box: both bit for bit against the oracle."""
+    say(f"prolong large patch prec={prec} ng={ng}")
+    dt = np.float64 if prec == hydro.FP64 else np.float32
+    pool, patches = make_pool([(18, 20, 22), (20, 24, 28)], ng, dt, 7)
+    links = [(1, 0, 4, 4, 4)]
+    dev = torch().from_numpy(pool.astype(dt)).to("cuda:0")
+    b = hydro.Batch(dev, patches, 1.4, flags=hydro.FLAG_NO_TUNE)
+    b.fill_ghosts()                                   # coarse ghosts used by the stencil
+    b.prolong(links, ghosts_only=True)
+    got = dev.double().cpu().numpy()
+    C = amr.fill_ghosts(sview(pool, patches[0]), ng, (P,) * 6)
+    Ff = amr.fill_ghosts(sview(pool, patches[1]), ng, (P,) * 6)
+    want = amr.prolong(C, ng, Ff, ng, (4, 4, 4), ghosts_only=True)
+    np.testing.assert_array_equal(sview(got, patches[1]), want.astype(dt).astype(np.float64))
+    b.close()
+
+
 def test_prolong_then_restrict_returns_the_coarse_cells():
     say("prolong-restrict round trip")
     b, dev, pool, patches, links, dt = _amr_batch(hydro.FP64, seed=5)
