@@ -24,7 +24,11 @@ Prints ONE JSON line.  Fields beyond the driver's contract:
                  planes or single-grid windows: two sweeps per HBM pass,
                  arithmetic-bound) it is reported as bound "alu":
                  algorithmic flops over its duration against the FP32 vector
-                 peak without packed FP32 (78.6 TFLOP/s);
+                 peak without packed FP32 (78.6 TFLOP/s), and `valu_issue`:
+                 its VALU wave instructions per launch from the committed
+                 counter summary (SQ_INSTS_VALU) over its duration against
+                 the chip's issue rate (one wave64 instruction per SIMD
+                 every 4 cycles: 6.144e11/s), the bound that holds it;
   step_roofline  the whole step against the same peak (120 B per FP32
                  zone-update, the three-sweep method's algorithmic bytes);
                  when a step fuses the x and y sweeps it moves 80 B per
@@ -793,9 +797,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def counter_traffic(workload, kernel, precision):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when it is missing or was taken on different kernel source."""
+def counter_entry(workload, kernel, precision):
+    """The committed counter summary's entry for `kernel`, or None when it is
+    missing or was taken on different kernel source."""
     try:
         data = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
@@ -805,8 +809,21 @@ def counter_traffic(workload, kernel, precision):
     for e in data.get("entries", []):
         if e.get("workload") == workload and e.get("kernel") == kernel and \
                 e.get("precision") == precision:
-            return e.get("bytes_per_launch")
+            return e
     return None
+
+
+def counter_traffic(workload, kernel, precision):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None (see counter_entry)."""
+    e = counter_entry(workload, kernel, precision)
+    return e.get("bytes_per_launch") if e else None
+
+
+# VALU issue rate of MI355X: each of the 4 SIMDs of a CU starts one wave64
+# instruction every 4 cycles (16 lanes per cycle), so 256 CUs at 2.4 GHz
+# issue 256 x 2.4e9 = 6.144e11 wave instructions per second
+VALU_WAVE_ISSUE_PER_S = 256 * 2.4e9
 
 
 def main():
@@ -877,6 +894,15 @@ def main():
                 "kernel": kname, "mean_ms": k32[dom], "flops_per_launch": flops,
                 "flops_per_zone_sweep": FLOPS_PER_ZONE_SWEEP, "hbm_bytes_per_launch": bytes_launch,
                 "hbm_gbs": achieved, "peak_packed": FP32_VECTOR_PEAK_PACKED_TFLOPS}
+        # what binds it: its counted VALU instructions (SQ_INSTS_VALU from the
+        # committed counter summary) over its duration against the issue rate
+        e = counter_entry(args.workload, names[dom].split(" (")[0], "fp32")
+        if e and e.get("valu_wave_insts_per_launch"):
+            wi = e["valu_wave_insts_per_launch"]
+            roof["valu_issue"] = {"wave_insts_per_launch": wi,
+                                  "achieved_per_s": wi / (k32[dom] * 1e-3),
+                                  "peak_per_s": VALU_WAVE_ISSUE_PER_S,
+                                  "frac": wi / (k32[dom] * 1e-3) / VALU_WAVE_ISSUE_PER_S}
     out = {
         "metric": METRIC,
         "value": value,
