@@ -294,18 +294,19 @@ __global__ void __launch_bounds__(kDiagBlock) profile_final_kernel(const double*
 // One-dimensional kinetic-energy spectrum along x
 // --------------------------------------------------------------------------
 //
-// A workgroup owns groups of P whole x-lines (y, z): groups blockIdx.x,
-// blockIdx.x + gridDim.x, ...  For each line it widens rho and m to FP64,
-// forms u = m / rho (IEEE division), packs two complex lines z1 = ux + i uy
-// and z2 = uz, and transforms all 2P in LDS with the in-place mixed-radix
-// Stockham FFT of fft.hpp (radices 16, 4, 2, 3; output in natural order).
-// For a real pair packed as a + i b,
+// A workgroup owns groups of P (even) whole x-lines (y, z): groups
+// blockIdx.x, blockIdx.x + gridDim.x, ...  For each line it widens rho and m
+// to FP64 and forms u = m / rho (IEEE division); it packs the complex lines
+// ux + i uy of every x-line and uz + i uz' of every pair of x-lines (3P/2
+// lines, no line of zeros), and transforms them in LDS with the in-place
+// mixed-radix Stockham FFT of fft.hpp (radices 16, 4, 2, 3; output in
+// natural order).  For a real pair packed as a + i b,
 // |A(k)|^2 + |B(k)|^2 = (|Z(k)|^2 + |Z(N-k)|^2) / 2, so the power summed over
-// the three components needs no unpacking.  Thread t accumulates k = t,
+// the components and lines needs no unpacking.  Thread t accumulates k = t,
 // t + 256, ... over its workgroup's lines (fixed order), writes its
 // partial spectrum, and one workgroup sums the partials in a fixed order.
 
-// x-lines per pass: the two complex lines of every x-line of a pass fill at
+// x-lines per pass: the 3/2 complex lines of every x-line of a pass fill at
 // most kSpecElems complex values of LDS
 constexpr int kSpecElems = 4096;
 constexpr int kSpecBlock = 512;  // threads of the spectrum kernel
@@ -319,7 +320,8 @@ __global__ void __launch_bounds__(kSpecBlock, P >= 4 ? 2 : 4) spectrum_kernel(Di
   const PatchDev& Pd = a.single;
   const int n = sp.n;
   double2* W = sbuf;       // W[t] = exp(-2 pi i t / n)
-  double2* buf = sbuf + n;  // 2P complex lines (fft_pad slots), transformed in place
+  double2* buf = sbuf + n;  // 3P/2 complex lines (fft_pad slots), transformed in place
+  static_assert(P % 2 == 0, "x-lines are paired for their uz lines");
   for (int t = threadIdx.x; t < n; t += kSpecBlock) {
     double sn, cs;
     sincospi(-2.0 * double(t) / double(n), &sn, &cs);
@@ -361,32 +363,37 @@ __global__ void __launch_bounds__(kSpecBlock, P >= 4 ? 2 : 4) spectrum_kernel(Di
       const int lp = c / n;
       const int x = c - lp * n;
       if (lp < P) {
-        double2 z1 = make_double2(0.0, 0.0), z2 = z1;  // a missing last line: zeros
+        double2 z1 = make_double2(0.0, 0.0);  // a missing last line: zeros
+        double uz = 0.0;
         if (grp * P + lp < lines) {
           const double r = double(fr[i]);
           z1 = make_double2(double(fm[i][0]) / r, double(fm[i][1]) / r);
-          z2 = make_double2(double(fm[i][2]) / r, 0.0);
+          uz = double(fm[i][2]) / r;
         }
-        buf[fft_pad(2 * lp * n + x)] = z1;
-        buf[fft_pad((2 * lp + 1) * n + x)] = z2;
+        buf[fft_pad(lp * n + x)] = z1;
+        // the real (even lp) or imaginary (odd lp) part of the pair's uz line
+        double* zp = reinterpret_cast<double*>(&buf[fft_pad((P + (lp >> 1)) * n + x)]);
+        zp[lp & 1] = uz;
       }
     }
     if (grp + int(gridDim.x) < groups) fetch(grp + gridDim.x);
     __syncthreads();
-    fft_lines_inplace<kSpecElems, kSpecBlock>(buf, 2 * P, n, sp, W);
+    fft_lines_inplace<kSpecElems, kSpecBlock>(buf, 3 * P / 2, n, sp, W);
+    // the lines of the pass that hold data: its x-lines, then the uz line of
+    // every pair with at least one x-line (a missing x-line left zeros)
+    const int have = min(P, lines - grp * P);
+    const int nz = (have + 1) >> 1;
 #pragma unroll
-    for (int lp = 0; lp < P; ++lp) {
-      if (grp * P + lp >= lines) break;
-      const int z = 2 * lp * n;
+    for (int q = 0; q < P + P / 2; ++q) {
+      if (q < P ? q >= have : q - P >= nz) continue;
+      const int z = q * n;
 #pragma unroll
       for (int i = 0; i < KPT; ++i) {
         const int k = threadIdx.x + i * kSpecBlock;
         if (k <= n / 2) {
           const int km = k == 0 ? 0 : n - k;
           const double2 a1 = buf[fft_pad(z + k)], b1 = buf[fft_pad(z + km)];
-          const double2 a2 = buf[fft_pad(z + n + k)], b2 = buf[fft_pad(z + n + km)];
-          acc[i] += 0.5 * ((a1.x * a1.x + a1.y * a1.y) + (b1.x * b1.x + b1.y * b1.y)) +
-                    0.5 * ((a2.x * a2.x + a2.y * a2.y) + (b2.x * b2.x + b2.y * b2.y));
+          acc[i] += 0.5 * ((a1.x * a1.x + a1.y * a1.y) + (b1.x * b1.x + b1.y * b1.y));
         }
       }
     }
@@ -498,14 +505,14 @@ static hipError_t launch_spectrum_t(const LaunchDiag& L, hipStream_t st) {
   FftPlan sp;
   if (!make_fft_plan(L.single.n[0], sp)) return hipErrorInvalidValue;
   // x-lines per pass: 8 (an FP64 state: 4, for its prefetch registers) for
-  // lines of up to 256 cells, else 2 (2P n <= kSpecElems)
+  // lines of up to 256 cells, else 2 (3P/2 n <= kSpecElems)
   constexpr int PS = sizeof(T) == 8 ? 4 : 8;
   if (sp.n <= 256) {
-    const size_t lds = size_t(sp.n + fft_lds(2 * PS * sp.n)) * sizeof(double2);
+    const size_t lds = size_t(sp.n + fft_lds(3 * PS / 2 * sp.n)) * sizeof(double2);
     hipLaunchKernelGGL((spectrum_kernel<T, PS>), dim3(unsigned(L.chunks)), dim3(kSpecBlock), lds,
                        st, a, sp);
   } else {
-    const size_t lds = size_t(sp.n + fft_lds(2 * 2 * sp.n)) * sizeof(double2);
+    const size_t lds = size_t(sp.n + fft_lds(3 * sp.n)) * sizeof(double2);
     hipLaunchKernelGGL((spectrum_kernel<T, 2>), dim3(unsigned(L.chunks)), dim3(kSpecBlock), lds,
                        st, a, sp);
   }
