@@ -9,7 +9,8 @@
 // so that sum_K E[K] = <|u|^2> / 2.
 //
 // Four passes over HBM, all in FP64 (an FP32 state is widened first):
-//   x  each x-line: u = m / rho, packed as (ux + i uy, uz), two complex FFTs
+//   x  each x-line: u = m / rho; ux + i uy of every x-line and uz + i uz' of
+//      every pair of x-lines as complex lines (3/2 complex FFTs per x-line)
 //      in LDS, unpacked into the three half spectra kx = 0 .. nx/2 (real
 //      input: the other half is their conjugate); written as three planes
 //      U_c[z][y][kx] of complex values.
@@ -108,31 +109,41 @@ __global__ void __launch_bounds__(kS3Block) spec3_x_kernel(Spec3Args a, FftPlan 
       const int e = threadIdx.x + i * kS3Block;
       const int lp = int(a.dnx.div(uint32_t(e))), x = e - lp * nx, line = grp * G + lp;
       if (lp < G) {
-        double2 z1 = make_double2(0.0, 0.0), z2 = z1;  // lines past the end: zeros
+        double2 z1 = make_double2(0.0, 0.0);  // lines past the end: zeros
+        double uz = 0.0;
         if (line < lines) {
           const double rho = double(r[i]);
           z1 = make_double2(double(m[i][0]) / rho, double(m[i][1]) / rho);
-          z2 = make_double2(double(m[i][2]) / rho, 0.0);
+          uz = double(m[i][2]) / rho;
         }
-        buf[fft_pad(2 * lp * nx + x)] = z1;
-        buf[fft_pad((2 * lp + 1) * nx + x)] = z2;
+        buf[fft_pad(lp * nx + x)] = z1;
+        // uz of x-lines 2q and 2q + 1 as the real and imaginary parts of
+        // line G + q (the odd last x-line of a pass with zeros beside it)
+        double* zp = reinterpret_cast<double*>(&buf[fft_pad((G + (lp >> 1)) * nx + x)]);
+        zp[lp & 1] = uz;
+        if ((G & 1) && lp == G - 1) zp[1] = 0.0;
       }
     }
     __syncthreads();
-    fft_lines_inplace<kS3Elems, kS3Block>(buf, 2 * G, nx, px, W);
-    // Z1 = X + i Y with X, Y the DFTs of the real lines ux, uy:
-    // X(k) = (Z1(k) + conj Z1(n-k)) / 2, Y(k) = -i (Z1(k) - conj Z1(n-k)) / 2
+    fft_lines_inplace<kS3Elems, kS3Block>(buf, G + (G + 1) / 2, nx, px, W);
+    // Z = X + i Y with X, Y the DFTs of two real lines (ux and uy of an
+    // x-line, or uz of two x-lines):
+    // X(k) = (Z(k) + conj Z(n-k)) / 2, Y(k) = -i (Z(k) - conj Z(n-k)) / 2
     for (int e = threadIdx.x; e < G * nh; e += kS3Block) {
       const int lp = int(a.dnh.div(uint32_t(e))), k = e - lp * nh, line = grp * G + lp;
       if (line >= lines) continue;
       const int z = int(a.dny.div(uint32_t(line))), y = line - z * ny;
-      const double2 zk = buf[fft_pad(2 * lp * nx + k)];
-      const double2 zm = conj2(buf[fft_pad(2 * lp * nx + (k == 0 ? 0 : nx - k))]);
+      const int km = k == 0 ? 0 : nx - k;
+      const double2 zk = buf[fft_pad(lp * nx + k)];
+      const double2 zm = conj2(buf[fft_pad(lp * nx + km)]);
       const double2 s = cadd(zk, zm), d = cmi(csub(zk, zm));
       const int64_t o = (int64_t(z) * ny + y) * nh + k;
       a.U[o] = make_double2(0.5 * s.x, 0.5 * s.y);
       a.U[o + a.cplane] = make_double2(0.5 * d.x, 0.5 * d.y);
-      a.U[o + 2 * a.cplane] = buf[fft_pad((2 * lp + 1) * nx + k)];
+      const int q = (G + (lp >> 1)) * nx;
+      const double2 wk = buf[fft_pad(q + k)], wm = conj2(buf[fft_pad(q + km)]);
+      const double2 w = (lp & 1) ? cmi(csub(wk, wm)) : cadd(wk, wm);
+      a.U[o + 2 * a.cplane] = make_double2(0.5 * w.x, 0.5 * w.y);
     }
   }
 }
@@ -330,7 +341,7 @@ static hipError_t launch_s3(const LaunchSpec3& L, hipStream_t st) {
   if (e != hipSuccess) return e;
   const int groups = (P.n[1] * P.n[2] + a.gx - 1) / a.gx;
   const int xgrid = std::min(groups, 8 * std::max(1, L.cu_count));
-  const size_t xlds = size_t(P.n[0] + fft_lds(2 * a.gx * P.n[0])) * sizeof(double2);
+  const size_t xlds = size_t(P.n[0] + fft_lds((a.gx + (a.gx + 1) / 2) * P.n[0])) * sizeof(double2);
   hipLaunchKernelGGL(spec3_x_kernel<T>, dim3(unsigned(xgrid)), dim3(kS3Block), xlds, st, a, px);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t ylds = size_t(P.n[1] + fft_lds(kS3T * (P.n[1] + 1))) * sizeof(double2);
