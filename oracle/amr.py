@@ -119,10 +119,14 @@ def restrict(F, ng_f, C, ng_c, o):
 
 
 def mc(a, b):
-    """Monotonised-central slope from one-sided differences a, b."""
+    """Monotonised-central slope from one-sided differences a, b: zero unless
+    a and b are both strictly positive or both strictly negative, else
+    sign(a) min(2|a|, 2|b|, |a+b|/2) (van Leer 1977), the sweeps' reading
+    (a sign test, not a product that can underflow)."""
     with np.errstate(invalid="ignore"):
         m = np.minimum(np.minimum(2.0 * np.abs(a), 2.0 * np.abs(b)), 0.5 * np.abs(a + b))
-    return np.where(a * b > 0.0, np.copysign(m, a), 0.0)
+    same = ((a > 0.0) & (b > 0.0)) | ((a < 0.0) & (b < 0.0))
+    return np.where(same, np.copysign(m, a), 0.0)
 
 
 def prolong(C, ng_c, F, ng_f, o, ghosts_only=False):

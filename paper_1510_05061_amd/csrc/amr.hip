@@ -182,10 +182,13 @@ __global__ void __launch_bounds__(kAmrBlock) restrict_kernel(AmrArgs<T> a) {
   }
 }
 
-// Monotonised-central slope from one-sided differences a and b.
+// Monotonised-central slope from one-sided differences a and b: zero unless
+// both are strictly positive or both strictly negative (a sign test: a
+// product of two tiny differences could underflow to zero).
 __device__ __forceinline__ double mc_slope(double a, double b) {
   const double m = fmin(fmin(2.0 * fabs(a), 2.0 * fabs(b)), 0.5 * fabs(a + b));
-  return a * b > 0.0 ? copysign(m, a) : 0.0;
+  const bool same = (a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0);
+  return same ? copysign(m, a) : 0.0;
 }
 
 // Fine cells (interior, or the stored ghost shell) of link blockIdx.y, one

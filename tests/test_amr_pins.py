@@ -33,6 +33,24 @@ def test_periodic_and_outflow_fill_equal_numpy_pad_of_the_interior(ng):
         np.testing.assert_array_equal(S, want)
 
 
+@pytest.mark.parametrize("ng", [1, 3])
+def test_periodic_and_outflow_fill_by_index_formula(ng):
+    # every stored cell (i, j, k), ghosts included, from the interior cell
+    # the boundary maps it to, written out with Python loops: periodic
+    # i -> i mod n, outflow i -> min(max(i, 0), n - 1), per axis
+    U = rand_state((3, 4, 5), 4)
+    nz, ny, nx = U.shape[1:]
+    for bc in (P, O):
+        S = amr.fill_ghosts(stored(U, ng), ng, (bc,) * 6)
+        def src(i, n):
+            return i % n if bc == P else min(max(i, 0), n - 1)
+        for k in range(-ng, nz + ng):
+            for j in range(-ng, ny + ng):
+                for i in range(-ng, nx + ng):
+                    want = U[:, src(k, nz), src(j, ny), src(i, nx)]
+                    assert np.array_equal(S[:, k + ng, j + ng, i + ng], want), (bc, i, j, k)
+
+
 def test_reflect_fill_is_a_mirror_with_the_normal_momentum_negated():
     ng = 3
     U = rand_state((6, 5, 7), 2)
@@ -143,3 +161,14 @@ def test_prolong_of_a_jump_keeps_flat_regions_flat():
     # coarse x-cells 0..3 with interior index <= 1 (stored 2..3) sit on flat
     # ground: their children equal the coarse value exactly
     np.testing.assert_array_equal(F[:, :, :, :2], 1.0)
+
+
+def test_limiter_is_a_sign_test_not_a_product():
+    # two one-sided differences of one strict sign whose product underflows
+    # keep the limited slope min(2|a|, 2|b|, |a+b|/2); opposite signs or a
+    # zero give none (van Leer's limiter; the sweeps read it the same way)
+    a = np.array([1e-200, -1e-200, 1e-200, 0.0, 3.0])
+    b = np.array([3e-200, -1e-200, -1e-200, 1.0, 1.0])
+    assert np.all(a * b == np.array([0.0, 0.0, -0.0, 0.0, 3.0]))   # the products underflow
+    np.testing.assert_array_equal(amr.mc(a, b),
+                                  np.array([2e-200, -1e-200, 0.0, 0.0, 2.0]))
